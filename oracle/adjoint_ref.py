@@ -1,0 +1,165 @@
+"""Second derivatives of the swap-potential energy, per term, in FP64.
+
+TEST INFRASTRUCTURE ONLY.  The paper defines the energy (Sec. 2: eq. 2b,
+eq. pot, eq. 3bp); its derivatives are the plain calculus of those terms.
+
+* ``hvp``: H v with H = d^2 E / dx dx (so the force JVP is -H v).  Pair term
+  phi(r), r = |x_j - x_i|, D = v_j - v_i, dr = rhat.D:
+      (Hv)_j = phi'' dr rhat + (phi'/r)(D - dr rhat),   (Hv)_i = -(Hv)_j.
+  Triplet term Lambda u(r_a) u(r_b) with centre c and partners a, b,
+  D_a = v_a - v_c, dr_a = rhat_a.D_a:
+      (Hv)_a = Lambda [(u''_a dr_a u_b + u'_a u'_b dr_b) rhat_a
+                       + u'_a u_b (D_a - dr_a rhat_a)/r_a],
+      (Hv)_b symmetric, (Hv)_c = -((Hv)_a + (Hv)_b).
+  u'' jumps at r_min and the pair energy jumps at r_cut, so H is defined
+  almost everywhere; tests keep finite-difference stencils away from both.
+* ``param_grad``: dE/d(eps, sigma, lambda) of every table entry at fixed
+  r_cut.  u = vhat does not depend on eps; d u / d sigma = -(dv/dsigma)/eps
+  beyond r_min (u is continuous at the moving r_min, so the boundary adds
+  nothing); Lambda_ijk = sqrt(Lambda_ij Lambda_ik) contributes half of
+  Lambda_ijk/lambda (or /eps) for each of its two entries that is the entry.
+* ``force_param_vjp``: a . dF/d(theta) for theta = (eps, sigma, lambda) of
+  every entry, by central differences of ``swap_ref`` forces in the
+  parameters (used only on small systems).
+
+Parity status: pinned by central finite differences of ``swap_ref`` (forces
+for ``hvp``, energy for ``param_grad``) and by the identities
+dE/dlambda = E3/lambda and dE/deps = (E2_swap + E3)/eps of a one-entry system.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import swap_ref
+from .swap_ref import KIND_SWAP, KIND_WCA
+
+
+def hvp(pos, types, L, table, v):
+    """Hessian of the total energy applied to v [N,3] (FP64)."""
+    P = swap_ref.interacting_pairs(pos, types, L, table)
+    N = P["N"]
+    v = np.asarray(v, dtype=np.float64)
+    out = np.zeros((N, 3))
+    i, j, d = P["i"], P["j"], P["d"]
+    r = np.sqrt(P["r2"])
+    _, d1, d2 = swap_ref.pair_phi(P["kind"], r, P["eps"], P["sigma"], P["n"])
+    rh = d / r[:, None]
+    D = v[j] - v[i]
+    dr = np.einsum("pa,pa->p", rh, D)
+    hj = (d2 * dr)[:, None] * rh + (d1 / r)[:, None] * (D - dr[:, None] * rh)
+    np.add.at(out, j, hj)
+    np.add.at(out, i, -hj)
+
+    E = swap_ref.directed_swap_edges(P)
+    a, b = swap_ref.triplets(E, N)
+    if a.size:
+        Lt = swap_ref.triplet_lambda(E, a, b)
+        c, pa, pb = E["c"][a], E["p"][a], E["p"][b]
+        ra, rb = E["r"][a], E["r"][b]
+        rha, rhb = E["d"][a] / ra[:, None], E["d"][b] / rb[:, None]
+        Da, Db = v[pa] - v[c], v[pb] - v[c]
+        dra = np.einsum("pa,pa->p", rha, Da)
+        drb = np.einsum("pa,pa->p", rhb, Db)
+        ua, ub = E["u"][a], E["u"][b]
+        u1a, u1b = E["u1"][a], E["u1"][b]
+        u2a, u2b = E["u2"][a], E["u2"][b]
+        ha = (Lt * (u2a * dra * ub + u1a * u1b * drb))[:, None] * rha \
+            + (Lt * u1a * ub / ra)[:, None] * (Da - dra[:, None] * rha)
+        hb = (Lt * (u2b * drb * ua + u1b * u1a * dra))[:, None] * rhb \
+            + (Lt * u1b * ua / rb)[:, None] * (Db - drb[:, None] * rhb)
+        np.add.at(out, pa, ha)
+        np.add.at(out, pb, hb)
+        np.add.at(out, c, -(ha + hb))
+    return out
+
+
+def param_grad(pos, types, L, table):
+    """dE/d(eps, sigma, lambda) per table entry -> array [nt, nt, 3].
+
+    Entry (a,b) and (b,a) are one parameter; the gradient is reported on both
+    (symmetric), each holding the full derivative with respect to that shared
+    parameter.
+    """
+    P = swap_ref.interacting_pairs(pos, types, L, table)
+    nt = table.kind.shape[0]
+    N = P["N"]
+    g = np.zeros((nt, nt, 3))
+    ty = np.asarray(types, dtype=np.int64)
+
+    def entry_key(ti, tj):
+        lo, hi = np.minimum(ti, tj), np.maximum(ti, tj)
+        return lo * nt + hi
+
+    acc = np.zeros((nt * nt, 3))
+    r = np.sqrt(P["r2"])
+    key = entry_key(ty[P["i"]], ty[P["j"]])
+    kind, eps, sig, n = P["kind"], P["eps"], P["sigma"], P["n"]
+    nn = np.where(kind == KIND_WCA, 6.0, n)
+    phi = swap_ref.mie(r, eps, sig, nn) + np.where(kind == KIND_WCA, eps, 0.0)
+    np.add.at(acc[:, 0], key, phi / eps)                                 # phi is linear in eps
+    np.add.at(acc[:, 1], key, swap_ref.mie_dsigma(r, eps, sig, nn))
+
+    E = swap_ref.directed_swap_edges(P)
+    a, b = swap_ref.triplets(E, N)
+    if a.size:
+        Lt = swap_ref.triplet_lambda(E, a, b)
+        c = E["c"][a]
+        ka = entry_key(ty[c], ty[E["p"][a]])
+        kb = entry_key(ty[c], ty[E["p"][b]])
+        ua, ub = E["u"][a], E["u"][b]
+        e = Lt * ua * ub
+        # Lambda_ijk = sqrt(lam_a eps_a lam_b eps_b): d/dlam_a = Lambda/(2 lam_a)
+        for kk, lamk, epsk in ((ka, E["lam"][a], E["eps"][a]), (kb, E["lam"][b], E["eps"][b])):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                dl = np.where(lamk != 0.0, 0.5 * e / lamk, 0.0)
+            np.add.at(acc[:, 2], kk, dl)
+            np.add.at(acc[:, 0], kk, 0.5 * e / epsk)
+        # d lambda-derivative when lambda = 0 : E3 is linear in sqrt(lam_a lam_b);
+        # for a one-entry system dE/dlam = sum u_a u_b eps.
+        zero = (E["lam"][a] == 0.0) & (E["lam"][b] == 0.0) & (ka == kb)
+        if np.any(zero):
+            np.add.at(acc[:, 2], ka[zero], (E["eps"][a] * ua * ub)[zero])
+        # sigma through u beyond r_min
+        ra, rb = E["r"][a], E["r"][b]
+        inside_a = E["r2"][a] <= E["rmin2"][a]
+        inside_b = E["r2"][b] <= E["rmin2"][b]
+        dua = np.where(inside_a, 0.0, -swap_ref.mie_dsigma(ra, 1.0, E["sigma"][a], E["n"][a]))
+        dub = np.where(inside_b, 0.0, -swap_ref.mie_dsigma(rb, 1.0, E["sigma"][b], E["n"][b]))
+        np.add.at(acc[:, 1], ka, Lt * dua * ub)
+        np.add.at(acc[:, 1], kb, Lt * ua * dub)
+    for x in range(nt):
+        for y in range(nt):
+            g[x, y] = acc[min(x, y) * nt + max(x, y)]
+    return g
+
+
+def _with_param(table, a, b, which, value):
+    t = table.copy()
+    arr = {0: t.epsilon, 1: t.sigma, 2: t.lam}[which]
+    arr[a, b] = value
+    arr[b, a] = value
+    return t
+
+
+def force_param_vjp(pos, types, L, table, adj, h=1e-6):
+    """sum_m adj_m . dF_m/dtheta for theta = (eps, sigma, lambda) of each entry."""
+    nt = table.kind.shape[0]
+    out = np.zeros((nt, nt, 3))
+    adj = np.asarray(adj, dtype=np.float64)
+    for a in range(nt):
+        for b in range(a, nt):
+            if table.kind[a, b] == 0:
+                continue
+            for w, arr in ((0, table.epsilon), (1, table.sigma), (2, table.lam)):
+                if w == 2 and table.kind[a, b] != KIND_SWAP:
+                    continue
+                p0 = float(arr[a, b])
+                step = h * max(1.0, abs(p0))
+                Fp = swap_ref.evaluate(pos, types, L, _with_param(table, a, b, w, p0 + step),
+                                       scales=False)["F"]
+                Fm = swap_ref.evaluate(pos, types, L, _with_param(table, a, b, w, p0 - step),
+                                       scales=False)["F"]
+                val = float(np.sum(adj * (Fp - Fm))) / (2.0 * step)
+                out[a, b, w] = val
+                out[b, a, w] = val
+    return out

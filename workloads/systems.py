@@ -1,0 +1,276 @@
+"""Input generators: positions, types, velocities, boxes and coefficient tables.
+
+Conventions shared by every generated system
+--------------------------------------------
+* Cubic periodic box, origin centred.  The edge ``L`` is rounded to the
+  nearest FP32 value (so that the engine's FP32 positions and the FP64 oracle
+  see the same box).
+* Positions are FP32 values in ``[-L/2, L/2)`` (shape ``(N, 3)``).
+* ``types`` is int32 in ``[0, ntypes)``; ``tags`` are ``0..N-1``.
+* Coefficient tables are symmetric ``ntypes x ntypes`` arrays of
+  (kind, epsilon, sigma, n, r_cut, lambda), one entry per unordered type pair,
+  following the per-type-pair coefficient set of the paper's potential
+  (Sec. 2, the revcross coefficient list: sigma, n, epsilon, lambda3, plus a
+  cutoff).  ``kind`` selects the pair function: 0 = no interaction,
+  1 = swap (generalized LJ + three-body), 2 = WCA (purely repulsive LJ).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+KIND_NONE = 0
+KIND_SWAP = 1
+KIND_WCA = 2
+# WCA is the 12-6 LJ cut at its minimum, 2^(1/6) sigma (Weeks-Chandler-Andersen).
+WCA_CUT_FACTOR = 2.0 ** (1.0 / 6.0)
+
+
+@dataclasses.dataclass
+class PairTable:
+    """Symmetric per-type-pair coefficient table (float64 / int arrays)."""
+    kind: np.ndarray      # int32 [nt, nt]
+    epsilon: np.ndarray   # float64 [nt, nt]
+    sigma: np.ndarray     # float64 [nt, nt]
+    n: np.ndarray         # int32 [nt, nt]   (exponent of the swap pair; 6 for WCA)
+    rcut: np.ndarray      # float64 [nt, nt]
+    lam: np.ndarray       # float64 [nt, nt] (three-body lambda; 0 unless swap)
+
+    @property
+    def ntypes(self) -> int:
+        return int(self.kind.shape[0])
+
+    @staticmethod
+    def empty(nt: int) -> "PairTable":
+        return PairTable(kind=np.zeros((nt, nt), np.int32),
+                         epsilon=np.zeros((nt, nt)), sigma=np.ones((nt, nt)),
+                         n=np.full((nt, nt), 6, np.int32), rcut=np.zeros((nt, nt)),
+                         lam=np.zeros((nt, nt)))
+
+    def set(self, a: int, b: int, kind: int, epsilon: float = 1.0, sigma: float = 1.0,
+            n: int = 6, rcut: Optional[float] = None, lam: float = 0.0) -> "PairTable":
+        if rcut is None:
+            rcut = WCA_CUT_FACTOR * sigma if kind == KIND_WCA else 0.0
+        for (p, q) in ((a, b), (b, a)):
+            self.kind[p, q] = kind
+            self.epsilon[p, q] = epsilon
+            self.sigma[p, q] = sigma
+            self.n[p, q] = n
+            self.rcut[p, q] = rcut
+            self.lam[p, q] = lam
+        return self
+
+    def copy(self) -> "PairTable":
+        return PairTable(*(np.array(getattr(self, f.name)) for f in dataclasses.fields(self)))
+
+    def with_lambda(self, lam: float) -> "PairTable":
+        t = self.copy()
+        t.lam = np.where(t.kind == KIND_SWAP, float(lam), 0.0)
+        return t
+
+    def max_rcut(self) -> float:
+        m = np.where(self.kind != KIND_NONE, self.rcut, 0.0)
+        return float(m.max())
+
+
+@dataclasses.dataclass
+class System:
+    """One periodic system: FP32 positions and the data the engine needs."""
+    pos: np.ndarray            # float32 [N, 3] in [-L/2, L/2)
+    types: np.ndarray          # int32 [N]
+    L: float                   # FP32-exact box edge (as a Python float)
+    table: PairTable
+    mass: np.ndarray           # float64 [ntypes]
+    vel: Optional[np.ndarray] = None   # float32 [N, 3]
+    name: str = ""
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def tags(self) -> np.ndarray:
+        return np.arange(self.N, dtype=np.int32)
+
+    @property
+    def box(self) -> np.ndarray:
+        return np.array([self.L, self.L, self.L], dtype=np.float64)
+
+
+def fp32_box(N: int, density: float) -> float:
+    """Cubic box edge for N particles at number density ``density``, rounded to FP32."""
+    return float(np.float32((N / density) ** (1.0 / 3.0)))
+
+
+def wrap_fp32(x: np.ndarray, L: float) -> np.ndarray:
+    """Round float64 coordinates to FP32 and fold them into [-L/2, L/2)."""
+    h = np.float32(0.5 * L)
+    xf = np.asarray(x, dtype=np.float64)
+    xf = xf - L * np.floor(xf / L + 0.5)
+    out = xf.astype(np.float32)
+    out = np.where(out >= h, out - np.float32(L), out)
+    out = np.where(out < -h, out + np.float32(L), out)
+    return out.astype(np.float32)
+
+
+def rsa_positions(rng: np.random.Generator, L: float, counts: Sequence[int],
+                  min_dist: np.ndarray, max_rounds: int = 200) -> tuple:
+    """Random sequential addition of ``counts[t]`` particles of each type.
+
+    A candidate is rejected when its periodic distance to any accepted
+    particle of type u is <= ``min_dist[t, u]``.  Types are placed in the order
+    given; candidates are drawn in batches and conflicts inside a batch are
+    resolved by dropping the later candidate.  Returns (pos float32, types).
+    """
+    nt = len(counts)
+    placed: List[np.ndarray] = [np.zeros((0, 3), np.float32) for _ in range(nt)]
+    half = 0.5 * L
+    for t in range(nt):
+        need = int(counts[t])
+        rounds = 0
+        while need > 0:
+            rounds += 1
+            if rounds > max_rounds:
+                raise RuntimeError("random sequential addition did not converge")
+            m = max(16, int(need * 1.15) + 16)
+            cand = wrap_fp32(rng.uniform(-half, half, size=(m, 3)), L)
+            c64 = cand.astype(np.float64) + half
+            c64 = np.minimum(c64, np.nextafter(L, 0.0))
+            keep = np.ones(m, dtype=bool)
+            for u in range(nt):
+                if placed[u].shape[0] == 0:
+                    continue
+                thr = float(min_dist[t, u])
+                if thr <= 0:
+                    continue
+                p64 = np.minimum(placed[u].astype(np.float64) + half, np.nextafter(L, 0.0))
+                tree = cKDTree(p64, boxsize=L)
+                d, _ = tree.query(c64, k=1, distance_upper_bound=thr * 1.000001 + 1e-12)
+                keep &= ~(d <= thr * 1.000001)
+            idx = np.nonzero(keep)[0]
+            sub = c64[idx]
+            thr = float(min_dist[t, t])
+            if thr > 0 and sub.shape[0] > 1:
+                tree = cKDTree(sub, boxsize=L)
+                pairs = tree.query_pairs(thr * 1.000001, output_type="ndarray")
+                if pairs.size:
+                    drop = np.zeros(sub.shape[0], dtype=bool)
+                    # greedy: walk pairs in order, drop the later index if both still kept
+                    for a, b in pairs[np.lexsort((pairs[:, 1], pairs[:, 0]))]:
+                        if not drop[a] and not drop[b]:
+                            drop[b] = True
+                    idx = idx[~drop]
+            idx = idx[:need]
+            placed[t] = np.concatenate([placed[t], cand[idx]], axis=0)
+            need -= idx.size
+    pos = np.concatenate(placed, axis=0).astype(np.float32)
+    types = np.concatenate([np.full(int(c), t, np.int32) for t, c in enumerate(counts)])
+    return pos, types
+
+
+def maxwell_velocities(rng: np.random.Generator, types: np.ndarray, mass: np.ndarray,
+                       kT: float) -> np.ndarray:
+    """Maxwell-Boltzmann velocities at temperature kT with zero net momentum."""
+    m = mass[types][:, None]
+    v = rng.standard_normal((types.shape[0], 3)) * np.sqrt(kT / m)
+    p = (m * v).sum(axis=0) / m.sum()
+    v = v - p[None, :]
+    return v.astype(np.float32)
+
+
+def swap_table_single(epsilon=1.0, sigma=1.0, n=10, rcut=1.5, lam=1.0) -> PairTable:
+    """One reactive type interacting through the swap potential."""
+    return PairTable.empty(1).set(0, 0, KIND_SWAP, epsilon, sigma, n, rcut, lam)
+
+
+def assembly_table(lam: float, eps_site=15.0, sigma_site=0.3, n=10, rcut_site=0.45,
+                   sigma_colloid=1.0, sigma_cross=0.65) -> PairTable:
+    """Type 0 = inert WCA colloid, type 1 = reactive site.
+
+    colloid-colloid WCA (sigma 1), colloid-site WCA (sigma 0.65),
+    site-site swap (eps 15, sigma 0.3, n 10, r_cut 0.45, lambda).
+    """
+    t = PairTable.empty(2)
+    t.set(0, 0, KIND_WCA, 1.0, sigma_colloid, 6)
+    t.set(0, 1, KIND_WCA, 1.0, sigma_cross, 6)
+    t.set(1, 1, KIND_SWAP, eps_site, sigma_site, n, rcut_site, lam)
+    return t
+
+
+def small_reactive(N=1000, density=0.2, seed=1001, min_dist=0.8, kT=0.1,
+                   table: Optional[PairTable] = None) -> System:
+    """N identical reactive particles (eps 1, sigma 1, n 10, r_cut 1.5, lambda 1)."""
+    rng = np.random.default_rng(seed)
+    L = fp32_box(N, density)
+    tab = table if table is not None else swap_table_single()
+    pos, types = rsa_positions(rng, L, [N], np.array([[min_dist]]))
+    mass = np.ones(tab.ntypes)
+    vel = maxwell_velocities(rng, types, mass, kT)
+    return System(pos=pos, types=types, L=L, table=tab, mass=mass, vel=vel,
+                  name=f"reactive N={N} rho={density}")
+
+
+def assembly_mixture(N=1048576, lam=1.0, density=0.3, seed=1003, kT=0.05,
+                     frac_sites=0.5) -> System:
+    """Inert WCA colloids + reactive sites at total density ``density``.
+
+    Minimum start distance 0.8 sigma_ab for every type pair.
+    """
+    rng = np.random.default_rng(seed)
+    L = fp32_box(N, density)
+    tab = assembly_table(lam)
+    n_sites = int(round(N * frac_sites))
+    counts = [N - n_sites, n_sites]
+    md = 0.8 * tab.sigma
+    pos, types = rsa_positions(rng, L, counts, md)
+    # interleave the two species in memory order (the engine re-orders anyway)
+    perm = rng.permutation(N)
+    pos, types = pos[perm], types[perm]
+    mass = np.ones(tab.ntypes)
+    vel = maxwell_velocities(rng, types, mass, kT)
+    return System(pos=pos, types=types, L=L, table=tab, mass=mass, vel=vel,
+                  name=f"assembly N={N} lambda={lam}", meta={"lam": lam})
+
+
+def replica_set(R=256, seed=1004, n_lo=500, n_hi=20000, kT=0.1) -> List[System]:
+    """Independent replicas with N ~ logU[n_lo, n_hi], rho ~ U[0.2, 0.4],
+    lambda ~ U[0, 1.5] and inert WCA fraction ~ U[0, 0.5].
+
+    Type 0 = reactive (swap eps 1, sigma 1, n 10, r_cut 1.5), type 1 = inert
+    WCA (sigma 1) against everything.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(R):
+        N = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        rho = float(rng.uniform(0.2, 0.4))
+        lam = float(rng.uniform(0.0, 1.5))
+        finert = float(rng.uniform(0.0, 0.5))
+        n_inert = int(round(N * finert))
+        L = fp32_box(N, rho)
+        tab = PairTable.empty(2)
+        tab.set(0, 0, KIND_SWAP, 1.0, 1.0, 10, 1.5, lam)
+        tab.set(0, 1, KIND_WCA, 1.0, 1.0, 6)
+        tab.set(1, 1, KIND_WCA, 1.0, 1.0, 6)
+        pos, types = rsa_positions(rng, L, [N - n_inert, n_inert], np.full((2, 2), 0.8))
+        mass = np.ones(2)
+        vel = maxwell_velocities(rng, types, mass, kT)
+        out.append(System(pos=pos, types=types, L=L, table=tab, mass=mass, vel=vel,
+                          name=f"replica {r}", meta={"lam": lam, "rho": rho, "finert": finert}))
+    return out
+
+
+def cluster(coords, L=20.0, types=None, table: Optional[PairTable] = None) -> System:
+    """A hand-placed configuration (coordinates are rounded to FP32)."""
+    c = np.asarray(coords, dtype=np.float64).reshape(-1, 3)
+    Lf = float(np.float32(L))
+    tab = table if table is not None else swap_table_single()
+    ty = np.zeros(c.shape[0], np.int32) if types is None else np.asarray(types, np.int32)
+    return System(pos=wrap_fp32(c, Lf), types=ty, L=Lf, table=tab,
+                  mass=np.ones(tab.ntypes), vel=np.zeros((c.shape[0], 3), np.float32),
+                  name="cluster")

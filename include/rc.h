@@ -1,0 +1,344 @@
+/*
+ * rc.h -- C ABI of the MI355X swap-potential engine.
+ *
+ * The engine evaluates, on one GPU, the associative bond-swap potential of
+ * Ciarella & Ellenbroek (arXiv 1912.08569, Sec. 2):
+ *
+ *   pair (kind RC_KIND_SWAP):  v(r) = 4 eps [(sigma/r)^(2n) - (sigma/r)^n],  r < r_cut     eq. (2b)
+ *   pair (kind RC_KIND_WCA):   4 eps [(sigma/r)^12 - (sigma/r)^6] + eps,      r < r_cut
+ *   switching factor:          vhat = 1 (r <= r_min = sigma 2^(1/n)), -v/eps beyond     eq. (pot)
+ *   three-body:                sum_i sum_{j<k} Lambda vhat(r_ij) vhat(r_ik),
+ *                              Lambda = lambda eps                                       eq. (3bp)
+ *   virial:                    W_ab = sum_terms sum_m (x_m - x_centre)_a F_m,b           eq. (p3)
+ *
+ * plus a BAOAB Langevin / velocity-Verlet integrator, cell-list binning with a
+ * Morton-ordered counting sort, a full neighbour list, exact bond counting,
+ * Hessian-vector products and parameter gradients of the energy, and a batch
+ * mode that advances many independent replicas in one launch per step.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is caller-owned DEVICE memory on the device
+ * that was current at rc_create, unless the comment says "host".  The library
+ * allocates device memory only inside an rc_ctx / rc_batch (parameter table,
+ * reduction scratch, status word); it never frees caller memory.
+ *
+ * Streams.  Every launch is asynchronous on the caller's hipStream_t (passed
+ * as void*; NULL = the null stream).  Functions that return a host value
+ * (rc_read_status, rc_md_run) synchronise that stream and say so.
+ *
+ * Errors.  Every function returns an int status: RC_OK or a negative RC_ERR_*.
+ * Argument errors are detected synchronously before any launch; nothing is
+ * launched then.  Conditions found on the device (neighbour-list overflow,
+ * non-finite forces, lost particles) are latched in a device status word and
+ * reported by rc_read_status.  rc_last_error(ctx) returns a message for the
+ * last failure of that context.  Nothing throws or aborts across the ABI.
+ *
+ * Particle layout (structure of float4, 16-byte aligned):
+ *   pos[i]   = (x, y, z, w) with x,y,z in [-L/2, L/2) and w holding the int32
+ *              bit pattern (tag << RC_TYPE_BITS) | type.  tag < 2^27.
+ *   vel[i]   = (vx, vy, vz, w) with w = path length travelled since the last
+ *              neighbour-list build (maintained by the library; the skin test).
+ *   force[i] = (fx, fy, fz, e_i): e_i is the per-particle energy (half of each
+ *              pair term, every triplet term to its centre), when requested.
+ *   image[i] = int4 periodic image counters (x, y, z, unused); may be NULL.
+ * Particle order is the library's: rc_build_cells re-orders particles along a
+ * Morton curve of the cell grid; identity travels with the tag in pos.w.
+ *
+ * Boxes are orthorhombic, periodic and origin centred; every edge must be an
+ * exactly representable FP32 value and at least 3 neighbour-list radii long.
+ */
+#ifndef RC_H
+#define RC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define RC_OK                  0
+#define RC_ERR_ARG            -1   /* invalid argument (nothing launched)             */
+#define RC_ERR_HIP            -2   /* a HIP runtime call failed                        */
+#define RC_ERR_NLIST_OVERFLOW -3   /* a particle has more than k_max neighbours        */
+#define RC_ERR_UNSUPPORTED    -4   /* valid but unsupported request                    */
+#define RC_ERR_NONFINITE      -5   /* a force, energy or position became non-finite    */
+#define RC_ERR_LOST_PARTICLE  -6   /* a particle moved more than L/2 in one step       */
+#define RC_ERR_WORKSPACE      -7   /* workspace too small                              */
+
+/* ---- pair kinds ------------------------------------------------------------ */
+#define RC_KIND_NONE 0   /* no interaction                                        */
+#define RC_KIND_SWAP 1   /* eq. (2b) pair term + the three-body term of eq. (3bp)  */
+#define RC_KIND_WCA  2   /* purely repulsive 12-6 LJ shifted by +eps               */
+
+#define RC_TYPE_BITS 4           /* pos.w = (tag << 4) | type                     */
+#define RC_MAX_TYPES 16
+#define RC_MAX_TAG   (1 << 27)
+
+/* ---- device status word: int32[RC_STATUS_WORDS] ---------------------------- */
+#define RC_STATUS_WORDS 8
+#define RC_ST_FLAGS      0   /* OR of RC_FLAG_*                                      */
+#define RC_ST_KMAX       1   /* largest neighbour count seen by the last list build */
+#define RC_ST_MAXPATH    2   /* largest path length since the build (float bits)   */
+#define RC_ST_FIRST_SOFT 3   /* first step whose new positions passed the soft skin */
+#define RC_ST_FIRST_HARD 4   /* first step whose force used a stale list           */
+#define RC_FLAG_NLIST_OVERFLOW 1
+#define RC_FLAG_REBUILD        2   /* a path length passed the soft skin threshold     */
+#define RC_FLAG_NONFINITE      4
+#define RC_FLAG_LOST           8
+#define RC_FLAG_STALE         16   /* a force was evaluated on a stale list           */
+#define RC_FLAG_TRIPLET_POOL  32   /* internal staging overflow (recovered; info)      */
+
+/* ---- parameters (host structs) -------------------------------------------- */
+/* One entry of the symmetric ntypes x ntypes table: the per-type-pair
+ * coefficients of the paper's potential (Sec. 2: sigma, n, epsilon, lambda3,
+ * and the cutoff).  SWAP requires eps > 0, sigma > 0, integer n >= 1,
+ * r_min = sigma 2^(1/n) < r_cut and lambda >= 0.  WCA requires eps >= 0,
+ * sigma > 0, r_cut > 0 (normally 2^(1/6) sigma); n and lambda are ignored.  */
+typedef struct rc_pair_coeff {
+    int kind;
+    int n;
+    double epsilon;
+    double sigma;
+    double r_cut;
+    double lambda;
+} rc_pair_coeff;
+
+typedef struct rc_box {
+    double L[3];   /* edges, FP32-exact */
+} rc_box;
+
+#define RC_INTEGRATOR_NVE      0   /* velocity Verlet                           */
+#define RC_INTEGRATOR_LANGEVIN 1   /* BAOAB (Leimkuhler-Matthews 2013)          */
+
+typedef struct rc_integrator {
+    int kind;                      /* RC_INTEGRATOR_*                            */
+    int pad;
+    double dt;
+    double kT;
+    double gamma;                  /* friction (1/time); ignored for NVE        */
+    uint64_t seed;                 /* Philox key: (seed mod 2^32, seed >> 32)   */
+    double mass[RC_MAX_TYPES];     /* mass per type (> 0)                       */
+} rc_integrator;
+
+typedef struct rc_ctx rc_ctx;
+
+/* ---- context ----------------------------------------------------------------
+ * rc_create: validate the table (must be symmetric), compile it into a device
+ * table on the current device and precompute r_cut^2 and the canonical
+ * r_min^2 = (sigma*sigma) * pow(2, 2/n) in FP64, and the neighbour-list radii
+ * r_list = r_cut + r_buff.  r_buff > 0 is the skin.  Host pointers.
+ * Returns RC_ERR_ARG on an invalid table, RC_ERR_UNSUPPORTED for
+ * ntypes > RC_MAX_TYPES.                                                      */
+int rc_create(rc_ctx** out, int ntypes, const rc_pair_coeff* table /* host [ntypes*ntypes] */,
+              double r_buff);
+int rc_destroy(rc_ctx* ctx);
+const char* rc_last_error(const rc_ctx* ctx);
+int rc_version(void);
+/* Replace lambda of every SWAP entry with table values (host, ntypes^2);
+ * takes effect for launches issued after it returns.                         */
+int rc_set_lambda(rc_ctx* ctx, const double* lambda /* host [ntypes*ntypes] */);
+/* Neighbour-list radius actually used for type pair (a, b) (host).           */
+int rc_get_rlist(const rc_ctx* ctx, int a, int b, double* r_list);
+
+/* ---- status ---------------------------------------------------------------
+ * rc_clear_status: zero a status word (async).  rc_read_status: synchronise
+ * `stream`, copy the word to host `out` and return the matching error code:
+ * RC_ERR_NLIST_OVERFLOW, RC_ERR_NONFINITE, RC_ERR_LOST_PARTICLE or RC_OK.    */
+int rc_clear_status(int* status /* device [RC_STATUS_WORDS] */, void* stream);
+int rc_read_status(const int* status, int* out /* host [RC_STATUS_WORDS] */, void* stream);
+
+/* ---- cell binning (hot-path step a1) -----------------------------------------
+ * Cells: nc_d = floor(L_d / r_list_max) >= 3 per axis; a particle's cell is
+ * floor((x + L/2) nc / L) clamped to [0, nc); cells are keyed by the 3-D
+ * Morton code of their integer coordinates.  rc_build_cells counts particles
+ * per key (atomics), takes an exclusive prefix scan into cell_start, scatters
+ * by (key, rank), orders each cell by previous index (deterministic), and
+ * permutes pos, vel (nullable) and image (nullable) in place into key order,
+ * so that a Morton walk of the grid is a walk of memory.  If rtag is not NULL
+ * it receives rtag[tag] = new index (device, N ints; requires tags < N).
+ * ws must hold rc_cells_workspace_bytes(ctx, N, box) bytes; it keeps the cell
+ * table for rc_build_nlist and must not be touched in between.
+ * Returns RC_ERR_ARG for N < 1, a non-FP32 box or a box shorter than three
+ * list radii, RC_ERR_WORKSPACE if ws_bytes is too small.                     */
+int rc_cells_workspace_bytes(const rc_ctx* ctx, int N, rc_box box, size_t* bytes /* host */);
+int rc_build_cells(rc_ctx* ctx, float* pos /* [N*4] */, float* vel /* [N*4] | NULL */,
+                   int* image /* [N*4] | NULL */, int* rtag /* [N] | NULL */, int N, rc_box box,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* ---- neighbour list (hot-path step a2) -----------------------------------------
+ * Full list (i -> j and j -> i) of every pair with r < r_list(t_i, t_j) =
+ * r_cut + r_buff, found by scanning the 27 cells around each particle's cell
+ * (cell table from the last rc_build_cells on ws).  Column-major:
+ * nlist[s * N + i] is the s-th neighbour of i, s < nn[i] <= k_max.  A
+ * particle with more than k_max neighbours sets RC_FLAG_NLIST_OVERFLOW and
+ * status[RC_ST_KMAX] = its count (its list is truncated).  If vel is not NULL
+ * the path lengths vel[i].w are reset to 0 (the skin reference).  The list is
+ * valid while every path length stays <= r_buff / 2: any pair then outside
+ * the list is at least r_cut apart (the paper's three-particle neighbour
+ * lists, SI "Performance").                                                  */
+int rc_build_nlist(rc_ctx* ctx, const float* pos, float* vel /* NULL ok */, int N, rc_box box,
+                   const void* ws, size_t ws_bytes, int k_max, int* nlist /* [k_max*N] */,
+                   int* nn /* [N] */, int* status /* [RC_STATUS_WORDS] | NULL */, void* stream);
+
+/* ---- forces, energy, virial (hot-path step a3) -------------------------------
+ * F = -grad(E2 + E3) of the pair terms (eq. 2b / WCA) and the three-body term
+ * (eq. 3bp with eq. pot), one term per centre i and unordered partner pair
+ * {j, k}; Lambda_ijk = sqrt(Lambda_ij Lambda_ik) when the entries differ.
+ * Cut decisions use the canonical FP64 predicate (minimum image
+ * d = x_j - x_i folded once by +-L, r^2 = (dx*dx + dy*dy) + dz*dz, no fused
+ * multiply-add, compared with r_cut*r_cut); the terms are evaluated in FP32.
+ * Default algorithm (the triplet kernel): each lane owns a centre, walks its
+ * list for the pair terms, stages the active swap partners of centres with two
+ * or more of them in LDS, and the wavefront enumerates all (j<k) triplets of
+ * its 64 centres across its lanes; forces on j and k go out with atomics, so
+ * the summation order (last bits) is not deterministic.
+ * flags:
+ *   RC_FORCE_ACCUMULATE  add into force instead of overwriting it
+ *   RC_FORCE_GATHER      atomic-free gather algorithm (each particle sums
+ *                        every term that moves it; deterministic)
+ * force[i].w receives the per-particle energy (added when accumulating).
+ * ev (device, nullable) receives 7 doubles: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
+ * with W the configurational virial of eq. (p3) (stress = -(K + W)/V),
+ * reduced in FP64 in a fixed order.                                          */
+#define RC_FORCE_ACCUMULATE 1u
+#define RC_FORCE_GATHER     4u
+int rc_compute_forces(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+                      rc_box box, float* force /* [N*4] */, double* ev /* [7] | NULL */,
+                      unsigned flags, int* status /* NULL ok */, void* stream);
+
+/* ---- integrator (hot-path step a5) -------------------------------------------
+ * BAOAB Langevin (the paper's "canonical Langevin dynamics", Sec. 3.2; scheme
+ * of Leimkuhler & Matthews 2013) or velocity Verlet (NVE):
+ *   RC_HALF_FIRST : v += dt/2 F/m ; x += dt/2 v ; v = c1 v + sqrt((1-c1^2) kT/m) xi ;
+ *                   x += dt/2 v ; wrap into [-L/2, L/2) (image += crossings) ;
+ *                   vel.w += |x_new - x_old|   (c1 = exp(-gamma dt); NVE: c1 = 1)
+ *   RC_HALF_SECOND: v += dt/2 F/m
+ * xi = three normals from Philox4x32-10 (key = seed, counter = (tag, step lo,
+ * step hi, 0)) by Box-Muller on u = (x + 1/2) 2^-32.  kin (nullable, device)
+ * receives sum m v_a v_b (xx, yy, zz, xy, xz, yz) of the velocities after the
+ * call.  A step that moves a particle by more than L/2 sets RC_FLAG_LOST; a
+ * non-finite position sets RC_FLAG_NONFINITE; a path length above r_buff/2
+ * sets RC_FLAG_REBUILD.                                                      */
+#define RC_HALF_FIRST  0
+#define RC_HALF_SECOND 1
+int rc_integrate_step(rc_ctx* ctx, float* pos, float* vel, const float* force,
+                      int* image /* NULL ok */, int N, rc_box box, const rc_integrator* cfg /* host */,
+                      uint64_t step, int half, double* kin /* [6] | NULL */,
+                      int* status /* NULL ok */, void* stream);
+
+/* ---- fused step (the metric path: a3 + a5 in one kernel) ---------------------
+ * One kernel per MD step.  Reads pos_in, writes pos_out (pos_in != pos_out,
+ * double buffered).  Each particle m gathers every force term that moves it:
+ * its pair terms, the triplets it centres, and the triplets in which it is a
+ * partner of a centre c (the other partners of c are found by walking c's
+ * list: a two-hop gather), so no atomics are needed and the result is
+ * deterministic.  Then it integrates.  Between steps vel holds the velocity
+ * after the O and second A of BAOAB (the final half kick is folded into the
+ * next step):
+ *   RC_STEP_START : v = vel (on-step velocity); B A O A       -> pos_out, vel
+ *   RC_STEP_CONT  : v = vel + dt/2 F/m (ends the previous step); B A O A
+ *   RC_STEP_FINISH: v = vel + dt/2 F/m; vel = v; pos_out untouched
+ *   RC_STEP_OBSERVE: v = vel (on-step); nothing written except ev and status
+ * ev (nullable, device) receives 13 doubles at x_in: E, W(6) as in
+ * rc_compute_forces, K(6) = sum m v v of the on-step velocity.  The kernel
+ * sets RC_FLAG_STALE (and RC_ST_FIRST_HARD = step) when an input path length
+ * exceeds r_buff/2, and RC_FLAG_REBUILD (RC_ST_FIRST_SOFT = step) when an
+ * output path length exceeds soft_frac * r_buff/2.                           */
+#define RC_STEP_START  0
+#define RC_STEP_CONT   1
+#define RC_STEP_FINISH 2
+#define RC_STEP_OBSERVE 3
+int rc_step_fused(rc_ctx* ctx, const float* pos_in, float* pos_out, float* vel, int* image,
+                  const int* nlist, const int* nn, int N, rc_box box,
+                  const rc_integrator* cfg /* host */, uint64_t step, int mode, double soft_frac,
+                  double* ev /* [13] | NULL */, int* status, void* stream);
+
+/* ---- bond count (hot-path step a4) -------------------------------------------
+ * Number of swap pairs i<j with r^2 < r_min^2 (canonical FP64 predicate, the
+ * bond criterion of the swap system), written to *count (device, uint64).
+ * Exact; independent of list order.  Requires a list built with this ctx.    */
+int rc_bond_count(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+                  rc_box box, unsigned long long* count /* device */, void* stream);
+
+/* ---- MD driver (hot-path step a6) --------------------------------------------
+ * Advances (pos, vel) by n_steps steps of cfg, starting at step index step0,
+ * on `stream`, and returns after synchronising it.  It (re)builds cells and
+ * the list at entry, then runs chunks of fused steps, each chunk either
+ * replayed from a captured hipGraph or launched directly, with one host sync
+ * per chunk.  A list rebuild happens at a chunk boundary when any path length
+ * passed soft_frac * r_buff/2.  If a chunk evaluated a force on a stale list
+ * (a path length above r_buff/2) the chunk is rolled back from its snapshot
+ * and replayed up to the step where the soft threshold was first crossed;
+ * the counter-based noise makes the replay exact.  Every log_period steps
+ * (and at the end) it appends one row of 13 doubles (E, W, K at that step) to
+ * ev_log and one bond count to bonds_log.  Buffers are caller owned:      */
+typedef struct rc_md_buffers {
+    float* pos;        /* [N*4] state in/out                                  */
+    float* pos_alt;    /* [N*4] second position buffer                        */
+    float* vel;        /* [N*4] state in/out (on-step velocities)             */
+    int* image;        /* [N*4] | NULL                                        */
+    int* rtag;         /* [N]   | NULL (tag -> index after the last build)    */
+    int* nlist;        /* [k_max*N]                                           */
+    int* nn;           /* [N]                                                 */
+    int k_max;
+    int pad;
+    void* cells_ws;    /* rc_cells_workspace_bytes                            */
+    size_t cells_ws_bytes;
+    float* snap_pos;   /* [N*4] | NULL (NULL disables rollback)               */
+    float* snap_vel;   /* [N*4] | NULL                                        */
+    int* snap_image;   /* [N*4] | NULL                                        */
+    int* status;       /* [RC_STATUS_WORDS]                                   */
+    double* ev_log;    /* [rows*13] | NULL, rows = n_steps/log_period + 1     */
+    unsigned long long* bonds_log; /* [rows] | NULL                           */
+} rc_md_buffers;
+
+typedef struct rc_md_options {
+    int use_graph;      /* capture chunks as hipGraphs (1) or launch directly */
+    int graph_steps;    /* steps per captured graph (even)                    */
+    int max_chunk;      /* steps between host syncs (upper bound)             */
+    int log_period;     /* 0 = log only at the start and the end              */
+    double soft_frac;   /* rebuild threshold as a fraction of r_buff/2        */
+} rc_md_options;
+
+typedef struct rc_md_stats {
+    int64_t steps_done;
+    int64_t rebuilds;
+    int64_t rollbacks;
+    int64_t chunks;
+    int64_t log_rows;
+    int32_t k_needed;   /* on RC_ERR_NLIST_OVERFLOW: the k_max needed          */
+    int32_t flags;      /* last status flags                                  */
+} rc_md_stats;
+
+int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,
+              const rc_integrator* cfg /* host */, uint64_t step0, int n_steps,
+              const rc_md_options* opt /* host, NULL = defaults */,
+              rc_md_stats* stats /* host, NULL ok */, void* stream);
+
+/* ---- differentiation (hot-path step a7) --------------------------------------
+ * rc_force_hvp: hv = H v with H = d^2 E / dx dx (FP32, per-particle float4,
+ *   w ignored/zero): second derivatives of the pair terms (phi'', phi'/r) and
+ *   of the triplets through vhat, vhat', vhat'' (vhat'' = -v''/eps beyond
+ *   r_min, 0 inside; H is defined off the r_min and r_cut shells).  The force
+ *   JVP is -hv.  Atomic-free gather (deterministic).
+ * rc_param_grad: grad[(a*nt + b)*3 + {0,1,2}] = dE/d(eps, sigma, lambda) of the
+ *   unordered entry {a, b} (reported on both (a,b) and (b,a)), FP64, fixed
+ *   r_cut.  Device output, overwritten.
+ * rc_param_vjp: out[(a*nt+b)*3 + w] = sum_m adj_m . dF_m/dtheta_w{a,b}
+ *   (FP64, device), for fitting through trajectories.                        */
+int rc_force_hvp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+                 rc_box box, const float* v /* [N*4] */, float* hv /* [N*4] */, void* stream);
+int rc_param_grad(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+                  rc_box box, double* grad /* [nt*nt*3] */, void* stream);
+int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+                 rc_box box, const float* adj /* [N*4] */, double* out /* [nt*nt*3] */,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RC_H */

@@ -1,0 +1,154 @@
+"""ctypes view of ``librc.so`` (the C ABI declared in ``include/rc.h``).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+library must be built (``paper_1912_08569_amd.build.build()``); there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rc.h")
+
+RC_OK = 0
+RC_ERR_ARG = -1
+RC_ERR_HIP = -2
+RC_ERR_NLIST_OVERFLOW = -3
+RC_ERR_UNSUPPORTED = -4
+RC_ERR_NONFINITE = -5
+RC_ERR_LOST_PARTICLE = -6
+RC_ERR_WORKSPACE = -7
+
+RC_KIND_NONE, RC_KIND_SWAP, RC_KIND_WCA = 0, 1, 2
+RC_TYPE_BITS = 4
+RC_MAX_TYPES = 16
+RC_STATUS_WORDS = 8
+RC_ST_FLAGS, RC_ST_KMAX, RC_ST_MAXPATH, RC_ST_FIRST_SOFT, RC_ST_FIRST_HARD = 0, 1, 2, 3, 4
+RC_FLAG_NLIST_OVERFLOW, RC_FLAG_REBUILD, RC_FLAG_NONFINITE, RC_FLAG_LOST, RC_FLAG_STALE = 1, 2, 4, 8, 16
+RC_FORCE_ACCUMULATE, RC_FORCE_GATHER = 1, 4
+RC_HALF_FIRST, RC_HALF_SECOND = 0, 1
+RC_STEP_START, RC_STEP_CONT, RC_STEP_FINISH, RC_STEP_OBSERVE = 0, 1, 2, 3
+RC_INTEGRATOR_NVE, RC_INTEGRATOR_LANGEVIN = 0, 1
+
+_ERR_NAMES = {
+    RC_ERR_ARG: "invalid argument", RC_ERR_HIP: "HIP runtime error",
+    RC_ERR_NLIST_OVERFLOW: "neighbour list overflow", RC_ERR_UNSUPPORTED: "unsupported",
+    RC_ERR_NONFINITE: "non-finite values", RC_ERR_LOST_PARTICLE: "lost particle",
+    RC_ERR_WORKSPACE: "workspace too small",
+}
+
+
+class RcError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"{_ERR_NAMES.get(code, 'error')} ({code}): {msg}")
+        self.code = code
+
+
+class PairCoeff(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n", ctypes.c_int), ("epsilon", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("r_cut", ctypes.c_double), ("lam", ctypes.c_double)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3)]
+
+
+class Integrator(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("pad", ctypes.c_int), ("dt", ctypes.c_double),
+                ("kT", ctypes.c_double), ("gamma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("mass", ctypes.c_double * RC_MAX_TYPES)]
+
+
+class MdBuffers(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("pos_alt", ctypes.c_void_p), ("vel", ctypes.c_void_p),
+                ("image", ctypes.c_void_p), ("rtag", ctypes.c_void_p), ("nlist", ctypes.c_void_p),
+                ("nn", ctypes.c_void_p), ("k_max", ctypes.c_int), ("pad", ctypes.c_int),
+                ("cells_ws", ctypes.c_void_p), ("cells_ws_bytes", ctypes.c_size_t),
+                ("snap_pos", ctypes.c_void_p), ("snap_vel", ctypes.c_void_p),
+                ("snap_image", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("ev_log", ctypes.c_void_p), ("bonds_log", ctypes.c_void_p)]
+
+
+class MdOptions(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int), ("graph_steps", ctypes.c_int),
+                ("max_chunk", ctypes.c_int), ("log_period", ctypes.c_int),
+                ("soft_frac", ctypes.c_double)]
+
+
+class MdStats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
+                ("rollbacks", ctypes.c_int64), ("chunks", ctypes.c_int64),
+                ("log_rows", ctypes.c_int64), ("k_needed", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_U = ctypes.c_uint
+_U64 = ctypes.c_uint64
+_D = ctypes.c_double
+
+_SIGS = {
+    "rc_version": ([], _I),
+    "rc_create": ([ctypes.POINTER(_VP), _I, ctypes.POINTER(PairCoeff), _D], _I),
+    "rc_destroy": ([_VP], _I),
+    "rc_last_error": ([_VP], ctypes.c_char_p),
+    "rc_set_lambda": ([_VP, ctypes.POINTER(_D)], _I),
+    "rc_get_rlist": ([_VP, _I, _I, ctypes.POINTER(_D)], _I),
+    "rc_clear_status": ([_VP, _VP], _I),
+    "rc_read_status": ([_VP, ctypes.POINTER(_I), _VP], _I),
+    "rc_cells_workspace_bytes": ([_VP, _I, Box, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "rc_build_cells": ([_VP, _VP, _VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _VP], _I),
+    "rc_build_nlist": ([_VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),
+    "rc_compute_forces": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
+    "rc_integrate_step": ([_VP, _VP, _VP, _VP, _VP, _I, Box, ctypes.POINTER(Integrator), _U64, _I,
+                           _VP, _VP, _VP], _I),
+    "rc_step_fused": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, Box, ctypes.POINTER(Integrator), _U64,
+                       _I, _D, _VP, _VP, _VP], _I),
+    "rc_bond_count": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP], _I),
+    "rc_md_run": ([_VP, ctypes.POINTER(MdBuffers), _I, Box, ctypes.POINTER(Integrator), _U64, _I,
+                   ctypes.POINTER(MdOptions), ctypes.POINTER(MdStats), _VP], _I),
+    "rc_force_hvp": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP, _VP], _I),
+    "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP], _I),
+    "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP, _VP], _I),
+}
+
+_lib = None
+
+
+def declared_symbols():
+    """Names of every function declared in include/rc.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|char\s*\*|const char\s*\*)\s*(rc_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def load():
+    """Load librc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP engine first "
+                           "(python -m paper_1912_08569_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(code: int, ctx=None):
+    if code != RC_OK:
+        msg = ""
+        if ctx is not None:
+            raw = load().rc_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        raise RcError(code, msg)

@@ -1,0 +1,211 @@
+"""Python binding of the C ABI: the same entry points, taking torch tensors.
+
+Each ``rc_*`` function here marshals torch device tensors into the pointers
+and sizes of the matching C function in ``include/rc.h`` and raises
+``RcError`` on a non-zero status.  torch supplies device memory and the
+current HIP stream; all arithmetic happens in ``librc.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import RcError, check
+
+__all__ = [
+    "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
+    "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
+    "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
+    "rc_param_grad", "rc_clear_status", "rc_read_status",
+]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("engine buffers must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("engine buffers must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def box(edges) -> L.Box:
+    """Box from a scalar edge or three edges (each must be an FP32 value)."""
+    v = [float(edges)] * 3 if np.isscalar(edges) else [float(x) for x in edges]
+    out = L.Box()
+    for d in range(3):
+        out.L[d] = v[d]
+    return out
+
+
+def integrator(kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0, mass: Sequence[float] = (1.0,)):
+    cfg = L.Integrator()
+    cfg.kind = L.RC_INTEGRATOR_LANGEVIN if kind == "langevin" else L.RC_INTEGRATOR_NVE
+    cfg.dt, cfg.kT, cfg.gamma, cfg.seed = float(dt), float(kT), float(gamma), int(seed)
+    for t in range(L.RC_MAX_TYPES):
+        cfg.mass[t] = float(mass[t]) if t < len(mass) else 1.0
+    return cfg
+
+
+def pack_positions(xyz, types, tags=None, device="cuda") -> torch.Tensor:
+    """(N,3) FP32 coordinates + types (+ tags) -> (N,4) float32 with w = (tag << 4) | type."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    N = xyz.shape[0]
+    tags = np.arange(N, dtype=np.int64) if tags is None else np.asarray(tags, dtype=np.int64)
+    w = ((tags << L.RC_TYPE_BITS) | np.asarray(types, dtype=np.int64)).astype(np.int32)
+    buf = np.empty((N, 4), dtype=np.float32)
+    buf[:, :3] = xyz
+    buf[:, 3] = w.view(np.float32)
+    return torch.from_numpy(buf).to(device)
+
+
+def unpack_positions(pos: torch.Tensor):
+    """(N,4) device tensor -> (xyz float32 (N,3), types, tags) as numpy."""
+    a = pos.detach().cpu().numpy()
+    w = a[:, 3].copy().view(np.int32)
+    return a[:, :3].copy(), (w & ((1 << L.RC_TYPE_BITS) - 1)).astype(np.int32), (w >> L.RC_TYPE_BITS).astype(np.int64)
+
+
+class Context:
+    """An rc_ctx: the compiled per-type-pair coefficient table."""
+
+    def __init__(self, table, r_buff: float = 0.3):
+        lib = L.load()
+        nt = int(np.asarray(table.kind).shape[0])
+        arr = (L.PairCoeff * (nt * nt))()
+        for a in range(nt):
+            for b in range(nt):
+                e = arr[a * nt + b]
+                e.kind = int(table.kind[a, b])
+                e.n = int(table.n[a, b])
+                e.epsilon = float(table.epsilon[a, b])
+                e.sigma = float(table.sigma[a, b])
+                e.r_cut = float(table.rcut[a, b])
+                e.lam = float(table.lam[a, b])
+        h = ctypes.c_void_p()
+        code = lib.rc_create(ctypes.byref(h), nt, arr, float(r_buff))
+        if code != L.RC_OK:
+            raise RcError(code, "rc_create rejected the table")
+        self.handle = h
+        self.ntypes = nt
+        self.r_buff = float(r_buff)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.load().rc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_lambda(self, lam):
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64),
+                                                   (self.ntypes, self.ntypes)))
+        check(L.load().rc_set_lambda(self.handle, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              self.handle)
+
+    def rlist(self, a: int, b: int) -> float:
+        out = ctypes.c_double()
+        check(L.load().rc_get_rlist(self.handle, a, b, ctypes.byref(out)), self.handle)
+        return out.value
+
+
+# ---------------------------------------------------------------------------
+# the C entry points
+# ---------------------------------------------------------------------------
+
+def rc_cells_workspace_bytes(ctx: Context, N: int, bx) -> int:
+    out = ctypes.c_size_t()
+    check(L.load().rc_cells_workspace_bytes(ctx.handle, int(N), bx, ctypes.byref(out)), ctx.handle)
+    return int(out.value)
+
+
+def rc_clear_status(status: torch.Tensor, stream=None):
+    check(L.load().rc_clear_status(_ptr(status), _stream(stream)))
+
+
+def rc_read_status(status: torch.Tensor, stream=None, raise_on_error=False):
+    out = (ctypes.c_int * L.RC_STATUS_WORDS)()
+    code = L.load().rc_read_status(_ptr(status), out, _stream(stream))
+    if raise_on_error:
+        check(code)
+    return code, list(out)
+
+
+def rc_build_cells(ctx: Context, pos, vel, image, rtag, bx, ws, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_build_cells(ctx.handle, _ptr(pos), _ptr(vel), _ptr(image), _ptr(rtag), N, bx,
+                                  _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), ctx.handle)
+
+
+def rc_build_nlist(ctx: Context, pos, vel, bx, ws, k_max, nlist, nn, status=None, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_build_nlist(ctx.handle, _ptr(pos), _ptr(vel), N, bx, _ptr(ws),
+                                  ws.numel() * ws.element_size(), int(k_max), _ptr(nlist), _ptr(nn),
+                                  _ptr(status), _stream(stream)), ctx.handle)
+
+
+def rc_compute_forces(ctx: Context, pos, nlist, nn, bx, force, ev=None, flags=0, status=None, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_compute_forces(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(force),
+                                     _ptr(ev), int(flags), _ptr(status), _stream(stream)), ctx.handle)
+
+
+def rc_integrate_step(ctx: Context, pos, vel, force, image, bx, cfg, step, half, kin=None, status=None,
+                      stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_integrate_step(ctx.handle, _ptr(pos), _ptr(vel), _ptr(force), _ptr(image), N, bx,
+                                     ctypes.byref(cfg), int(step), int(half), _ptr(kin), _ptr(status),
+                                     _stream(stream)), ctx.handle)
+
+
+def rc_step_fused(ctx: Context, pos_in, pos_out, vel, image, nlist, nn, bx, cfg, step, mode,
+                  soft_frac=0.8, ev=None, status=None, stream=None):
+    N = pos_in.shape[0]
+    check(L.load().rc_step_fused(ctx.handle, _ptr(pos_in), _ptr(pos_out), _ptr(vel), _ptr(image),
+                                 _ptr(nlist), _ptr(nn), N, bx, ctypes.byref(cfg), int(step), int(mode),
+                                 float(soft_frac), _ptr(ev), _ptr(status), _stream(stream)), ctx.handle)
+
+
+def rc_bond_count(ctx: Context, pos, nlist, nn, bx, count, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_bond_count(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(count),
+                                 _stream(stream)), ctx.handle)
+
+
+def rc_md_run(ctx: Context, bufs: L.MdBuffers, N, bx, cfg, step0, n_steps, opts: Optional[L.MdOptions] = None,
+              stream=None) -> L.MdStats:
+    st = L.MdStats()
+    code = L.load().rc_md_run(ctx.handle, ctypes.byref(bufs), int(N), bx, ctypes.byref(cfg), int(step0),
+                              int(n_steps), ctypes.byref(opts) if opts is not None else None,
+                              ctypes.byref(st), _stream(stream))
+    if code != L.RC_OK:
+        err = RcError(code, L.load().rc_last_error(ctx.handle).decode())
+        err.stats = st
+        raise err
+    return st
+
+
+def rc_force_hvp(ctx: Context, pos, nlist, nn, bx, v, hv, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_force_hvp(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(v), _ptr(hv),
+                                _stream(stream)), ctx.handle)
+
+
+def rc_param_grad(ctx: Context, pos, nlist, nn, bx, grad, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_param_grad(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(grad),
+                                 _stream(stream)), ctx.handle)

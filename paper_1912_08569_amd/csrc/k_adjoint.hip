@@ -1,0 +1,250 @@
+// Differentiation of the swap-potential energy: Hessian-vector products and
+// parameter gradients, both as atomic-free per-particle gathers.
+//
+// With w_ma = sqrt(Lambda_ma) vhat(r_ma) for swap partners inside r_cut and
+// S_m = sum_a w_ma, the gradient of E with respect to x_m is
+//     grad_m E = - sum_a rhat_ma G_ma,
+//     G_ma = phi'(r_ma) + w'_ma (S_m + S_a - 2 w_ma)
+// (the triplet sum of eq. 3bp over j<k regrouped per centre), so
+//     (H v)_m = - sum_a [ dG_ma rhat_ma + G_ma (D_ma - dr_ma rhat_ma) / r_ma ],
+//     D_ma = v_a - v_m,  dr_ma = rhat_ma . D_ma,
+//     dG_ma = phi'' dr + w'' dr (S_m + S_a - 2 w) + w' (dS_m + dS_a - 2 w' dr),
+//     dS_m = sum_b w'_mb dr_mb.
+// S_a and dS_a come from a two-hop walk over a's list.
+#include "rc_internal.h"
+
+namespace rc {
+
+static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+__device__ __forceinline__ void load_table_adj(DevEntry* s_tab, const Table& t) {
+    const int n = t.nt * t.nt;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) s_tab[q] = t.e[q];
+    __syncthreads();
+}
+
+struct Deriv {  // value and first two r-derivatives of one term, plus geometry
+    float r, rx, ry, rz;  // r and rhat
+};
+
+// pair: phi'(r), phi''(r)
+__device__ __forceinline__ void pair_d12(const DevEntry& e, float r2, float r, float& d1, float& d2) {
+    const float q = qpow(e.sig2 / r2, e.n);
+    const float q2 = q * q, n = (float)e.n;
+    d1 = 4.0f * e.eps * n * (q - 2.0f * q2) / r;
+    d2 = 4.0f * e.eps * (2.0f * n * (2.0f * n + 1.0f) * q2 - n * (n + 1.0f) * q) / r2;
+}
+
+// w = sqrt(Lambda) vhat and its first two r-derivatives
+__device__ __forceinline__ void w_d012(const DevEntry& e, bool inside, float r2, float r, float& w,
+                                       float& w1, float& w2) {
+    if (inside) {
+        w = e.sqrt_lam;
+        w1 = 0.0f;
+        w2 = 0.0f;
+        return;
+    }
+    const float q = qpow(e.sig2 / r2, e.n);
+    const float q2 = q * q, n = (float)e.n;
+    w = e.sqrt_lam * 4.0f * (q - q2);
+    w1 = e.sqrt_lam * 4.0f * n * (2.0f * q2 - q) / r;
+    w2 = -e.sqrt_lam * 4.0f * (2.0f * n * (2.0f * n + 1.0f) * q2 - n * (n + 1.0f) * q) / r2;
+}
+
+// S_c and dS_c = sum_b w'_cb rhat_cb . (v_b - v_c) over c's swap partners
+__device__ __forceinline__ void centre_sums(int c, const float4& pc, const float4& vc, const int* nlist,
+                                            const int* nn, int N, const float4* pos, const float4* v,
+                                            const DevEntry* tab, int nt, const Box& box, double& S,
+                                            double& dS) {
+    const int tc = ptype(pc.w);
+    const int cnt = nn[c];
+    S = 0.0;
+    dS = 0.0;
+    for (int t = 0; t < cnt; ++t) {
+        const int b = nlist[(size_t)t * N + c];
+        const float4 pb = pos[b];
+        const DevEntry& e = tab[tc * nt + ptype(pb.w)];
+        if (e.kind != RC_KIND_SWAP) continue;
+        double dx, dy, dz;
+        const double r2d = canon_r2(pc, pb, box, dx, dy, dz);
+        if (!(r2d < e.rcut2)) continue;
+        const float r2 = (float)r2d, r = sqrtf(r2);
+        float w, w1, w2;
+        w_d012(e, r2d <= e.rmin2, r2, r, w, w1, w2);
+        const float4 vb = v[b];
+        const float dr = ((float)dx * (vb.x - vc.x) + (float)dy * (vb.y - vc.y) + (float)dz * (vb.z - vc.z)) / r;
+        S += (double)w;
+        dS += (double)(w1 * dr);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
+    extern __shared__ DevEntry s_tab[];
+    load_table_adj(s_tab, a.tab);
+    const int nt = a.tab.nt;
+    const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    if (m >= a.N) return;
+    const float4 pm = a.pos[m];
+    const float4 vm = a.v[m];
+    const int tm = ptype(pm.w);
+    const int cnt = a.nn[m];
+    double Sm, dSm;
+    centre_sums(m, pm, vm, a.nlist, a.nn, a.N, a.pos, a.v, s_tab, nt, a.box, Sm, dSm);
+    float hx = 0.f, hy = 0.f, hz = 0.f;
+    for (int s = 0; s < cnt; ++s) {
+        const int j = a.nlist[(size_t)s * a.N + m];
+        const float4 pj = a.pos[j];
+        const DevEntry& e = s_tab[tm * nt + ptype(pj.w)];
+        if (e.kind == RC_KIND_NONE) continue;
+        double dxd, dyd, dzd;
+        const double r2d = canon_r2(pm, pj, a.box, dxd, dyd, dzd);
+        if (!(r2d < e.rcut2)) continue;
+        const float r2 = (float)r2d, r = sqrtf(r2), ir = 1.0f / r;
+        const float rx = (float)dxd * ir, ry = (float)dyd * ir, rz = (float)dzd * ir;
+        const float4 vj = a.v[j];
+        const float Dx = vj.x - vm.x, Dy = vj.y - vm.y, Dz = vj.z - vm.z;
+        const float dr = rx * Dx + ry * Dy + rz * Dz;
+        float G, dG;
+        pair_d12(e, r2, r, G, dG);
+        dG *= dr;
+        if (e.kind == RC_KIND_SWAP) {
+            float w, w1, w2;
+            w_d012(e, r2d <= e.rmin2, r2, r, w, w1, w2);
+            if (w1 != 0.0f || w2 != 0.0f) {
+                double Sj, dSj;
+                centre_sums(j, pj, vj, a.nlist, a.nn, a.N, a.pos, a.v, s_tab, nt, a.box, Sj, dSj);
+                const float X = (float)((Sm - (double)w) + (Sj - (double)w));
+                const float dX = (float)((dSm - (double)(w1 * dr)) + (dSj - (double)(w1 * dr)));
+                G += w1 * X;
+                dG += w2 * dr * X + w1 * dX;
+            }
+        }
+        const float c = G * ir;
+        hx -= dG * rx + c * (Dx - dr * rx);
+        hy -= dG * ry + c * (Dy - dr * ry);
+        hz -= dG * rz + c * (Dz - dr * rz);
+    }
+    a.hv[m] = make_float4(hx, hy, hz, 0.0f);
+}
+
+hipError_t launch_hvp(const HvpArgs& a, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    hipLaunchKernelGGL(k_hvp, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dE / d(eps, sigma, lambda) per table entry, at fixed r_cut.
+//  pair (half per list direction):  d/deps = phi/eps,  d/dsigma = 4 eps n (2q^2 - q)/sigma
+//  triplets of centre m, per active partner a with entry e:
+//     d/dlambda_e  = w_a (S - w_a) / (2 lambda_e)        (lambda_e > 0)
+//                  = eps_e u_a (U_e - u_a) / 2            (lambda_e = 0, same-entry pairs)
+//     d/deps_e     = w_a (S - w_a) / (2 eps_e)
+//     d/dsigma_e   = sqrt(Lambda) du_a/dsigma (S - w_a),  du/dsigma = -4 n (2q^2 - q)/sigma beyond r_min
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_param_grad(ParamArgs a) {
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    const int nt = a.tab.nt, ne = nt * nt;
+    DevEntry* s_tab = reinterpret_cast<DevEntry*>(s_raw);
+    double* s_acc = reinterpret_cast<double*>(s_raw + sizeof(DevEntry) * ne);
+    for (int q = threadIdx.x; q < ne * 3; q += blockDim.x) s_acc[q] = 0.0;
+    load_table_adj(s_tab, a.tab);
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < a.N) {
+        const float4 pm = a.pos[m];
+        const int tm = ptype(pm.w);
+        const int cnt = a.nn[m];
+        double S = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int s = 0; s < cnt; ++s) {
+                const int j = a.nlist[(size_t)s * a.N + m];
+                const float4 pj = a.pos[j];
+                const int tj = ptype(pj.w);
+                const DevEntry& e = s_tab[tm * nt + tj];
+                if (e.kind == RC_KIND_NONE) continue;
+                double dx, dy, dz;
+                const double r2d = canon_r2(pm, pj, a.box, dx, dy, dz);
+                if (!(r2d < e.rcut2)) continue;
+                const int key = (tm < tj ? tm * nt + tj : tj * nt + tm) * 3;
+                const float r2 = (float)r2d;
+                const bool inside = r2d <= e.rmin2;
+                if (pass == 0) {
+                    float phi, g;
+                    pair_eval(e, r2, phi, g);
+                    const float q = qpow(e.sig2 / r2, e.n);
+                    atomicAdd(&s_acc[key + 0], 0.5 * (double)(phi / e.eps));
+                    atomicAdd(&s_acc[key + 1],
+                              0.5 * (double)(4.0f * e.eps * (float)e.n * (2.0f * q * q - q) / e.sigma));
+                    if (e.kind == RC_KIND_SWAP) S += (double)(e.sqrt_lam * vhat_value(e, inside, r2));
+                } else {
+                    if (e.kind != RC_KIND_SWAP) continue;
+                    const float u = vhat_value(e, inside, r2);
+                    const float w = e.sqrt_lam * u;
+                    const double excl = S - (double)w;
+                    if (e.lam > 0.0f) {
+                        atomicAdd(&s_acc[key + 2], (double)w * excl / (2.0 * (double)e.lam));
+                    } else {
+                        // lambda = 0: E3 of same-entry pairs is lambda eps sum u_a u_b
+                        double U = 0.0;
+                        for (int t = 0; t < cnt; ++t) {
+                            const int k = a.nlist[(size_t)t * a.N + m];
+                            const float4 pk = a.pos[k];
+                            if (k == j || ptype(pk.w) != tj) continue;
+                            double ex, ey, ez;
+                            const double r2k = canon_r2(pm, pk, a.box, ex, ey, ez);
+                            if (!(r2k < e.rcut2)) continue;
+                            U += (double)vhat_value(e, r2k <= e.rmin2, (float)r2k);
+                        }
+                        atomicAdd(&s_acc[key + 2], 0.5 * (double)e.eps * (double)u * U);
+                    }
+                    atomicAdd(&s_acc[key + 0], (double)w * excl / (2.0 * (double)e.eps));
+                    if (!inside) {
+                        const float q = qpow(e.sig2 / r2, e.n);
+                        const float du = -4.0f * (float)e.n * (2.0f * q * q - q) / e.sigma;
+                        atomicAdd(&s_acc[key + 1], (double)(e.sqrt_lam * du) * excl);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ne * 3; q += blockDim.x) a.part[(size_t)blockIdx.x * ne * 3 + q] = s_acc[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_param(const double* __restrict__ part, int nblocks,
+                                                        int nt, double* __restrict__ out) {
+    // one block per output value (upper-triangle key), mirrored to both entries
+    __shared__ double red[kBlock];
+    const int q = blockIdx.x;
+    const int ne3 = nt * nt * 3;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[(size_t)b * ne3 + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int key = q / 3, comp = q % 3;
+        const int ta = key / nt, tb = key % nt;
+        if (ta <= tb) {
+            out[(ta * nt + tb) * 3 + comp] = red[0];
+            out[(tb * nt + ta) * 3 + comp] = red[0];
+        }
+    }
+}
+
+hipError_t launch_param(const ParamArgs& a, hipStream_t s) {
+    const int ne = a.tab.nt * a.tab.nt;
+    const size_t shm = sizeof(DevEntry) * ne + sizeof(double) * ne * 3;
+    hipLaunchKernelGGL(k_param_grad, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_param(const double* part, int nblocks, int nt, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_param, dim3(nt * nt * 3), dim3(kBlock), 0, s, part, nblocks, nt, out);
+    return hipGetLastError();
+}
+
+}  // namespace rc

@@ -1,0 +1,563 @@
+// Forces, energy and virial of the swap potential; the fused MD step; bond
+// counting.  gfx950, wave64.
+//
+// Notation: for a centre c and a swap partner a inside r_cut, w_ca =
+// sqrt(Lambda_ca) vhat(r_ca) and w'_ca/r = sqrt(Lambda_ca) vhat'(r_ca)/r_ca,
+// so that a triplet term is w_ca w_cb (eq. 3bp with
+// Lambda_cab = sqrt(Lambda_ca Lambda_cb)).  d = x_a - x_c (minimum image).
+//   force on partner a from (c; a, b):  -w'_ca/r_ca w_cb d_ca
+//   force on the centre:                minus the sum of the two
+#include "rc_internal.h"
+
+namespace rc {
+
+static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+__device__ __forceinline__ void load_table(DevEntry* s_tab, const Table& t) {
+    const int n = t.nt * t.nt;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) s_tab[q] = t.e[q];
+    __syncthreads();
+}
+
+// Walks the list of particle m and evaluates its pair terms and the swap
+// partners inside the cutoff.  The functor gets (j, pj, entry, r2d, r2f, d).
+template <typename F>
+__device__ __forceinline__ void for_each_interacting(int m, const float4& pm, int tm, const int* nlist,
+                                                     int cnt, int N, const float4* pos,
+                                                     const DevEntry* tab, int nt, const Box& box,
+                                                     F&& f) {
+    for (int s = 0; s < cnt; ++s) {
+        const int j = nlist[(size_t)s * N + m];
+        const float4 pj = pos[j];
+        const DevEntry& e = tab[tm * nt + ptype(pj.w)];
+        if (e.kind == RC_KIND_NONE) continue;
+        double dx, dy, dz;
+        const double r2d = canon_r2(pm, pj, box, dx, dy, dz);
+        if (!(r2d < e.rcut2)) continue;
+        f(j, pj, e, r2d, (float)r2d, (float)dx, (float)dy, (float)dz);
+    }
+}
+
+// sum of w_ck over the swap partners k of centre c inside r_cut, except 'skip'
+__device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, int skip,
+                                                       const int* nlist, const int* nn, int N,
+                                                       const float4* pos, const DevEntry* tab,
+                                                       int nt, const Box& box) {
+    const int tc = ptype(pc.w);
+    const int cnt = nn[c];
+    float s = 0.0f;
+    for (int t = 0; t < cnt; ++t) {
+        const int k = nlist[(size_t)t * N + c];
+        if (k == skip) continue;
+        const float4 pk = pos[k];
+        const DevEntry& e = tab[tc * nt + ptype(pk.w)];
+        if (e.kind != RC_KIND_SWAP) continue;
+        double dx, dy, dz;
+        const double r2d = canon_r2(pc, pk, box, dx, dy, dz);
+        if (!(r2d < e.rcut2)) continue;
+        s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, (float)r2d);
+    }
+    return s;
+}
+
+struct Acc {
+    float fx, fy, fz, e;
+    float w[6];  // xx yy zz xy xz yz
+};
+
+__device__ __forceinline__ void acc_virial(Acc& a, float c, float dx, float dy, float dz) {
+    // adds c * d (x) d  (a term (r)_a (F)_b with F = c d)
+    a.w[0] += c * dx * dx;
+    a.w[1] += c * dy * dy;
+    a.w[2] += c * dz * dz;
+    a.w[3] += c * dx * dy;
+    a.w[4] += c * dx * dz;
+    a.w[5] += c * dy * dz;
+}
+
+// Every force term acting on particle m, gathered (no atomics):
+//  * pair terms with every list neighbour,
+//  * the triplets m centres (second walk, only with >= 2 active partners),
+//  * the triplets in which m is a partner of a centre c (two-hop walk over
+//    c's list for the other partners of c; skipped when vhat'(r_cm) = 0).
+// Energy: half of each pair term, every triplet term of m's own centre.
+// Virial: half of each pair term; the full triplet term at its centre.
+template <bool EV>
+__device__ __forceinline__ void gather_particle(int m, const float4& pm, const float4* pos,
+                                                const int* nlist, const int* nn, int N,
+                                                const DevEntry* tab, int nt, const Box& box,
+                                                Acc& acc) {
+    const int tm = ptype(pm.w);
+    const int cnt = nn[m];
+    int nact = 0;
+    double S = 0.0;
+    for_each_interacting(m, pm, tm, nlist, cnt, N, pos, tab, nt, box,
+                         [&](int j, const float4& pj, const DevEntry& e, double r2d, float r2,
+                             float dx, float dy, float dz) {
+                             float phi, g;
+                             pair_eval(e, r2, phi, g);
+                             acc.fx += g * dx;
+                             acc.fy += g * dy;
+                             acc.fz += g * dz;
+                             if (EV) {
+                                 acc.e += 0.5f * phi;
+                                 acc_virial(acc, -0.5f * g, dx, dy, dz);
+                             }
+                             if (e.kind == RC_KIND_SWAP) {
+                                 float u, u1r;
+                                 vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                                 ++nact;
+                                 S += (double)(e.sqrt_lam * u);
+                                 if (u1r != 0.0f && e.sqrt_lam != 0.0f) {
+                                     // m is a partner of centre j
+                                     const float ex = partner_sum_excluding(j, pj, m, nlist, nn, N, pos,
+                                                                            tab, nt, box);
+                                     const float c = e.sqrt_lam * u1r * ex;
+                                     acc.fx += c * dx;
+                                     acc.fy += c * dy;
+                                     acc.fz += c * dz;
+                                 }
+                             }
+                         });
+    if (nact >= 2) {
+        float prefix = 0.0f;
+        for_each_interacting(m, pm, tm, nlist, cnt, N, pos, tab, nt, box,
+                             [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx,
+                                 float dy, float dz) {
+                                 if (e.kind != RC_KIND_SWAP) return;
+                                 float u, u1r;
+                                 vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                                 const float w = e.sqrt_lam * u;
+                                 const float excl = (float)(S - (double)w);
+                                 const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
+                                 acc.fx += c * dx;
+                                 acc.fy += c * dy;
+                                 acc.fz += c * dz;
+                                 if (EV) {
+                                     acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
+                                     prefix += w;
+                                     acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
+                                 }
+                             });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// atomic-free gather force kernel (RC_FORCE_GATHER)
+// ---------------------------------------------------------------------------
+template <bool EV>
+__global__ __launch_bounds__(kBlock) void k_forces_gather(ForceArgs a) {
+    extern __shared__ DevEntry s_tab[];
+    load_table(s_tab, a.tab);
+    const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    Acc acc = {};
+    if (m < a.N) {
+        const float4 pm = a.pos[m];
+        gather_particle<EV>(m, pm, a.pos, a.nlist, a.nn, a.N, s_tab, a.tab.nt, a.box, acc);
+        float4 f = make_float4(acc.fx, acc.fy, acc.fz, acc.e);
+        if (a.accumulate) {
+            const float4 o = a.force[m];
+            f.x += o.x;
+            f.y += o.y;
+            f.z += o.z;
+            f.w += o.w;
+        }
+        a.force[m] = f;
+        if (a.status && !(isfinite(f.x) && isfinite(f.y) && isfinite(f.z)))
+            atomicOr(&a.status[RC_ST_FLAGS], RC_FLAG_NONFINITE);
+    }
+    if (EV) {
+        double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
+        block_sum_store<7>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// triplet kernel (default of rc_compute_forces): one wavefront per block.
+// Pair terms per lane; the active partners of centres with two or more of
+// them are staged in an LDS pool; the wave then enumerates every (j<k)
+// triplet of its 64 centres across its lanes.  Forces on partners leave with
+// global atomics, the centre's share is gathered in LDS first.
+// ---------------------------------------------------------------------------
+constexpr int kPool = 512;   // staged partners per wave and round
+
+__global__ __launch_bounds__(kWave) void k_forces_triplet(ForceArgs a, int want_ev) {
+    extern __shared__ DevEntry s_tab[];
+    __shared__ int p_j[kPool];
+    __shared__ float p_w[kPool], p_g[kPool], p_dx[kPool], p_dy[kPool], p_dz[kPool];
+    __shared__ int l_pool[kWave], l_k[kWave], l_tri[kWave + 1];
+    __shared__ float l_f[kWave][4];
+    load_table(s_tab, a.tab);
+    const int nt = a.tab.nt;
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * kWave + lane;
+    const bool live = i < a.N;
+    float4 pi = live ? a.pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ti = ptype(pi.w);
+    const int cnt = live ? a.nn[i] : 0;
+    float fx = 0.f, fy = 0.f, fz = 0.f, en = 0.f;
+    float w6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int nact = 0;
+    for_each_interacting(i, pi, ti, a.nlist, cnt, a.N, a.pos, s_tab, nt, a.box,
+                         [&](int, const float4&, const DevEntry& e, double, float r2, float dx, float dy,
+                             float dz) {
+                             float phi, g;
+                             pair_eval(e, r2, phi, g);
+                             fx += g * dx;
+                             fy += g * dy;
+                             fz += g * dz;
+                             en += 0.5f * phi;
+                             const float c = -0.5f * g;
+                             w6[0] += c * dx * dx; w6[1] += c * dy * dy; w6[2] += c * dz * dz;
+                             w6[3] += c * dx * dy; w6[4] += c * dx * dz; w6[5] += c * dy * dz;
+                             nact += (e.kind == RC_KIND_SWAP);
+                         });
+    // ---- wave-wide triplet stage -------------------------------------------
+    const int k = (nact >= 2) ? nact : 0;
+    int incl = k;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
+    }
+    const int off = incl - k;
+    const int total = __shfl(incl, kWave - 1, kWave);
+    l_f[lane][0] = l_f[lane][1] = l_f[lane][2] = l_f[lane][3] = 0.f;
+    int round_start = 0;
+    bool done = (k == 0);
+    while (round_start < total) {
+        const bool mine = !done && off >= round_start && off + k <= round_start + kPool;
+        // the admitted lanes form a run; the next round starts at the first lane left out
+        int next = total;
+        {
+            int cand = (!done && !mine) ? off : total;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o, kWave));
+            next = cand;
+        }
+        if (mine) {
+            int q = off - round_start;
+            for_each_interacting(i, pi, ti, a.nlist, cnt, a.N, a.pos, s_tab, nt, a.box,
+                                 [&](int j, const float4&, const DevEntry& e, double r2d, float r2,
+                                     float dx, float dy, float dz) {
+                                     if (e.kind != RC_KIND_SWAP) return;
+                                     float u, u1r;
+                                     vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                                     p_j[q] = j;
+                                     p_w[q] = e.sqrt_lam * u;
+                                     p_g[q] = e.sqrt_lam * u1r;
+                                     p_dx[q] = dx;
+                                     p_dy[q] = dy;
+                                     p_dz[q] = dz;
+                                     ++q;
+                                 });
+        }
+        const int tcount = mine ? k * (k - 1) / 2 : 0;
+        int tinc = tcount;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            int t = __shfl_up(tinc, o, kWave);
+            if (lane >= o) tinc += t;
+        }
+        l_tri[lane] = tinc - tcount;
+        if (lane == kWave - 1) l_tri[kWave] = tinc;
+        l_pool[lane] = off - round_start;
+        l_k[lane] = mine ? k : 0;
+        __syncthreads();
+        const int T = l_tri[kWave];
+        for (int t = lane; t < T; t += kWave) {
+            int lo = 0, hi = kWave - 1;  // owner: last lane with l_tri <= t
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (l_tri[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int c = lo, kc = l_k[c];
+            int loc = t - l_tri[c], aa = 0;
+            while (loc >= kc - 1 - aa) {
+                loc -= kc - 1 - aa;
+                ++aa;
+            }
+            const int qa = l_pool[c] + aa, qb = l_pool[c] + aa + 1 + loc;
+            const float wa = p_w[qa], wb = p_w[qb];
+            const float ca = -p_g[qa] * wb, cb = -p_g[qb] * wa;  // force on a = ca d_a
+            const float fax = ca * p_dx[qa], fay = ca * p_dy[qa], faz = ca * p_dz[qa];
+            const float fbx = cb * p_dx[qb], fby = cb * p_dy[qb], fbz = cb * p_dz[qb];
+            float* Fa = reinterpret_cast<float*>(a.force + p_j[qa]);
+            float* Fb = reinterpret_cast<float*>(a.force + p_j[qb]);
+            atomicAdd(Fa + 0, fax); atomicAdd(Fa + 1, fay); atomicAdd(Fa + 2, faz);
+            atomicAdd(Fb + 0, fbx); atomicAdd(Fb + 1, fby); atomicAdd(Fb + 2, fbz);
+            atomicAdd(&l_f[c][0], -(fax + fbx));
+            atomicAdd(&l_f[c][1], -(fay + fby));
+            atomicAdd(&l_f[c][2], -(faz + fbz));
+            atomicAdd(&l_f[c][3], wa * wb);
+            w6[0] += ca * p_dx[qa] * p_dx[qa] + cb * p_dx[qb] * p_dx[qb];
+            w6[1] += ca * p_dy[qa] * p_dy[qa] + cb * p_dy[qb] * p_dy[qb];
+            w6[2] += ca * p_dz[qa] * p_dz[qa] + cb * p_dz[qb] * p_dz[qb];
+            w6[3] += ca * p_dx[qa] * p_dy[qa] + cb * p_dx[qb] * p_dy[qb];
+            w6[4] += ca * p_dx[qa] * p_dz[qa] + cb * p_dx[qb] * p_dz[qb];
+            w6[5] += ca * p_dy[qa] * p_dz[qa] + cb * p_dy[qb] * p_dz[qb];
+        }
+        __syncthreads();
+        if (mine) done = true;
+        round_start = next;
+    }
+    __syncthreads();
+    fx += l_f[lane][0];
+    fy += l_f[lane][1];
+    fz += l_f[lane][2];
+    en += l_f[lane][3];
+    if (live) {
+        float* Fi = reinterpret_cast<float*>(a.force + i);
+        atomicAdd(Fi + 0, fx);
+        atomicAdd(Fi + 1, fy);
+        atomicAdd(Fi + 2, fz);
+        atomicAdd(Fi + 3, en);
+        if (a.status && !(isfinite(fx) && isfinite(fy) && isfinite(fz)))
+            atomicOr(&a.status[RC_ST_FLAGS], RC_FLAG_NONFINITE);
+    }
+    if (want_ev) {
+        double v[7] = {en, w6[0], w6[1], w6[2], w6[3], w6[4], w6[5]};
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) a.ev_part[(size_t)blockIdx.x * kEvWords + q] = v[q];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_f4(float4* __restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s) {
+    if (!a.accumulate)
+        hipLaunchKernelGGL(k_zero_f4, dim3(std::min(nblk(a.N, kBlock), 4096)), dim3(kBlock), 0, s,
+                           a.force, a.N);
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    hipLaunchKernelGGL(k_forces_triplet, dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a,
+                       a.ev_part ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    if (a.ev_part)
+        hipLaunchKernelGGL(k_forces_gather<true>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    else
+        hipLaunchKernelGGL(k_forces_gather<false>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fused MD step: gather forces at x_in, finish the previous step's final half
+// kick, then B A O A into pos_out.  One kernel per step, no atomics on data.
+// ---------------------------------------------------------------------------
+template <bool EV>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a) {
+    extern __shared__ DevEntry s_tab[];
+    load_table(s_tab, a.tab);
+    const int nt = a.tab.nt;
+    const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    const bool live = m < a.N;
+    const uint64_t step = a.step + (a.step_base ? *a.step_base : 0ull);
+    Acc acc = {};
+    float kin[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float path = 0.0f, path_in = 0.0f;
+    bool bad = false, lost = false;
+    if (live) {
+        const float4 pm = a.pos_in[m];
+        const float4 vm = a.vel[m];
+        path_in = vm.w;
+        gather_particle<EV>(m, pm, a.pos_in, a.nlist, a.nn, a.N, s_tab, nt, a.box, acc);
+        const int tm = ptype(pm.w);
+        const float minv = a.minv[tm];
+        const float hdt = 0.5f * a.dt;
+        float vx = vm.x, vy = vm.y, vz = vm.z;
+        if (a.mode == RC_STEP_CONT || a.mode == RC_STEP_FINISH) {  // final B of the previous step
+            vx += hdt * acc.fx * minv;
+            vy += hdt * acc.fy * minv;
+            vz += hdt * acc.fz * minv;
+        }
+        if (EV) {
+            const float mm = 1.0f / minv;
+            kin[0] = mm * vx * vx; kin[1] = mm * vy * vy; kin[2] = mm * vz * vz;
+            kin[3] = mm * vx * vy; kin[4] = mm * vx * vz; kin[5] = mm * vy * vz;
+        }
+        if (a.mode == RC_STEP_FINISH || a.mode == RC_STEP_OBSERVE) {
+            if (a.mode == RC_STEP_FINISH) a.vel[m] = make_float4(vx, vy, vz, vm.w);
+            path = vm.w;
+        } else {
+            vx += hdt * acc.fx * minv;  // B
+            vy += hdt * acc.fy * minv;
+            vz += hdt * acc.fz * minv;
+            float sx = hdt * vx, sy = hdt * vy, sz = hdt * vz;  // A (first half of the drift)
+            if (a.langevin) {                                  // O
+                float z0, z1, z2;
+                thermostat_normals(a.seed, (uint32_t)ptag(pm.w), step, z0, z1, z2);
+                const float c2 = a.c2[tm];
+                vx = a.c1 * vx + c2 * z0;
+                vy = a.c1 * vy + c2 * z1;
+                vz = a.c1 * vz + c2 * z2;
+            }
+            sx += hdt * vx;  // A
+            sy += hdt * vy;
+            sz += hdt * vz;
+            float x = pm.x + sx, y = pm.y + sy, z = pm.z + sz;
+            int ix = 0, iy = 0, iz = 0;
+            if (x >= a.box.hf[0]) { x -= a.box.Lf[0]; ix = 1; } else if (x < -a.box.hf[0]) { x += a.box.Lf[0]; ix = -1; }
+            if (y >= a.box.hf[1]) { y -= a.box.Lf[1]; iy = 1; } else if (y < -a.box.hf[1]) { y += a.box.Lf[1]; iy = -1; }
+            if (z >= a.box.hf[2]) { z -= a.box.Lf[2]; iz = 1; } else if (z < -a.box.hf[2]) { z += a.box.Lf[2]; iz = -1; }
+            path = vm.w + sqrtf(sx * sx + sy * sy + sz * sz);
+            lost = fabsf(sx) > a.box.hf[0] || fabsf(sy) > a.box.hf[1] || fabsf(sz) > a.box.hf[2];
+            bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
+                    isfinite(vz));
+            a.pos_out[m] = make_float4(x, y, z, pm.w);
+            a.vel[m] = make_float4(vx, vy, vz, path);
+            if (a.image && (ix | iy | iz)) {
+                int4 im = a.image[m];
+                im.x += ix;
+                im.y += iy;
+                im.z += iz;
+                a.image[m] = im;
+            }
+        }
+    }
+    // ---- status: wave-aggregated ----------------------------------------------
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool soft = live && (a.mode == RC_STEP_START || a.mode == RC_STEP_CONT) && path > a.soft;
+    const bool hard = live && path_in > a.hard;
+    const unsigned long long bs = __ballot(soft), bh = __ballot(hard), bb = __ballot(bad),
+                             bl = __ballot(lost);
+    const float pmax = wave_maxf(live ? path : 0.0f);
+    if (lane == 0) {
+        int fl = (bs ? RC_FLAG_REBUILD : 0) | (bh ? RC_FLAG_STALE : 0) | (bb ? RC_FLAG_NONFINITE : 0) |
+                 (bl ? RC_FLAG_LOST : 0);
+        if (fl) {
+            atomicOr(&a.status[RC_ST_FLAGS], fl);
+            if (bs) atomicMin(&a.status[RC_ST_FIRST_SOFT], (int)(step & 0x7fffffff));
+            if (bh) atomicMin(&a.status[RC_ST_FIRST_HARD], (int)(step & 0x7fffffff));
+        }
+        atomicMax(&a.status[RC_ST_MAXPATH], __float_as_int(pmax));
+    }
+    if (EV) {
+        double v[13] = {acc.e,  acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5],
+                        kin[0], kin[1],   kin[2],   kin[3],   kin[4],   kin[5]};
+        block_sum_store<13>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
+    }
+}
+
+hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    if (ev)
+        hipLaunchKernelGGL(k_step<true>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    else
+        hipLaunchKernelGGL(k_step<false>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    return hipGetLastError();
+}
+
+void step_kernel_info(bool ev, const void** fn) {
+    *fn = ev ? reinterpret_cast<const void*>(&k_step<true>) : reinterpret_cast<const void*>(&k_step<false>);
+}
+
+// ---------------------------------------------------------------------------
+// bond count: swap pairs i<j with canonical r^2 < r_min^2
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+__global__ __launch_bounds__(kBlock) void k_bonds(const float4* __restrict__ pos,
+                                                 const int* __restrict__ nlist,
+                                                 const int* __restrict__ nn, int N, Table tab, Box box,
+                                                 unsigned long long* __restrict__ count) {
+    extern __shared__ DevEntry s_tab[];
+    load_table(s_tab, tab);
+    const int i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    unsigned c = 0;
+    if (i < N) {
+        const float4 pi = pos[i];
+        const int ti = ptype(pi.w);
+        const int cnt = nn[i];
+        for (int s = 0; s < cnt; ++s) {
+            const int j = nlist[(size_t)s * N + i];
+            if (j <= i) continue;
+            const float4 pj = pos[j];
+            const DevEntry& e = s_tab[ti * tab.nt + ptype(pj.w)];
+            if (e.kind != RC_KIND_SWAP) continue;
+            double dx, dy, dz;
+            if (canon_r2(pi, pj, box, dx, dy, dz) < e.rmin2) ++c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int N, Table tab, Box box,
+                        unsigned long long* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
+    const size_t shm = sizeof(DevEntry) * tab.nt * tab.nt;
+    hipLaunchKernelGGL(k_bonds, dim3(nblk(N, kBlock)), dim3(kBlock), shm, s, pos, nlist, nn, N, tab,
+                       box, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fixed-order FP64 reduction of block partial rows
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* __restrict__ part, int nblocks,
+                                                       int first, int count, double* __restrict__ out) {
+    // one block per output word; each thread sums a strided slice, then a tree
+    __shared__ double red[kBlock];
+    const int q = first + blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[(size_t)b * kEvWords + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3(count), dim3(kBlock), 0, s, part, nblocks, first, count, out);
+    return hipGetLastError();
+}
+
+__global__ void k_status_reset_chunk(int* st) {
+    // keep KMAX and MAXPATH, clear the chunk-local markers
+    st[RC_ST_FLAGS] = 0;
+    st[RC_ST_FIRST_SOFT] = 0x7fffffff;
+    st[RC_ST_FIRST_HARD] = 0x7fffffff;
+}
+hipError_t launch_status_reset_chunk(int* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_reset_chunk, dim3(1), dim3(1), 0, s, status);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_words(int* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+hipError_t launch_zero_words(int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+__global__ void k_add_step(unsigned long long* p, unsigned long long v) { *p += v; }
+hipError_t launch_add_step(unsigned long long* p, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+void add_step_kernel_info(const void** fn) { *fn = reinterpret_cast<const void*>(&k_add_step); }
+
+__global__ void k_set_step(unsigned long long* p, unsigned long long v) { *p = v; }
+hipError_t launch_set_step(unsigned long long* p, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+}  // namespace rc

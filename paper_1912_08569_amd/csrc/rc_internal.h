@@ -1,0 +1,373 @@
+// Internal declarations of the swap-potential engine (HIP, gfx950).
+//
+// Device data layout and the inline device helpers shared by the kernels:
+// the compiled per-type-pair table, the canonical FP64 cut predicate, the
+// FP32 pair / switching-factor evaluation, Morton keys of the cell grid and
+// the Philox4x32-10 thermostat noise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rc.h"
+
+namespace rc {
+
+constexpr int kBlock = 256;          // threads per block of the particle kernels
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kEvWords = 13;         // E, W(6), K(6)
+constexpr int kScanItems = 8;        // counts per thread in the scan kernels
+constexpr int kScanTile = kBlock * kScanItems;
+
+// One compiled table entry (64 bytes).  FP32 values feed the term arithmetic;
+// the FP64 squares feed the canonical cut / bond decisions.
+struct alignas(16) DevEntry {
+    int kind;          // RC_KIND_*
+    int n;             // exponent (6 for WCA)
+    float eps;         // epsilon
+    float sig2;        // sigma^2
+    float sqrt_lam;    // sqrt(lambda * eps)  (triplet weight per partner)
+    float rlist2;      // (r_cut + r_buff)^2 * (1 + 1e-5), list radius
+    double rcut2;      // r_cut * r_cut
+    double rmin2;      // (sigma*sigma) * pow(2, 2/n)
+    float inv_eps;     // 1/eps (SWAP), 0 otherwise
+    float sigma;       // sigma
+    float lam;         // lambda (SWAP), 0 otherwise
+    float pad[3];
+};
+
+struct Box {
+    double L[3];
+    double h[3];       // L/2
+    float Lf[3];
+    float hf[3];
+};
+
+// --------------------------------------------------------------------------
+// particle word helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int ptype(float w) { return __float_as_int(w) & ((1 << RC_TYPE_BITS) - 1); }
+__device__ __forceinline__ int ptag(float w) { return __float_as_int(w) >> RC_TYPE_BITS; }
+
+// --------------------------------------------------------------------------
+// canonical FP64 predicate: d = x_j - x_i folded once by +-L,
+// r^2 = (dx*dx + dy*dy) + dz*dz with separately rounded products and sums.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double fold(double d, double L, double h) {
+    if (d > h) d -= L;
+    else if (d < -h) d += L;
+    return d;
+}
+
+__device__ __forceinline__ double canon_r2(const float4& pi, const float4& pj, const Box& b,
+                                           double& dx, double& dy, double& dz) {
+    dx = fold(__dsub_rn((double)pj.x, (double)pi.x), b.L[0], b.h[0]);
+    dy = fold(__dsub_rn((double)pj.y, (double)pi.y), b.L[1], b.h[1]);
+    dz = fold(__dsub_rn((double)pj.z, (double)pi.z), b.L[2], b.h[2]);
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// --------------------------------------------------------------------------
+// FP32 term arithmetic
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float ipowf(float x, int n) {
+    float r = 1.0f;
+    while (n) {
+        if (n & 1) r *= x;
+        x *= x;
+        n >>= 1;
+    }
+    return r;
+}
+
+// q = (sigma/r)^n from s2 = sigma^2 / r^2
+__device__ __forceinline__ float qpow(float s2, int n) {
+    float q = ipowf(s2, n >> 1);
+    if (n & 1) q *= sqrtf(s2);
+    return q;
+}
+
+// Pair term (eq. 2b for SWAP; WCA = n 6 plus the +eps shift): energy phi and
+// g = phi'(r)/r, so that the force on i from the pair is g * (x_j - x_i).
+__device__ __forceinline__ void pair_eval(const DevEntry& e, float r2, float& phi, float& g) {
+    float s2 = e.sig2 / r2;
+    float q = qpow(s2, e.n);
+    float q2 = q * q;
+    phi = 4.0f * e.eps * (q2 - q) + (e.kind == RC_KIND_WCA ? e.eps : 0.0f);
+    g = 4.0f * e.eps * (float)e.n * (q - 2.0f * q2) / r2;
+}
+
+// Switching factor of eq. (pot) inside the cutoff: u and u'(r)/r.
+// 'inside' is the canonical FP64 decision r^2 <= r_min^2.
+__device__ __forceinline__ void vhat_eval(const DevEntry& e, bool inside, float r2, float& u,
+                                          float& u1r) {
+    if (inside) {
+        u = 1.0f;
+        u1r = 0.0f;
+        return;
+    }
+    float s2 = e.sig2 / r2;
+    float q = qpow(s2, e.n);
+    float q2 = q * q;
+    u = 4.0f * (q - q2);
+    u1r = 4.0f * (float)e.n * (2.0f * q2 - q) / r2;
+}
+
+__device__ __forceinline__ float vhat_value(const DevEntry& e, bool inside, float r2) {
+    if (inside) return 1.0f;
+    float q = qpow(e.sig2 / r2, e.n);
+    return 4.0f * (q - q * q);
+}
+
+// --------------------------------------------------------------------------
+// Morton keys of the cell grid (10 bits per axis)
+// --------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+__host__ __device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+struct Grid {
+    int nc[3];
+    int bits;            // Morton bits per axis
+    float inv_w[3];      // nc / L
+    uint32_t nkeys;      // 8^bits
+};
+
+__device__ __forceinline__ int cell_coord(float x, float h, float inv_w, int nc) {
+    int c = (int)floorf((x + h) * inv_w);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller normals
+// --------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+__device__ __forceinline__ float u01(uint32_t x) {
+    return ((float)x + 0.5f) * 2.3283064365386963e-10f;  // (x + 1/2) 2^-32
+}
+
+__device__ __forceinline__ void thermostat_normals(uint64_t seed, uint32_t tag, uint64_t step,
+                                                   float& z0, float& z1, float& z2) {
+    U4 w = philox10(U4{tag, (uint32_t)step, (uint32_t)(step >> 32), 0u}, (uint32_t)seed,
+                    (uint32_t)(seed >> 32));
+    float r0 = sqrtf(-2.0f * logf(u01(w.x)));
+    float r1 = sqrtf(-2.0f * logf(u01(w.z)));
+    float s0, c0, s1, c1;
+    sincosf(6.283185307179586f * u01(w.y), &s0, &c0);
+    sincosf(6.283185307179586f * u01(w.w), &s1, &c1);
+    z0 = r0 * c0;
+    z1 = r0 * s0;
+    z2 = r1 * c1;
+}
+
+// --------------------------------------------------------------------------
+// wave / block reductions
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Sum NW doubles per thread over the block; thread 0 writes them to out[0..NW).
+template <int NW>
+__device__ __forceinline__ void block_sum_store(double (&v)[NW], double* out) {
+    __shared__ double red[kBlock / kWave][NW];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) red[wid][q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < NW) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// XCD-aware block order: consecutive dispatch slots go round-robin over the
+// 8 XCDs, so hand each XCD one contiguous range of (Morton ordered) particles
+// to keep neighbour gathers inside that XCD's L2.
+__device__ __forceinline__ int xcd_block(int nblocks) {
+    const int b = blockIdx.x;
+    const int per = nblocks / 8;
+    if (per == 0 || b >= per * 8) return b;
+    return (b % 8) * per + b / 8;
+}
+
+// --------------------------------------------------------------------------
+// argument bundles and launchers (defined in the kernel translation units)
+// --------------------------------------------------------------------------
+struct Table {
+    const DevEntry* e;   // [nt*nt]
+    int nt;
+};
+
+struct StepArgs {
+    const float4* pos_in;
+    float4* pos_out;
+    float4* vel;
+    int4* image;
+    const int* nlist;
+    const int* nn;
+    int N;
+    int mode;
+    Table tab;
+    Box box;
+    float minv[RC_MAX_TYPES];  // 1/m per type
+    float c2[RC_MAX_TYPES];    // sqrt((1 - c1^2) kT / m) per type
+    float dt, c1;
+    int langevin;
+    float hard, soft;          // path-length thresholds (stale list, rebuild)
+    uint64_t seed;
+    uint64_t step;             // step index (added to *step_base if not NULL)
+    const unsigned long long* step_base;
+    double* ev_part;           // [nblocks*13] | NULL
+    int* status;
+};
+
+hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
+void step_kernel_info(bool ev, const void** fn);
+
+struct ForceArgs {
+    const float4* pos;
+    const int* nlist;
+    const int* nn;
+    int N;
+    Table tab;
+    Box box;
+    float4* force;
+    double* ev_part;   // [nblocks*13] | NULL
+    int accumulate;
+    int* status;
+};
+hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s);
+hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s);
+
+struct IntegrateArgs {
+    float4* pos;
+    float4* vel;
+    const float4* force;
+    int4* image;
+    int N;
+    int half;
+    Box box;
+    float minv[RC_MAX_TYPES];
+    float c2[RC_MAX_TYPES];
+    float dt, c1;
+    int langevin;
+    float soft;
+    uint64_t seed, step;
+    double* kin_part;   // [nblocks*13] | NULL (slots 7..12 used)
+    int* status;
+};
+hipError_t launch_integrate(const IntegrateArgs& a, hipStream_t s);
+
+struct CellsArgs {
+    float4* pos;
+    float4* vel;
+    int4* image;
+    int* rtag;
+    int N;
+    Box box;
+    Grid g;
+    // workspace
+    int* counts;       // [nkeys]
+    int* cell_start;   // [nkeys + 1]
+    int* keys;         // [N]
+    int* rank;         // [N]
+    int* order;        // [N]
+    int* block_sums;   // [nkeys / kScanTile + 1]
+    float4* tpos;
+    float4* tvel;
+    int4* timage;
+};
+hipError_t launch_cells(const CellsArgs& a, hipStream_t s);
+
+struct NlistArgs {
+    const float4* pos;
+    float4* vel;
+    int N;
+    Box box;
+    Grid g;
+    const int* cell_start;
+    Table tab;
+    int k_max;
+    int* nlist;
+    int* nn;
+    int* status;
+};
+hipError_t launch_nlist(const NlistArgs& a, hipStream_t s);
+
+hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int N, Table tab,
+                        Box box, unsigned long long* count, hipStream_t s);
+
+// reduce nblocks partial rows of 13 doubles into out[first .. first+count)
+hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
+                              hipStream_t s);
+hipError_t launch_status_reset_chunk(int* status, hipStream_t s);
+hipError_t launch_zero_words(int* p, int n, hipStream_t s);
+hipError_t launch_add_step(unsigned long long* p, unsigned long long v, hipStream_t s);
+hipError_t launch_set_step(unsigned long long* p, unsigned long long v, hipStream_t s);
+void add_step_kernel_info(const void** fn);
+
+struct HvpArgs {
+    const float4* pos;
+    const int* nlist;
+    const int* nn;
+    int N;
+    Table tab;
+    Box box;
+    const float4* v;
+    float4* hv;
+};
+hipError_t launch_hvp(const HvpArgs& a, hipStream_t s);
+
+struct ParamArgs {
+    const float4* pos;
+    const int* nlist;
+    const int* nn;
+    int N;
+    Table tab;
+    Box box;
+    const float4* adj;     // NULL for the energy gradient
+    double* part;          // [nblocks * nt*nt*3]
+};
+hipError_t launch_param(const ParamArgs& a, hipStream_t s);
+hipError_t launch_reduce_param(const double* part, int nblocks, int nt, double* out,
+                               hipStream_t s);
+
+}  // namespace rc

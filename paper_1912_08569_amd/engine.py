@@ -1,0 +1,194 @@
+"""``System``: device buffers of one periodic system and calls into the engine.
+
+Owns the torch tensors the C ABI works on (positions in two buffers,
+velocities, image counters, tag map, neighbour list, cell workspace, status
+word, rollback snapshots) and forwards to the ``rc_*`` entry points.  No
+arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as rcl
+from . import api
+from ._lib import RcError
+
+
+@dataclasses.dataclass
+class RunResult:
+    stats: rcl.MdStats
+    ev: Optional[np.ndarray]        # [rows, 13]: E, W(6), K(6)
+    bonds: Optional[np.ndarray]     # [rows]
+
+
+class System:
+    """One periodic system on the current GPU.
+
+    ``pos`` (N,3) FP32 in [-L/2, L/2), ``types`` (N,), ``L`` (FP32 edge or 3 edges),
+    ``table`` (kind, epsilon, sigma, n, rcut, lam arrays), optional ``vel`` (N,3).
+    """
+
+    def __init__(self, pos, types, L, table, vel=None, mass=None, r_buff: float = 0.3, k_max: int = 32,
+                 rollback: bool = True, device: str = "cuda"):
+        self.device = torch.device(device)
+        self.ctx = api.Context(table, r_buff)
+        self.table = table
+        self.N = int(np.asarray(pos).shape[0])
+        self.edges = [float(L)] * 3 if np.isscalar(L) else [float(x) for x in L]
+        self.box = api.box(self.edges)
+        nt = self.ctx.ntypes
+        ty = np.asarray(types)
+        if ty.size and (ty.min() < 0 or ty.max() >= nt):
+            raise ValueError(f"particle types must lie in [0, {nt})")
+        self.mass = np.ones(nt) if mass is None else np.asarray(mass, dtype=np.float64)
+        N = self.N
+        dev = self.device
+        self.pos = api.pack_positions(pos, types, device=dev)
+        self.pos_alt = torch.empty_like(self.pos)
+        v = np.zeros((N, 4), np.float32)
+        if vel is not None:
+            v[:, :3] = np.asarray(vel, dtype=np.float32)
+        self.vel = torch.from_numpy(v).to(dev)
+        self.image = torch.zeros((N, 4), dtype=torch.int32, device=dev)
+        self.rtag = torch.zeros(N, dtype=torch.int32, device=dev)
+        self.k_max = int(k_max)
+        self.nlist = torch.zeros(self.k_max * N, dtype=torch.int32, device=dev)
+        self.nn = torch.zeros(N, dtype=torch.int32, device=dev)
+        ws = api.rc_cells_workspace_bytes(self.ctx, N, self.box)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.status = torch.zeros(rcl.RC_STATUS_WORDS, dtype=torch.int32, device=dev)
+        self.force = torch.zeros((N, 4), dtype=torch.float32, device=dev)
+        self.ev = torch.zeros(13, dtype=torch.float64, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.rollback = rollback
+        if rollback:
+            self.snap_pos = torch.empty_like(self.pos)
+            self.snap_vel = torch.empty_like(self.vel)
+            self.snap_image = torch.empty_like(self.image)
+        self.built = False
+
+    @classmethod
+    def from_workload(cls, sysw, **kw):
+        return cls(sysw.pos, sysw.types, sysw.L, sysw.table, vel=sysw.vel, mass=sysw.mass, **kw)
+
+    # ---- neighbour list -----------------------------------------------------------
+    def _grow(self, k_needed: int):
+        self.k_max = int(max(k_needed + 4, int(self.k_max * 1.5)))
+        self.nlist = torch.zeros(self.k_max * self.N, dtype=torch.int32, device=self.device)
+
+    def build(self):
+        """Bin, re-order and build the neighbour list (grows k_max on overflow)."""
+        for _ in range(4):
+            api.rc_build_cells(self.ctx, self.pos, self.vel, self.image, self.rtag, self.box, self.ws)
+            api.rc_clear_status(self.status)
+            api.rc_build_nlist(self.ctx, self.pos, self.vel, self.box, self.ws, self.k_max, self.nlist,
+                               self.nn, self.status)
+            code, st = api.rc_read_status(self.status)
+            if code == rcl.RC_ERR_NLIST_OVERFLOW:
+                self._grow(st[rcl.RC_ST_KMAX])
+                continue
+            if code != rcl.RC_OK:
+                raise RcError(code, "neighbour list build")
+            self.built = True
+            return st[rcl.RC_ST_KMAX]
+        raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
+
+    # ---- single evaluations -----------------------------------------------------
+    def compute_forces(self, gather: bool = False, ev: bool = True):
+        """Forces (N,4: xyz + per-particle energy) and, if ev, [E, W(6)] (float64)."""
+        if not self.built:
+            self.build()
+        flags = rcl.RC_FORCE_GATHER if gather else 0
+        api.rc_compute_forces(self.ctx, self.pos, self.nlist, self.nn, self.box, self.force,
+                              self.ev if ev else None, flags, self.status)
+        return self.force, (self.ev[:7] if ev else None)
+
+    def bond_count(self) -> int:
+        if not self.built:
+            self.build()
+        api.rc_bond_count(self.ctx, self.pos, self.nlist, self.nn, self.box, self.count)
+        return int(self.count.item())
+
+    def hvp(self, v: torch.Tensor) -> torch.Tensor:
+        """H v for v of shape (N,4) in the engine's particle order."""
+        if not self.built:
+            self.build()
+        out = torch.empty_like(self.pos)
+        api.rc_force_hvp(self.ctx, self.pos, self.nlist, self.nn, self.box, v.contiguous(), out)
+        return out
+
+    def param_grad(self) -> np.ndarray:
+        if not self.built:
+            self.build()
+        nt = self.ctx.ntypes
+        g = torch.zeros(nt * nt * 3, dtype=torch.float64, device=self.device)
+        api.rc_param_grad(self.ctx, self.pos, self.nlist, self.nn, self.box, g)
+        return g.cpu().numpy().reshape(nt, nt, 3)
+
+    # ---- dynamics ------------------------------------------------------------------
+    def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
+        return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))
+
+    def md_buffers(self, ev_log=None, bonds_log=None) -> rcl.MdBuffers:
+        b = rcl.MdBuffers()
+        p = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        b.pos, b.pos_alt, b.vel = p(self.pos), p(self.pos_alt), p(self.vel)
+        b.image, b.rtag, b.nlist, b.nn = p(self.image), p(self.rtag), p(self.nlist), p(self.nn)
+        b.k_max = self.k_max
+        b.cells_ws = p(self.ws)
+        b.cells_ws_bytes = self.ws.numel()
+        if self.rollback:
+            b.snap_pos, b.snap_vel, b.snap_image = p(self.snap_pos), p(self.snap_vel), p(self.snap_image)
+        b.status = p(self.status)
+        b.ev_log, b.bonds_log = p(ev_log), p(bonds_log)
+        return b
+
+    def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
+            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8) -> RunResult:
+        """Advance n_steps with the fused step kernel under the chunked driver."""
+        rows = (n_steps // log_period + 2) if log_period > 0 else 1
+        ev_log = torch.zeros((rows, 13), dtype=torch.float64, device=self.device)
+        bonds_log = torch.zeros(rows, dtype=torch.int64, device=self.device)
+        opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac))
+        for _ in range(4):
+            try:
+                st = api.rc_md_run(self.ctx, self.md_buffers(ev_log, bonds_log), self.N, self.box, cfg, step0,
+                                   n_steps, opts)
+                break
+            except RcError as e:
+                if e.code != rcl.RC_ERR_NLIST_OVERFLOW:
+                    raise
+                done = int(e.stats.steps_done)
+                self._grow(int(e.stats.k_needed))
+                step0 += done
+                n_steps -= done
+        else:
+            raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
+        self.built = True
+        n = int(st.log_rows)
+        return RunResult(stats=st, ev=ev_log[:n].cpu().numpy(), bonds=bonds_log[:n].cpu().numpy())
+
+    # ---- state in tag order ----------------------------------------------------------
+    def state_by_tag(self):
+        """(pos (N,3) float32, vel (N,3), image (N,3), types) in tag order."""
+        xyz, types, tags = api.unpack_positions(self.pos)
+        order = np.argsort(tags)
+        v = self.vel.cpu().numpy()[:, :3]
+        im = self.image.cpu().numpy()[:, :3]
+        return xyz[order], v[order], im[order], types[order]
+
+    def by_tag(self, arr: torch.Tensor) -> np.ndarray:
+        """Re-order a per-particle device array into tag order (numpy)."""
+        _, _, tags = api.unpack_positions(self.pos)
+        a = arr.detach().cpu().numpy()
+        out = np.empty_like(a)
+        out[tags] = a
+        return out
+
+    def to_engine_order(self, arr_by_tag: np.ndarray) -> torch.Tensor:
+        _, _, tags = api.unpack_positions(self.pos)
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(arr_by_tag)[tags])).to(self.device)

@@ -1,0 +1,159 @@
+"""Throughput of the swap-potential MD step on one MI355X.
+
+Workload: the 1,048,576-particle self-assembly mixture (50 % inert WCA
+colloids, 50 % reactive swap sites: eps 15, sigma 0.3, n 10, r_cut 0.45,
+lambda 1; colloid-site WCA sigma 0.65), cubic periodic box at density 0.3,
+seeded non-overlapping start, BAOAB Langevin kT 0.05, dt 0.001, gamma 1.
+A step is one pass of the whole hot path: the fused force+integrate kernel,
+the skin test, the cell/neighbour-list rebuilds when the skin is used up, and
+the chunk bookkeeping of the driver; energy, virial, kinetic tensor and bond
+count are logged every 100 steps.  Inputs are resident on the GPU before the
+timed region starts.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel,
+CPU-oracle baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--warmup", type=int, default=200)
+    p.add_argument("--N", type=int, default=1048576)
+    p.add_argument("--lam", type=float, default=1.0)
+    p.add_argument("--log-period", type=int, default=100)
+    p.add_argument("--no-graph", action="store_true")
+    p.add_argument("--kernel-reps", type=int, default=200)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
+    return p.parse_args()
+
+
+def cpu_baseline(sysw, seconds):
+    """The C brute-force oracle (plain O(N^2) FP64, OpenMP) on sampled particles.
+
+    Per sampled particle it evaluates every pair and triplet term acting on
+    it against all N particles, which is what one step costs it per particle
+    (the integration itself is negligible next to it).  Rate = sampled
+    particles per second = particle-timesteps/s of the oracle.
+    """
+    from oracle import brute
+    brute.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(99)
+    m = 2 * cores
+    t0 = time.perf_counter()
+    brute.forces_subset(sysw.pos, sysw.types, sysw.L, sysw.table, rng.choice(sysw.N, m, replace=False), cores)
+    dt = time.perf_counter() - t0
+    M = int(max(m, min(200000, m * seconds / max(dt, 1e-3))))
+    idx = rng.choice(sysw.N, M, replace=False)
+    t0 = time.perf_counter()
+    brute.forces_subset(sysw.pos, sysw.types, sysw.L, sysw.table, idx, cores)
+    dt = time.perf_counter() - t0
+    return {"value": M / dt, "unit": "particle-timesteps/s", "cores": cores, "kind": "oracle",
+            "sample": f"forces on {M} random particles of the {sysw.N}-particle system, each against all "
+                      f"{sysw.N} particles (FP64 brute force, {dt:.1f} s)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_1912_08569_amd import System, api
+    from paper_1912_08569_amd import _lib as rcl
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    sysw = W.assembly_mixture(N=a.N, lam=a.lam, seed=1003, kT=0.05)
+    print(f"# generated {sysw.name} in {time.perf_counter() - t_gen:.1f}s, L={sysw.L}", file=sys.stderr,
+          flush=True)
+    S = System.from_workload(sysw, r_buff=0.3, k_max=32)
+    cfg = S.integrator(dt=0.001, kT=0.05, gamma=1.0, seed=2003)
+    S.build()
+    use_graph = not a.no_graph
+    # warm-up (also relaxes the random start)
+    S.run(a.warmup, cfg, step0=0, log_period=a.log_period, use_graph=use_graph)
+    torch.cuda.synchronize()
+    # ---- timed region: exactly `steps` steps ------------------------------------------
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    res = S.run(a.steps, cfg, step0=a.warmup, log_period=a.log_period, use_graph=use_graph)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_events = e0.elapsed_time(e1)
+    sec = wall
+    value = a.N * a.steps / sec
+    st = res.stats
+    print(f"# {a.steps} steps in {sec * 1e3:.1f} ms ({sec / a.steps * 1e6:.2f} us/step; events "
+          f"{ms_events:.1f} ms); rebuilds {st.rebuilds} rollbacks {st.rollbacks} chunks {st.chunks}",
+          file=sys.stderr, flush=True)
+    # ---- dominant kernel: the fused step, timed on its own stream with events ---------
+    nn = S.nn
+    kbar = float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())   # nn = n_swap | n_other << 16
+    # work on copies so the physical state is untouched; launches come from C (no Python per launch)
+    pos_a, pos_b = S.pos.clone(), S.pos.clone()
+    vel = S.vel.clone()
+    status = torch.zeros(rcl.RC_STATUS_WORDS, dtype=torch.int32, device=S.device)
+    api.rc_time_fused_steps(S.ctx, pos_a, pos_b, vel, S.nlist, S.nn, S.box, cfg, 10 ** 7, 10, status)
+    ms = api.rc_time_fused_steps(S.ctx, pos_a, pos_b, vel, S.nlist, S.nn, S.box, cfg, 10 ** 7 + 10,
+                                 a.kernel_reps, status)
+    t_kernel = ms / a.kernel_reps * 1e-3
+    bytes_per_particle = 16 + 16 + 4 + 4.0 * kbar + 16 + 16   # pos, vel, nn, list in; pos, vel out
+    achieved = a.N * bytes_per_particle / t_kernel / 1e9
+    traffic = None
+    if os.path.exists(a.traffic):
+        try:
+            with open(a.traffic) as f:
+                tr = json.load(f)
+            if tr.get("kernel") == "k_step" and int(tr.get("N", 0)) == a.N:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_step (fused force + BAOAB)", "kernel_us": round(t_kernel * 1e6, 3),
+            "algorithmic_bytes_per_particle": round(bytes_per_particle, 2), "mean_list_length": round(kbar, 3)}
+    out = {
+        "metric": "particle-timesteps/s", "value": value, "unit": "particle-timesteps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": sec / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"swap/WCA self-assembly mixture, N={a.N}, density 0.3, lambda {a.lam}, "
+                               "Langevin kT 0.05 dt 0.001, log every 100 steps",
+                   "N": a.N, "lambda": a.lam, "graph": use_graph, "rebuilds": int(st.rebuilds),
+                   "rollbacks": int(st.rollbacks), "chunks": int(st.chunks),
+                   "bonds_final": int(res.bonds[-1]) if res.bonds is not None and len(res.bonds) else None},
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysw, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -42,6 +42,11 @@
  *   force[i] = (fx, fy, fz, e_i): e_i is the per-particle energy (half of each
  *              pair term, every triplet term to its centre), when requested.
  *   image[i] = int4 periodic image counters (x, y, z, unused); may be NULL.
+ *   nlist/nn = the neighbour list of rc_build_nlist: nlist is [k_max][N] int32
+ *              (column-major).  Swap-kind neighbours of i fill slots 0 .. ns-1
+ *              from the front, all other neighbours slots k_max-1 down to
+ *              k_max-no from the back; nn[i] = ns | (no << 16), ns + no <= k_max.
+ *              Every consumer takes k_max.
  * Particle order is the library's: rc_build_cells re-orders particles along a
  * Morton curve of the cell grid; identity travels with the tag in pos.w.
  *
@@ -178,7 +183,9 @@ int rc_build_cells(rc_ctx* ctx, float* pos /* [N*4] */, float* vel /* [N*4] | NU
  * the path lengths vel[i].w are reset to 0 (the skin reference).  The list is
  * valid while every path length stays <= r_buff / 2: any pair then outside
  * the list is at least r_cut apart (the paper's three-particle neighbour
- * lists, SI "Performance").                                                  */
+ * lists, SI "Performance").  Layout: swap-kind neighbours first, the others
+ * from the back of the column (nn[i] = ns | (no << 16), see above), so that
+ * the triplet walks read swap partners only.                                 */
 int rc_build_nlist(rc_ctx* ctx, const float* pos, float* vel /* NULL ok */, int N, rc_box box,
                    const void* ws, size_t ws_bytes, int k_max, int* nlist /* [k_max*N] */,
                    int* nn /* [N] */, int* status /* [RC_STATUS_WORDS] | NULL */, void* stream);
@@ -205,7 +212,7 @@ int rc_build_nlist(rc_ctx* ctx, const float* pos, float* vel /* NULL ok */, int 
  * reduced in FP64 in a fixed order.                                          */
 #define RC_FORCE_ACCUMULATE 1u
 #define RC_FORCE_GATHER     4u
-int rc_compute_forces(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+int rc_compute_forces(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                       rc_box box, float* force /* [N*4] */, double* ev /* [7] | NULL */,
                       unsigned flags, int* status /* NULL ok */, void* stream);
 
@@ -252,15 +259,23 @@ int rc_integrate_step(rc_ctx* ctx, float* pos, float* vel, const float* force,
 #define RC_STEP_FINISH 2
 #define RC_STEP_OBSERVE 3
 int rc_step_fused(rc_ctx* ctx, const float* pos_in, float* pos_out, float* vel, int* image,
-                  const int* nlist, const int* nn, int N, rc_box box,
+                  const int* nlist, const int* nn, int k_max, int N, rc_box box,
                   const rc_integrator* cfg /* host */, uint64_t step, int mode, double soft_frac,
                   double* ev /* [13] | NULL */, int* status, void* stream);
+
+/* Measurement helper: launch `reps` RC_STEP_CONT fused steps back to back from
+ * host code (alternating pos_a -> pos_b -> pos_a ...; status is written to
+ * status), bracketed by hipEvents on `stream`; synchronises and returns the
+ * elapsed milliseconds in *ms (host).  Used to time the step kernel alone. */
+int rc_time_fused_steps(rc_ctx* ctx, float* pos_a, float* pos_b, float* vel, const int* nlist,
+                        const int* nn, int k_max, int N, rc_box box, const rc_integrator* cfg /* host */,
+                        uint64_t step0, int reps, int* status, float* ms /* host */, void* stream);
 
 /* ---- bond count (hot-path step a4) -------------------------------------------
  * Number of swap pairs i<j with r^2 < r_min^2 (canonical FP64 predicate, the
  * bond criterion of the swap system), written to *count (device, uint64).
  * Exact; independent of list order.  Requires a list built with this ctx.    */
-int rc_bond_count(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+int rc_bond_count(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                   rc_box box, unsigned long long* count /* device */, void* stream);
 
 /* ---- MD driver (hot-path step a6) --------------------------------------------
@@ -329,11 +344,11 @@ int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,
  *   r_cut.  Device output, overwritten.
  * rc_param_vjp: out[(a*nt+b)*3 + w] = sum_m adj_m . dF_m/dtheta_w{a,b}
  *   (FP64, device), for fitting through trajectories.                        */
-int rc_force_hvp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+int rc_force_hvp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                  rc_box box, const float* v /* [N*4] */, float* hv /* [N*4] */, void* stream);
-int rc_param_grad(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+int rc_param_grad(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                   rc_box box, double* grad /* [nt*nt*3] */, void* stream);
-int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int N,
+int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                  rc_box box, const float* adj /* [N*4] */, double* out /* [nt*nt*3] */,
                  void* stream);
 

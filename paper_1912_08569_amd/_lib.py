@@ -11,7 +11,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librc.so")
+# RC_LIBRARY selects another build of the same ABI (default: the in-tree librc.so)
+LIB_PATH = os.environ.get("RC_LIBRARY") or os.path.join(HERE, "librc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "rc.h")
 
 RC_OK = 0
@@ -104,17 +105,19 @@ _SIGS = {
     "rc_cells_workspace_bytes": ([_VP, _I, Box, ctypes.POINTER(ctypes.c_size_t)], _I),
     "rc_build_cells": ([_VP, _VP, _VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _VP], _I),
     "rc_build_nlist": ([_VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),
-    "rc_compute_forces": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
+    "rc_compute_forces": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
     "rc_integrate_step": ([_VP, _VP, _VP, _VP, _VP, _I, Box, ctypes.POINTER(Integrator), _U64, _I,
                            _VP, _VP, _VP], _I),
-    "rc_step_fused": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, Box, ctypes.POINTER(Integrator), _U64,
+    "rc_step_fused": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, Box, ctypes.POINTER(Integrator), _U64,
                        _I, _D, _VP, _VP, _VP], _I),
-    "rc_bond_count": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP], _I),
+    "rc_bond_count": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
+    "rc_time_fused_steps": ([_VP, _VP, _VP, _VP, _VP, _VP, _I, _I, Box, ctypes.POINTER(Integrator), _U64, _I,
+                             _VP, ctypes.POINTER(ctypes.c_float), _VP], _I),
     "rc_md_run": ([_VP, ctypes.POINTER(MdBuffers), _I, Box, ctypes.POINTER(Integrator), _U64, _I,
                    ctypes.POINTER(MdOptions), ctypes.POINTER(MdStats), _VP], _I),
-    "rc_force_hvp": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP, _VP], _I),
-    "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP], _I),
-    "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, Box, _VP, _VP, _VP], _I),
+    "rc_force_hvp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
+    "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
+    "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
 }
 
 _lib = None

@@ -20,7 +20,7 @@ __all__ = [
     "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
-    "rc_param_grad", "rc_clear_status", "rc_read_status",
+    "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
 ]
 
 
@@ -158,9 +158,14 @@ def rc_build_nlist(ctx: Context, pos, vel, bx, ws, k_max, nlist, nn, status=None
                                   _ptr(status), _stream(stream)), ctx.handle)
 
 
+def _kmax(nlist, N):
+    return int(nlist.numel() // max(N, 1))
+
+
 def rc_compute_forces(ctx: Context, pos, nlist, nn, bx, force, ev=None, flags=0, status=None, stream=None):
     N = pos.shape[0]
-    check(L.load().rc_compute_forces(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(force),
+    check(L.load().rc_compute_forces(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
+                                     _ptr(force),
                                      _ptr(ev), int(flags), _ptr(status), _stream(stream)), ctx.handle)
 
 
@@ -176,13 +181,13 @@ def rc_step_fused(ctx: Context, pos_in, pos_out, vel, image, nlist, nn, bx, cfg,
                   soft_frac=0.8, ev=None, status=None, stream=None):
     N = pos_in.shape[0]
     check(L.load().rc_step_fused(ctx.handle, _ptr(pos_in), _ptr(pos_out), _ptr(vel), _ptr(image),
-                                 _ptr(nlist), _ptr(nn), N, bx, ctypes.byref(cfg), int(step), int(mode),
+                                 _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, ctypes.byref(cfg), int(step), int(mode),
                                  float(soft_frac), _ptr(ev), _ptr(status), _stream(stream)), ctx.handle)
 
 
 def rc_bond_count(ctx: Context, pos, nlist, nn, bx, count, stream=None):
     N = pos.shape[0]
-    check(L.load().rc_bond_count(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(count),
+    check(L.load().rc_bond_count(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(count),
                                  _stream(stream)), ctx.handle)
 
 
@@ -199,13 +204,26 @@ def rc_md_run(ctx: Context, bufs: L.MdBuffers, N, bx, cfg, step0, n_steps, opts:
     return st
 
 
+def rc_time_fused_steps(ctx: Context, pos_a, pos_b, vel, nlist, nn, bx, cfg, step0, reps, status,
+                        stream=None) -> float:
+    """Milliseconds for `reps` back-to-back fused step launches (HIP events)."""
+    ms = ctypes.c_float()
+    N = pos_a.shape[0]
+    check(L.load().rc_time_fused_steps(ctx.handle, _ptr(pos_a), _ptr(pos_b), _ptr(vel), _ptr(nlist), _ptr(nn),
+                                       _kmax(nlist, N), N, bx, ctypes.byref(cfg), int(step0), int(reps), _ptr(status),
+                                       ctypes.byref(ms), _stream(stream)), ctx.handle)
+    return float(ms.value)
+
+
 def rc_force_hvp(ctx: Context, pos, nlist, nn, bx, v, hv, stream=None):
     N = pos.shape[0]
-    check(L.load().rc_force_hvp(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(v), _ptr(hv),
+    check(L.load().rc_force_hvp(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(v),
+                                _ptr(hv),
                                 _stream(stream)), ctx.handle)
 
 
 def rc_param_grad(ctx: Context, pos, nlist, nn, bx, grad, stream=None):
     N = pos.shape[0]
-    check(L.load().rc_param_grad(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), N, bx, _ptr(grad),
+    check(L.load().rc_param_grad(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
+                                 _ptr(grad),
                                  _stream(stream)), ctx.handle)

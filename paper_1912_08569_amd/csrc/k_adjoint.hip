@@ -53,11 +53,11 @@ __device__ __forceinline__ void w_d012(const DevEntry& e, bool inside, float r2,
 
 // S_c and dS_c = sum_b w'_cb rhat_cb . (v_b - v_c) over c's swap partners
 __device__ __forceinline__ void centre_sums(int c, const float4& pc, const float4& vc, const int* nlist,
-                                            const int* nn, int N, const float4* pos, const float4* v,
+                                            const int* nn, int k_max, int N, const float4* pos, const float4* v,
                                             const DevEntry* tab, int nt, const Box& box, double& S,
                                             double& dS) {
     const int tc = ptype(pc.w);
-    const int cnt = nn[c];
+    const int cnt = nn_swap(nn[c]);   // swap-kind neighbours fill the front of the column
     S = 0.0;
     dS = 0.0;
     for (int t = 0; t < cnt; ++t) {
@@ -87,12 +87,14 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
     const float4 pm = a.pos[m];
     const float4 vm = a.v[m];
     const int tm = ptype(pm.w);
-    const int cnt = a.nn[m];
+    const int packed = a.nn[m];
+    const int ns = nn_swap(packed), cnt = ns + nn_other(packed);
     double Sm, dSm;
-    centre_sums(m, pm, vm, a.nlist, a.nn, a.N, a.pos, a.v, s_tab, nt, a.box, Sm, dSm);
+    centre_sums(m, pm, vm, a.nlist, a.nn, a.k_max, a.N, a.pos, a.v, s_tab, nt, a.box, Sm, dSm);
     float hx = 0.f, hy = 0.f, hz = 0.f;
     for (int s = 0; s < cnt; ++s) {
-        const int j = a.nlist[(size_t)s * a.N + m];
+        const int slot = s < ns ? s : a.k_max - 1 - (s - ns);
+        const int j = a.nlist[(size_t)slot * a.N + m];
         const float4 pj = a.pos[j];
         const DevEntry& e = s_tab[tm * nt + ptype(pj.w)];
         if (e.kind == RC_KIND_NONE) continue;
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
             w_d012(e, r2d <= e.rmin2, r2, r, w, w1, w2);
             if (w1 != 0.0f || w2 != 0.0f) {
                 double Sj, dSj;
-                centre_sums(j, pj, vj, a.nlist, a.nn, a.N, a.pos, a.v, s_tab, nt, a.box, Sj, dSj);
+                centre_sums(j, pj, vj, a.nlist, a.nn, a.k_max, a.N, a.pos, a.v, s_tab, nt, a.box, Sj, dSj);
                 const float X = (float)((Sm - (double)w) + (Sj - (double)w));
                 const float dX = (float)((dSm - (double)(w1 * dr)) + (dSj - (double)(w1 * dr)));
                 G += w1 * X;
@@ -153,11 +155,14 @@ __global__ __launch_bounds__(kBlock) void k_param_grad(ParamArgs a) {
     if (m < a.N) {
         const float4 pm = a.pos[m];
         const int tm = ptype(pm.w);
-        const int cnt = a.nn[m];
+        const int packed = a.nn[m];
+        const int ns = nn_swap(packed), cnt = ns + nn_other(packed);
         double S = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int s = 0; s < cnt; ++s) {
-                const int j = a.nlist[(size_t)s * a.N + m];
+            const int upto = pass == 0 ? cnt : ns;   // the triplet pass reads the swap range only
+            for (int s = 0; s < upto; ++s) {
+                const int slot = s < ns ? s : a.k_max - 1 - (s - ns);
+                const int j = a.nlist[(size_t)slot * a.N + m];
                 const float4 pj = a.pos[j];
                 const int tj = ptype(pj.w);
                 const DevEntry& e = s_tab[tm * nt + tj];
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_param_grad(ParamArgs a) {
                     } else {
                         // lambda = 0: E3 of same-entry pairs is lambda eps sum u_a u_b
                         double U = 0.0;
-                        for (int t = 0; t < cnt; ++t) {
+                        for (int t = 0; t < ns; ++t) {
                             const int k = a.nlist[(size_t)t * a.N + m];
                             const float4 pk = a.pos[k];
                             if (k == j || ptype(pk.w) != tj) continue;

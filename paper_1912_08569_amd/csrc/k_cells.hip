@@ -201,14 +201,18 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
 // folded by the box (exact image choice) and an FP32 square; the list radius
 // carries a 1e-5 relative margin for that rounding.
 __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
-    extern __shared__ float s_rl2[];  // [nt*nt]
+    extern __shared__ float s_rl2[];  // [nt*nt] list radii^2, then [nt*nt] swap flags
     const int nt = a.tab.nt;
-    for (int q = threadIdx.x; q < nt * nt; q += blockDim.x) s_rl2[q] = a.tab.e[q].rlist2;
+    int* s_swap = reinterpret_cast<int*>(s_rl2 + nt * nt);
+    for (int q = threadIdx.x; q < nt * nt; q += blockDim.x) {
+        s_rl2[q] = a.tab.e[q].rlist2;
+        s_swap[q] = a.tab.e[q].kind == RC_KIND_SWAP;
+    }
     __syncthreads();
     const int nb = gridDim.x;
     const int i = xcd_block(nb) * blockDim.x + threadIdx.x;
     const bool live = i < a.N;
-    int cnt = 0;
+    int ns = 0, no = 0, total = 0;
     if (live) {
         const float4 pi = a.pos[i];
         const int ti = ptype(pi.w);
@@ -237,31 +241,68 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
                         float dy = (float)fold((double)pj.y - (double)pi.y, a.box.L[1], a.box.h[1]);
                         float dz = (float)fold((double)pj.z - (double)pi.z, a.box.L[2], a.box.h[2]);
                         float r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 < s_rl2[ti * nt + ptype(pj.w)]) {
-                            if (cnt < a.k_max) a.nlist[(size_t)cnt * a.N + i] = j;
-                            ++cnt;
+                        const int q = ti * nt + ptype(pj.w);
+                        if (r2 < s_rl2[q]) {
+                            if (s_swap[q]) {
+                                if (ns + no < a.k_max) a.nlist[(size_t)ns * a.N + i] = j;
+                                ++ns;
+                            } else {
+                                if (ns + no < a.k_max) a.nlist[(size_t)(a.k_max - 1 - no) * a.N + i] = j;
+                                ++no;
+                            }
                         }
                     }
                 }
             }
         }
-        a.nn[i] = cnt < a.k_max ? cnt : a.k_max;
+        total = ns + no;
+        // on overflow the stored prefix is what fitted (the status reports it)
+        if (ns + no > a.k_max) {
+            const int keep_s = min(ns, a.k_max);
+            ns = keep_s;
+            no = a.k_max - keep_s;
+        }
+        a.nn[i] = ns | (no << 16);
         if (a.vel) a.vel[i].w = 0.0f;
     }
-    if (a.status) {
-        int m = cnt;
+    const int cnt = total;
+    // block maximum of the list length (no same-address atomics per wave)
+    __shared__ int s_m[kBlock / kWave];
+    int m = cnt;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-        if ((threadIdx.x & (kWave - 1)) == 0) {
-            atomicMax(&a.status[RC_ST_KMAX], m);
-            if (m > a.k_max) atomicOr(&a.status[RC_ST_FLAGS], RC_FLAG_NLIST_OVERFLOW);
-        }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t = max(t, s_m[w]);
+        a.block_max[blockIdx.x] = t;
+    }
+}
+
+// one block: fold the per-block maxima into the status word
+__global__ __launch_bounds__(1024) void k_nlist_status(const int* __restrict__ block_max, int nb, int k_max,
+                                                      int* __restrict__ status) {
+    __shared__ int red[1024];
+    int m = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) m = max(m, block_max[b]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        status[RC_ST_KMAX] = max(status[RC_ST_KMAX], red[0]);
+        if (red[0] > k_max) status[RC_ST_FLAGS] |= RC_FLAG_NLIST_OVERFLOW;
     }
 }
 
 hipError_t launch_nlist(const NlistArgs& a, hipStream_t s) {
-    const size_t shm = sizeof(float) * a.tab.nt * a.tab.nt;
-    hipLaunchKernelGGL(k_nlist, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    const size_t shm = 2 * sizeof(float) * a.tab.nt * a.tab.nt;
+    const int nb = nblk(a.N, kBlock);
+    hipLaunchKernelGGL(k_nlist, dim3(nb), dim3(kBlock), shm, s, a);
+    if (a.status) hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status);
     return hipGetLastError();
 }
 

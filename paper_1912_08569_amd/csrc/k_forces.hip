@@ -19,44 +19,43 @@ __device__ __forceinline__ void load_table(DevEntry* s_tab, const Table& t) {
     __syncthreads();
 }
 
-// Walks the list of particle m and evaluates its pair terms and the swap
-// partners inside the cutoff.  The functor gets (j, pj, entry, r2d, r2f, d).
-template <typename F>
-__device__ __forceinline__ void for_each_interacting(int m, const float4& pm, int tm, const int* nlist,
-                                                     int cnt, int N, const float4* pos,
-                                                     const DevEntry* tab, int nt, const Box& box,
-                                                     F&& f) {
-    for (int s = 0; s < cnt; ++s) {
-        const int j = nlist[(size_t)s * N + m];
+// Walk of particle m's list: the swap range (slots 0 .. ns-1) and, unless
+// SWAP_ONLY, the other range (slots k_max-1 down to k_max-no).  For every
+// neighbour j != skip inside its cutoff (canonical FP64 decision) the functor
+// gets (j, pj, entry, r2 in FP64, r2 in FP32, d = x_j - x_m in FP32).
+template <bool SWAP_ONLY, typename F>
+__device__ __forceinline__ void walk_list(int m, const float4& pm, int tm, const int* nlist, int packed,
+                                          int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
+                                          const Box& box, int skip, F&& f) {
+    auto visit = [&](int j) {
+        if (j == skip) return;
         const float4 pj = pos[j];
         const DevEntry& e = tab[tm * nt + ptype(pj.w)];
-        if (e.kind == RC_KIND_NONE) continue;
+        if (e.kind == RC_KIND_NONE) return;
         double dx, dy, dz;
         const double r2d = canon_r2(pm, pj, box, dx, dy, dz);
-        if (!(r2d < e.rcut2)) continue;
+        if (!(r2d < e.rcut2)) return;
         f(j, pj, e, r2d, (float)r2d, (float)dx, (float)dy, (float)dz);
+    };
+    const int ns = nn_swap(packed);
+    for (int s = 0; s < ns; ++s) visit(nlist[(size_t)s * N + m]);
+    if (!SWAP_ONLY) {
+        const int no = nn_other(packed);
+        for (int s = 0; s < no; ++s) visit(nlist[(size_t)(k_max - 1 - s) * N + m]);
     }
 }
 
 // sum of w_ck over the swap partners k of centre c inside r_cut, except 'skip'
+// (only c's swap range is read: for a bonded pair it usually holds skip alone)
 __device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, int skip,
-                                                       const int* nlist, const int* nn, int N,
+                                                       const int* nlist, const int* nn, int k_max, int N,
                                                        const float4* pos, const DevEntry* tab,
                                                        int nt, const Box& box) {
-    const int tc = ptype(pc.w);
-    const int cnt = nn[c];
     float s = 0.0f;
-    for (int t = 0; t < cnt; ++t) {
-        const int k = nlist[(size_t)t * N + c];
-        if (k == skip) continue;
-        const float4 pk = pos[k];
-        const DevEntry& e = tab[tc * nt + ptype(pk.w)];
-        if (e.kind != RC_KIND_SWAP) continue;
-        double dx, dy, dz;
-        const double r2d = canon_r2(pc, pk, box, dx, dy, dz);
-        if (!(r2d < e.rcut2)) continue;
-        s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, (float)r2d);
-    }
+    walk_list<true>(c, pc, ptype(pc.w), nlist, nn[c], k_max, N, pos, tab, nt, box, skip,
+                    [&](int, const float4&, const DevEntry& e, double r2d, float r2, float, float, float) {
+                        s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, r2);
+                    });
     return s;
 }
 
@@ -77,68 +76,207 @@ __device__ __forceinline__ void acc_virial(Acc& a, float c, float dx, float dy, 
 
 // Every force term acting on particle m, gathered (no atomics):
 //  * pair terms with every list neighbour,
-//  * the triplets m centres (second walk, only with >= 2 active partners),
 //  * the triplets in which m is a partner of a centre c (two-hop walk over
-//    c's list for the other partners of c; skipped when vhat'(r_cm) = 0).
+//    c's swap range for the other partners of c; skipped when vhat'(r_cm) = 0),
+//  * the triplets m centres (second walk of m's swap range, only with >= 2
+//    active partners).
 // Energy: half of each pair term, every triplet term of m's own centre.
 // Virial: half of each pair term; the full triplet term at its centre.
 template <bool EV>
-__device__ __forceinline__ void gather_particle(int m, const float4& pm, const float4* pos,
-                                                const int* nlist, const int* nn, int N,
-                                                const DevEntry* tab, int nt, const Box& box,
-                                                Acc& acc) {
+__device__ __forceinline__ void gather_particle(int m, const float4& pm, int packed, const float4* pos,
+                                                const int* nlist, const int* nn, int k_max, int N,
+                                                const DevEntry* tab, int nt, const Box& box, Acc& acc) {
     const int tm = ptype(pm.w);
-    const int cnt = nn[m];
     int nact = 0;
     double S = 0.0;
-    for_each_interacting(m, pm, tm, nlist, cnt, N, pos, tab, nt, box,
-                         [&](int j, const float4& pj, const DevEntry& e, double r2d, float r2,
-                             float dx, float dy, float dz) {
-                             float phi, g;
-                             pair_eval(e, r2, phi, g);
-                             acc.fx += g * dx;
-                             acc.fy += g * dy;
-                             acc.fz += g * dz;
-                             if (EV) {
-                                 acc.e += 0.5f * phi;
-                                 acc_virial(acc, -0.5f * g, dx, dy, dz);
-                             }
-                             if (e.kind == RC_KIND_SWAP) {
-                                 float u, u1r;
-                                 vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
-                                 ++nact;
-                                 S += (double)(e.sqrt_lam * u);
-                                 if (u1r != 0.0f && e.sqrt_lam != 0.0f) {
-                                     // m is a partner of centre j
-                                     const float ex = partner_sum_excluding(j, pj, m, nlist, nn, N, pos,
-                                                                            tab, nt, box);
-                                     const float c = e.sqrt_lam * u1r * ex;
-                                     acc.fx += c * dx;
-                                     acc.fy += c * dy;
-                                     acc.fz += c * dz;
-                                 }
-                             }
-                         });
-    if (nact >= 2) {
-        float prefix = 0.0f;
-        for_each_interacting(m, pm, tm, nlist, cnt, N, pos, tab, nt, box,
-                             [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx,
-                                 float dy, float dz) {
-                                 if (e.kind != RC_KIND_SWAP) return;
-                                 float u, u1r;
-                                 vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
-                                 const float w = e.sqrt_lam * u;
-                                 const float excl = (float)(S - (double)w);
-                                 const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
+    walk_list<false>(m, pm, tm, nlist, packed, k_max, N, pos, tab, nt, box, -1,
+                     [&](int j, const float4& pj, const DevEntry& e, double r2d, float r2, float dx, float dy,
+                         float dz) {
+                         float phi, g;
+                         pair_eval(e, r2, phi, g);
+                         acc.fx += g * dx;
+                         acc.fy += g * dy;
+                         acc.fz += g * dz;
+                         if (EV) {
+                             acc.e += 0.5f * phi;
+                             acc_virial(acc, -0.5f * g, dx, dy, dz);
+                         }
+                         if (e.kind == RC_KIND_SWAP) {
+                             float u, u1r;
+                             vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                             ++nact;
+                             S += (double)(e.sqrt_lam * u);
+                             if (u1r != 0.0f && e.sqrt_lam != 0.0f) {
+                                 // m is a partner of centre j: the other partners of j
+                                 const float c = e.sqrt_lam * u1r *
+                                                 partner_sum_excluding(j, pj, m, nlist, nn, k_max, N, pos, tab, nt, box);
                                  acc.fx += c * dx;
                                  acc.fy += c * dy;
                                  acc.fz += c * dz;
-                                 if (EV) {
-                                     acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
-                                     prefix += w;
-                                     acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
-                                 }
-                             });
+                             }
+                         }
+                     });
+    if (nact >= 2) {
+        float prefix = 0.0f;
+        walk_list<true>(m, pm, tm, nlist, packed, k_max, N, pos, tab, nt, box, -1,
+                        [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
+                            float dz) {
+                            float u, u1r;
+                            vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                            const float w = e.sqrt_lam * u;
+                            const float excl = (float)(S - (double)w);
+                            const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
+                            acc.fx += c * dx;
+                            acc.fy += c * dy;
+                            acc.fz += c * dz;
+                            if (EV) {
+                                acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
+                                prefix += w;
+                                acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
+                            }
+                        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-cooperative gather (one wavefront per block).  The 64 lanes own
+// 64 consecutive particles; their (particle, list slot) entries are laid out
+// flat (exclusive scan of the list lengths) and every lane evaluates one entry
+// per pass, so a wave needs about (sum of list lengths)/64 passes instead of
+// one pass per slot of its longest list.  Per-entry contributions are staged
+// in LDS and each owner lane sums its own entries in slot order
+// (deterministic).  Triplets the owner centres are added afterwards by a walk
+// of its swap range, only when it has two or more active swap partners.
+// ---------------------------------------------------------------------------
+template <bool EV>
+struct Stage {
+    static constexpr int n = EV ? 12 : 5;  // fx fy fz w active [e w0..w5]
+};
+
+template <bool EV>
+__device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
+                                            const float4* pos, const int* nlist, const int* nn, int k_max,
+                                            int N, const DevEntry* tab, int nt, const Box& box, Acc& acc) {
+    constexpr int NC = Stage<EV>::n;
+    __shared__ int s_off[kWave + 1];
+    __shared__ int s_ns[kWave];
+    __shared__ float4 s_pos[kWave];
+    __shared__ float s_c[NC][kWave];
+    const int lane = threadIdx.x;
+    const int ns = live ? nn_swap(packed) : 0;
+    const int cnt = live ? ns + nn_other(packed) : 0;
+    int inc = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    const int my_off = inc - cnt;
+    s_off[lane] = my_off;
+    if (lane == kWave - 1) s_off[kWave] = inc;
+    s_ns[lane] = ns;
+    s_pos[lane] = pm;
+    __syncthreads();
+    const int T = s_off[kWave];
+    double S = 0.0;
+    int nact = 0;
+    for (int base = 0; base < T; base += kWave) {
+        const int e = base + lane;
+        float c[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) c[q] = 0.0f;
+        if (e < T) {
+            int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const int sl = e - s_off[lo], nso = s_ns[lo];
+            const int slot = sl < nso ? sl : k_max - 1 - (sl - nso);
+            const int mo = base_m + lo;
+            const int j = nlist[(size_t)slot * N + mo];
+            const float4 po = s_pos[lo];
+            const float4 pj = pos[j];
+            const DevEntry& en = tab[ptype(po.w) * nt + ptype(pj.w)];
+            if (en.kind != RC_KIND_NONE) {
+                double dxd, dyd, dzd;
+                const double r2d = canon_r2(po, pj, box, dxd, dyd, dzd);
+                if (r2d < en.rcut2) {
+                    const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                    float phi, g;
+                    pair_eval(en, r2, phi, g);
+                    float f = g;
+                    if (EV) {
+                        c[5] = 0.5f * phi;
+                        const float h = -0.5f * g;
+                        c[6] = h * dx * dx; c[7] = h * dy * dy; c[8] = h * dz * dz;
+                        c[9] = h * dx * dy; c[10] = h * dx * dz; c[11] = h * dy * dz;
+                    }
+                    if (en.kind == RC_KIND_SWAP) {
+                        float u, u1r;
+                        vhat_eval(en, r2d <= en.rmin2, r2, u, u1r);
+                        c[3] = en.sqrt_lam * u;
+                        c[4] = 1.0f;
+                        if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
+                            f += en.sqrt_lam * u1r *
+                                 partner_sum_excluding(j, pj, mo, nlist, nn, k_max, N, pos, tab, nt, box);
+                    }
+                    c[0] = f * dx;
+                    c[1] = f * dy;
+                    c[2] = f * dz;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NC; ++q) s_c[q][lane] = c[q];
+        __syncthreads();
+        const int lo = max(my_off, base) - base, hi = min(my_off + cnt, base + kWave) - base;
+        for (int q = lo; q < hi; ++q) {
+            acc.fx += s_c[0][q];
+            acc.fy += s_c[1][q];
+            acc.fz += s_c[2][q];
+            S += (double)s_c[3][q];
+            nact += s_c[4][q] != 0.0f;
+            if (EV) {
+                acc.e += s_c[5][q];
+#pragma unroll
+                for (int w = 0; w < 6; ++w) acc.w[w] += s_c[6 + w][q];
+            }
+        }
+        __syncthreads();
+    }
+    if (live && nact >= 2) {
+        const int m = base_m + lane;
+        float prefix = 0.0f;
+        walk_list<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, tab, nt, box, -1,
+                        [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
+                            float dz) {
+                            float u, u1r;
+                            vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                            const float w = e.sqrt_lam * u;
+                            const float excl = (float)(S - (double)w);
+                            const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
+                            acc.fx += c * dx;
+                            acc.fy += c * dy;
+                            acc.fz += c * dz;
+                            if (EV) {
+                                acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
+                                prefix += w;
+                                acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
+                            }
+                        });
+    }
+}
+
+// wave-wide sums of NW doubles; lane 0 stores them
+template <int NW>
+__device__ __forceinline__ void wave_sum_store(double (&v)[NW], double* out) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) out[q] = v[q];
     }
 }
 
@@ -146,14 +284,17 @@ __device__ __forceinline__ void gather_particle(int m, const float4& pm, const f
 // atomic-free gather force kernel (RC_FORCE_GATHER)
 // ---------------------------------------------------------------------------
 template <bool EV>
-__global__ __launch_bounds__(kBlock) void k_forces_gather(ForceArgs a) {
+__global__ __launch_bounds__(kWave) void k_forces_gather(ForceArgs a) {
     extern __shared__ DevEntry s_tab[];
     load_table(s_tab, a.tab);
-    const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    const int m = xcd_block(gridDim.x) * kWave + threadIdx.x;
+    const bool live = m < a.N;
+    const float4 pm = live ? a.pos[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int packed = live ? a.nn[m] : 0;
     Acc acc = {};
-    if (m < a.N) {
-        const float4 pm = a.pos[m];
-        gather_particle<EV>(m, pm, a.pos, a.nlist, a.nn, a.N, s_tab, a.tab.nt, a.box, acc);
+    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N, s_tab, a.tab.nt,
+                    a.box, acc);
+    if (live) {
         float4 f = make_float4(acc.fx, acc.fy, acc.fz, acc.e);
         if (a.accumulate) {
             const float4 o = a.force[m];
@@ -168,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_gather(ForceArgs a) {
     }
     if (EV) {
         double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
-        block_sum_store<7>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
+        wave_sum_store<7>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
     }
 }
 
@@ -198,7 +339,7 @@ __global__ __launch_bounds__(kWave) void k_forces_triplet(ForceArgs a, int want_
     float fx = 0.f, fy = 0.f, fz = 0.f, en = 0.f;
     float w6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int nact = 0;
-    for_each_interacting(i, pi, ti, a.nlist, cnt, a.N, a.pos, s_tab, nt, a.box,
+    walk_list<false>(i, pi, ti, a.nlist, cnt, a.k_max, a.N, a.pos, s_tab, nt, a.box, -1,
                          [&](int, const float4&, const DevEntry& e, double, float r2, float dx, float dy,
                              float dz) {
                              float phi, g;
@@ -237,10 +378,9 @@ __global__ __launch_bounds__(kWave) void k_forces_triplet(ForceArgs a, int want_
         }
         if (mine) {
             int q = off - round_start;
-            for_each_interacting(i, pi, ti, a.nlist, cnt, a.N, a.pos, s_tab, nt, a.box,
+            walk_list<true>(i, pi, ti, a.nlist, cnt, a.k_max, a.N, a.pos, s_tab, nt, a.box, -1,
                                  [&](int j, const float4&, const DevEntry& e, double r2d, float r2,
                                      float dx, float dy, float dz) {
-                                     if (e.kind != RC_KIND_SWAP) return;
                                      float u, u1r;
                                      vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
                                      p_j[q] = j;
@@ -345,9 +485,9 @@ hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s) {
 hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
     if (a.ev_part)
-        hipLaunchKernelGGL(k_forces_gather<true>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+        hipLaunchKernelGGL(k_forces_gather<true>, dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
     else
-        hipLaunchKernelGGL(k_forces_gather<false>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+        hipLaunchKernelGGL(k_forces_gather<false>, dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
     return hipGetLastError();
 }
 
@@ -356,22 +496,24 @@ hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) {
 // kick, then B A O A into pos_out.  One kernel per step, no atomics on data.
 // ---------------------------------------------------------------------------
 template <bool EV>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a) {
+__global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     load_table(s_tab, a.tab);
     const int nt = a.tab.nt;
-    const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    const int m = xcd_block(gridDim.x) * kWave + threadIdx.x;
     const bool live = m < a.N;
     const uint64_t step = a.step + (a.step_base ? *a.step_base : 0ull);
     Acc acc = {};
     float kin[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float path = 0.0f, path_in = 0.0f;
     bool bad = false, lost = false;
+    const float4 pm = live ? a.pos_in[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int packed = live ? a.nn[m] : 0;
+    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, s_tab, nt,
+                    a.box, acc);
     if (live) {
-        const float4 pm = a.pos_in[m];
-        const float4 vm = a.vel[m];
         path_in = vm.w;
-        gather_particle<EV>(m, pm, a.pos_in, a.nlist, a.nn, a.N, s_tab, nt, a.box, acc);
         const int tm = ptype(pm.w);
         const float minv = a.minv[tm];
         const float hdt = 0.5f * a.dt;
@@ -425,36 +567,37 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a) {
             }
         }
     }
-    // ---- status: wave-aggregated ----------------------------------------------
-    const int lane = threadIdx.x & (kWave - 1);
+    // ---- status: per-block slots, plain stores (no same-address atomics) ----------
+    // Each block (one wave) ORs its flags and keeps its first soft/hard step in
+    // its own slot of blk[]; k_fold_status folds the slots once per chunk.
     const bool soft = live && (a.mode == RC_STEP_START || a.mode == RC_STEP_CONT) && path > a.soft;
     const bool hard = live && path_in > a.hard;
     const unsigned long long bs = __ballot(soft), bh = __ballot(hard), bb = __ballot(bad),
                              bl = __ballot(lost);
-    const float pmax = wave_maxf(live ? path : 0.0f);
-    if (lane == 0) {
-        int fl = (bs ? RC_FLAG_REBUILD : 0) | (bh ? RC_FLAG_STALE : 0) | (bb ? RC_FLAG_NONFINITE : 0) |
-                 (bl ? RC_FLAG_LOST : 0);
+    if (threadIdx.x == 0) {
+        const int fl = (bs ? RC_FLAG_REBUILD : 0) | (bh ? RC_FLAG_STALE : 0) | (bb ? RC_FLAG_NONFINITE : 0) |
+                       (bl ? RC_FLAG_LOST : 0);
         if (fl) {
-            atomicOr(&a.status[RC_ST_FLAGS], fl);
-            if (bs) atomicMin(&a.status[RC_ST_FIRST_SOFT], (int)(step & 0x7fffffff));
-            if (bh) atomicMin(&a.status[RC_ST_FIRST_HARD], (int)(step & 0x7fffffff));
+            int* slot = a.blk + 3 * blockIdx.x;
+            const int st = (int)(step & 0x7fffffff);
+            slot[0] |= fl;
+            if (fl & RC_FLAG_REBUILD) slot[1] = min(slot[1], st);
+            if (fl & RC_FLAG_STALE) slot[2] = min(slot[2], st);
         }
-        atomicMax(&a.status[RC_ST_MAXPATH], __float_as_int(pmax));
     }
     if (EV) {
         double v[13] = {acc.e,  acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5],
                         kin[0], kin[1],   kin[2],   kin[3],   kin[4],   kin[5]};
-        block_sum_store<13>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
+        wave_sum_store<13>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
     }
 }
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
     if (ev)
-        hipLaunchKernelGGL(k_step<true>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+        hipLaunchKernelGGL(k_step<true>, dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
     else
-        hipLaunchKernelGGL(k_step<false>, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+        hipLaunchKernelGGL(k_step<false>, dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
     return hipGetLastError();
 }
 
@@ -465,41 +608,136 @@ void step_kernel_info(bool ev, const void** fn) {
 // ---------------------------------------------------------------------------
 // bond count: swap pairs i<j with canonical r^2 < r_min^2
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long* p) { *p = 0ull; }
-
 __global__ __launch_bounds__(kBlock) void k_bonds(const float4* __restrict__ pos,
                                                  const int* __restrict__ nlist,
-                                                 const int* __restrict__ nn, int N, Table tab, Box box,
-                                                 unsigned long long* __restrict__ count) {
+                                                 const int* __restrict__ nn, int k_max, int N, Table tab, Box box,
+                                                 unsigned long long* __restrict__ part) {
     extern __shared__ DevEntry s_tab[];
+    __shared__ unsigned s_w[kBlock / kWave];
     load_table(s_tab, tab);
-    const int i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned c = 0;
     if (i < N) {
         const float4 pi = pos[i];
-        const int ti = ptype(pi.w);
-        const int cnt = nn[i];
-        for (int s = 0; s < cnt; ++s) {
-            const int j = nlist[(size_t)s * N + i];
-            if (j <= i) continue;
-            const float4 pj = pos[j];
-            const DevEntry& e = s_tab[ti * tab.nt + ptype(pj.w)];
-            if (e.kind != RC_KIND_SWAP) continue;
-            double dx, dy, dz;
-            if (canon_r2(pi, pj, box, dx, dy, dz) < e.rmin2) ++c;
-        }
+        walk_list<true>(i, pi, ptype(pi.w), nlist, nn[i], k_max, N, pos, s_tab, tab.nt, box, -1,
+                        [&](int j, const float4&, const DevEntry& e, double r2d, float, float, float, float) {
+                            if (j > i && r2d < e.rmin2) ++c;
+                        });
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd(count, (unsigned long long)c);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+        part[blockIdx.x] = t;
+    }
 }
 
-hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int N, Table tab, Box box,
-                        unsigned long long* count, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
+// one block: sum nb partial counts into *out (fixed order: exact either way)
+__global__ __launch_bounds__(1024) void k_sum_u64(const unsigned long long* __restrict__ part, int nb,
+                                                 unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[1024];
+    unsigned long long s = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab, Box box,
+                        unsigned long long* count, unsigned long long* part, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * tab.nt * tab.nt;
-    hipLaunchKernelGGL(k_bonds, dim3(nblk(N, kBlock)), dim3(kBlock), shm, s, pos, nlist, nn, N, tab,
-                       box, count);
+    const int nb = nblk(N, kBlock);
+    hipLaunchKernelGGL(k_bonds, dim3(nb), dim3(kBlock), shm, s, pos, nlist, nn, k_max, N, tab, box, part);
+    hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(1024), 0, s, part, nb, count);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_words_at(int* p) { *p = 0; }
+
+// One block: fold the per-block slots of the step kernel into the status word
+// (OR of flags, min of first steps), reset the slots, and store the largest
+// vel.w (path length) of all particles in status[RC_ST_MAXPATH].
+__global__ __launch_bounds__(1024) void k_fold_status(int* __restrict__ blk, int nb, const float4* __restrict__ vel,
+                                                     int N, int* __restrict__ status) {
+    __shared__ int r_fl[1024], r_s[1024], r_h[1024];
+    __shared__ float r_p[1024];
+    int fl = 0, fs = 0x7fffffff, fh = 0x7fffffff;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        fl |= blk[3 * b];
+        fs = min(fs, blk[3 * b + 1]);
+        fh = min(fh, blk[3 * b + 2]);
+        blk[3 * b] = 0;
+        blk[3 * b + 1] = 0x7fffffff;
+        blk[3 * b + 2] = 0x7fffffff;
+    }
+    float pm = 0.0f;
+    if (vel)
+        for (int i = threadIdx.x; i < N; i += blockDim.x) pm = fmaxf(pm, vel[i].w);
+    r_fl[threadIdx.x] = fl;
+    r_s[threadIdx.x] = fs;
+    r_h[threadIdx.x] = fh;
+    r_p[threadIdx.x] = pm;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            r_fl[threadIdx.x] |= r_fl[threadIdx.x + w];
+            r_s[threadIdx.x] = min(r_s[threadIdx.x], r_s[threadIdx.x + w]);
+            r_h[threadIdx.x] = min(r_h[threadIdx.x], r_h[threadIdx.x + w]);
+            r_p[threadIdx.x] = fmaxf(r_p[threadIdx.x], r_p[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        status[RC_ST_FLAGS] |= r_fl[0];
+        status[RC_ST_FIRST_SOFT] = min(status[RC_ST_FIRST_SOFT], r_s[0]);
+        status[RC_ST_FIRST_HARD] = min(status[RC_ST_FIRST_HARD], r_h[0]);
+        if (vel) status[RC_ST_MAXPATH] = __float_as_int(r_p[0]);
+    }
+}
+
+// largest vel.w (path length) -> status[RC_ST_MAXPATH] (one atomic per block)
+__global__ __launch_bounds__(kBlock) void k_path_max(const float4* __restrict__ vel, int N,
+                                                    int* __restrict__ status) {
+    __shared__ float s_w[kBlock / kWave];
+    float m = 0.0f;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+        m = fmaxf(m, vel[i].w);
+    m = wave_maxf(m);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kBlock / kWave; ++w) t = fmaxf(t, s_w[w]);
+        atomicMax(&status[RC_ST_MAXPATH], __float_as_int(t));
+    }
+}
+
+hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s) {
+    if (vel) {
+        hipLaunchKernelGGL(k_zero_words_at, dim3(1), dim3(1), 0, s, status + RC_ST_MAXPATH);
+        hipLaunchKernelGGL(k_path_max, dim3(std::min(nblk(N, kBlock), 256)), dim3(kBlock), 0, s, vel, N, status);
+    }
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(1024), 0, s, blk, nb, nullptr, N, status);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_blk_reset(int* __restrict__ blk, int nb) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        blk[3 * b] = 0;
+        blk[3 * b + 1] = 0x7fffffff;
+        blk[3 * b + 2] = 0x7fffffff;
+    }
+}
+
+hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_blk_reset, dim3(std::min(nblk(nb, kBlock), 1024)), dim3(kBlock), 0, s, blk, nb);
     return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ struct rc_ctx {
     double* d_part = nullptr;        // block partial rows (13 doubles each) or param partials
     size_t part_bytes = 0;
     unsigned long long* d_step_base = nullptr;
+    int* d_blk = nullptr;            // per-block status slots of the step kernel
+    int blk_cap = 0;                 // slots allocated (blocks)
     GraphCache gc;
     std::string err;
 };
@@ -99,7 +101,7 @@ int make_grid(rc_ctx* c, const Box& b, Grid& g) {
 }
 
 struct CellsLayout {
-    size_t counts, start, keys, rank, order, bsums, tpos, tvel, timage, total;
+    size_t counts, start, keys, rank, order, bsums, bmax, tpos, tvel, timage, total;
 };
 
 CellsLayout cells_layout(int N, const Grid& g) {
@@ -113,6 +115,7 @@ CellsLayout cells_layout(int N, const Grid& g) {
     l.rank = o; o = al(o + 4 * (size_t)N);
     l.order = o; o = al(o + 4 * (size_t)N);
     l.bsums = o; o = al(o + 4 * (nk / kScanTile + 2));
+    l.bmax = o; o = al(o + 4 * ((size_t)N / kBlock + 2));
     l.tpos = o; o = al(o + 16 * (size_t)N);
     l.tvel = o; o = al(o + 16 * (size_t)N);
     l.timage = o; o = al(o + 16 * (size_t)N);
@@ -132,6 +135,23 @@ int ensure_part(rc_ctx* c, size_t bytes) {
 }
 
 Table dev_table(const rc_ctx* c) { return Table{c->d_tab, c->nt}; }
+
+void drop_graphs_ns(rc_ctx* c);
+
+// per-block status slots for nb blocks (allocated once per size, reset to neutral)
+int ensure_blk(rc_ctx* c, int nb, hipStream_t s) {
+    if (c->blk_cap >= nb) return RC_OK;
+    drop_graphs_ns(c);   // graphs hold the old pointer
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->d_blk) (void)hipFree(c->d_blk);
+    c->d_blk = nullptr;
+    c->blk_cap = 0;
+    const int want = std::max(nb, 1024);
+    HIP_TRY(c, hipMalloc(&c->d_blk, sizeof(int) * 3 * (size_t)want));
+    HIP_TRY(c, launch_blk_reset(c->d_blk, want, s));
+    c->blk_cap = want;
+    return RC_OK;
+}
 
 int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin) {
     if (!cfg) return fail(c, RC_ERR_ARG, "integrator is NULL");
@@ -162,6 +182,12 @@ int check_common(rc_ctx* c, int N, const void* pos) {
     if (N >= RC_MAX_TAG) return fail(c, RC_ERR_UNSUPPORTED, "N must be < 2^27");
     if (!pos) return fail(c, RC_ERR_ARG, "positions are NULL");
     if (reinterpret_cast<uintptr_t>(pos) & 15) return fail(c, RC_ERR_ARG, "positions not 16-byte aligned");
+    return RC_OK;
+}
+
+int check_list(rc_ctx* c, const int* nlist, const int* nn, int k_max) {
+    if (!nlist || !nn) return fail(c, RC_ERR_ARG, "nlist / nn are NULL");
+    if (k_max < 1 || k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
     return RC_OK;
 }
 
@@ -252,6 +278,10 @@ int rc_create(rc_ctx** out, int ntypes, const rc_pair_coeff* table, double r_buf
     return RC_OK;
 }
 
+static void drop_graphs(rc_ctx* c);
+namespace {
+void drop_graphs_ns(rc_ctx* c) { drop_graphs(c); }
+}
 static void drop_graphs(rc_ctx* c) {
     for (int p = 0; p < 2; ++p) {
         if (c->gc.exec[p]) (void)hipGraphExecDestroy(c->gc.exec[p]);
@@ -268,6 +298,7 @@ int rc_destroy(rc_ctx* c) {
     if (c->d_tab) (void)hipFree(c->d_tab);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_step_base) (void)hipFree(c->d_step_base);
+    if (c->d_blk) (void)hipFree(c->d_blk);
     delete c;
     return RC_OK;
 }
@@ -382,11 +413,12 @@ int rc_build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, c
     a.nlist = nlist;
     a.nn = nn;
     a.status = status;
+    a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
     HIP_TRY(c, launch_nlist(a, S(stream)));
     return RC_OK;
 }
 
-int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int N, rc_box box,
+int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
                       float* force, double* ev, unsigned flags, int* status, void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
@@ -395,12 +427,14 @@ int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* 
     Box b;
     if ((r = make_box(c, box, b))) return r;
     const bool gather = flags & RC_FORCE_GATHER;
-    const int nb = gather ? nblocks(N, kBlock) : nblocks(N, kWave);
+    const int nb = nblocks(N, kWave);   // both force kernels run one wavefront per block
     if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
     ForceArgs a{};
     a.pos = reinterpret_cast<const float4*>(pos);
     a.nlist = nlist;
     a.nn = nn;
+    a.k_max = k_max;
     a.N = N;
     a.tab = dev_table(c);
     a.box = b;
@@ -449,18 +483,20 @@ int rc_integrate_step(rc_ctx* c, float* pos, float* vel, const float* force, int
 }
 
 static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* pos_out, float* vel, int* image,
-                          const int* nlist, const int* nn, int N, const Box& b, const rc_integrator* cfg,
+                          const int* nlist, const int* nn, int k_max, int N, const Box& b, const rc_integrator* cfg,
                           double soft_frac, int* status) {
     float c1;
     int lang;
     int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang);
     if (r) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
     a.pos_in = reinterpret_cast<const float4*>(pos_in);
     a.pos_out = reinterpret_cast<float4*>(pos_out);
     a.vel = reinterpret_cast<float4*>(vel);
     a.image = reinterpret_cast<int4*>(image);
     a.nlist = nlist;
     a.nn = nn;
+    a.k_max = k_max;
     a.N = N;
     a.tab = dev_table(c);
     a.box = b;
@@ -471,11 +507,13 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
     a.soft = (float)(0.5 * c->r_buff * soft_frac);
     a.seed = cfg->seed;
     a.status = status;
+    if ((r = ensure_blk(c, nblocks(N, kStepBlock), nullptr))) return r;
+    a.blk = c->d_blk;
     return RC_OK;
 }
 
 int rc_step_fused(rc_ctx* c, const float* pos_in, float* pos_out, float* vel, int* image, const int* nlist,
-                  const int* nn, int N, rc_box box, const rc_integrator* cfg, uint64_t step, int mode,
+                  const int* nn, int k_max, int N, rc_box box, const rc_integrator* cfg, uint64_t step, int mode,
                   double soft_frac, double* ev, int* status, void* stream) {
     int r = check_common(c, N, pos_in);
     if (r) return r;
@@ -487,40 +525,82 @@ int rc_step_fused(rc_ctx* c, const float* pos_in, float* pos_out, float* vel, in
     Box b;
     if ((r = make_box(c, box, b))) return r;
     StepArgs a{};
-    if ((r = fill_step_args(c, a, pos_in, pos_out, vel, image, nlist, nn, N, b, cfg, soft_frac, status))) return r;
-    const int nb = nblocks(N, kBlock);
+    if ((r = fill_step_args(c, a, pos_in, pos_out, vel, image, nlist, nn, k_max, N, b, cfg, soft_frac, status))) return r;
+    const int nb = nblocks(N, kStepBlock);
     if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     a.mode = mode;
     a.step = step;
     a.step_base = nullptr;
     a.ev_part = ev ? c->d_part : nullptr;
     HIP_TRY(c, launch_step(a, ev != nullptr, S(stream)));
+    HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, status, S(stream)));
     if (ev && (r = reduce_rows(c, nb, 0, kEvWords, ev, S(stream)))) return r;
     return RC_OK;
 }
 
-int rc_bond_count(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int N, rc_box box,
+int rc_time_fused_steps(rc_ctx* c, float* pos_a, float* pos_b, float* vel, const int* nlist, const int* nn,
+                        int k_max, int N, rc_box box, const rc_integrator* cfg, uint64_t step0, int reps, int* status,
+                        float* ms, void* stream) {
+    int r = check_common(c, N, pos_a);
+    if (r) return r;
+    if (!pos_b || pos_b == pos_a || !vel || !nlist || !nn || !status || !ms || reps < 1)
+        return fail(c, RC_ERR_ARG, "bad arguments to rc_time_fused_steps");
+    Box b;
+    if ((r = make_box(c, box, b))) return r;
+    StepArgs a{};
+    if ((r = fill_step_args(c, a, pos_a, pos_b, vel, nullptr, nlist, nn, k_max, N, b, cfg, 0.8, status))) return r;
+    a.mode = RC_STEP_CONT;
+    a.step_base = nullptr;
+    a.ev_part = nullptr;
+    hipStream_t s = S(stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    float4* P[2] = {reinterpret_cast<float4*>(pos_a), reinterpret_cast<float4*>(pos_b)};
+    hipError_t err = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && err == hipSuccess; ++k) {
+        a.pos_in = P[k & 1];
+        a.pos_out = P[(k + 1) & 1];
+        a.step = step0 + (uint64_t)k;
+        err = launch_step(a, false, s);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = launch_fold_status(c->d_blk, nblocks(N, kStepBlock), nullptr, N, status, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(c, err, "rc_time_fused_steps");
+    return RC_OK;
+}
+
+int rc_bond_count(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
                   unsigned long long* count, void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
     if (!nlist || !nn || !count) return fail(c, RC_ERR_ARG, "nlist / nn / count are NULL");
     Box b;
     if ((r = make_box(c, box, b))) return r;
-    HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(pos), nlist, nn, N, dev_table(c), b, count, S(stream)));
+    if ((r = ensure_part(c, sizeof(unsigned long long) * (size_t)(nblocks(N, kBlock) + 1)))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(pos), nlist, nn, k_max, N, dev_table(c), b, count,
+                            reinterpret_cast<unsigned long long*>(c->d_part), S(stream)));
     return RC_OK;
 }
 
-int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int N, rc_box box, const float* v,
+int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box, const float* v,
                  float* hv, void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
     if (!nlist || !nn || !v || !hv) return fail(c, RC_ERR_ARG, "nlist / nn / v / hv are NULL");
     Box b;
     if ((r = make_box(c, box, b))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
     HvpArgs a{};
     a.pos = reinterpret_cast<const float4*>(pos);
     a.nlist = nlist;
     a.nn = nn;
+    a.k_max = k_max;
     a.N = N;
     a.tab = dev_table(c);
     a.box = b;
@@ -530,7 +610,7 @@ int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, i
     return RC_OK;
 }
 
-int rc_param_grad(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int N, rc_box box, double* grad,
+int rc_param_grad(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box, double* grad,
                   void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
@@ -540,10 +620,12 @@ int rc_param_grad(rc_ctx* c, const float* pos, const int* nlist, const int* nn, 
     const int nb = nblocks(N, kBlock);
     const int nv = c->nt * c->nt * 3;
     if ((r = ensure_part(c, sizeof(double) * (size_t)nv * nb))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
     ParamArgs a{};
     a.pos = reinterpret_cast<const float4*>(pos);
     a.nlist = nlist;
     a.nn = nn;
+    a.k_max = k_max;
     a.N = N;
     a.tab = dev_table(c);
     a.box = b;
@@ -554,7 +636,7 @@ int rc_param_grad(rc_ctx* c, const float* pos, const int* nlist, const int* nn, 
     return RC_OK;
 }
 
-int rc_param_vjp(rc_ctx* c, const float*, const int*, const int*, int, rc_box, const float*, double*, void*) {
+int rc_param_vjp(rc_ctx* c, const float*, const int*, const int*, int, int, rc_box, const float*, double*, void*) {
     return fail(c, RC_ERR_UNSUPPORTED, "rc_param_vjp is not available in this build");
 }
 
@@ -567,7 +649,7 @@ static int build_graphs(rc_ctx* c, const StepArgs& tmpl, int G) {
     step_kernel_info(false, &fn);
     const void* add_fn;
     add_step_kernel_info(&add_fn);
-    const int nb = nblocks(tmpl.N, kBlock);
+    const int nb = nblocks(tmpl.N, kStepBlock);
     const size_t shm = sizeof(DevEntry) * c->nt * c->nt;
     for (int p = 0; p < 2; ++p) {
         hipGraph_t g;
@@ -588,7 +670,7 @@ static int build_graphs(rc_ctx* c, const StepArgs& tmpl, int G) {
             hipKernelNodeParams kp{};
             kp.func = const_cast<void*>(fn);
             kp.gridDim = dim3(nb);
-            kp.blockDim = dim3(kBlock);
+            kp.blockDim = dim3(kStepBlock);
             kp.sharedMemBytes = (unsigned)shm;
             kp.kernelParams = args;
             kp.extra = nullptr;
@@ -638,7 +720,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     Box b;
     if ((r = make_box(c, box, b))) return r;
     hipStream_t s = S(stream);
-    const int nb = nblocks(N, kBlock);
+    const int nb = nblocks(N, kStepBlock);
     if ((r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     rc_md_stats st{};
     int hst[RC_STATUS_WORDS];
@@ -646,7 +728,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     float* P[2] = {buf->pos, buf->pos_alt};
     int cur = 0;
     StepArgs tmpl{};
-    if ((r = fill_step_args(c, tmpl, buf->pos, buf->pos_alt, buf->vel, buf->image, buf->nlist, buf->nn, N, b, cfg,
+    if ((r = fill_step_args(c, tmpl, buf->pos, buf->pos_alt, buf->vel, buf->image, buf->nlist, buf->nn, buf->k_max, N, b, cfg,
                             opt.soft_frac, buf->status)))
         return r;
 
@@ -680,8 +762,8 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     auto log_now = [&](int which, bool ev_step) -> int {
         (void)ev_step;
         if (buf->bonds_log) {
-            HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(P[which]), buf->nlist, buf->nn, N, dev_table(c), b,
-                                    buf->bonds_log + row, s));
+            HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(P[which]), buf->nlist, buf->nn, buf->k_max, N, dev_table(c), b,
+                                    buf->bonds_log + row, reinterpret_cast<unsigned long long*>(c->d_part), s));
         }
         return RC_OK;
     };
@@ -784,6 +866,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
             return RC_OK;
         };
         if ((r = run_steps(chunk_start, C))) return finish(r);
+        HIP_TRY(c, launch_fold_status(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
         HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         ++st.chunks;
@@ -807,6 +890,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
             n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, C));
             HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
             if ((r = run_steps(chunk_start, n_re))) return finish(r);
+            HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
             done = chunk_start + n_re;
             ++st.rollbacks;
             if ((r = rebuild(cur))) return finish(r);

@@ -16,6 +16,7 @@ namespace rc {
 constexpr int kBlock = 256;          // threads per block of the particle kernels
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kEvWords = 13;         // E, W(6), K(6)
+constexpr int kStepBlock = 64;       // one wavefront per block: the step and gather kernels
 constexpr int kScanItems = 8;        // counts per thread in the scan kernels
 constexpr int kScanTile = kBlock * kScanItems;
 
@@ -44,6 +45,14 @@ struct Box {
 };
 
 // --------------------------------------------------------------------------
+// neighbour-list column layout: swap-kind neighbours of i fill slots
+// 0 .. ns-1 from the front, all other neighbours fill slots k_max-1 down to
+// k_max-no from the back; nn[i] = ns | (no << 16).
+// --------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int nn_swap(int packed) { return packed & 0xffff; }
+__host__ __device__ __forceinline__ int nn_other(int packed) { return packed >> 16; }
+
+// --------------------------------------------------------------------------
 // particle word helpers
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int ptype(float w) { return __float_as_int(w) & ((1 << RC_TYPE_BITS) - 1); }
@@ -61,10 +70,13 @@ __device__ __forceinline__ double fold(double d, double L, double h) {
 
 __device__ __forceinline__ double canon_r2(const float4& pi, const float4& pj, const Box& b,
                                            double& dx, double& dy, double& dz) {
-    dx = fold(__dsub_rn((double)pj.x, (double)pi.x), b.L[0], b.h[0]);
-    dy = fold(__dsub_rn((double)pj.y, (double)pi.y), b.L[1], b.h[1]);
-    dz = fold(__dsub_rn((double)pj.z, (double)pi.z), b.L[2], b.h[2]);
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+#pragma clang fp contract(off)
+    dx = fold((double)pj.x - (double)pi.x, b.L[0], b.h[0]);
+    dy = fold((double)pj.y - (double)pi.y, b.L[1], b.h[1]);
+    dz = fold((double)pj.z - (double)pi.z, b.L[2], b.h[2]);
+    // plain operators under contract(off): each product and sum rounds separately
+    const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    return (xx + yy) + zz;
 }
 
 // --------------------------------------------------------------------------
@@ -245,6 +257,7 @@ struct StepArgs {
     const int* nn;
     int N;
     int mode;
+    int k_max;                 // list slots allocated per particle (nlist is [k_max][N])
     Table tab;
     Box box;
     float minv[RC_MAX_TYPES];  // 1/m per type
@@ -257,6 +270,7 @@ struct StepArgs {
     const unsigned long long* step_base;
     double* ev_part;           // [nblocks*13] | NULL
     int* status;
+    int* blk;                  // [nblocks*3] per-block flag / first-soft / first-hard slots
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
@@ -267,6 +281,7 @@ struct ForceArgs {
     const int* nlist;
     const int* nn;
     int N;
+    int k_max;         // list slots allocated per particle
     Table tab;
     Box box;
     float4* force;
@@ -329,11 +344,15 @@ struct NlistArgs {
     int* nlist;
     int* nn;
     int* status;
+    int* block_max;    // [ceil(N / kBlock)] scratch (largest list length per block)
 };
 hipError_t launch_nlist(const NlistArgs& a, hipStream_t s);
 
-hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int N, Table tab,
-                        Box box, unsigned long long* count, hipStream_t s);
+// count: device u64 result; part: scratch of ceil(N / kBlock) u64
+hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                        Box box, unsigned long long* count, unsigned long long* part, hipStream_t s);
+hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s);
+hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s);
 
 // reduce nblocks partial rows of 13 doubles into out[first .. first+count)
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
@@ -348,6 +367,7 @@ struct HvpArgs {
     const float4* pos;
     const int* nlist;
     const int* nn;
+    int k_max;
     int N;
     Table tab;
     Box box;
@@ -360,6 +380,7 @@ struct ParamArgs {
     const float4* pos;
     const int* nlist;
     const int* nn;
+    int k_max;
     int N;
     Table tab;
     Box box;

@@ -81,6 +81,12 @@ def test_boundary_straddling_pairs():
     assert ref["n_triplets"] >= 6
 
 
+def idx_sorted_types(sysg, idx):
+    """Tags of engine indices idx (so that types in tag order can be looked up)."""
+    _, _, tags = __import__("paper_1912_08569_amd").unpack_positions(sysg.pos)
+    return tags[np.asarray(idx)]
+
+
 def test_nlist_contains_every_interacting_pair():
     s = W.assembly_mixture(N=20000, lam=1.0, seed=5)
     sysg = _system(s)
@@ -91,11 +97,20 @@ def test_nlist_contains_every_interacting_pair():
     idx_of_tag = np.empty(s.N, np.int64)
     idx_of_tag[tags] = np.arange(s.N)
     nl = sysg.nlist.cpu().numpy().reshape(sysg.k_max, s.N)
-    nn = sysg.nn.cpu().numpy()
+    packed = sysg.nn.cpu().numpy()
+    ns, no = packed & 0xFFFF, packed >> 16          # swap range at the front, the rest at the back
     have = set()
-    for slot in range(nn.max()):
-        m = nn > slot
+    for slot in range(ns.max()):
+        m = ns > slot
         have.update(zip(np.nonzero(m)[0].tolist(), nl[slot][m].tolist()))
+    for slot in range(no.max()):
+        m = no > slot
+        have.update(zip(np.nonzero(m)[0].tolist(), nl[sysg.k_max - 1 - slot][m].tolist()))
+    # the front range holds exactly the swap-kind neighbours
+    kinds = s.table.kind
+    for slot in range(ns.max()):
+        m = np.nonzero(ns > slot)[0]
+        assert np.all(kinds[ty[idx_sorted_types(sysg, m)], ty[idx_sorted_types(sysg, nl[slot][m])]] == W.KIND_SWAP)
     for a, b in zip(P["i"], P["j"]):
         ia, ib = int(idx_of_tag[a]), int(idx_of_tag[b])
         assert (ia, ib) in have and (ib, ia) in have

@@ -316,6 +316,10 @@ typedef struct rc_md_options {
     int max_chunk;      /* steps between host syncs (upper bound)             */
     int log_period;     /* 0 = log only at the start and the end              */
     double soft_frac;   /* rebuild threshold as a fraction of r_buff/2        */
+    int adapt;          /* 1: size chunks from the measured growth of the path
+                           lengths so that rollbacks stay rare; 0: always
+                           max_chunk steps (rollbacks repair stale chunks)    */
+    int pad;
 } rc_md_options;
 
 typedef struct rc_md_stats {

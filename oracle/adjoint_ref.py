@@ -34,8 +34,14 @@ from . import swap_ref
 from .swap_ref import KIND_SWAP, KIND_WCA
 
 
-def hvp(pos, types, L, table, v):
-    """Hessian of the total energy applied to v [N,3] (FP64)."""
+def hvp(pos, types, L, table, v, with_scale=False):
+    """Hessian of the total energy applied to v [N,3] (FP64).
+
+    With ``with_scale`` also returns, per particle, the sum of the magnitudes
+    of the term contributions it receives, each taken with absolute-summed
+    sub-terms (|phi''| |dr| + |phi'/r| |D_perp| for a pair; likewise for the
+    factors of a triplet term): the error scale of a parity test.
+    """
     P = swap_ref.interacting_pairs(pos, types, L, table)
     N = P["N"]
     v = np.asarray(v, dtype=np.float64)
@@ -49,6 +55,16 @@ def hvp(pos, types, L, table, v):
     hj = (d2 * dr)[:, None] * rh + (d1 / r)[:, None] * (D - dr[:, None] * rh)
     np.add.at(out, j, hj)
     np.add.at(out, i, -hj)
+    scale = np.zeros(N)
+    if with_scale:
+        nn_ = np.where(P["kind"] == KIND_WCA, 6.0, P["n"])
+        q = np.power(P["sigma"] / r, nn_)
+        d2s = 4.0 * P["eps"] * (2.0 * nn_ * (2.0 * nn_ + 1.0) * q * q + nn_ * (nn_ + 1.0) * q) / (r * r)
+        d1s = 4.0 * P["eps"] * nn_ * (2.0 * q * q + q) / r
+        Dn = np.linalg.norm(D, axis=1)
+        sc = d2s * Dn + (d1s / r) * Dn
+        np.add.at(scale, i, sc)
+        np.add.at(scale, j, sc)
 
     E = swap_ref.directed_swap_edges(P)
     a, b = swap_ref.triplets(E, N)
@@ -70,6 +86,24 @@ def hvp(pos, types, L, table, v):
         np.add.at(out, pa, ha)
         np.add.at(out, pb, hb)
         np.add.at(out, c, -(ha + hb))
+        if with_scale:
+            usa, usb = E["us"][a], E["us"][b]
+            u1sa, u1sb = E["u1s"][a], E["u1s"][b]
+            # |u''| scale beyond r_min: 4 (2n(2n+1) q^2 + n(n+1) q)/r^2 ; inside: 0
+            def u2s(k):
+                n_ = E["n"][k]
+                q_ = np.power(E["sigma"][k] / E["r"][k], n_)
+                inside = E["r2"][k] <= E["rmin2"][k]
+                val = 4.0 * (2.0 * n_ * (2.0 * n_ + 1.0) * q_ * q_ + n_ * (n_ + 1.0) * q_) / E["r"][k] ** 2
+                return np.where(inside, 0.0, val)
+            Dan, Dbn = np.linalg.norm(Da, axis=1), np.linalg.norm(Db, axis=1)
+            sa = np.abs(Lt) * ((u2s(a) * Dan * usb + u1sa * u1sb * Dbn) + u1sa * usb * Dan / ra)
+            sb = np.abs(Lt) * ((u2s(b) * Dbn * usa + u1sb * u1sa * Dan) + u1sb * usa * Dbn / rb)
+            np.add.at(scale, pa, sa)
+            np.add.at(scale, pb, sb)
+            np.add.at(scale, c, sa + sb)
+    if with_scale:
+        return out, scale
     return out
 
 

@@ -711,7 +711,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
         return fail(c, RC_ERR_ARG, "md buffers incomplete");
     if (buf->k_max < 1 || buf->k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
-    rc_md_options opt{1, 16, 256, 0, 0.8};
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
     if (opt.max_chunk < 1) opt.max_chunk = 256;
@@ -811,7 +811,9 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
         // ---- plan the chunk ---------------------------------------------------
         int64_t C = std::min<int64_t>(n_steps - done, opt.max_chunk);
         if (!can_roll) C = 1;
-        else if (rate > 0.0) {
+        else if (!opt.adapt) {
+            // fixed chunks: stale chunks are rolled back
+        } else if (rate > 0.0) {
             const double room = (double)hard - (double)last_maxpath;
             const int64_t safe = (int64_t)std::floor(room / (1.5 * rate));
             C = std::max<int64_t>(1, std::min<int64_t>(C, safe));

@@ -148,12 +148,13 @@ class System:
         return b
 
     def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
-            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8) -> RunResult:
+            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True) -> RunResult:
         """Advance n_steps with the fused step kernel under the chunked driver."""
         rows = (n_steps // log_period + 2) if log_period > 0 else 1
         ev_log = torch.zeros((rows, 13), dtype=torch.float64, device=self.device)
         bonds_log = torch.zeros(rows, dtype=torch.int64, device=self.device)
-        opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac))
+        opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
+                             int(adapt), 0)
         for _ in range(4):
             try:
                 st = api.rc_md_run(self.ctx, self.md_buffers(ev_log, bonds_log), self.N, self.box, cfg, step0,

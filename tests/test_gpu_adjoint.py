@@ -1,0 +1,101 @@
+"""Differentiation on the GPU: Hessian-vector products and parameter
+gradients against the oracle's analytic second derivatives (themselves
+pinned by finite differences in the CPU tests)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint_ref
+
+pytestmark = pytest.mark.gpu
+
+HVP_TOL = 2e-5   # of the per-particle term scale (second derivatives of (sigma/r)^(2n) in FP32)
+
+
+def _system(s, **kw):
+    from paper_1912_08569_amd import System
+    return System.from_workload(s, **kw)
+
+
+def _hvp_check(s, seed=0):
+    S = _system(s)
+    S.build()
+    x, _, _, ty = S.state_by_tag()
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((s.N, 3))
+    v /= np.linalg.norm(v)
+    v4 = np.zeros((s.N, 4), np.float32)
+    v4[:, :3] = v
+    hv = S.by_tag(S.hvp(S.to_engine_order(v4)))[:, :3]
+    torch.cuda.synchronize()
+    ref, scale = adjoint_ref.hvp(x, ty, s.L, s.table, v4[:, :3].astype(np.float64), with_scale=True)
+    err = np.abs(hv - ref).max(axis=1)
+    bad = err > HVP_TOL * scale + 1e-30
+    assert not bad.any(), f"HVP error {np.max(err / np.maximum(scale, 1e-30)):.3e} x scale"
+    return S, v4
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.6, 1.0, 1.5])
+def test_hvp_small(lam):
+    s = W.small_reactive(N=2000, density=0.3, seed=61, table=W.swap_table_single(lam=lam))
+    _hvp_check(s)
+
+
+def test_hvp_dense_triplets():
+    s = W.small_reactive(N=3000, density=0.55, seed=31, min_dist=0.85, table=W.swap_table_single(lam=0.4))
+    _hvp_check(s, seed=3)
+
+
+def test_hvp_differentiation_workload():
+    # 32768 reactive particles at density 0.25, eps 10, sigma 1, n 10, lambda 1
+    s = W.small_reactive(N=32768, density=0.25, seed=1005, table=W.swap_table_single(epsilon=10.0, lam=1.0))
+    _hvp_check(s, seed=3005)
+
+
+def test_hvp_mixture():
+    s = W.assembly_mixture(N=20000, lam=1.0, seed=62)
+    _hvp_check(s, seed=5)
+
+
+def test_hvp_symmetry_and_translation():
+    s = W.small_reactive(N=2000, density=0.3, seed=63, table=W.swap_table_single(lam=0.8))
+    S = _system(s)
+    S.build()
+    rng = np.random.default_rng(1)
+    v = torch.from_numpy(np.concatenate([rng.standard_normal((s.N, 3)), np.zeros((s.N, 1))], 1)
+                         .astype(np.float32)).cuda()
+    w = torch.from_numpy(np.concatenate([rng.standard_normal((s.N, 3)), np.zeros((s.N, 1))], 1)
+                         .astype(np.float32)).cuda()
+    Hv, Hw = S.hvp(v), S.hvp(w)
+    a = float((w.double() * Hv.double()).sum())
+    b = float((v.double() * Hw.double()).sum())
+    assert a == pytest.approx(b, rel=1e-4)
+    t = torch.zeros_like(v)
+    t[:, :3] = torch.tensor([0.3, -1.0, 0.7])
+    Ht = S.hvp(t)
+    assert float(Ht.abs().max()) < 1e-4 * float(Hv.abs().max())
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.7, 1.3])
+def test_param_grad(lam):
+    s = W.assembly_mixture(N=20000, lam=lam, seed=64)
+    S = _system(s)
+    S.build()
+    g = S.param_grad()
+    x, _, _, ty = S.state_by_tag()
+    ref = adjoint_ref.param_grad(x, ty, s.L, s.table)
+    scale = np.abs(ref).max() + 1e-30
+    assert np.abs(g - ref).max() <= 1e-5 * scale, (g, ref)
+
+
+def test_param_grad_identities_on_gpu():
+    from oracle import swap_ref
+    s = W.small_reactive(N=4000, density=0.35, seed=65, table=W.swap_table_single(epsilon=2.0, lam=1.3))
+    S = _system(s)
+    S.build()
+    g = S.param_grad()[0, 0]
+    x, _, _, ty = S.state_by_tag()
+    ref = swap_ref.evaluate(x, ty, s.L, s.table)
+    assert g[2] == pytest.approx(ref["E3"] / 1.3, rel=1e-5)
+    assert g[0] == pytest.approx(ref["E"] / 2.0, rel=1e-5, abs=1e-5 * ref["A_E"])

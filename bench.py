@@ -43,7 +43,20 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 256 MiB device copy (to scale FETCH/WRITE counters)")
     return p.parse_args()
+
+
+def step_kernel_source_hash():
+    """Hash of the sources the fused step kernel is built from (counter validity)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1912_08569_amd", "csrc")
+    for name in ("k_forces.hip", "rc_internal.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(sysw, seconds):
@@ -130,7 +143,8 @@ def main():
         try:
             with open(a.traffic) as f:
                 tr = json.load(f)
-            if tr.get("kernel") == "k_step" and int(tr.get("N", 0)) == a.N:
+            if (tr.get("kernel") == "k_step" and int(tr.get("N", 0)) == a.N
+                    and tr.get("source_hash") == step_kernel_source_hash()):
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -150,6 +164,14 @@ def main():
                    "bonds_final": int(res.bonds[-1]) if res.bonds is not None and len(res.bonds) else None},
         "roofline": roof,
     }
+    if a.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = int(src.numel() * 4)
+    out["step_kernel_source_hash"] = step_kernel_source_hash()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysw, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -128,23 +128,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ keys
 }
 
 // One thread per key: order the cell's entries by previous index (the
-// arrival order of the atomics is not deterministic) and gather the
-// particle data into key order.
-__global__ __launch_bounds__(kBlock) void k_sort_permute(const int* __restrict__ start, int nkeys,
-                                                        int* __restrict__ order,
-                                                        const float4* __restrict__ pos,
-                                                        const float4* __restrict__ vel,
-                                                        const int4* __restrict__ image,
-                                                        float4* __restrict__ tpos,
-                                                        float4* __restrict__ tvel,
-                                                        int4* __restrict__ timage,
-                                                        int* __restrict__ rtag, int nrtag) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+// arrival order of the binning atomics is not deterministic).  Cells hold a
+// few particles; empty and single cells return at once.
+__global__ __launch_bounds__(kBlock) void k_sort_cells(const int* __restrict__ start, int nkeys,
+                                                      int* __restrict__ order) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nkeys) return;
     const int s = start[k], e = start[k + 1];
-    if (e <= s) return;
-    for (int a = s + 1; a < e; ++a) {  // insertion sort (cells hold a few particles)
-        int v = order[a];
+    for (int a = s + 1; a < e; ++a) {
+        const int v = order[a];
         int b = a - 1;
         while (b >= s && order[b] > v) {
             order[b + 1] = order[b];
@@ -152,16 +144,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_permute(const int* __restrict__
         }
         order[b + 1] = v;
     }
-    for (int q = s; q < e; ++q) {
-        int o = order[q];
-        float4 p = pos[o];
-        tpos[q] = p;
-        if (vel) tvel[q] = vel[o];
-        if (image) timage[q] = image[o];
-        if (rtag) {
-            const int tg = ptag(p.w);
-            if (tg >= 0 && tg < nrtag) rtag[tg] = q;
-        }
+}
+
+// One thread per new index q: gather the particle data into key order
+// (coalesced writes; the reads follow the previous order, which is close to
+// the new one after the first build).
+__global__ __launch_bounds__(kBlock) void k_permute(const int* __restrict__ order, int N,
+                                                   const float4* __restrict__ pos,
+                                                   const float4* __restrict__ vel,
+                                                   const int4* __restrict__ image,
+                                                   float4* __restrict__ tpos, float4* __restrict__ tvel,
+                                                   int4* __restrict__ timage, int* __restrict__ rtag) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const int o = order[q];
+    const float4 p = pos[o];
+    tpos[q] = p;
+    if (vel) tvel[q] = vel[o];
+    if (image) timage[q] = image[o];
+    if (rtag) {
+        const int tg = ptag(p.w);
+        if (tg >= 0 && tg < N) rtag[tg] = q;
     }
 }
 
@@ -181,8 +184,9 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
                        a.cell_start);
     hipLaunchKernelGGL(k_scatter, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.keys, a.rank,
                        a.cell_start, a.N, a.order);
-    hipLaunchKernelGGL(k_sort_permute, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a.cell_start, nk,
-                       a.order, a.pos, a.vel, a.image, a.tpos, a.tvel, a.timage, a.rtag, a.N);
+    hipLaunchKernelGGL(k_sort_cells, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a.cell_start, nk, a.order);
+    hipLaunchKernelGGL(k_permute, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.order, a.N, a.pos, a.vel, a.image,
+                       a.tpos, a.tvel, a.timage, a.rtag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(a.pos, a.tpos, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);

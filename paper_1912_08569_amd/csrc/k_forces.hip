@@ -152,16 +152,18 @@ template <bool EV>
 struct Stage {
     static constexpr int n = EV ? 12 : 5;  // fx fy fz w active [e w0..w5]
 };
+constexpr int kPerLane = 2;  // flattened entries each lane evaluates per pass
 
 template <bool EV>
 __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
                                             const float4* pos, const int* nlist, const int* nn, int k_max,
                                             int N, const DevEntry* tab, int nt, const Box& box, Acc& acc) {
     constexpr int NC = Stage<EV>::n;
+    constexpr int W = kPerLane * kWave;  // entries per pass
     __shared__ int s_off[kWave + 1];
     __shared__ int s_ns[kWave];
     __shared__ float4 s_pos[kWave];
-    __shared__ float s_c[NC][kWave];
+    __shared__ float s_c[NC][W];
     const int lane = threadIdx.x;
     const int ns = live ? nn_swap(packed) : 0;
     const int cnt = live ? ns + nn_other(packed) : 0;
@@ -180,58 +182,74 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     const int T = s_off[kWave];
     double S = 0.0;
     int nact = 0;
-    for (int base = 0; base < T; base += kWave) {
-        const int e = base + lane;
-        float c[NC];
+    for (int base = 0; base < T; base += W) {
+        // locate and load all entries of this pass first, so their memory
+        // latencies overlap (list index, then neighbour position)
+        int own[kPerLane], jj[kPerLane];
+        float4 pj[kPerLane];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) c[q] = 0.0f;
-        if (e < T) {
-            int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= e) lo = mid;
-                else hi = mid - 1;
-            }
-            const int sl = e - s_off[lo], nso = s_ns[lo];
-            const int slot = sl < nso ? sl : k_max - 1 - (sl - nso);
-            const int mo = base_m + lo;
-            const int j = nlist[(size_t)slot * N + mo];
-            const float4 po = s_pos[lo];
-            const float4 pj = pos[j];
-            const DevEntry& en = tab[ptype(po.w) * nt + ptype(pj.w)];
-            if (en.kind != RC_KIND_NONE) {
-                double dxd, dyd, dzd;
-                const double r2d = canon_r2(po, pj, box, dxd, dyd, dzd);
-                if (r2d < en.rcut2) {
-                    const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
-                    float phi, g;
-                    pair_eval(en, r2, phi, g);
-                    float f = g;
-                    if (EV) {
-                        c[5] = 0.5f * phi;
-                        const float h = -0.5f * g;
-                        c[6] = h * dx * dx; c[7] = h * dy * dy; c[8] = h * dz * dz;
-                        c[9] = h * dx * dy; c[10] = h * dx * dz; c[11] = h * dy * dz;
-                    }
-                    if (en.kind == RC_KIND_SWAP) {
-                        float u, u1r;
-                        vhat_eval(en, r2d <= en.rmin2, r2, u, u1r);
-                        c[3] = en.sqrt_lam * u;
-                        c[4] = 1.0f;
-                        if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
-                            f += en.sqrt_lam * u1r *
-                                 partner_sum_excluding(j, pj, mo, nlist, nn, k_max, N, pos, tab, nt, box);
-                    }
-                    c[0] = f * dx;
-                    c[1] = f * dy;
-                    c[2] = f * dz;
+        for (int u = 0; u < kPerLane; ++u) {
+            const int e = base + u * kWave + lane;
+            own[u] = -1;
+            jj[u] = 0;
+            if (e < T) {
+                int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= e) lo = mid;
+                    else hi = mid - 1;
                 }
+                const int sl = e - s_off[lo], nso = s_ns[lo];
+                const int slot = sl < nso ? sl : k_max - 1 - (sl - nso);
+                own[u] = lo;
+                jj[u] = nlist[(size_t)slot * N + base_m + lo];
             }
         }
 #pragma unroll
-        for (int q = 0; q < NC; ++q) s_c[q][lane] = c[q];
+        for (int u = 0; u < kPerLane; ++u) pj[u] = own[u] >= 0 ? pos[jj[u]] : pm;
+#pragma unroll
+        for (int u = 0; u < kPerLane; ++u) {
+            float c[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) c[q] = 0.0f;
+            if (own[u] >= 0) {
+                const int mo = base_m + own[u];
+                const float4 po = s_pos[own[u]];
+                const DevEntry& en = tab[ptype(po.w) * nt + ptype(pj[u].w)];
+                if (en.kind != RC_KIND_NONE) {
+                    double dxd, dyd, dzd;
+                    const double r2d = canon_r2(po, pj[u], box, dxd, dyd, dzd);
+                    if (r2d < en.rcut2) {
+                        const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                        float phi, g;
+                        pair_eval(en, r2, phi, g);
+                        float f = g;
+                        if (EV) {
+                            c[5] = 0.5f * phi;
+                            const float h = -0.5f * g;
+                            c[6] = h * dx * dx; c[7] = h * dy * dy; c[8] = h * dz * dz;
+                            c[9] = h * dx * dy; c[10] = h * dx * dz; c[11] = h * dy * dz;
+                        }
+                        if (en.kind == RC_KIND_SWAP) {
+                            float uu, u1r;
+                            vhat_eval(en, r2d <= en.rmin2, r2, uu, u1r);
+                            c[3] = en.sqrt_lam * uu;
+                            c[4] = 1.0f;
+                            if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
+                                f += en.sqrt_lam * u1r *
+                                     partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt, box);
+                        }
+                        c[0] = f * dx;
+                        c[1] = f * dy;
+                        c[2] = f * dz;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NC; ++q) s_c[q][u * kWave + lane] = c[q];
+        }
         __syncthreads();
-        const int lo = max(my_off, base) - base, hi = min(my_off + cnt, base + kWave) - base;
+        const int lo = max(my_off, base) - base, hi = min(my_off + cnt, base + W) - base;
         for (int q = lo; q < hi; ++q) {
             acc.fx += s_c[0][q];
             acc.fy += s_c[1][q];
@@ -659,17 +677,18 @@ hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int 
     return hipGetLastError();
 }
 
-__global__ void k_zero_words_at(int* p) { *p = 0; }
-
-// One block: fold the per-block slots of the step kernel into the status word
-// (OR of flags, min of first steps), reset the slots, and store the largest
-// vel.w (path length) of all particles in status[RC_ST_MAXPATH].
-__global__ __launch_bounds__(1024) void k_fold_status(int* __restrict__ blk, int nb, const float4* __restrict__ vel,
-                                                     int N, int* __restrict__ status) {
-    __shared__ int r_fl[1024], r_s[1024], r_h[1024];
-    __shared__ float r_p[1024];
+// Fold the per-block slots of the step kernel into the status word (OR of
+// flags, min of first steps), reset the slots, and raise status[MAXPATH] to
+// the largest vel.w (path lengths only grow between list builds, and a build
+// zeroes the status word).  One launch per chunk; one atomic per block and word.
+__global__ __launch_bounds__(kBlock) void k_fold_status(int* __restrict__ blk, int nb,
+                                                       const float4* __restrict__ vel, int N,
+                                                       int* __restrict__ status) {
+    __shared__ int r_fl[kBlock / kWave], r_s[kBlock / kWave], r_h[kBlock / kWave];
+    __shared__ float r_p[kBlock / kWave];
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     int fl = 0, fs = 0x7fffffff, fh = 0x7fffffff;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    for (int b = tid; b < nb; b += stride) {
         fl |= blk[3 * b];
         fs = min(fs, blk[3 * b + 1]);
         fh = min(fh, blk[3 * b + 2]);
@@ -679,52 +698,44 @@ __global__ __launch_bounds__(1024) void k_fold_status(int* __restrict__ blk, int
     }
     float pm = 0.0f;
     if (vel)
-        for (int i = threadIdx.x; i < N; i += blockDim.x) pm = fmaxf(pm, vel[i].w);
-    r_fl[threadIdx.x] = fl;
-    r_s[threadIdx.x] = fs;
-    r_h[threadIdx.x] = fh;
-    r_p[threadIdx.x] = pm;
+        for (int i = tid; i < N; i += stride) pm = fmaxf(pm, vel[i].w);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        fl |= __shfl_xor(fl, o, kWave);
+        fs = min(fs, __shfl_xor(fs, o, kWave));
+        fh = min(fh, __shfl_xor(fh, o, kWave));
+        pm = fmaxf(pm, __shfl_xor(pm, o, kWave));
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        r_fl[w] = fl;
+        r_s[w] = fs;
+        r_h[w] = fh;
+        r_p[w] = pm;
+    }
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            r_fl[threadIdx.x] |= r_fl[threadIdx.x + w];
-            r_s[threadIdx.x] = min(r_s[threadIdx.x], r_s[threadIdx.x + w]);
-            r_h[threadIdx.x] = min(r_h[threadIdx.x], r_h[threadIdx.x + w]);
-            r_p[threadIdx.x] = fmaxf(r_p[threadIdx.x], r_p[threadIdx.x + w]);
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / kWave; ++q) {
+            fl |= r_fl[q];
+            fs = min(fs, r_s[q]);
+            fh = min(fh, r_h[q]);
+            pm = fmaxf(pm, r_p[q]);
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        status[RC_ST_FLAGS] |= r_fl[0];
-        status[RC_ST_FIRST_SOFT] = min(status[RC_ST_FIRST_SOFT], r_s[0]);
-        status[RC_ST_FIRST_HARD] = min(status[RC_ST_FIRST_HARD], r_h[0]);
-        if (vel) status[RC_ST_MAXPATH] = __float_as_int(r_p[0]);
-    }
-}
-
-// largest vel.w (path length) -> status[RC_ST_MAXPATH] (one atomic per block)
-__global__ __launch_bounds__(kBlock) void k_path_max(const float4* __restrict__ vel, int N,
-                                                    int* __restrict__ status) {
-    __shared__ float s_w[kBlock / kWave];
-    float m = 0.0f;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
-        m = fmaxf(m, vel[i].w);
-    m = wave_maxf(m);
-    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float t = 0.0f;
-        for (int w = 0; w < kBlock / kWave; ++w) t = fmaxf(t, s_w[w]);
-        atomicMax(&status[RC_ST_MAXPATH], __float_as_int(t));
+        fl |= r_fl[0];
+        fs = min(fs, r_s[0]);
+        fh = min(fh, r_h[0]);
+        pm = fmaxf(pm, r_p[0]);
+        if (fl) atomicOr(&status[RC_ST_FLAGS], fl);
+        if (fs != 0x7fffffff) atomicMin(&status[RC_ST_FIRST_SOFT], fs);
+        if (fh != 0x7fffffff) atomicMin(&status[RC_ST_FIRST_HARD], fh);
+        if (vel) atomicMax(&status[RC_ST_MAXPATH], __float_as_int(pm));
     }
 }
 
 hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s) {
-    if (vel) {
-        hipLaunchKernelGGL(k_zero_words_at, dim3(1), dim3(1), 0, s, status + RC_ST_MAXPATH);
-        hipLaunchKernelGGL(k_path_max, dim3(std::min(nblk(N, kBlock), 256)), dim3(kBlock), 0, s, vel, N, status);
-    }
-    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(1024), 0, s, blk, nb, nullptr, N, status);
+    const int work = vel ? std::max(N, nb) : nb;
+    hipLaunchKernelGGL(k_fold_status, dim3(std::max(1, std::min(nblk(work, kBlock), 256))), dim3(kBlock), 0, s,
+                       blk, nb, vel, N, status);
     return hipGetLastError();
 }
 

@@ -356,6 +356,67 @@ int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn,
                  rc_box box, const float* adj /* [N*4] */, double* out /* [nt*nt*3] */,
                  void* stream);
 
+/* ---- batches of independent replicas (hot-path step a8) -----------------------
+ * A batch holds R independent periodic systems of uneven size, box and
+ * coefficient table (e.g. a lambda sweep) and advances all of them with one
+ * launch per kernel: the cell sort, the list build, the fused step and the
+ * bond count each cover every replica at once.
+ *
+ * Slots.  Replica r owns the particle slots [off_r, off_r + n_r) of every
+ * per-particle array; off_0 = 0 and off_{r+1} = off_r + 64*ceil(n_r/64), so
+ * each wavefront lies in one replica.  The slots between replicas are unused
+ * (zeroed by rc_batch_build_cells; nn = 0 there).  n_slots = off_R is the
+ * length N of every per-particle array (pos, vel, image, nlist column, nn,
+ * force); rc_batch_layout reports it and the offsets.  A particle's tag is
+ * its global tag, off_r + (its tag inside the replica); the thermostat noise
+ * uses the tag inside the replica and the replica's seed, so replica r of a
+ * batch follows the same trajectory, bit for bit, as the same system run
+ * alone with rc_md_run and that seed.
+ *
+ * rc_batch_create: tables is host [R][ntypes][ntypes] (one table per
+ *   replica, validated like rc_create's), counts host [R] (n_r >= 1), boxes
+ *   host [R].  Each replica's cell grid follows its own table's largest list
+ *   radius.  Fails with RC_ERR_ARG on an invalid table, count or box and with
+ *   RC_ERR_UNSUPPORTED when R > 65535, n_slots >= 2^27 or the batch needs
+ *   more than 2^24 cell keys.
+ * rc_batch_set_seeds: host [R] thermostat keys (default: cfg.seed + r).
+ * rc_batch_compute_forces: force [n_slots*4] as rc_compute_forces with
+ *   RC_FORCE_GATHER (overwritten; unused slots untouched); ev = device
+ *   [R][7] (E, W) per replica, or NULL.
+ * rc_batch_bond_count: counts = device [R] u64, overwritten.
+ * rc_batch_step_fused: one fused step of every replica (modes as
+ *   rc_step_fused); ev = device [R][13] or NULL; status as rc_step_fused.
+ * rc_batch_run: rc_md_run over the whole batch: buf arrays are n_slots long,
+ *   ev_log is [rows][R][13] and bonds_log [rows][R].  A list build of the
+ *   batch happens when any replica needs one.  Synchronises the stream.
+ * rc_batch_time_fused_steps: as rc_time_fused_steps for the batch.          */
+typedef struct rc_batch rc_batch;
+
+int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tables /* host */,
+                    const int* counts /* host [R] */, const rc_box* boxes /* host [R] */, double r_buff);
+int rc_batch_destroy(rc_batch* b);
+const char* rc_batch_last_error(const rc_batch* b);
+int rc_batch_layout(const rc_batch* b, int* n_slots /* host */, int* offsets /* host [R+1] | NULL */);
+int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds /* host [R] */);
+int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes /* host */);
+int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
+                         void* stream);
+int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
+                         int* nlist, int* nn, int* status, void* stream);
+int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, const int* nn, int k_max, float* force,
+                            double* ev /* [R*7] | NULL */, int* status, void* stream);
+int rc_batch_bond_count(rc_batch* b, const float* pos, const int* nlist, const int* nn, int k_max,
+                        unsigned long long* counts /* [R] */, void* stream);
+int rc_batch_step_fused(rc_batch* b, const float* pos_in, float* pos_out, float* vel, int* image, const int* nlist,
+                        const int* nn, int k_max, const rc_integrator* cfg /* host */, uint64_t step, int mode,
+                        double soft_frac, double* ev /* [R*13] | NULL */, int* status, void* stream);
+int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_integrator* cfg /* host */, uint64_t step0,
+                 int n_steps, const rc_md_options* opt /* host, NULL = defaults */,
+                 rc_md_stats* stats /* host, NULL ok */, void* stream);
+int rc_batch_time_fused_steps(rc_batch* b, float* pos_a, float* pos_b, float* vel, const int* nlist, const int* nn,
+                              int k_max, const rc_integrator* cfg /* host */, uint64_t step0, int reps, int* status,
+                              float* ms /* host */, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -118,6 +118,24 @@ _SIGS = {
     "rc_force_hvp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
     "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
     "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
+    # batches
+    "rc_batch_create": ([ctypes.POINTER(_VP), _I, _I, ctypes.POINTER(PairCoeff), ctypes.POINTER(_I),
+                         ctypes.POINTER(Box), _D], _I),
+    "rc_batch_destroy": ([_VP], _I),
+    "rc_batch_last_error": ([_VP], ctypes.c_char_p),
+    "rc_batch_layout": ([_VP, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
+    "rc_batch_set_seeds": ([_VP, ctypes.POINTER(_U64)], _I),
+    "rc_batch_cells_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "rc_batch_build_cells": ([_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP], _I),
+    "rc_batch_build_nlist": ([_VP, _VP, _VP, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),
+    "rc_batch_compute_forces": ([_VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _VP], _I),
+    "rc_batch_bond_count": ([_VP, _VP, _VP, _VP, _I, _VP, _VP], _I),
+    "rc_batch_step_fused": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(Integrator), _U64, _I, _D,
+                             _VP, _VP, _VP], _I),
+    "rc_batch_run": ([_VP, ctypes.POINTER(MdBuffers), ctypes.POINTER(Integrator), _U64, _I,
+                      ctypes.POINTER(MdOptions), ctypes.POINTER(MdStats), _VP], _I),
+    "rc_batch_time_fused_steps": ([_VP, _VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(Integrator), _U64, _I, _VP,
+                                   ctypes.POINTER(ctypes.c_float), _VP], _I),
 }
 
 _lib = None
@@ -148,10 +166,13 @@ def load():
     return lib
 
 
-def check(code: int, ctx=None):
+def check(code: int, ctx=None, batch=None):
     if code != RC_OK:
         msg = ""
         if ctx is not None:
             raw = load().rc_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        elif batch is not None:
+            raw = load().rc_batch_last_error(batch)
             msg = raw.decode() if raw else ""
         raise RcError(code, msg)

@@ -21,6 +21,9 @@ __all__ = [
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
+    "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
+    "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
+    "rc_batch_time_fused_steps",
 ]
 
 
@@ -76,6 +79,18 @@ def unpack_positions(pos: torch.Tensor):
     return a[:, :3].copy(), (w & ((1 << L.RC_TYPE_BITS) - 1)).astype(np.int32), (w >> L.RC_TYPE_BITS).astype(np.int64)
 
 
+def _fill_table(arr, base, table, nt):
+    for a in range(nt):
+        for b in range(nt):
+            e = arr[base + a * nt + b]
+            e.kind = int(table.kind[a, b])
+            e.n = int(table.n[a, b])
+            e.epsilon = float(table.epsilon[a, b])
+            e.sigma = float(table.sigma[a, b])
+            e.r_cut = float(table.rcut[a, b])
+            e.lam = float(table.lam[a, b])
+
+
 class Context:
     """An rc_ctx: the compiled per-type-pair coefficient table."""
 
@@ -83,15 +98,7 @@ class Context:
         lib = L.load()
         nt = int(np.asarray(table.kind).shape[0])
         arr = (L.PairCoeff * (nt * nt))()
-        for a in range(nt):
-            for b in range(nt):
-                e = arr[a * nt + b]
-                e.kind = int(table.kind[a, b])
-                e.n = int(table.n[a, b])
-                e.epsilon = float(table.epsilon[a, b])
-                e.sigma = float(table.sigma[a, b])
-                e.r_cut = float(table.rcut[a, b])
-                e.lam = float(table.lam[a, b])
+        _fill_table(arr, 0, table, nt)
         h = ctypes.c_void_p()
         code = lib.rc_create(ctypes.byref(h), nt, arr, float(r_buff))
         if code != L.RC_OK:
@@ -227,3 +234,112 @@ def rc_param_grad(ctx: Context, pos, nlist, nn, bx, grad, stream=None):
     check(L.load().rc_param_grad(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
                                  _ptr(grad),
                                  _stream(stream)), ctx.handle)
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+class BatchContext:
+    """An rc_batch: R replicas with their own tables, particle counts and boxes."""
+
+    def __init__(self, tables, counts, boxes, r_buff: float = 0.3):
+        lib = L.load()
+        R = len(tables)
+        if not (len(counts) == R and len(boxes) == R and R > 0):
+            raise ValueError("tables, counts and boxes need one entry per replica")
+        nt = int(np.asarray(tables[0].kind).shape[0])
+        arr = (L.PairCoeff * (R * nt * nt))()
+        for r, t in enumerate(tables):
+            if np.asarray(t.kind).shape[0] != nt:
+                raise ValueError("every replica's table must have the same number of types")
+            _fill_table(arr, r * nt * nt, t, nt)
+        cnt = (ctypes.c_int * R)(*[int(c) for c in counts])
+        bxs = (L.Box * R)()
+        for r, b in enumerate(boxes):
+            bxs[r] = b if isinstance(b, L.Box) else box(b)
+        h = ctypes.c_void_p()
+        code = lib.rc_batch_create(ctypes.byref(h), R, nt, arr, cnt, bxs, float(r_buff))
+        if code != L.RC_OK:
+            raise RcError(code, "rc_batch_create rejected the replicas")
+        self.handle = h
+        self.R = R
+        self.ntypes = nt
+        self.r_buff = float(r_buff)
+        n = ctypes.c_int()
+        offs = (ctypes.c_int * (R + 1))()
+        check(lib.rc_batch_layout(h, ctypes.byref(n), offs), batch=h)
+        self.n_slots = int(n.value)
+        self.offsets = np.array(list(offs), dtype=np.int64)
+        self.counts = np.array([int(c) for c in counts], dtype=np.int64)
+
+    def set_seeds(self, seeds):
+        arr = (ctypes.c_uint64 * self.R)(*[int(x) for x in seeds])
+        check(L.load().rc_batch_set_seeds(self.handle, arr), batch=self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.load().rc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rc_batch_cells_workspace_bytes(bc: BatchContext) -> int:
+    out = ctypes.c_size_t()
+    check(L.load().rc_batch_cells_workspace_bytes(bc.handle, ctypes.byref(out)), batch=bc.handle)
+    return int(out.value)
+
+
+def rc_batch_build_cells(bc: BatchContext, pos, vel, image, rtag, ws, stream=None):
+    check(L.load().rc_batch_build_cells(bc.handle, _ptr(pos), _ptr(vel), _ptr(image), _ptr(rtag), _ptr(ws),
+                                        ws.numel() * ws.element_size(), _stream(stream)), batch=bc.handle)
+
+
+def rc_batch_build_nlist(bc: BatchContext, pos, vel, ws, k_max, nlist, nn, status=None, stream=None):
+    check(L.load().rc_batch_build_nlist(bc.handle, _ptr(pos), _ptr(vel), _ptr(ws), ws.numel() * ws.element_size(),
+                                        int(k_max), _ptr(nlist), _ptr(nn), _ptr(status), _stream(stream)),
+          batch=bc.handle)
+
+
+def rc_batch_compute_forces(bc: BatchContext, pos, nlist, nn, force, ev=None, status=None, stream=None):
+    check(L.load().rc_batch_compute_forces(bc.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, bc.n_slots),
+                                           _ptr(force), _ptr(ev), _ptr(status), _stream(stream)), batch=bc.handle)
+
+
+def rc_batch_bond_count(bc: BatchContext, pos, nlist, nn, counts, stream=None):
+    check(L.load().rc_batch_bond_count(bc.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, bc.n_slots),
+                                       _ptr(counts), _stream(stream)), batch=bc.handle)
+
+
+def rc_batch_step_fused(bc: BatchContext, pos_in, pos_out, vel, image, nlist, nn, cfg, step, mode, soft_frac=0.8,
+                        ev=None, status=None, stream=None):
+    check(L.load().rc_batch_step_fused(bc.handle, _ptr(pos_in), _ptr(pos_out), _ptr(vel), _ptr(image), _ptr(nlist),
+                                       _ptr(nn), _kmax(nlist, bc.n_slots), ctypes.byref(cfg), int(step), int(mode),
+                                       float(soft_frac), _ptr(ev), _ptr(status), _stream(stream)), batch=bc.handle)
+
+
+def rc_batch_run(bc: BatchContext, bufs: L.MdBuffers, cfg, step0, n_steps, opts: Optional[L.MdOptions] = None,
+                 stream=None) -> L.MdStats:
+    st = L.MdStats()
+    code = L.load().rc_batch_run(bc.handle, ctypes.byref(bufs), ctypes.byref(cfg), int(step0), int(n_steps),
+                                 ctypes.byref(opts) if opts is not None else None, ctypes.byref(st), _stream(stream))
+    if code != L.RC_OK:
+        err = RcError(code, L.load().rc_batch_last_error(bc.handle).decode())
+        err.stats = st
+        raise err
+    return st
+
+
+def rc_batch_time_fused_steps(bc: BatchContext, pos_a, pos_b, vel, nlist, nn, cfg, step0, reps, status,
+                              stream=None) -> float:
+    """Milliseconds for `reps` back-to-back batch step launches (HIP events)."""
+    ms = ctypes.c_float()
+    check(L.load().rc_batch_time_fused_steps(bc.handle, _ptr(pos_a), _ptr(pos_b), _ptr(vel), _ptr(nlist), _ptr(nn),
+                                             _kmax(nlist, bc.n_slots), ctypes.byref(cfg), int(step0), int(reps),
+                                             _ptr(status), ctypes.byref(ms), _stream(stream)), batch=bc.handle)
+    return float(ms.value)

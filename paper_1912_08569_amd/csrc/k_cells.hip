@@ -158,6 +158,12 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int* __restrict__ orde
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     const int o = order[q];
+    if (o < 0) {   // an unused slot of a batch: zeroed
+        tpos[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (vel) tvel[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (image) timage[q] = make_int4(0, 0, 0, 0);
+        return;
+    }
     const float4 p = pos[o];
     tpos[q] = p;
     if (vel) tvel[q] = vel[o];
@@ -168,7 +174,82 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int* __restrict__ orde
     }
 }
 
+// ---- batches: the same counting sort over the concatenated key ranges ------
+__global__ __launch_bounds__(kBlock) void k_bin_batch(CellsArgsB a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
+    if (i >= d.off + d.n) return;
+    const float4 p = a.pos[i];
+    const int cx = cell_coord(p.x, d.box.hf[0], d.grid.inv_w[0], d.grid.nc[0]);
+    const int cy = cell_coord(p.y, d.box.hf[1], d.grid.inv_w[1], d.grid.nc[1]);
+    const int cz = cell_coord(p.z, d.box.hf[2], d.grid.inv_w[2], d.grid.nc[2]);
+    const int key = (int)(d.key_base + morton3(cx, cy, cz));
+    a.keys[i] = key;
+    a.rank[i] = atomicAdd(&a.counts[key], 1);
+}
+
+// scatter into the replica's own slots (compact position + its shift)
+__global__ __launch_bounds__(kBlock) void k_scatter_batch(CellsArgsB a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
+    if (i >= d.off + d.n) return;
+    a.order[a.cell_start[a.keys[i]] + a.rank[i] + d.shift] = i;
+}
+
+// per key: the replica owning it (first r with key_end[r] > k), then the
+// same in-cell ordering by previous index as the single-system sort
+__global__ __launch_bounds__(kBlock) void k_sort_cells_batch(CellsArgsB a) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.nkeys) return;
+    const int s0 = a.cell_start[k], e0 = a.cell_start[k + 1];
+    if (e0 - s0 < 2) return;
+    int lo = 0, hi = a.R - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.key_end[mid] > k) hi = mid;
+        else lo = mid + 1;
+    }
+    const int sh = a.rep[lo].shift;
+    int* order = a.order;
+    const int s = s0 + sh, e = e0 + sh;
+    for (int p = s + 1; p < e; ++p) {
+        const int v = order[p];
+        int q = p - 1;
+        while (q >= s && order[q] > v) {
+            order[q + 1] = order[q];
+            --q;
+        }
+        order[q + 1] = v;
+    }
+}
+
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s) {
+    const int nk = (int)a.nkeys;
+    const int nsb = nblk(nk, kScanTile);
+    if (nsb > 8192) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(nblk(nk, kBlock), 2048)), dim3(kBlock), 0, s, a.counts, nk, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(nblk(a.N, kBlock), 2048)), dim3(kBlock), 0, s, a.order, a.N, -1);
+    hipLaunchKernelGGL(k_bin_batch, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kBlock), 0, s, a.counts, nk, a.block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a.block_sums, nsb, a.cell_start, nk);
+    hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kBlock), 0, s, a.counts, nk, a.block_sums, a.cell_start);
+    hipLaunchKernelGGL(k_scatter_batch, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_cells_batch, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_permute, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.order, a.N, a.pos, a.vel, a.image,
+                       a.tpos, a.tvel, a.timage, a.rtag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(a.pos, a.tpos, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && a.vel)
+        e = hipMemcpyAsync(a.vel, a.tvel, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && a.image)
+        e = hipMemcpyAsync(a.image, a.timage, sizeof(int4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
+    return e;
+}
 
 hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
     const int nk = (int)a.g.nkeys;
@@ -200,10 +281,87 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // neighbour list
 // ---------------------------------------------------------------------------
-// One thread per particle i (key order): scan the 27 cells around i's cell and
+// List of one particle i (key order): scan the 27 cells around i's cell and
 // keep every j != i inside r_list(t_i, t_j).  Distances use FP64 differences
 // folded by the box (exact image choice) and an FP32 square; the list radius
-// carries a 1e-5 relative margin for that rounding.
+// carries a 1e-5 relative margin for that rounding.  Cell k's particles sit
+// at cell_start[key_base + k] + shift onwards.  rl(q, rl2, swap) gives entry
+// q's squared list radius and whether it is a swap pair.  Returns the full
+// neighbour count and stores nn[i] (clipped to k_max).
+template <class Radii>
+__device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, const Grid& g, uint32_t key_base,
+                                        int shift, const int* __restrict__ cell_start, const float4* __restrict__ pos,
+                                        int nt, int k_max, int N, int* __restrict__ nlist, int* __restrict__ nn,
+                                        Radii rl) {
+    int ns = 0, no = 0;
+    const int ti = ptype(pi.w);
+    const int cx = cell_coord(pi.x, b.hf[0], g.inv_w[0], g.nc[0]);
+    const int cy = cell_coord(pi.y, b.hf[1], g.inv_w[1], g.nc[1]);
+    const int cz = cell_coord(pi.z, b.hf[2], g.inv_w[2], g.nc[2]);
+    for (int oz = -1; oz <= 1; ++oz) {
+        int z = cz + oz;
+        z += (z < 0) ? g.nc[2] : 0;
+        z -= (z >= g.nc[2]) ? g.nc[2] : 0;
+        for (int oy = -1; oy <= 1; ++oy) {
+            int y = cy + oy;
+            y += (y < 0) ? g.nc[1] : 0;
+            y -= (y >= g.nc[1]) ? g.nc[1] : 0;
+            for (int ox = -1; ox <= 1; ++ox) {
+                int x = cx + ox;
+                x += (x < 0) ? g.nc[0] : 0;
+                x -= (x >= g.nc[0]) ? g.nc[0] : 0;
+                const uint32_t key = key_base + morton3(x, y, z);
+                const int s = cell_start[key] + shift, e = cell_start[key + 1] + shift;
+                for (int j = s; j < e; ++j) {
+                    if (j == i) continue;
+                    const float4 pj = pos[j];
+                    float dx = (float)fold((double)pj.x - (double)pi.x, b.L[0], b.h[0]);
+                    float dy = (float)fold((double)pj.y - (double)pi.y, b.L[1], b.h[1]);
+                    float dz = (float)fold((double)pj.z - (double)pi.z, b.L[2], b.h[2]);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    float rl2;
+                    bool swap;
+                    rl(ti * nt + ptype(pj.w), rl2, swap);
+                    if (r2 < rl2) {
+                        if (swap) {
+                            if (ns + no < k_max) nlist[(size_t)ns * N + i] = j;
+                            ++ns;
+                        } else {
+                            if (ns + no < k_max) nlist[(size_t)(k_max - 1 - no) * N + i] = j;
+                            ++no;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    const int total = ns + no;
+    // on overflow the stored prefix is what fitted (the status reports it)
+    if (ns + no > k_max) {
+        const int keep_s = min(ns, k_max);
+        ns = keep_s;
+        no = k_max - keep_s;
+    }
+    nn[i] = ns | (no << 16);
+    return total;
+}
+
+// block maximum of the list length (no same-address atomics per wave)
+__device__ __forceinline__ void block_max_store(int cnt, int* __restrict__ out) {
+    __shared__ int s_m[kBlock / kWave];
+    int m = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t = max(t, s_m[w]);
+        *out = t;
+    }
+}
+
+// One thread per particle (key order).
 __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
     extern __shared__ float s_rl2[];  // [nt*nt] list radii^2, then [nt*nt] swap flags
     const int nt = a.tab.nt;
@@ -215,73 +373,38 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
     __syncthreads();
     const int nb = gridDim.x;
     const int i = xcd_block(nb) * blockDim.x + threadIdx.x;
-    const bool live = i < a.N;
-    int ns = 0, no = 0, total = 0;
-    if (live) {
-        const float4 pi = a.pos[i];
-        const int ti = ptype(pi.w);
-        const Grid& g = a.g;
-        const int cx = cell_coord(pi.x, a.box.hf[0], g.inv_w[0], g.nc[0]);
-        const int cy = cell_coord(pi.y, a.box.hf[1], g.inv_w[1], g.nc[1]);
-        const int cz = cell_coord(pi.z, a.box.hf[2], g.inv_w[2], g.nc[2]);
-        for (int oz = -1; oz <= 1; ++oz) {
-            int z = cz + oz;
-            z += (z < 0) ? g.nc[2] : 0;
-            z -= (z >= g.nc[2]) ? g.nc[2] : 0;
-            for (int oy = -1; oy <= 1; ++oy) {
-                int y = cy + oy;
-                y += (y < 0) ? g.nc[1] : 0;
-                y -= (y >= g.nc[1]) ? g.nc[1] : 0;
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int x = cx + ox;
-                    x += (x < 0) ? g.nc[0] : 0;
-                    x -= (x >= g.nc[0]) ? g.nc[0] : 0;
-                    const uint32_t key = morton3(x, y, z);
-                    const int s = a.cell_start[key], e = a.cell_start[key + 1];
-                    for (int j = s; j < e; ++j) {
-                        if (j == i) continue;
-                        const float4 pj = a.pos[j];
-                        float dx = (float)fold((double)pj.x - (double)pi.x, a.box.L[0], a.box.h[0]);
-                        float dy = (float)fold((double)pj.y - (double)pi.y, a.box.L[1], a.box.h[1]);
-                        float dz = (float)fold((double)pj.z - (double)pi.z, a.box.L[2], a.box.h[2]);
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        const int q = ti * nt + ptype(pj.w);
-                        if (r2 < s_rl2[q]) {
-                            if (s_swap[q]) {
-                                if (ns + no < a.k_max) a.nlist[(size_t)ns * a.N + i] = j;
-                                ++ns;
-                            } else {
-                                if (ns + no < a.k_max) a.nlist[(size_t)(a.k_max - 1 - no) * a.N + i] = j;
-                                ++no;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        total = ns + no;
-        // on overflow the stored prefix is what fitted (the status reports it)
-        if (ns + no > a.k_max) {
-            const int keep_s = min(ns, a.k_max);
-            ns = keep_s;
-            no = a.k_max - keep_s;
-        }
-        a.nn[i] = ns | (no << 16);
+    int total = 0;
+    if (i < a.N) {
+        total = list_one(i, a.pos[i], a.box, a.g, 0u, 0, a.cell_start, a.pos, nt, a.k_max, a.N, a.nlist, a.nn,
+                         [&](int q, float& rl2, bool& swap) {
+                             rl2 = s_rl2[q];
+                             swap = s_swap[q] != 0;
+                         });
         if (a.vel) a.vel[i].w = 0.0f;
     }
-    const int cnt = total;
-    // block maximum of the list length (no same-address atomics per wave)
-    __shared__ int s_m[kBlock / kWave];
-    int m = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) s_m[threadIdx.x / kWave] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) t = max(t, s_m[w]);
-        a.block_max[blockIdx.x] = t;
+    block_max_store(total, a.block_max + blockIdx.x);
+}
+
+// Batches: each wave lies in one replica, which gives the box, grid, key
+// range and table; empty slots get an empty list.
+__global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int total = 0;
+    if (i < a.N) {
+        const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
+        const DevEntry* t = a.tab.e + d.tab;
+        if (i < d.off + d.n) {
+            total = list_one(i, a.pos[i], d.box, d.grid, d.key_base, d.shift, a.cell_start, a.pos, a.tab.nt, a.k_max,
+                             a.N, a.nlist, a.nn, [&](int q, float& rl2, bool& swap) {
+                                 rl2 = t[q].rlist2;
+                                 swap = t[q].kind == RC_KIND_SWAP;
+                             });
+        } else {
+            a.nn[i] = 0;
+        }
+        if (a.vel) a.vel[i].w = 0.0f;
     }
+    block_max_store(total, a.block_max + blockIdx.x);
 }
 
 // one block: fold the per-block maxima into the status word
@@ -306,6 +429,13 @@ hipError_t launch_nlist(const NlistArgs& a, hipStream_t s) {
     const size_t shm = 2 * sizeof(float) * a.tab.nt * a.tab.nt;
     const int nb = nblk(a.N, kBlock);
     hipLaunchKernelGGL(k_nlist, dim3(nb), dim3(kBlock), shm, s, a);
+    if (a.status) hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s) {
+    const int nb = nblk(a.N, kBlock);
+    hipLaunchKernelGGL(k_nlist_batch, dim3(nb), dim3(kBlock), 0, s, a);
     if (a.status) hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status);
     return hipGetLastError();
 }

@@ -8,310 +8,37 @@
 //   force on partner a from (c; a, b):  -w'_ca/r_ca w_cb d_ca
 //   force on the centre:                minus the sum of the two
 #include "rc_internal.h"
+#include "rc_gather.h"
 
 namespace rc {
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
-__device__ __forceinline__ void load_table(DevEntry* s_tab, const Table& t) {
-    const int n = t.nt * t.nt;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) s_tab[q] = t.e[q];
-    __syncthreads();
-}
-
-// Walk of particle m's list: the swap range (slots 0 .. ns-1) and, unless
-// SWAP_ONLY, the other range (slots k_max-1 down to k_max-no).  For every
-// neighbour j != skip inside its cutoff (canonical FP64 decision) the functor
-// gets (j, pj, entry, r2 in FP64, r2 in FP32, d = x_j - x_m in FP32).
-template <bool SWAP_ONLY, typename F>
-__device__ __forceinline__ void walk_list(int m, const float4& pm, int tm, const int* nlist, int packed,
-                                          int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
-                                          const Box& box, int skip, F&& f) {
-    auto visit = [&](int j) {
-        if (j == skip) return;
-        const float4 pj = pos[j];
-        const DevEntry& e = tab[tm * nt + ptype(pj.w)];
-        if (e.kind == RC_KIND_NONE) return;
-        double dx, dy, dz;
-        const double r2d = canon_r2(pm, pj, box, dx, dy, dz);
-        if (!(r2d < e.rcut2)) return;
-        f(j, pj, e, r2d, (float)r2d, (float)dx, (float)dy, (float)dz);
-    };
-    const int ns = nn_swap(packed);
-    for (int s = 0; s < ns; ++s) visit(nlist[(size_t)s * N + m]);
-    if (!SWAP_ONLY) {
-        const int no = nn_other(packed);
-        for (int s = 0; s < no; ++s) visit(nlist[(size_t)(k_max - 1 - s) * N + m]);
-    }
-}
-
-// sum of w_ck over the swap partners k of centre c inside r_cut, except 'skip'
-// (only c's swap range is read: for a bonded pair it usually holds skip alone)
-__device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, int skip,
-                                                       const int* nlist, const int* nn, int k_max, int N,
-                                                       const float4* pos, const DevEntry* tab,
-                                                       int nt, const Box& box) {
-    float s = 0.0f;
-    walk_list<true>(c, pc, ptype(pc.w), nlist, nn[c], k_max, N, pos, tab, nt, box, skip,
-                    [&](int, const float4&, const DevEntry& e, double r2d, float r2, float, float, float) {
-                        s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, r2);
-                    });
-    return s;
-}
-
-struct Acc {
-    float fx, fy, fz, e;
-    float w[6];  // xx yy zz xy xz yz
-};
-
-__device__ __forceinline__ void acc_virial(Acc& a, float c, float dx, float dy, float dz) {
-    // adds c * d (x) d  (a term (r)_a (F)_b with F = c d)
-    a.w[0] += c * dx * dx;
-    a.w[1] += c * dy * dy;
-    a.w[2] += c * dz * dz;
-    a.w[3] += c * dx * dy;
-    a.w[4] += c * dx * dz;
-    a.w[5] += c * dy * dz;
-}
-
-// Every force term acting on particle m, gathered (no atomics):
-//  * pair terms with every list neighbour,
-//  * the triplets in which m is a partner of a centre c (two-hop walk over
-//    c's swap range for the other partners of c; skipped when vhat'(r_cm) = 0),
-//  * the triplets m centres (second walk of m's swap range, only with >= 2
-//    active partners).
-// Energy: half of each pair term, every triplet term of m's own centre.
-// Virial: half of each pair term; the full triplet term at its centre.
-template <bool EV>
-__device__ __forceinline__ void gather_particle(int m, const float4& pm, int packed, const float4* pos,
-                                                const int* nlist, const int* nn, int k_max, int N,
-                                                const DevEntry* tab, int nt, const Box& box, Acc& acc) {
-    const int tm = ptype(pm.w);
-    int nact = 0;
-    double S = 0.0;
-    walk_list<false>(m, pm, tm, nlist, packed, k_max, N, pos, tab, nt, box, -1,
-                     [&](int j, const float4& pj, const DevEntry& e, double r2d, float r2, float dx, float dy,
-                         float dz) {
-                         float phi, g;
-                         pair_eval(e, r2, phi, g);
-                         acc.fx += g * dx;
-                         acc.fy += g * dy;
-                         acc.fz += g * dz;
-                         if (EV) {
-                             acc.e += 0.5f * phi;
-                             acc_virial(acc, -0.5f * g, dx, dy, dz);
-                         }
-                         if (e.kind == RC_KIND_SWAP) {
-                             float u, u1r;
-                             vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
-                             ++nact;
-                             S += (double)(e.sqrt_lam * u);
-                             if (u1r != 0.0f && e.sqrt_lam != 0.0f) {
-                                 // m is a partner of centre j: the other partners of j
-                                 const float c = e.sqrt_lam * u1r *
-                                                 partner_sum_excluding(j, pj, m, nlist, nn, k_max, N, pos, tab, nt, box);
-                                 acc.fx += c * dx;
-                                 acc.fy += c * dy;
-                                 acc.fz += c * dz;
-                             }
-                         }
-                     });
-    if (nact >= 2) {
-        float prefix = 0.0f;
-        walk_list<true>(m, pm, tm, nlist, packed, k_max, N, pos, tab, nt, box, -1,
-                        [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
-                            float dz) {
-                            float u, u1r;
-                            vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
-                            const float w = e.sqrt_lam * u;
-                            const float excl = (float)(S - (double)w);
-                            const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
-                            acc.fx += c * dx;
-                            acc.fy += c * dy;
-                            acc.fz += c * dz;
-                            if (EV) {
-                                acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
-                                prefix += w;
-                                acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
-                            }
-                        });
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Wavefront-cooperative gather (one wavefront per block).  The 64 lanes own
-// 64 consecutive particles; their (particle, list slot) entries are laid out
-// flat (exclusive scan of the list lengths) and every lane evaluates one entry
-// per pass, so a wave needs about (sum of list lengths)/64 passes instead of
-// one pass per slot of its longest list.  Per-entry contributions are staged
-// in LDS and each owner lane sums its own entries in slot order
-// (deterministic).  Triplets the owner centres are added afterwards by a walk
-// of its swap range, only when it has two or more active swap partners.
-// ---------------------------------------------------------------------------
-template <bool EV>
-struct Stage {
-    static constexpr int n = EV ? 12 : 5;  // fx fy fz w active [e w0..w5]
-};
-constexpr int kPerLane = 2;  // flattened entries each lane evaluates per pass
-
-template <bool EV>
-__device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
-                                            const float4* pos, const int* nlist, const int* nn, int k_max,
-                                            int N, const DevEntry* tab, int nt, const Box& box, Acc& acc) {
-    constexpr int NC = Stage<EV>::n;
-    constexpr int W = kPerLane * kWave;  // entries per pass
-    __shared__ int s_off[kWave + 1];
-    __shared__ int s_ns[kWave];
-    __shared__ float4 s_pos[kWave];
-    __shared__ float s_c[NC][W];
-    const int lane = threadIdx.x;
-    const int ns = live ? nn_swap(packed) : 0;
-    const int cnt = live ? ns + nn_other(packed) : 0;
-    int inc = cnt;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += t;
-    }
-    const int my_off = inc - cnt;
-    s_off[lane] = my_off;
-    if (lane == kWave - 1) s_off[kWave] = inc;
-    s_ns[lane] = ns;
-    s_pos[lane] = pm;
-    __syncthreads();
-    const int T = s_off[kWave];
-    double S = 0.0;
-    int nact = 0;
-    for (int base = 0; base < T; base += W) {
-        // locate and load all entries of this pass first, so their memory
-        // latencies overlap (list index, then neighbour position)
-        int own[kPerLane], jj[kPerLane];
-        float4 pj[kPerLane];
-#pragma unroll
-        for (int u = 0; u < kPerLane; ++u) {
-            const int e = base + u * kWave + lane;
-            own[u] = -1;
-            jj[u] = 0;
-            if (e < T) {
-                int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[mid] <= e) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int sl = e - s_off[lo], nso = s_ns[lo];
-                const int slot = sl < nso ? sl : k_max - 1 - (sl - nso);
-                own[u] = lo;
-                jj[u] = nlist[(size_t)slot * N + base_m + lo];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kPerLane; ++u) pj[u] = own[u] >= 0 ? pos[jj[u]] : pm;
-#pragma unroll
-        for (int u = 0; u < kPerLane; ++u) {
-            float c[NC];
-#pragma unroll
-            for (int q = 0; q < NC; ++q) c[q] = 0.0f;
-            if (own[u] >= 0) {
-                const int mo = base_m + own[u];
-                const float4 po = s_pos[own[u]];
-                const DevEntry& en = tab[ptype(po.w) * nt + ptype(pj[u].w)];
-                if (en.kind != RC_KIND_NONE) {
-                    double dxd, dyd, dzd;
-                    const double r2d = canon_r2(po, pj[u], box, dxd, dyd, dzd);
-                    if (r2d < en.rcut2) {
-                        const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
-                        float phi, g;
-                        pair_eval(en, r2, phi, g);
-                        float f = g;
-                        if (EV) {
-                            c[5] = 0.5f * phi;
-                            const float h = -0.5f * g;
-                            c[6] = h * dx * dx; c[7] = h * dy * dy; c[8] = h * dz * dz;
-                            c[9] = h * dx * dy; c[10] = h * dx * dz; c[11] = h * dy * dz;
-                        }
-                        if (en.kind == RC_KIND_SWAP) {
-                            float uu, u1r;
-                            vhat_eval(en, r2d <= en.rmin2, r2, uu, u1r);
-                            c[3] = en.sqrt_lam * uu;
-                            c[4] = 1.0f;
-                            if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
-                                f += en.sqrt_lam * u1r *
-                                     partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt, box);
-                        }
-                        c[0] = f * dx;
-                        c[1] = f * dy;
-                        c[2] = f * dz;
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NC; ++q) s_c[q][u * kWave + lane] = c[q];
-        }
-        __syncthreads();
-        const int lo = max(my_off, base) - base, hi = min(my_off + cnt, base + W) - base;
-        for (int q = lo; q < hi; ++q) {
-            acc.fx += s_c[0][q];
-            acc.fy += s_c[1][q];
-            acc.fz += s_c[2][q];
-            S += (double)s_c[3][q];
-            nact += s_c[4][q] != 0.0f;
-            if (EV) {
-                acc.e += s_c[5][q];
-#pragma unroll
-                for (int w = 0; w < 6; ++w) acc.w[w] += s_c[6 + w][q];
-            }
-        }
-        __syncthreads();
-    }
-    if (live && nact >= 2) {
-        const int m = base_m + lane;
-        float prefix = 0.0f;
-        walk_list<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, tab, nt, box, -1,
-                        [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
-                            float dz) {
-                            float u, u1r;
-                            vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
-                            const float w = e.sqrt_lam * u;
-                            const float excl = (float)(S - (double)w);
-                            const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
-                            acc.fx += c * dx;
-                            acc.fy += c * dy;
-                            acc.fz += c * dz;
-                            if (EV) {
-                                acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
-                                prefix += w;
-                                acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
-                            }
-                        });
-    }
-}
-
-// wave-wide sums of NW doubles; lane 0 stores them
-template <int NW>
-__device__ __forceinline__ void wave_sum_store(double (&v)[NW], double* out) {
-#pragma unroll
-    for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NW; ++q) out[q] = v[q];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // atomic-free gather force kernel (RC_FORCE_GATHER)
 // ---------------------------------------------------------------------------
-template <bool EV>
+template <bool EV, bool BATCH>
 __global__ __launch_bounds__(kWave) void k_forces_gather(ForceArgs a) {
     extern __shared__ DevEntry s_tab[];
-    load_table(s_tab, a.tab);
-    const int m = xcd_block(gridDim.x) * kWave + threadIdx.x;
-    const bool live = m < a.N;
+    const int blk = xcd_block(gridDim.x);
+    Box box_r;
+    int lim = a.N;
+    if constexpr (BATCH) {
+        const RepDesc& d = a.rep[a.chunk_rep[blk]];
+        box_r = d.box;
+        lim = d.off + d.n;
+        load_table(s_tab, Table{a.tab.e + d.tab, a.tab.nt});
+    } else {
+        box_r = a.box;
+        load_table(s_tab, a.tab);
+    }
+    const int m = blk * kWave + threadIdx.x;
+    const bool live = m < lim;
     const float4 pm = live ? a.pos[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int packed = live ? a.nn[m] : 0;
     Acc acc = {};
-    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N, s_tab, a.tab.nt,
-                    a.box, acc);
+    const OneSystem sys{s_tab, a.tab.nt, box_r};
+    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N, sys, acc);
     if (live) {
         float4 f = make_float4(acc.fx, acc.fy, acc.fz, acc.e);
         if (a.accumulate) {
@@ -327,7 +54,7 @@ __global__ __launch_bounds__(kWave) void k_forces_gather(ForceArgs a) {
     }
     if (EV) {
         double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
-        wave_sum_store<7>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
+        wave_sum_store<7>(v, a.ev_part + (size_t)blk * kEvWords);
     }
 }
 
@@ -503,9 +230,18 @@ hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s) {
 hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
     if (a.ev_part)
-        hipLaunchKernelGGL(k_forces_gather<true>, dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+        hipLaunchKernelGGL((k_forces_gather<true, false>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
     else
-        hipLaunchKernelGGL(k_forces_gather<false>, dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+        hipLaunchKernelGGL((k_forces_gather<false, false>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    if (a.ev_part)
+        hipLaunchKernelGGL((k_forces_gather<true, true>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+    else
+        hipLaunchKernelGGL((k_forces_gather<false, true>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
     return hipGetLastError();
 }
 
@@ -513,13 +249,33 @@ hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) {
 // fused MD step: gather forces at x_in, finish the previous step's final half
 // kick, then B A O A into pos_out.  One kernel per step, no atomics on data.
 // ---------------------------------------------------------------------------
-template <bool EV>
+// With BATCH the wave's 64-slot chunk names its replica, which supplies the
+// box, the coefficient table, the slot bound and the noise key; the noise
+// counter uses the tag relative to the replica's first slot, so a replica
+// draws the same numbers as the same system run on its own.
+template <bool EV, bool BATCH>
 __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
-    load_table(s_tab, a.tab);
     const int nt = a.tab.nt;
-    const int m = xcd_block(gridDim.x) * kWave + threadIdx.x;
-    const bool live = m < a.N;
+    const int blk = xcd_block(gridDim.x);
+    const int m = blk * kWave + threadIdx.x;
+    Box box_r;
+    int lim = a.N, tag0 = 0;
+    uint64_t seed = a.seed;
+    if constexpr (BATCH) {
+        const int r = a.chunk_rep[blk];
+        const RepDesc& d = a.rep[r];
+        box_r = d.box;
+        lim = d.off + d.n;
+        tag0 = d.off;
+        seed = a.seeds[r];
+        load_table(s_tab, Table{a.tab.e + d.tab, nt});
+    } else {
+        box_r = a.box;
+        load_table(s_tab, a.tab);
+    }
+    const Box& box = box_r;
+    const bool live = m < lim;
     const uint64_t step = a.step + (a.step_base ? *a.step_base : 0ull);
     Acc acc = {};
     float kin[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -528,8 +284,8 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     const float4 pm = live ? a.pos_in[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int packed = live ? a.nn[m] : 0;
-    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, s_tab, nt,
-                    a.box, acc);
+    const OneSystem sys{s_tab, nt, box};
+    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, sys, acc);
     if (live) {
         path_in = vm.w;
         const int tm = ptype(pm.w);
@@ -556,7 +312,7 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
             float sx = hdt * vx, sy = hdt * vy, sz = hdt * vz;  // A (first half of the drift)
             if (a.langevin) {                                  // O
                 float z0, z1, z2;
-                thermostat_normals(a.seed, (uint32_t)ptag(pm.w), step, z0, z1, z2);
+                thermostat_normals(seed, (uint32_t)(ptag(pm.w) - tag0), step, z0, z1, z2);
                 const float c2 = a.c2[tm];
                 vx = a.c1 * vx + c2 * z0;
                 vy = a.c1 * vy + c2 * z1;
@@ -567,11 +323,11 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
             sz += hdt * vz;
             float x = pm.x + sx, y = pm.y + sy, z = pm.z + sz;
             int ix = 0, iy = 0, iz = 0;
-            if (x >= a.box.hf[0]) { x -= a.box.Lf[0]; ix = 1; } else if (x < -a.box.hf[0]) { x += a.box.Lf[0]; ix = -1; }
-            if (y >= a.box.hf[1]) { y -= a.box.Lf[1]; iy = 1; } else if (y < -a.box.hf[1]) { y += a.box.Lf[1]; iy = -1; }
-            if (z >= a.box.hf[2]) { z -= a.box.Lf[2]; iz = 1; } else if (z < -a.box.hf[2]) { z += a.box.Lf[2]; iz = -1; }
+            if (x >= box.hf[0]) { x -= box.Lf[0]; ix = 1; } else if (x < -box.hf[0]) { x += box.Lf[0]; ix = -1; }
+            if (y >= box.hf[1]) { y -= box.Lf[1]; iy = 1; } else if (y < -box.hf[1]) { y += box.Lf[1]; iy = -1; }
+            if (z >= box.hf[2]) { z -= box.Lf[2]; iz = 1; } else if (z < -box.hf[2]) { z += box.Lf[2]; iz = -1; }
             path = vm.w + sqrtf(sx * sx + sy * sy + sz * sz);
-            lost = fabsf(sx) > a.box.hf[0] || fabsf(sy) > a.box.hf[1] || fabsf(sz) > a.box.hf[2];
+            lost = fabsf(sx) > box.hf[0] || fabsf(sy) > box.hf[1] || fabsf(sz) > box.hf[2];
             bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
                     isfinite(vz));
             a.pos_out[m] = make_float4(x, y, z, pm.w);
@@ -606,22 +362,34 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     if (EV) {
         double v[13] = {acc.e,  acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5],
                         kin[0], kin[1],   kin[2],   kin[3],   kin[4],   kin[5]};
-        wave_sum_store<13>(v, a.ev_part + (size_t)blockIdx.x * kEvWords);
+        wave_sum_store<13>(v, a.ev_part + (size_t)blk * kEvWords);
     }
 }
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
     if (ev)
-        hipLaunchKernelGGL(k_step<true>, dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
+        hipLaunchKernelGGL((k_step<true, false>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
     else
-        hipLaunchKernelGGL(k_step<false>, dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
+        hipLaunchKernelGGL((k_step<false, false>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
     return hipGetLastError();
 }
 
 void step_kernel_info(bool ev, const void** fn) {
-    *fn = ev ? reinterpret_cast<const void*>(&k_step<true>) : reinterpret_cast<const void*>(&k_step<false>);
+    *fn = ev ? reinterpret_cast<const void*>(&k_step<true, false>)
+             : reinterpret_cast<const void*>(&k_step<false, false>);
 }
+
+hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    if (ev)
+        hipLaunchKernelGGL((k_step<true, true>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
+    else
+        hipLaunchKernelGGL((k_step<false, true>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
+    return hipGetLastError();
+}
+
+void step_batch_kernel_info(const void** fn) { *fn = reinterpret_cast<const void*>(&k_step<false, true>); }
 
 // ---------------------------------------------------------------------------
 // bond count: swap pairs i<j with canonical r^2 < r_min^2
@@ -674,6 +442,57 @@ hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int 
     const int nb = nblk(N, kBlock);
     hipLaunchKernelGGL(k_bonds, dim3(nb), dim3(kBlock), shm, s, pos, nlist, nn, k_max, N, tab, box, part);
     hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(1024), 0, s, part, nb, count);
+    return hipGetLastError();
+}
+
+// Bond counts of a batch: one 64-slot chunk per block (a chunk lies in one
+// replica), a count per chunk, then one exact integer sum per replica.
+__global__ __launch_bounds__(kWave) void k_bonds_batch(const float4* __restrict__ pos,
+                                                      const int* __restrict__ nlist, const int* __restrict__ nn,
+                                                      int k_max, int N, Table tab, const RepDesc* __restrict__ rep,
+                                                      const int* __restrict__ chunk_rep,
+                                                      unsigned long long* __restrict__ part) {
+    extern __shared__ DevEntry s_tab[];
+    const RepDesc& d = rep[chunk_rep[blockIdx.x]];
+    load_table(s_tab, Table{tab.e + d.tab, tab.nt});
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    unsigned c = 0;
+    if (i < d.off + d.n) {
+        const float4 pi = pos[i];
+        walk_list<true>(i, pi, ptype(pi.w), nlist, nn[i], k_max, N, pos, s_tab, tab.nt, d.box, -1,
+                        [&](int j, const float4&, const DevEntry& e, double r2d, float, float, float, float) {
+                            if (j > i && r2d < e.rmin2) ++c;
+                        });
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if (threadIdx.x == 0) part[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_u64_batch(const unsigned long long* __restrict__ part,
+                                                         const RepDesc* __restrict__ rep,
+                                                         unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[kBlock];
+    const RepDesc& d = rep[blockIdx.x];
+    const int c0 = d.off / kWave, nc = (d.n + kWave - 1) / kWave;
+    unsigned long long s = 0;
+    for (int b = threadIdx.x; b < nc; b += blockDim.x) s += part[c0 + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t launch_bonds_batch(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                              const RepDesc* rep, const int* chunk_rep, int R, unsigned long long* count,
+                              unsigned long long* part, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * tab.nt * tab.nt;
+    hipLaunchKernelGGL(k_bonds_batch, dim3(nblk(N, kWave)), dim3(kWave), shm, s, pos, nlist, nn, k_max, N, tab,
+                       rep, chunk_rep, part);
+    hipLaunchKernelGGL(k_sum_u64_batch, dim3(R), dim3(kBlock), 0, s, part, rep, count);
     return hipGetLastError();
 }
 
@@ -774,6 +593,33 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* __restrict
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_rows, dim3(count), dim3(kBlock), 0, s, part, nblocks, first, count, out);
+    return hipGetLastError();
+}
+
+// The same fixed-order sum per replica over its own chunk rows (grid: words x
+// replicas), so a replica's sums equal those of the system run on its own.
+__global__ __launch_bounds__(kBlock) void k_reduce_rows_batch(const double* __restrict__ part,
+                                                             const RepDesc* __restrict__ rep, int first,
+                                                             double* __restrict__ out, int out_stride) {
+    __shared__ double red[kBlock];
+    const RepDesc& d = rep[blockIdx.y];
+    const double* p = part + (size_t)(d.off / kWave) * kEvWords;
+    const int nblocks = (d.n + kWave - 1) / kWave;
+    const int q = first + blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += p[(size_t)b * kEvWords + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)blockIdx.y * out_stride + blockIdx.x] = red[0];
+}
+
+hipError_t launch_reduce_rows_batch(const double* part, const RepDesc* rep, int R, int first, int count,
+                                    double* out, int out_stride, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_rows_batch, dim3(count, R), dim3(kBlock), 0, s, part, rep, first, out, out_stride);
     return hipGetLastError();
 }
 

@@ -1,0 +1,445 @@
+// C ABI of the batch mode: many independent replicas (uneven size, box and
+// table) behind one set of launches per step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rc_host.h"
+
+using namespace rc;
+using namespace rc::host;
+
+struct rc_batch {
+    rc_ctx c;                     // error text, tables, partial rows, status slots, graphs
+    int R = 0;
+    int n_slots = 0;
+    uint32_t nkeys = 0;
+    std::vector<int> counts;
+    std::vector<int> offsets;     // [R + 1]
+    std::vector<RepDesc> desc;
+    std::vector<uint64_t> seeds;  // host copy of d_seeds
+    bool seeds_set = false;
+    RepDesc* d_rep = nullptr;
+    int* d_chunk_rep = nullptr;
+    uint32_t* d_key_end = nullptr;
+    uint64_t* d_seeds = nullptr;
+};
+
+namespace {
+
+void free_batch(rc_batch* b) {
+    rc_ctx* c = &b->c;
+    drop_graphs(c);
+    if (c->d_tab) (void)hipFree(c->d_tab);
+    if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_step_base) (void)hipFree(c->d_step_base);
+    if (c->d_blk) (void)hipFree(c->d_blk);
+    if (b->d_rep) (void)hipFree(b->d_rep);
+    if (b->d_chunk_rep) (void)hipFree(b->d_chunk_rep);
+    if (b->d_key_end) (void)hipFree(b->d_key_end);
+    if (b->d_seeds) (void)hipFree(b->d_seeds);
+    delete b;
+}
+
+int check_pos(rc_batch* b, const void* pos) {
+    if (!pos) return fail(&b->c, RC_ERR_ARG, "positions are NULL");
+    if (reinterpret_cast<uintptr_t>(pos) & 15) return fail(&b->c, RC_ERR_ARG, "positions not 16-byte aligned");
+    return RC_OK;
+}
+
+Table all_tables(const rc_batch* b) { return Table{b->c.d_tab, b->c.nt}; }
+
+// seeds of the next launches: the ones set, else cfg.seed + r
+int ensure_seeds(rc_batch* b, const rc_integrator* cfg, hipStream_t s) {
+    if (b->seeds_set) return RC_OK;
+    std::vector<uint64_t> want(b->R);
+    for (int r = 0; r < b->R; ++r) want[r] = cfg->seed + (uint64_t)r;
+    if (want == b->seeds) return RC_OK;
+    HIP_TRY(&b->c, hipStreamSynchronize(s));
+    HIP_TRY(&b->c, hipMemcpy(b->d_seeds, want.data(), sizeof(uint64_t) * b->R, hipMemcpyHostToDevice));
+    b->seeds = want;
+    return RC_OK;
+}
+
+int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* pos_out, float* vel, int* image,
+                         const int* nlist, const int* nn, int k_max, const rc_integrator* cfg, double soft_frac,
+                         int* status, hipStream_t s) {
+    rc_ctx* c = &b->c;
+    float c1;
+    int lang;
+    int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang);
+    if (r) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    if ((r = ensure_seeds(b, cfg, s))) return r;
+    a.pos_in = reinterpret_cast<const float4*>(pos_in);
+    a.pos_out = reinterpret_cast<float4*>(pos_out);
+    a.vel = reinterpret_cast<float4*>(vel);
+    a.image = reinterpret_cast<int4*>(image);
+    a.nlist = nlist;
+    a.nn = nn;
+    a.k_max = k_max;
+    a.N = b->n_slots;
+    a.tab = all_tables(b);
+    a.dt = (float)cfg->dt;
+    a.c1 = c1;
+    a.langevin = lang;
+    a.hard = (float)(0.5 * c->r_buff);
+    a.soft = (float)(0.5 * c->r_buff * soft_frac);
+    a.seed = 0;
+    a.status = status;
+    a.rep = b->d_rep;
+    a.chunk_rep = b->d_chunk_rep;
+    a.seeds = b->d_seeds;
+    if ((r = ensure_blk(c, nblocks(b->n_slots, kStepBlock), nullptr))) return r;
+    a.blk = c->d_blk;
+    return RC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tables, const int* counts,
+                    const rc_box* boxes, double r_buff) {
+    if (!out) return RC_ERR_ARG;
+    *out = nullptr;
+    if (R < 1 || ntypes < 1 || !tables || !counts || !boxes) return RC_ERR_ARG;
+    if (ntypes > RC_MAX_TYPES || R > 65535) return RC_ERR_UNSUPPORTED;
+    if (!(r_buff > 0.0) || !std::isfinite(r_buff)) return RC_ERR_ARG;
+    rc_batch* b = new (std::nothrow) rc_batch();
+    if (!b) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    const int nt2 = ntypes * ntypes;
+    c->nt = ntypes;
+    c->r_buff = r_buff;
+    c->host_tab.resize((size_t)R * nt2);
+    b->R = R;
+    b->counts.assign(counts, counts + R);
+    b->offsets.resize(R + 1);
+    b->desc.resize(R);
+    int64_t slots = 0, compact = 0;
+    uint64_t keys = 0;
+    double rmax_all = 0.0;
+    for (int r = 0; r < R; ++r) {
+        double rl = 0.0;
+        if (compile_table(ntypes, tables + (size_t)r * nt2, r_buff, c->host_tab.data() + (size_t)r * nt2, &rl,
+                          nullptr) != RC_OK || counts[r] < 1) {
+            free_batch(b);
+            return RC_ERR_ARG;
+        }
+        rmax_all = std::max(rmax_all, rl);
+        RepDesc& d = b->desc[r];
+        if (make_box(c, boxes[r], d.box) || make_grid(c, rl, d.box, d.grid)) {
+            free_batch(b);
+            return RC_ERR_ARG;
+        }
+        d.key_base = (uint32_t)keys;
+        d.off = (int)slots;
+        d.n = counts[r];
+        d.shift = (int)(slots - compact);
+        d.tab = r * nt2;
+        b->offsets[r] = (int)slots;
+        keys += d.grid.nkeys;
+        compact += counts[r];
+        slots += (int64_t)kWave * ((counts[r] + kWave - 1) / kWave);
+        if (slots >= RC_MAX_TAG || keys > (uint64_t)8192 * kScanTile) {
+            free_batch(b);
+            return RC_ERR_UNSUPPORTED;
+        }
+    }
+    b->offsets[R] = (int)slots;
+    b->n_slots = (int)slots;
+    b->nkeys = (uint32_t)keys;
+    c->rlist_max = rmax_all;
+    std::vector<int> chunk_rep(slots / kWave);
+    std::vector<uint32_t> key_end(R);
+    for (int r = 0; r < R; ++r) {
+        for (int q = b->offsets[r] / kWave; q < b->offsets[r + 1] / kWave; ++q) chunk_rep[q] = r;
+        key_end[r] = b->desc[r].key_base + b->desc[r].grid.nkeys;
+    }
+    b->seeds.assign(R, 0);
+    bool ok = hipGetDevice(&c->device) == hipSuccess &&
+              hipMalloc(&c->d_tab, sizeof(DevEntry) * (size_t)R * nt2) == hipSuccess &&
+              hipMemcpy(c->d_tab, c->host_tab.data(), sizeof(DevEntry) * (size_t)R * nt2, hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMalloc(&c->d_step_base, sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&b->d_rep, sizeof(RepDesc) * R) == hipSuccess &&
+              hipMemcpy(b->d_rep, b->desc.data(), sizeof(RepDesc) * R, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&b->d_chunk_rep, sizeof(int) * chunk_rep.size()) == hipSuccess &&
+              hipMemcpy(b->d_chunk_rep, chunk_rep.data(), sizeof(int) * chunk_rep.size(), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMalloc(&b->d_key_end, sizeof(uint32_t) * R) == hipSuccess &&
+              hipMemcpy(b->d_key_end, key_end.data(), sizeof(uint32_t) * R, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&b->d_seeds, sizeof(uint64_t) * R) == hipSuccess &&
+              hipMemcpy(b->d_seeds, b->seeds.data(), sizeof(uint64_t) * R, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        free_batch(b);
+        return RC_ERR_HIP;
+    }
+    *out = b;
+    return RC_OK;
+}
+
+int rc_batch_destroy(rc_batch* b) {
+    if (!b) return RC_ERR_ARG;
+    free_batch(b);
+    return RC_OK;
+}
+
+const char* rc_batch_last_error(const rc_batch* b) { return b ? b->c.err.c_str() : "null batch"; }
+
+int rc_batch_layout(const rc_batch* b, int* n_slots, int* offsets) {
+    if (!b || !n_slots) return RC_ERR_ARG;
+    *n_slots = b->n_slots;
+    if (offsets) std::memcpy(offsets, b->offsets.data(), sizeof(int) * (b->R + 1));
+    return RC_OK;
+}
+
+int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds) {
+    if (!b || !seeds) return RC_ERR_ARG;
+    HIP_TRY(&b->c, hipDeviceSynchronize());
+    HIP_TRY(&b->c, hipMemcpy(b->d_seeds, seeds, sizeof(uint64_t) * b->R, hipMemcpyHostToDevice));
+    b->seeds.assign(seeds, seeds + b->R);
+    b->seeds_set = true;
+    return RC_OK;
+}
+
+int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes) {
+    if (!b || !bytes) return RC_ERR_ARG;
+    *bytes = cells_layout(b->n_slots, b->nkeys).total;
+    return RC_OK;
+}
+
+int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (!b) return RC_ERR_ARG;
+    int r = check_pos(b, pos);
+    if (r) return r;
+    const CellsLayout l = cells_layout(b->n_slots, b->nkeys);
+    if (!ws || ws_bytes < l.total) return fail(&b->c, RC_ERR_WORKSPACE, "cells workspace needs %zu bytes", l.total);
+    char* w = static_cast<char*>(ws);
+    CellsArgsB a{};
+    a.pos = reinterpret_cast<float4*>(pos);
+    a.vel = reinterpret_cast<float4*>(vel);
+    a.image = reinterpret_cast<int4*>(image);
+    a.rtag = rtag;
+    a.N = b->n_slots;
+    a.rep = b->d_rep;
+    a.chunk_rep = b->d_chunk_rep;
+    a.key_end = b->d_key_end;
+    a.R = b->R;
+    a.nkeys = b->nkeys;
+    a.counts = reinterpret_cast<int*>(w + l.counts);
+    a.cell_start = reinterpret_cast<int*>(w + l.start);
+    a.keys = reinterpret_cast<int*>(w + l.keys);
+    a.rank = reinterpret_cast<int*>(w + l.rank);
+    a.order = reinterpret_cast<int*>(w + l.order);
+    a.block_sums = reinterpret_cast<int*>(w + l.bsums);
+    a.tpos = reinterpret_cast<float4*>(w + l.tpos);
+    a.tvel = reinterpret_cast<float4*>(w + l.tvel);
+    a.timage = reinterpret_cast<int4*>(w + l.timage);
+    HIP_TRY(&b->c, launch_cells_batch(a, S(stream)));
+    return RC_OK;
+}
+
+int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
+                         int* nlist, int* nn, int* status, void* stream) {
+    if (!b) return RC_ERR_ARG;
+    int r = check_pos(b, pos);
+    if (r) return r;
+    if ((r = check_list(&b->c, nlist, nn, k_max))) return r;
+    const CellsLayout l = cells_layout(b->n_slots, b->nkeys);
+    if (!ws || ws_bytes < l.total) return fail(&b->c, RC_ERR_WORKSPACE, "cells workspace needs %zu bytes", l.total);
+    NlistArgsB a{};
+    a.pos = reinterpret_cast<const float4*>(pos);
+    a.vel = reinterpret_cast<float4*>(vel);
+    a.N = b->n_slots;
+    a.rep = b->d_rep;
+    a.chunk_rep = b->d_chunk_rep;
+    a.tab = all_tables(b);
+    a.cell_start = reinterpret_cast<const int*>(static_cast<const char*>(ws) + l.start);
+    a.k_max = k_max;
+    a.nlist = nlist;
+    a.nn = nn;
+    a.status = status;
+    a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
+    HIP_TRY(&b->c, launch_nlist_batch(a, S(stream)));
+    return RC_OK;
+}
+
+int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, const int* nn, int k_max, float* force,
+                            double* ev, int* status, void* stream) {
+    if (!b) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    int r = check_pos(b, pos);
+    if (r) return r;
+    if (!force) return fail(c, RC_ERR_ARG, "force is NULL");
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    const int nb = nblocks(b->n_slots, kWave);
+    if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
+    ForceArgs a{};
+    a.pos = reinterpret_cast<const float4*>(pos);
+    a.nlist = nlist;
+    a.nn = nn;
+    a.k_max = k_max;
+    a.N = b->n_slots;
+    a.tab = all_tables(b);
+    a.force = reinterpret_cast<float4*>(force);
+    a.ev_part = ev ? c->d_part : nullptr;
+    a.accumulate = 0;
+    a.status = status;
+    a.rep = b->d_rep;
+    a.chunk_rep = b->d_chunk_rep;
+    hipStream_t s = S(stream);
+    HIP_TRY(c, launch_forces_gather_batch(a, s));
+    if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_rep, b->R, 0, 7, ev, 7, s));
+    return RC_OK;
+}
+
+int rc_batch_bond_count(rc_batch* b, const float* pos, const int* nlist, const int* nn, int k_max,
+                        unsigned long long* counts, void* stream) {
+    if (!b) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    int r = check_pos(b, pos);
+    if (r) return r;
+    if (!counts) return fail(c, RC_ERR_ARG, "counts is NULL");
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    if ((r = ensure_part(c, sizeof(unsigned long long) * (size_t)nblocks(b->n_slots, kWave)))) return r;
+    HIP_TRY(c, launch_bonds_batch(reinterpret_cast<const float4*>(pos), nlist, nn, k_max, b->n_slots, all_tables(b),
+                                  b->d_rep, b->d_chunk_rep, b->R, counts,
+                                  reinterpret_cast<unsigned long long*>(c->d_part), S(stream)));
+    return RC_OK;
+}
+
+int rc_batch_step_fused(rc_batch* b, const float* pos_in, float* pos_out, float* vel, int* image, const int* nlist,
+                        const int* nn, int k_max, const rc_integrator* cfg, uint64_t step, int mode, double soft_frac,
+                        double* ev, int* status, void* stream) {
+    if (!b) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    int r = check_pos(b, pos_in);
+    if (r) return r;
+    if (!vel || !status) return fail(c, RC_ERR_ARG, "vel / status are NULL");
+    if ((mode == RC_STEP_START || mode == RC_STEP_CONT) && (!pos_out || pos_out == pos_in))
+        return fail(c, RC_ERR_ARG, "pos_out must be a second buffer");
+    if (mode < RC_STEP_START || mode > RC_STEP_OBSERVE) return fail(c, RC_ERR_ARG, "bad mode");
+    if (!(soft_frac > 0.0 && soft_frac <= 1.0)) return fail(c, RC_ERR_ARG, "soft_frac must be in (0, 1]");
+    hipStream_t s = S(stream);
+    StepArgs a{};
+    if ((r = fill_step_args_batch(b, a, pos_in, pos_out, vel, image, nlist, nn, k_max, cfg, soft_frac, status, s)))
+        return r;
+    const int nb = nblocks(b->n_slots, kStepBlock);
+    if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
+    a.mode = mode;
+    a.step = step;
+    a.step_base = nullptr;
+    a.ev_part = ev ? c->d_part : nullptr;
+    HIP_TRY(c, launch_step_batch(a, ev != nullptr, s));
+    HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, b->n_slots, status, s));
+    if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_rep, b->R, 0, kEvWords, ev, kEvWords, s));
+    return RC_OK;
+}
+
+int rc_batch_time_fused_steps(rc_batch* b, float* pos_a, float* pos_b, float* vel, const int* nlist, const int* nn,
+                              int k_max, const rc_integrator* cfg, uint64_t step0, int reps, int* status, float* ms,
+                              void* stream) {
+    if (!b) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    int r = check_pos(b, pos_a);
+    if (r) return r;
+    if (!pos_b || pos_b == pos_a || !vel || !status || !ms || reps < 1)
+        return fail(c, RC_ERR_ARG, "bad arguments to rc_batch_time_fused_steps");
+    hipStream_t s = S(stream);
+    StepArgs a{};
+    if ((r = fill_step_args_batch(b, a, pos_a, pos_b, vel, nullptr, nlist, nn, k_max, cfg, 0.8, status, s))) return r;
+    a.mode = RC_STEP_CONT;
+    a.step_base = nullptr;
+    a.ev_part = nullptr;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    float4* P[2] = {reinterpret_cast<float4*>(pos_a), reinterpret_cast<float4*>(pos_b)};
+    hipError_t err = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && err == hipSuccess; ++k) {
+        a.pos_in = P[k & 1];
+        a.pos_out = P[(k + 1) & 1];
+        a.step = step0 + (uint64_t)k;
+        err = launch_step_batch(a, false, s);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = launch_fold_status(c->d_blk, nblocks(b->n_slots, kStepBlock), nullptr, b->n_slots,
+                                                    status, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(c, err, "rc_batch_time_fused_steps");
+    return RC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BatchOps final : DriveOps {
+    rc_batch* b;
+    const rc_md_buffers* buf;
+    hipStream_t s;
+    int rebuild(float* pos) override {
+        int rr = rc_batch_build_cells(b, pos, buf->vel, buf->image, buf->rtag, buf->cells_ws, buf->cells_ws_bytes, s);
+        if (rr) return rr;
+        HIP_TRY(&b->c, launch_zero_words(buf->status, RC_STATUS_WORDS, s));
+        return rc_batch_build_nlist(b, pos, buf->vel, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
+                                    buf->nn, buf->status, s);
+    }
+    int bonds(const float* pos, int row) override {
+        HIP_TRY(&b->c, launch_bonds_batch(reinterpret_cast<const float4*>(pos), buf->nlist, buf->nn, buf->k_max,
+                                          b->n_slots, all_tables(b), b->d_rep, b->d_chunk_rep, b->R,
+                                          buf->bonds_log + (size_t)row * b->R,
+                                          reinterpret_cast<unsigned long long*>(b->c.d_part), s));
+        return RC_OK;
+    }
+    hipError_t launch(const StepArgs& a, bool ev) override { return launch_step_batch(a, ev, s); }
+    int reduce_ev(int row) override {
+        HIP_TRY(&b->c, launch_reduce_rows_batch(b->c.d_part, b->d_rep, b->R, 0, kEvWords,
+                                                buf->ev_log + (size_t)row * b->R * kEvWords, kEvWords, s));
+        return RC_OK;
+    }
+    const void* graph_fn() override {
+        const void* fn;
+        step_batch_kernel_info(&fn);
+        return fn;
+    }
+};
+
+}  // namespace
+
+extern "C" int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_integrator* cfg, uint64_t step0,
+                            int n_steps, const rc_md_options* opt_in, rc_md_stats* stats, void* stream) {
+    if (!b || !buf) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    int r = check_pos(b, buf->pos);
+    if (r) return r;
+    if (!buf->pos_alt || !buf->vel || !buf->nlist || !buf->nn || !buf->cells_ws || !buf->status)
+        return fail(c, RC_ERR_ARG, "md buffers incomplete");
+    if (buf->k_max < 1 || buf->k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
+    if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0};
+    if (opt_in) opt = *opt_in;
+    if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
+    if (opt.max_chunk < 1) opt.max_chunk = 256;
+    if (!(opt.soft_frac > 0.0 && opt.soft_frac <= 1.0)) opt.soft_frac = 0.8;
+    hipStream_t s = S(stream);
+    const int nb = nblocks(b->n_slots, kStepBlock);
+    if ((r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
+    StepArgs tmpl{};
+    if ((r = fill_step_args_batch(b, tmpl, buf->pos, buf->pos_alt, buf->vel, buf->image, buf->nlist, buf->nn,
+                                  buf->k_max, cfg, opt.soft_frac, buf->status, s)))
+        return r;
+    BatchOps ops;
+    ops.b = b;
+    ops.buf = buf;
+    ops.s = s;
+    return md_drive(c, ops, buf, b->n_slots, tmpl, step0, n_steps, opt, stats, s);
+}

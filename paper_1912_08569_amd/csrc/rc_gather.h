@@ -1,0 +1,248 @@
+// Device-side building blocks shared by the force, step and batch kernels:
+// list walks, the two-hop partner sum, and the wavefront-cooperative gather.
+//
+// Notation: for a centre c and a swap partner a inside r_cut, w_ca =
+// sqrt(Lambda_ca) vhat(r_ca); a triplet term is w_ca w_cb (eq. 3bp with
+// Lambda_cab = sqrt(Lambda_ca Lambda_cb)); d = x_a - x_c (minimum image).
+#pragma once
+
+#include "rc_internal.h"
+
+namespace rc {
+
+// The system a particle belongs to: its box and its coefficient table.
+// One periodic system (table staged in LDS):
+struct OneSystem {
+    const DevEntry* tab;
+    int nt;
+    Box box;
+    __device__ __forceinline__ const DevEntry* table(int) const { return tab; }
+    __device__ __forceinline__ const Box& boxof(int) const { return box; }
+};
+
+__device__ __forceinline__ void load_table(DevEntry* s_tab, const Table& t) {
+    const int n = t.nt * t.nt;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) s_tab[q] = t.e[q];
+    __syncthreads();
+}
+
+// Walk of particle m's list: the swap range (slots 0 .. ns-1) and, unless
+// SWAP_ONLY, the other range (slots k_max-1 down to k_max-no).  For every
+// neighbour j != skip inside its cutoff (canonical FP64 decision) the functor
+// gets (j, pj, entry, r2 in FP64, r2 in FP32, d = x_j - x_m in FP32).
+template <bool SWAP_ONLY, typename F>
+__device__ __forceinline__ void walk_list(int m, const float4& pm, int tm, const int* nlist, int packed,
+                                          int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
+                                          const Box& box, int skip, F&& f) {
+    auto visit = [&](int j) {
+        if (j == skip) return;
+        const float4 pj = pos[j];
+        const DevEntry& e = tab[tm * nt + ptype(pj.w)];
+        if (e.kind == RC_KIND_NONE) return;
+        double dx, dy, dz;
+        const double r2d = canon_r2(pm, pj, box, dx, dy, dz);
+        if (!(r2d < e.rcut2)) return;
+        f(j, pj, e, r2d, (float)r2d, (float)dx, (float)dy, (float)dz);
+    };
+    const int ns = nn_swap(packed);
+    for (int s = 0; s < ns; ++s) visit(nlist[(size_t)s * N + m]);
+    if (!SWAP_ONLY) {
+        const int no = nn_other(packed);
+        for (int s = 0; s < no; ++s) visit(nlist[(size_t)(k_max - 1 - s) * N + m]);
+    }
+}
+
+// sum of w_ck over the swap partners k of centre c inside r_cut, except 'skip'
+// (only c's swap range is read: for a bonded pair it usually holds skip alone)
+__device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, int skip,
+                                                       const int* nlist, const int* nn, int k_max, int N,
+                                                       const float4* pos, const DevEntry* tab,
+                                                       int nt, const Box& box) {
+    float s = 0.0f;
+    walk_list<true>(c, pc, ptype(pc.w), nlist, nn[c], k_max, N, pos, tab, nt, box, skip,
+                    [&](int, const float4&, const DevEntry& e, double r2d, float r2, float, float, float) {
+                        s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, r2);
+                    });
+    return s;
+}
+
+struct Acc {
+    float fx, fy, fz, e;
+    float w[6];  // xx yy zz xy xz yz
+};
+
+__device__ __forceinline__ void acc_virial(Acc& a, float c, float dx, float dy, float dz) {
+    // adds c * d (x) d  (a term (r)_a (F)_b with F = c d)
+    a.w[0] += c * dx * dx;
+    a.w[1] += c * dy * dy;
+    a.w[2] += c * dz * dz;
+    a.w[3] += c * dx * dy;
+    a.w[4] += c * dx * dz;
+    a.w[5] += c * dy * dz;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-cooperative gather (one wavefront per block).  The 64 lanes own
+// 64 consecutive particles; their (particle, list slot) entries are laid out
+// flat (exclusive scan of the list lengths) and every lane evaluates one entry
+// per pass, so a wave needs about (sum of list lengths)/64 passes instead of
+// one pass per slot of its longest list.  Per-entry contributions are staged
+// in LDS and each owner lane sums its own entries in slot order
+// (deterministic).  Triplets the owner centres are added afterwards by a walk
+// of its swap range, only when it has two or more active swap partners.
+// ---------------------------------------------------------------------------
+template <bool EV>
+struct Stage {
+    static constexpr int n = EV ? 12 : 5;  // fx fy fz w active [e w0..w5]
+};
+constexpr int kPerLane = 2;  // flattened entries each lane evaluates per pass
+
+template <bool EV, class Ctx>
+__device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
+                                            const float4* pos, const int* nlist, const int* nn, int k_max,
+                                            int N, const Ctx& ctx, Acc& acc) {
+    const int nt = ctx.nt;
+    constexpr int NC = Stage<EV>::n;
+    constexpr int W = kPerLane * kWave;  // entries per pass
+    __shared__ int s_off[kWave + 1];
+    __shared__ int s_ns[kWave];
+    __shared__ float4 s_pos[kWave];
+    __shared__ float s_c[NC][W];
+    const int lane = threadIdx.x;
+    const int ns = live ? nn_swap(packed) : 0;
+    const int cnt = live ? ns + nn_other(packed) : 0;
+    int inc = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    const int my_off = inc - cnt;
+    s_off[lane] = my_off;
+    if (lane == kWave - 1) s_off[kWave] = inc;
+    s_ns[lane] = ns;
+    s_pos[lane] = pm;
+    __syncthreads();
+    const int T = s_off[kWave];
+    double S = 0.0;
+    int nact = 0;
+    for (int base = 0; base < T; base += W) {
+        // locate and load all entries of this pass first, so their memory
+        // latencies overlap (list index, then neighbour position)
+        int own[kPerLane], jj[kPerLane];
+        float4 pj[kPerLane];
+#pragma unroll
+        for (int u = 0; u < kPerLane; ++u) {
+            const int e = base + u * kWave + lane;
+            own[u] = -1;
+            jj[u] = 0;
+            if (e < T) {
+                int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int sl = e - s_off[lo], nso = s_ns[lo];
+                const int slot = sl < nso ? sl : k_max - 1 - (sl - nso);
+                own[u] = lo;
+                jj[u] = nlist[(size_t)slot * N + base_m + lo];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPerLane; ++u) pj[u] = own[u] >= 0 ? pos[jj[u]] : pm;
+#pragma unroll
+        for (int u = 0; u < kPerLane; ++u) {
+            float c[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) c[q] = 0.0f;
+            if (own[u] >= 0) {
+                const int mo = base_m + own[u];
+                const float4 po = s_pos[own[u]];
+                const DevEntry* tab = ctx.table(own[u]);
+                const Box& box = ctx.boxof(own[u]);
+                const DevEntry& en = tab[ptype(po.w) * nt + ptype(pj[u].w)];
+                if (en.kind != RC_KIND_NONE) {
+                    double dxd, dyd, dzd;
+                    const double r2d = canon_r2(po, pj[u], box, dxd, dyd, dzd);
+                    if (r2d < en.rcut2) {
+                        const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                        float phi, g;
+                        pair_eval(en, r2, phi, g);
+                        float f = g;
+                        if (EV) {
+                            c[5] = 0.5f * phi;
+                            const float h = -0.5f * g;
+                            c[6] = h * dx * dx; c[7] = h * dy * dy; c[8] = h * dz * dz;
+                            c[9] = h * dx * dy; c[10] = h * dx * dz; c[11] = h * dy * dz;
+                        }
+                        if (en.kind == RC_KIND_SWAP) {
+                            float uu, u1r;
+                            vhat_eval(en, r2d <= en.rmin2, r2, uu, u1r);
+                            c[3] = en.sqrt_lam * uu;
+                            c[4] = 1.0f;
+                            if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
+                                f += en.sqrt_lam * u1r *
+                                     partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt, box);
+                        }
+                        c[0] = f * dx;
+                        c[1] = f * dy;
+                        c[2] = f * dz;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NC; ++q) s_c[q][u * kWave + lane] = c[q];
+        }
+        __syncthreads();
+        const int lo = max(my_off, base) - base, hi = min(my_off + cnt, base + W) - base;
+        for (int q = lo; q < hi; ++q) {
+            acc.fx += s_c[0][q];
+            acc.fy += s_c[1][q];
+            acc.fz += s_c[2][q];
+            S += (double)s_c[3][q];
+            nact += s_c[4][q] != 0.0f;
+            if (EV) {
+                acc.e += s_c[5][q];
+#pragma unroll
+                for (int w = 0; w < 6; ++w) acc.w[w] += s_c[6 + w][q];
+            }
+        }
+        __syncthreads();
+    }
+    if (live && nact >= 2) {
+        const int m = base_m + lane;
+        float prefix = 0.0f;
+        walk_list<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, ctx.table(lane), nt, ctx.boxof(lane), -1,
+                        [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
+                            float dz) {
+                            float u, u1r;
+                            vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                            const float w = e.sqrt_lam * u;
+                            const float excl = (float)(S - (double)w);
+                            const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
+                            acc.fx += c * dx;
+                            acc.fy += c * dy;
+                            acc.fz += c * dz;
+                            if (EV) {
+                                acc.e += w * prefix;  // sum over pairs b < a of w_b w_a
+                                prefix += w;
+                                acc_virial(acc, -c, dx, dy, dz);  // (d) (x) (force on a = -c d)
+                            }
+                        });
+    }
+}
+
+// wave-wide sums of NW doubles; lane 0 stores them
+template <int NW>
+__device__ __forceinline__ void wave_sum_store(double (&v)[NW], double* out) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) out[q] = v[q];
+    }
+}
+
+
+}  // namespace rc

@@ -1,0 +1,97 @@
+// Host-side internals shared by the single-system and the batch C ABI:
+// the context, argument checks, workspace layout, the table compiler, step
+// graphs and the chunked MD driver.
+#pragma once
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "rc_internal.h"
+
+struct GraphCache {
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // start parity 0 / 1
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    rc::StepArgs key{};
+    const void* fn = nullptr;
+    int steps = 0;
+    bool valid = false;
+};
+
+struct rc_ctx {
+    int device = 0;
+    int nt = 0;
+    std::vector<rc_pair_coeff> table;   // as given (one table; a batch keeps its own copies)
+    double r_buff = 0.0;
+    double rlist_max = 0.0;
+    std::vector<rc::DevEntry> host_tab;
+    rc::DevEntry* d_tab = nullptr;
+    double* d_part = nullptr;           // block partial rows (13 doubles each) or param partials
+    size_t part_bytes = 0;
+    unsigned long long* d_step_base = nullptr;
+    int* d_blk = nullptr;               // per-block status slots of the step kernel
+    int blk_cap = 0;                    // slots allocated (blocks)
+    GraphCache gc;
+    std::string err;
+};
+
+namespace rc {
+namespace host {
+
+int fail(rc_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int hip_fail(rc_ctx* c, hipError_t e, const char* where);
+
+#define HIP_TRY(ctx, expr)                                              \
+    do {                                                                \
+        hipError_t _e = (expr);                                         \
+        if (_e != hipSuccess) return ::rc::host::hip_fail((ctx), _e, #expr); \
+    } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline int nblocks(long n, int b) { return (int)((n + b - 1) / b); }
+
+int make_box(rc_ctx* c, const rc_box& in, Box& b);
+int make_grid(rc_ctx* c, double rlist_max, const Box& b, Grid& g);
+
+struct CellsLayout {
+    size_t counts, start, keys, rank, order, bsums, bmax, tpos, tvel, timage, total;
+};
+CellsLayout cells_layout(int N, uint32_t nkeys);
+
+int ensure_part(rc_ctx* c, size_t bytes);
+int ensure_blk(rc_ctx* c, int nb, hipStream_t s);
+int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin);
+int check_list(rc_ctx* c, const int* nlist, const int* nn, int k_max);
+
+// Validate one ntypes x ntypes table and compile it; returns RC_OK or
+// RC_ERR_ARG with a message in *why.
+int compile_table(int nt, const rc_pair_coeff* table, double r_buff, DevEntry* out, double* rlist_max,
+                  std::string* why);
+
+void drop_graphs(rc_ctx* c);
+
+// What the chunked driver needs from a system (one or a batch).
+struct DriveOps {
+    virtual ~DriveOps() = default;
+    // cell sort (permutes pos, vel, image) and list build from pos; the list
+    // kernels leave KMAX and the overflow flag in the status word
+    virtual int rebuild(float* pos) = 0;
+    // bond count(s) of the state in pos into log row `row`
+    virtual int bonds(const float* pos, int row) = 0;
+    // one step launch with a filled StepArgs (ev: partial rows to ctx->d_part)
+    virtual hipError_t launch(const StepArgs& a, bool ev) = 0;
+    // reduce the partial rows of the last ev launch into log row `row`
+    virtual int reduce_ev(int row) = 0;
+    // kernel that the step graphs replay
+    virtual const void* graph_fn() = 0;
+};
+
+// Chunked driver: speculative chunks of fused steps (graph replays where no
+// log step intervenes), one status read per chunk, rollback and replay of
+// stale chunks, rebuilds, the final half kick and the logs.  tmpl holds every
+// launch argument except positions, mode, step and ev_part; N counts slots.
+int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const StepArgs& tmpl, uint64_t step0,
+             int n_steps, rc_md_options opt, rc_md_stats* stats, hipStream_t s);
+
+}  // namespace host
+}  // namespace rc

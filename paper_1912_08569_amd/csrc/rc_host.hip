@@ -1,0 +1,467 @@
+// Host-side internals shared by the single-system and the batch C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "rc_host.h"
+
+namespace rc {
+namespace host {
+
+int fail(rc_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+int hip_fail(rc_ctx* c, hipError_t e, const char* where) {
+    return fail(c, RC_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+static bool fp32_exact(double x) { return (double)(float)x == x; }
+
+int make_box(rc_ctx* c, const rc_box& in, Box& b) {
+    for (int d = 0; d < 3; ++d) {
+        const double L = in.L[d];
+        if (!(L > 0.0) || !std::isfinite(L)) return fail(c, RC_ERR_ARG, "box edge %d is not positive", d);
+        if (!fp32_exact(L)) return fail(c, RC_ERR_ARG, "box edge %d = %.17g is not an FP32 value", d, L);
+        b.L[d] = L;
+        b.h[d] = 0.5 * L;
+        b.Lf[d] = (float)L;
+        b.hf[d] = (float)(0.5 * L);
+    }
+    return RC_OK;
+}
+
+int make_grid(rc_ctx* c, double rlist_max, const Box& b, Grid& g) {
+    int maxnc = 0;
+    for (int d = 0; d < 3; ++d) {
+        if (b.L[d] < 3.0 * rlist_max)
+            return fail(c, RC_ERR_ARG, "box edge %.6g shorter than three list radii (%.6g)", b.L[d],
+                        3.0 * rlist_max);
+        int nc = (int)std::floor(b.L[d] / (rlist_max * (1.0 + 1e-5)));
+        nc = std::max(3, std::min(nc, 256));
+        g.nc[d] = nc;
+        g.inv_w[d] = (float)(nc / b.L[d]);
+        maxnc = std::max(maxnc, nc);
+    }
+    int bits = 0;
+    while ((1 << bits) < maxnc) ++bits;
+    g.bits = bits;
+    g.nkeys = 1u << (3 * bits);
+    return RC_OK;
+}
+
+CellsLayout cells_layout(int N, uint32_t nkeys) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    CellsLayout l{};
+    size_t o = 0;
+    const size_t nk = nkeys;
+    l.counts = o; o = al(o + 4 * nk);
+    l.start = o; o = al(o + 4 * (nk + 1));
+    l.keys = o; o = al(o + 4 * (size_t)N);
+    l.rank = o; o = al(o + 4 * (size_t)N);
+    l.order = o; o = al(o + 4 * (size_t)N);
+    l.bsums = o; o = al(o + 4 * (nk / kScanTile + 2));
+    l.bmax = o; o = al(o + 4 * ((size_t)N / kBlock + 2));
+    l.tpos = o; o = al(o + 16 * (size_t)N);
+    l.tvel = o; o = al(o + 16 * (size_t)N);
+    l.timage = o; o = al(o + 16 * (size_t)N);
+    l.total = o;
+    return l;
+}
+
+int ensure_part(rc_ctx* c, size_t bytes) {
+    if (c->part_bytes >= bytes) return RC_OK;
+    if (c->d_part) (void)hipFree(c->d_part);
+    c->d_part = nullptr;
+    c->part_bytes = 0;
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    HIP_TRY(c, hipMalloc(&c->d_part, want));
+    c->part_bytes = want;
+    return RC_OK;
+}
+
+void drop_graphs(rc_ctx* c) {
+    for (int p = 0; p < 2; ++p) {
+        if (c->gc.exec[p]) (void)hipGraphExecDestroy(c->gc.exec[p]);
+        if (c->gc.graph[p]) (void)hipGraphDestroy(c->gc.graph[p]);
+        c->gc.exec[p] = nullptr;
+        c->gc.graph[p] = nullptr;
+    }
+    c->gc.valid = false;
+}
+
+// per-block status slots for nb blocks (allocated once per size, reset to neutral)
+int ensure_blk(rc_ctx* c, int nb, hipStream_t s) {
+    if (c->blk_cap >= nb) return RC_OK;
+    drop_graphs(c);   // graphs hold the old pointer
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->d_blk) (void)hipFree(c->d_blk);
+    c->d_blk = nullptr;
+    c->blk_cap = 0;
+    const int want = std::max(nb, 1024);
+    HIP_TRY(c, hipMalloc(&c->d_blk, sizeof(int) * 3 * (size_t)want));
+    HIP_TRY(c, launch_blk_reset(c->d_blk, want, s));
+    c->blk_cap = want;
+    return RC_OK;
+}
+
+int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin) {
+    if (!cfg) return fail(c, RC_ERR_ARG, "integrator is NULL");
+    if (cfg->kind != RC_INTEGRATOR_NVE && cfg->kind != RC_INTEGRATOR_LANGEVIN)
+        return fail(c, RC_ERR_ARG, "unknown integrator kind %d", cfg->kind);
+    if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return fail(c, RC_ERR_ARG, "dt must be positive");
+    langevin = cfg->kind == RC_INTEGRATOR_LANGEVIN;
+    if (langevin && (!(cfg->gamma >= 0.0) || !(cfg->kT >= 0.0)))
+        return fail(c, RC_ERR_ARG, "Langevin needs gamma >= 0 and kT >= 0");
+    const double e1 = langevin ? std::exp(-cfg->gamma * cfg->dt) : 1.0;
+    c1 = (float)e1;
+    for (int t = 0; t < RC_MAX_TYPES; ++t) {
+        minv[t] = 0.0f;
+        c2[t] = 0.0f;
+    }
+    for (int t = 0; t < c->nt; ++t) {
+        const double m = cfg->mass[t];
+        if (!(m > 0.0) || !std::isfinite(m)) return fail(c, RC_ERR_ARG, "mass of type %d must be positive", t);
+        minv[t] = (float)(1.0 / m);
+        c2[t] = langevin ? (float)std::sqrt((1.0 - e1 * e1) * cfg->kT / m) : 0.0f;
+    }
+    return RC_OK;
+}
+
+int check_list(rc_ctx* c, const int* nlist, const int* nn, int k_max) {
+    if (!nlist || !nn) return fail(c, RC_ERR_ARG, "nlist / nn are NULL");
+    if (k_max < 1 || k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
+    return RC_OK;
+}
+
+int compile_table(int nt, const rc_pair_coeff* table, double r_buff, DevEntry* out, double* rlist_max,
+                  std::string* why) {
+    auto bad = [&](const char* msg, int a, int b) {
+        if (why) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "table entry (%d, %d): %s", a, b, msg);
+            *why = buf;
+        }
+        return RC_ERR_ARG;
+    };
+    double rmax = 0.0;
+    for (int a = 0; a < nt; ++a) {
+        for (int b = 0; b < nt; ++b) {
+            const rc_pair_coeff& p = table[a * nt + b];
+            const rc_pair_coeff& q = table[b * nt + a];
+            if (p.kind != q.kind || p.n != q.n || p.epsilon != q.epsilon || p.sigma != q.sigma ||
+                p.r_cut != q.r_cut || (p.kind == RC_KIND_SWAP && p.lambda != q.lambda))
+                return bad("not symmetric", a, b);
+            DevEntry e{};
+            e.kind = p.kind;
+            if (p.kind == RC_KIND_SWAP) {
+                const double rmin = p.sigma * std::pow(2.0, 1.0 / p.n);
+                if (!(p.epsilon > 0.0) || !(p.sigma > 0.0) || p.n < 1 || p.n > 200 || !(p.lambda >= 0.0) ||
+                    !(p.r_cut > rmin) || !std::isfinite(p.r_cut))
+                    return bad("swap entry needs eps > 0, sigma > 0, 1 <= n <= 200, lambda >= 0, r_cut > r_min",
+                               a, b);
+                e.n = p.n;
+                e.sqrt_lam = (float)std::sqrt(p.lambda * p.epsilon);
+                e.inv_eps = (float)(1.0 / p.epsilon);
+                e.lam = (float)p.lambda;
+            } else if (p.kind == RC_KIND_WCA) {
+                if (!(p.epsilon >= 0.0) || !(p.sigma > 0.0) || !(p.r_cut > 0.0) || !std::isfinite(p.r_cut))
+                    return bad("WCA entry needs eps >= 0, sigma > 0, r_cut > 0", a, b);
+                e.n = 6;
+            } else if (p.kind != RC_KIND_NONE) {
+                return bad("unknown kind", a, b);
+            }
+            if (p.kind != RC_KIND_NONE) {
+                e.eps = (float)p.epsilon;
+                e.sigma = (float)p.sigma;
+                e.sig2 = (float)(p.sigma * p.sigma);
+                e.rcut2 = p.r_cut * p.r_cut;
+                e.rmin2 = (p.sigma * p.sigma) * std::pow(2.0, 2.0 / (double)(p.kind == RC_KIND_SWAP ? p.n : 6));
+                const double rl = p.r_cut + r_buff;
+                e.rlist2 = (float)(rl * rl * (1.0 + 1e-5));
+                rmax = std::max(rmax, rl);
+            }
+            out[a * nt + b] = e;
+        }
+    }
+    if (rmax == 0.0) rmax = r_buff;
+    *rlist_max = rmax;
+    return RC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step graphs: G launches of the CONT step alternating the two position
+// buffers, then one add of G to the device step base; one graph per start
+// parity.  Built with explicit kernel nodes (no capture, no memset nodes).
+// ---------------------------------------------------------------------------
+static int build_graphs(rc_ctx* c, const void* fn, const StepArgs& tmpl, int G) {
+    drop_graphs(c);
+    const void* add_fn;
+    add_step_kernel_info(&add_fn);
+    const int nb = nblocks(tmpl.N, kStepBlock);
+    const size_t shm = sizeof(DevEntry) * c->nt * c->nt;
+    for (int p = 0; p < 2; ++p) {
+        hipGraph_t g;
+        HIP_TRY(c, hipGraphCreate(&g, 0));
+        c->gc.graph[p] = g;
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < G; ++k) {
+            StepArgs a = tmpl;
+            const bool from_alt = ((k + p) & 1) != 0;
+            const float4* A = tmpl.pos_in;                        // "pos"
+            float4* B = tmpl.pos_out;                             // "pos_alt"
+            a.pos_in = from_alt ? B : A;
+            a.pos_out = from_alt ? const_cast<float4*>(A) : B;
+            a.mode = RC_STEP_CONT;
+            a.step = (uint64_t)k;
+            a.step_base = c->d_step_base;
+            a.ev_part = nullptr;
+            void* args[] = {&a};
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(fn);
+            kp.gridDim = dim3(nb);
+            kp.blockDim = dim3(kStepBlock);
+            kp.sharedMemBytes = (unsigned)shm;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            HIP_TRY(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+            prev = node;
+        }
+        {
+            unsigned long long* p_base = c->d_step_base;
+            unsigned long long inc = (unsigned long long)G;
+            void* args[] = {&p_base, &inc};
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(add_fn);
+            kp.gridDim = dim3(1);
+            kp.blockDim = dim3(1);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            HIP_TRY(c, hipGraphAddKernelNode(&node, g, &prev, 1, &kp));
+        }
+        HIP_TRY(c, hipGraphInstantiate(&c->gc.exec[p], g, nullptr, nullptr, 0));
+    }
+    c->gc.key = tmpl;
+    c->gc.fn = fn;
+    c->gc.steps = G;
+    c->gc.valid = true;
+    return RC_OK;
+}
+
+static bool same_args(const StepArgs& x, const StepArgs& y) { return std::memcmp(&x, &y, sizeof(StepArgs)) == 0; }
+
+int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const StepArgs& tmpl, uint64_t step0,
+             int n_steps, rc_md_options opt, rc_md_stats* stats, hipStream_t s) {
+    const bool can_roll = buf->snap_pos && buf->snap_vel && (buf->snap_image || !buf->image);
+    const int nb = nblocks(N, kStepBlock);
+    int r;
+    rc_md_stats st{};
+    int hst[RC_STATUS_WORDS] = {0};
+
+    float* P[2] = {buf->pos, buf->pos_alt};
+    int cur = 0;
+
+    auto rebuild = [&](int which) -> int {
+        int rr = ops.rebuild(P[which]);
+        if (rr) return rr;
+        HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        ++st.rebuilds;
+        if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW) {
+            st.k_needed = hst[RC_ST_KMAX];
+            return fail(c, RC_ERR_NLIST_OVERFLOW, "a particle has %d neighbours (k_max %d)", hst[RC_ST_KMAX],
+                        buf->k_max);
+        }
+        return RC_OK;
+    };
+    auto finish = [&](int code) -> int {
+        if (stats) {
+            st.flags = hst[RC_ST_FLAGS];
+            *stats = st;
+        }
+        return code;
+    };
+
+    int row = 0;
+    auto log_now = [&](int which) -> int {
+        if (buf->bonds_log) return ops.bonds(P[which], row);
+        return RC_OK;
+    };
+
+    // direct launch of one step from P[cur]
+    auto direct = [&](uint64_t step, int mode, bool ev) -> int {
+        StepArgs a = tmpl;
+        a.pos_in = reinterpret_cast<const float4*>(P[cur]);
+        a.pos_out = reinterpret_cast<float4*>(P[cur ^ 1]);
+        a.mode = mode;
+        a.step = step;
+        a.step_base = nullptr;
+        a.ev_part = ev ? c->d_part : nullptr;
+        HIP_TRY(c, ops.launch(a, ev));
+        if (ev && buf->ev_log) return ops.reduce_ev(row);
+        return RC_OK;
+    };
+
+    if ((r = rebuild(cur))) return finish(r);
+    HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+
+    const bool logging = buf->ev_log || buf->bonds_log;
+    const int lp = opt.log_period;
+    bool first = true;
+    int64_t done = 0;
+    double rate = 0.0;           // growth of the largest path length per step
+    float last_maxpath = 0.0f;
+    const float hard = tmpl.hard;
+    const bool graphs = opt.use_graph != 0;
+    const int G = opt.graph_steps;
+    if (graphs) {
+        StepArgs key = tmpl;
+        key.pos_in = reinterpret_cast<const float4*>(buf->pos);
+        key.pos_out = reinterpret_cast<float4*>(buf->pos_alt);
+        const void* fn = ops.graph_fn();
+        if (!c->gc.valid || c->gc.steps != G || c->gc.fn != fn || !same_args(c->gc.key, key)) {
+            if ((r = build_graphs(c, fn, key, G))) return finish(r);
+        }
+    }
+    uint64_t dev_base = ~0ull;   // value *d_step_base will hold once queued work ran
+
+    while (done < n_steps) {
+        // ---- plan the chunk ---------------------------------------------------
+        int64_t C = std::min<int64_t>(n_steps - done, opt.max_chunk);
+        if (!can_roll) C = 1;
+        else if (!opt.adapt) {
+            // fixed chunks: stale chunks are rolled back
+        } else if (rate > 0.0) {
+            const double room = (double)hard - (double)last_maxpath;
+            const int64_t safe = (int64_t)std::floor(room / (1.5 * rate));
+            C = std::max<int64_t>(1, std::min<int64_t>(C, safe));
+        } else if (first) {
+            C = std::min<int64_t>(C, 8);
+        }
+        const int64_t chunk_start = done;
+        const int row_start = row;
+        const int cur_start = cur;
+        const bool first_start = first;
+        if (can_roll) {
+            HIP_TRY(c, hipMemcpyAsync(buf->snap_pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(c, hipMemcpyAsync(buf->snap_vel, buf->vel, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+            if (buf->image)
+                HIP_TRY(c, hipMemcpyAsync(buf->snap_image, buf->image, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+        }
+        HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+        // ---- run it --------------------------------------------------------------
+        auto run_steps = [&](int64_t from, int64_t count) -> int {
+            int64_t k = 0;
+            while (k < count) {
+                const int64_t d = from + k;
+                const uint64_t step = step0 + (uint64_t)d;
+                const bool ev = logging && lp > 0 && (d % lp) == 0;
+                if (ev) {
+                    int rr = log_now(cur);
+                    if (rr) return rr;
+                }
+                if (graphs && !first && !ev && count - k >= G) {
+                    // a graph replay must not cross a logging step
+                    bool clear = true;
+                    if (logging && lp > 0) {
+                        const int64_t next_log = ((d + lp - 1) / lp) * lp;
+                        clear = next_log >= d + G || next_log == d;
+                        if (next_log == d) clear = false;
+                    }
+                    if (clear) {
+                        if (dev_base != step) HIP_TRY(c, launch_set_step(c->d_step_base, step, s));
+                        HIP_TRY(c, hipGraphLaunch(c->gc.exec[cur], s));
+                        dev_base = step + G;
+                        k += G;
+                        continue;  // G is even: cur is unchanged
+                    }
+                }
+                int rr = direct(step, first ? RC_STEP_START : RC_STEP_CONT, ev);
+                if (rr) return rr;
+                if (ev) ++row;
+                first = false;
+                cur ^= 1;
+                ++k;
+            }
+            return RC_OK;
+        };
+        if ((r = run_steps(chunk_start, C))) return finish(r);
+        HIP_TRY(c, launch_fold_status(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
+        HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        ++st.chunks;
+        const int f = hst[RC_ST_FLAGS];
+        if (f & RC_FLAG_LOST) return finish(fail(c, RC_ERR_LOST_PARTICLE, "a particle moved more than L/2 in one step"));
+        if (f & RC_FLAG_NONFINITE) return finish(fail(c, RC_ERR_NONFINITE, "non-finite position or velocity"));
+        float mp;
+        std::memcpy(&mp, &hst[RC_ST_MAXPATH], sizeof mp);
+        if (f & RC_FLAG_STALE) {
+            if (!can_roll) return finish(fail(c, RC_ERR_ARG, "stale list without rollback buffers"));
+            // roll back and replay up to the first soft crossing, then rebuild
+            cur = cur_start;
+            first = first_start;
+            row = row_start;
+            HIP_TRY(c, hipMemcpyAsync(P[cur], buf->snap_pos, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(c, hipMemcpyAsync(buf->vel, buf->snap_vel, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+            if (buf->image)
+                HIP_TRY(c, hipMemcpyAsync(buf->image, buf->snap_image, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+            const int64_t soft_step = (int64_t)hst[RC_ST_FIRST_SOFT];
+            int64_t n_re = soft_step - (int64_t)((step0 + (uint64_t)chunk_start) & 0x7fffffff) + 1;
+            n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, C));
+            HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+            if ((r = run_steps(chunk_start, n_re))) return finish(r);
+            HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
+            done = chunk_start + n_re;
+            ++st.rollbacks;
+            if ((r = rebuild(cur))) return finish(r);
+            rate = std::max(rate, (double)mp / std::max<int64_t>(1, C));
+            last_maxpath = 0.0f;
+            HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+            continue;
+        }
+        done = chunk_start + C;
+        rate = std::max(0.5 * rate, (double)(mp - last_maxpath) / (double)C);
+        last_maxpath = mp;
+        if (f & RC_FLAG_REBUILD) {
+            if ((r = rebuild(cur))) return finish(r);
+            last_maxpath = 0.0f;
+            HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+        }
+    }
+    // ---- final half kick (and the last log row) ------------------------------------
+    {
+        const bool ev = logging && buf->ev_log;
+        if (logging) {
+            if ((r = log_now(cur))) return finish(r);
+        }
+        if (!first) {
+            if ((r = direct(step0 + (uint64_t)n_steps, RC_STEP_FINISH, ev))) return finish(r);
+        } else if (ev) {
+            // zero steps: report the state as it is
+            if ((r = direct(step0, RC_STEP_OBSERVE, ev))) return finish(r);
+        }
+        if (logging) ++row;
+    }
+    if (cur != 0) HIP_TRY(c, hipMemcpyAsync(buf->pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    st.steps_done = done;
+    st.log_rows = row;
+    return finish(RC_OK);
+}
+
+}  // namespace host
+}  // namespace rc

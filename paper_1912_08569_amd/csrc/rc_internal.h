@@ -153,6 +153,22 @@ struct Grid {
     uint32_t nkeys;      // 8^bits
 };
 
+// One replica of a batch.  Replica r owns the particle slots [off, off + n)
+// with off a multiple of 64, so every wavefront of a particle kernel lies in
+// one replica; the slots from off + n to the next replica's off are unused.
+// Its cells own the keys [key_base, key_base + grid.nkeys) of the batch's key
+// space, so the counting sort keeps every replica inside its slots.
+struct RepDesc {
+    Box box;
+    Grid grid;
+    uint32_t key_base;
+    int off;       // first slot
+    int n;         // particles
+    int shift;     // off minus the replica's first position in the compact key order
+    int tab;       // first entry of its nt*nt table in the batch table array
+    int pad;
+};
+
 __device__ __forceinline__ int cell_coord(float x, float h, float inv_w, int nc) {
     int c = (int)floorf((x + h) * inv_w);
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
@@ -268,13 +284,19 @@ struct StepArgs {
     uint64_t seed;
     uint64_t step;             // step index (added to *step_base if not NULL)
     const unsigned long long* step_base;
-    double* ev_part;           // [nblocks*13] | NULL
+    double* ev_part;           // [nblocks*13] | NULL (row of logical block c at c*13)
     int* status;
     int* blk;                  // [nblocks*3] per-block flag / first-soft / first-hard slots
+    // batches only (tab.e then holds every replica's table, box is unused)
+    const RepDesc* rep;        // [R]
+    const int* chunk_rep;      // [N / 64] replica of each 64-slot chunk
+    const uint64_t* seeds;     // [R] thermostat keys
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
 void step_kernel_info(bool ev, const void** fn);
+hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s);
+void step_batch_kernel_info(const void** fn);
 
 struct ForceArgs {
     const float4* pos;
@@ -288,9 +310,12 @@ struct ForceArgs {
     double* ev_part;   // [nblocks*13] | NULL
     int accumulate;
     int* status;
+    const RepDesc* rep;    // batches only
+    const int* chunk_rep;
 };
 hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s);
 hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s);
+hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s);
 
 struct IntegrateArgs {
     float4* pos;
@@ -390,5 +415,53 @@ struct ParamArgs {
 hipError_t launch_param(const ParamArgs& a, hipStream_t s);
 hipError_t launch_reduce_param(const double* part, int nblocks, int nt, double* out,
                                hipStream_t s);
+
+// ---- batches ---------------------------------------------------------------
+struct CellsArgsB {
+    float4* pos;
+    float4* vel;
+    int4* image;
+    int* rtag;
+    int N;                  // slots
+    const RepDesc* rep;
+    const int* chunk_rep;
+    const uint32_t* key_end;  // [R] key_base + nkeys of each replica (ascending)
+    int R;
+    uint32_t nkeys;         // whole batch
+    int* counts;
+    int* cell_start;
+    int* keys;
+    int* rank;
+    int* order;
+    int* block_sums;
+    float4* tpos;
+    float4* tvel;
+    int4* timage;
+};
+hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s);
+
+struct NlistArgsB {
+    const float4* pos;
+    float4* vel;
+    int N;                  // slots
+    const RepDesc* rep;
+    const int* chunk_rep;
+    Table tab;              // every replica's table
+    const int* cell_start;
+    int k_max;
+    int* nlist;
+    int* nn;
+    int* status;
+    int* block_max;
+};
+hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s);
+
+// per-replica bond counts: part = one u64 per 64-slot chunk, count = [R]
+hipError_t launch_bonds_batch(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                              const RepDesc* rep, const int* chunk_rep, int R, unsigned long long* count,
+                              unsigned long long* part, hipStream_t s);
+// per-replica fixed-order sums of chunk rows: out[r * out_stride + q], q < count
+hipError_t launch_reduce_rows_batch(const double* part, const RepDesc* rep, int R, int first, int count,
+                                    double* out, int out_stride, hipStream_t s);
 
 }  // namespace rc

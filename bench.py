@@ -46,6 +46,12 @@ def parse():
     p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 256 MiB device copy (to scale FETCH/WRITE counters)")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-replica comparison")
+    p.add_argument("--batch-steps", type=int, default=1000)
+    p.add_argument("--seq-steps", type=int, default=200, help="steps of each replica run alone")
+    p.add_argument("--no-tune", action="store_true", help="batched run with the default launch settings")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the forward/adjoint timings")
+    p.add_argument("--only-extras", action="store_true", help="skip the 1M-particle run (debugging)")
     return p.parse_args()
 
 
@@ -54,7 +60,7 @@ def step_kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1912_08569_amd", "csrc")
-    for name in ("k_forces.hip", "rc_internal.h"):
+    for name in ("k_forces.hip", "rc_internal.h", "rc_gather.h"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -86,6 +92,123 @@ def cpu_baseline(sysw, seconds):
                       f"{sysw.N} particles (FP64 brute force, {dt:.1f} s)"}
 
 
+def batch_bench(a):
+    """256 replicas (N ~ logU[500, 20000], lambda ~ U[0, 1.5], density 0.2-0.4, 0-50 % inert WCA) advanced
+    by one launch per step, against the same replicas run one after the other with the single-system
+    engine.  Both log energies, virials and bonds every 100 steps."""
+    import torch
+
+    import workloads as W
+    from paper_1912_08569_amd import Batch, System, tune
+
+    t_gen = time.perf_counter()
+    reps = W.replica_set()
+    R = len(reps)
+    ntot = int(sum(s.N for s in reps))
+    print(f"# replicas: R={R}, {ntot} particles, generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    mk_cfg = lambda S, seed=0: S.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=seed)  # noqa: E731
+    tuned = None
+    r_buff, width, G = 0.3, 2, 16
+    if not a.no_tune:
+        factory = lambda rb: Batch(reps, r_buff=rb, seeds=range(R))  # noqa: E731
+        probe = factory(0.3)
+        cfg = mk_cfg(probe)
+        del probe
+        tuned = tune.autotune(factory, cfg, signature=f"replica_set R={R} N={ntot} seed=1004",
+                              r_buffs=(0.2, 0.3, 0.45), steps=200, warmup=100, cache=None,
+                              log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        r_buff, width, G = tuned["r_buff"], tuned["width"], tuned["graph_steps"]
+    B = Batch(reps, r_buff=r_buff, seeds=range(R))
+    B.set_gather_width(width)
+    cfg = mk_cfg(B)
+    B.run(200, cfg, step0=0, log_period=a.log_period, graph_steps=G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = B.run(a.batch_steps, cfg, step0=200, log_period=a.log_period, graph_steps=G)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    batched = ntot * a.batch_steps / tb
+    print(f"# batched: {a.batch_steps} steps in {tb * 1e3:.1f} ms ({tb / a.batch_steps * 1e6:.2f} us/step), "
+          f"rebuilds {rb.stats.rebuilds}", file=sys.stderr, flush=True)
+    del B
+    torch.cuda.empty_cache()
+    # the same replicas alone, one after the other (default settings of the single-system engine)
+    systems = [System.from_workload(s, r_buff=0.3) for s in reps]
+    cfgs = [mk_cfg(S, seed=r) for r, S in enumerate(systems)]
+    for S, c in zip(systems, cfgs):
+        S.run(20, c, step0=0, log_period=a.log_period)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for S, c in zip(systems, cfgs):
+        S.run(a.seq_steps, c, step0=20, log_period=a.log_period)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    seq = ntot * a.seq_steps / ts
+    print(f"# sequential: {R} x {a.seq_steps} steps in {ts * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    out = {"workload": f"{R} replicas, N ~ logU[500, 20000] ({ntot} particles), lambda ~ U[0, 1.5], "
+                       "density 0.2-0.4, inert fraction 0-0.5, Langevin kT 0.1 dt 0.002, log every 100 steps",
+           "unit": "particle-timesteps/s", "batched": batched, "batched_ms_per_step": tb / a.batch_steps * 1e3,
+           "batched_steps": a.batch_steps, "sequential_plain": seq,
+           "sequential_ms_per_replica_step": ts / (R * a.seq_steps) * 1e3, "sequential_steps": a.seq_steps,
+           "speedup": batched / seq, "settings": {"r_buff": r_buff, "gather_width": width, "graph_steps": G}}
+    if tuned is not None:
+        out["autotune"] = [{k: c[k] for k in ("r_buff", "width", "graph_steps", "us_per_step")}
+                           for c in tuned["candidates"]]
+    del systems
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_bench(a):
+    """Forward vs adjoint on 32768 reactive particles (density 0.25, eps 10, sigma 1, n 10, lambda 1):
+    forces + energy/virial, dE/d(eps, sigma, lambda), and H v for 64 random unit vectors."""
+    import torch
+
+    import workloads as W
+    from paper_1912_08569_amd import System
+
+    s = W.small_reactive(N=32768, density=0.25, seed=1005, table=W.swap_table_single(epsilon=10.0, lam=1.0))
+    S = System.from_workload(s)
+    S.build()
+    rng = np.random.default_rng(7)
+    V = rng.standard_normal((64, s.N, 3))
+    V /= np.linalg.norm(V.reshape(64, -1), axis=1)[:, None, None]
+    vs = []
+    for k in range(64):
+        v = np.zeros((s.N, 4), np.float32)
+        v[:, :3] = V[k]
+        vs.append(S.to_engine_order(v))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3   # us
+
+    from paper_1912_08569_amd import api
+    from paper_1912_08569_amd import _lib as rcl
+    nt = S.ctx.ntypes
+    g = torch.zeros(nt * nt * 3, dtype=torch.float64, device=S.device)
+    hv = torch.empty_like(S.pos)
+    fwd = timed(lambda: api.rc_compute_forces(S.ctx, S.pos, S.nlist, S.nn, S.box, S.force, S.ev,
+                                              rcl.RC_FORCE_GATHER, S.status), 200)
+    fwd_tri = timed(lambda: api.rc_compute_forces(S.ctx, S.pos, S.nlist, S.nn, S.box, S.force, S.ev, 0,
+                                                  S.status), 200)
+    grad = timed(lambda: api.rc_param_grad(S.ctx, S.pos, S.nlist, S.nn, S.box, g), 200)
+    it = iter(range(10 ** 9))
+    hvp = timed(lambda: api.rc_force_hvp(S.ctx, S.pos, S.nlist, S.nn, S.box, vs[next(it) % 64], hv), 640)
+    return {"workload": "32768 reactive particles, density 0.25, eps 10, sigma 1, n 10, lambda 1",
+            "forward_us": fwd, "forward_triplet_kernel_us": fwd_tri, "param_grad_us": grad,
+            "hvp_us_per_vector": hvp, "fwd_plus_param_grad_over_fwd": (fwd + grad) / fwd,
+            "hvp_over_fwd": hvp / fwd, "hvp_64_vectors_ms": hvp * 64 / 1e3}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -99,6 +222,14 @@ def main():
     from paper_1912_08569_amd import _lib as rcl
 
     torch.cuda.set_device(0)
+    if a.only_extras:
+        out = {}
+        if not a.no_adjoint:
+            out["adjoint"] = adjoint_bench(a)
+        if not a.no_batch:
+            out["batch"] = batch_bench(a)
+        print(json.dumps(out), flush=True)
+        return
     t_gen = time.perf_counter()
     sysw = W.assembly_mixture(N=a.N, lam=a.lam, seed=1003, kT=0.05)
     print(f"# generated {sysw.name} in {time.perf_counter() - t_gen:.1f}s, L={sysw.L}", file=sys.stderr,
@@ -182,6 +313,12 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = int(src.numel() * 4)
     out["step_kernel_source_hash"] = step_kernel_source_hash()
+    del S
+    torch.cuda.empty_cache()
+    if not a.no_adjoint:
+        out["adjoint"] = adjoint_bench(a)
+    if not a.no_batch:
+        out["batch"] = batch_bench(a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysw, a.cpu_seconds)
     print(json.dumps(out), flush=True)

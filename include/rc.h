@@ -147,6 +147,11 @@ int rc_version(void);
 int rc_set_lambda(rc_ctx* ctx, const double* lambda /* host [ntypes*ntypes] */);
 /* Neighbour-list radius actually used for type pair (a, b) (host).           */
 int rc_get_rlist(const rc_ctx* ctx, int a, int b, double* r_list);
+/* Gather width of the fused step kernel: the flattened (particle, list slot)
+ * entries each lane of a wavefront evaluates per pass (1, 2 or 4; default 2).
+ * A tuning knob only: every width sums each particle's terms in the same
+ * order, so results are bit-identical.  RC_ERR_ARG for other values.        */
+int rc_set_gather_width(rc_ctx* ctx, int width);
 
 /* ---- status ---------------------------------------------------------------
  * rc_clear_status: zero a status word (async).  rc_read_status: synchronise
@@ -380,6 +385,7 @@ int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn,
  *   RC_ERR_UNSUPPORTED when R > 65535, n_slots >= 2^27 or the batch needs
  *   more than 2^24 cell keys.
  * rc_batch_set_seeds: host [R] thermostat keys (default: cfg.seed + r).
+ * rc_batch_set_gather_width: as rc_set_gather_width, for the batch.
  * rc_batch_compute_forces: force [n_slots*4] as rc_compute_forces with
  *   RC_FORCE_GATHER (overwritten; unused slots untouched); ev = device
  *   [R][7] (E, W) per replica, or NULL.
@@ -398,6 +404,7 @@ int rc_batch_destroy(rc_batch* b);
 const char* rc_batch_last_error(const rc_batch* b);
 int rc_batch_layout(const rc_batch* b, int* n_slots /* host */, int* offsets /* host [R+1] | NULL */);
 int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds /* host [R] */);
+int rc_batch_set_gather_width(rc_batch* b, int width);
 int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes /* host */);
 int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
                          void* stream);

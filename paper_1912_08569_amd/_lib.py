@@ -100,6 +100,7 @@ _SIGS = {
     "rc_last_error": ([_VP], ctypes.c_char_p),
     "rc_set_lambda": ([_VP, ctypes.POINTER(_D)], _I),
     "rc_get_rlist": ([_VP, _I, _I, ctypes.POINTER(_D)], _I),
+    "rc_set_gather_width": ([_VP, _I], _I),
     "rc_clear_status": ([_VP, _VP], _I),
     "rc_read_status": ([_VP, ctypes.POINTER(_I), _VP], _I),
     "rc_cells_workspace_bytes": ([_VP, _I, Box, ctypes.POINTER(ctypes.c_size_t)], _I),
@@ -125,6 +126,7 @@ _SIGS = {
     "rc_batch_last_error": ([_VP], ctypes.c_char_p),
     "rc_batch_layout": ([_VP, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "rc_batch_set_seeds": ([_VP, ctypes.POINTER(_U64)], _I),
+    "rc_batch_set_gather_width": ([_VP, _I], _I),
     "rc_batch_cells_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I),
     "rc_batch_build_cells": ([_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP], _I),
     "rc_batch_build_nlist": ([_VP, _VP, _VP, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),

@@ -124,6 +124,9 @@ class Context:
         check(L.load().rc_set_lambda(self.handle, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
               self.handle)
 
+    def set_gather_width(self, width: int):
+        check(L.load().rc_set_gather_width(self.handle, int(width)), self.handle)
+
     def rlist(self, a: int, b: int) -> float:
         out = ctypes.c_double()
         check(L.load().rc_get_rlist(self.handle, a, b, ctypes.byref(out)), self.handle)
@@ -276,6 +279,9 @@ class BatchContext:
     def set_seeds(self, seeds):
         arr = (ctypes.c_uint64 * self.R)(*[int(x) for x in seeds])
         check(L.load().rc_batch_set_seeds(self.handle, arr), batch=self.handle)
+
+    def set_gather_width(self, width: int):
+        check(L.load().rc_batch_set_gather_width(self.handle, int(width)), batch=self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

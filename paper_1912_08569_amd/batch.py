@@ -129,6 +129,10 @@ class Batch:
         return self.bonds.cpu().numpy().astype(np.int64)
 
     # ---- dynamics -----------------------------------------------------------------------------
+    def set_gather_width(self, width: int):
+        """Entries per lane and pass of the fused step kernel (1, 2, 4): speed only."""
+        self.bc.set_gather_width(width)
+
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
         return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))
 

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(kWave) void k_forces_gather(ForceArgs a) {
     const int packed = live ? a.nn[m] : 0;
     Acc acc = {};
     const OneSystem sys{s_tab, a.tab.nt, box_r};
-    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N, sys, acc);
+    wave_gather<EV, kDefaultWidth>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N, sys,
+                                   acc);
     if (live) {
         float4 f = make_float4(acc.fx, acc.fy, acc.fz, acc.e);
         if (a.accumulate) {
@@ -253,7 +254,7 @@ hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) {
 // box, the coefficient table, the slot bound and the noise key; the noise
 // counter uses the tag relative to the replica's first slot, so a replica
 // draws the same numbers as the same system run on its own.
-template <bool EV, bool BATCH>
+template <bool EV, bool BATCH, int PL>
 __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int nt = a.tab.nt;
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int packed = live ? a.nn[m] : 0;
     const OneSystem sys{s_tab, nt, box};
-    wave_gather<EV>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, sys, acc);
+    wave_gather<EV, PL>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, sys, acc);
     if (live) {
         path_in = vm.w;
         const int tm = ptype(pm.w);
@@ -366,30 +367,35 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     }
 }
 
-hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) {
-    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
-    if (ev)
-        hipLaunchKernelGGL((k_step<true, false>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
-    else
-        hipLaunchKernelGGL((k_step<false, false>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
-    return hipGetLastError();
+// Step kernels by (ev, batch, width); log steps always use the default width.
+template <bool BATCH>
+static const void* step_fn(bool ev, int width) {
+    if (ev) return reinterpret_cast<const void*>(&k_step<true, BATCH, kDefaultWidth>);
+    switch (width) {
+        case 1: return reinterpret_cast<const void*>(&k_step<false, BATCH, 1>);
+        case 4: return reinterpret_cast<const void*>(&k_step<false, BATCH, 4>);
+        default: return reinterpret_cast<const void*>(&k_step<false, BATCH, 2>);
+    }
 }
 
-void step_kernel_info(bool ev, const void** fn) {
-    *fn = ev ? reinterpret_cast<const void*>(&k_step<true, false>)
-             : reinterpret_cast<const void*>(&k_step<false, false>);
+static hipError_t launch_step_any(const void* fn, const StepArgs& a, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    StepArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchKernel(fn, dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), args, shm, s);
 }
+
+hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) {
+    return launch_step_any(step_fn<false>(ev, a.width), a, s);
+}
+
+void step_kernel_info(bool ev, int width, const void** fn) { *fn = step_fn<false>(ev, width); }
 
 hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s) {
-    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
-    if (ev)
-        hipLaunchKernelGGL((k_step<true, true>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
-    else
-        hipLaunchKernelGGL((k_step<false, true>), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), shm, s, a);
-    return hipGetLastError();
+    return launch_step_any(step_fn<true>(ev, a.width), a, s);
 }
 
-void step_batch_kernel_info(const void** fn) { *fn = reinterpret_cast<const void*>(&k_step<false, true>); }
+void step_batch_kernel_info(int width, const void** fn) { *fn = step_fn<true>(false, width); }
 
 // ---------------------------------------------------------------------------
 // bond count: swap pairs i<j with canonical r^2 < r_min^2

@@ -100,6 +100,13 @@ int rc_set_lambda(rc_ctx* c, const double* lambda) {
     return RC_OK;
 }
 
+int rc_set_gather_width(rc_ctx* c, int width) {
+    if (!c) return RC_ERR_ARG;
+    if (width != 1 && width != 2 && width != 4) return fail(c, RC_ERR_ARG, "gather width must be 1, 2 or 4");
+    c->gather_width = width;
+    return RC_OK;
+}
+
 int rc_get_rlist(const rc_ctx* c, int a, int b, double* r_list) {
     if (!c || !r_list || a < 0 || b < 0 || a >= c->nt || b >= c->nt) return RC_ERR_ARG;
     const rc_pair_coeff& p = c->table[a * c->nt + b];
@@ -284,6 +291,7 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
     a.soft = (float)(0.5 * c->r_buff * soft_frac);
     a.seed = cfg->seed;
     a.status = status;
+    a.width = c->gather_width;
     if ((r = ensure_blk(c, nblocks(N, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
     return RC_OK;
@@ -449,7 +457,7 @@ struct PlainOps final : DriveOps {
     }
     const void* graph_fn() override {
         const void* fn;
-        step_kernel_info(false, &fn);
+        step_kernel_info(false, c->gather_width, &fn);
         return fn;
     }
 };

@@ -92,6 +92,7 @@ int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* p
     a.rep = b->d_rep;
     a.chunk_rep = b->d_chunk_rep;
     a.seeds = b->d_seeds;
+    a.width = c->gather_width;
     if ((r = ensure_blk(c, nblocks(b->n_slots, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
     return RC_OK;
@@ -203,6 +204,13 @@ int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds) {
     HIP_TRY(&b->c, hipMemcpy(b->d_seeds, seeds, sizeof(uint64_t) * b->R, hipMemcpyHostToDevice));
     b->seeds.assign(seeds, seeds + b->R);
     b->seeds_set = true;
+    return RC_OK;
+}
+
+int rc_batch_set_gather_width(rc_batch* b, int width) {
+    if (!b) return RC_ERR_ARG;
+    if (width != 1 && width != 2 && width != 4) return fail(&b->c, RC_ERR_ARG, "gather width must be 1, 2 or 4");
+    b->c.gather_width = width;
     return RC_OK;
 }
 
@@ -408,7 +416,7 @@ struct BatchOps final : DriveOps {
     }
     const void* graph_fn() override {
         const void* fn;
-        step_batch_kernel_info(&fn);
+        step_batch_kernel_info(b->c.gather_width, &fn);
         return fn;
     }
 };

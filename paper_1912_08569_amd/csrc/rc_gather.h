@@ -95,9 +95,12 @@ template <bool EV>
 struct Stage {
     static constexpr int n = EV ? 12 : 5;  // fx fy fz w active [e w0..w5]
 };
-constexpr int kPerLane = 2;  // flattened entries each lane evaluates per pass
+// PL = flattened entries each lane evaluates per pass (the gather width).
+// The owner sums its entries in slot order whatever PL is, so every width
+// gives the same bits.
+constexpr int kDefaultWidth = 2;
 
-template <bool EV, class Ctx>
+template <bool EV, int kPerLane, class Ctx>
 __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
                                             const float4* pos, const int* nlist, const int* nn, int k_max,
                                             int N, const Ctx& ctx, Acc& acc) {

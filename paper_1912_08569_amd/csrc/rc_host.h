@@ -31,6 +31,7 @@ struct rc_ctx {
     unsigned long long* d_step_base = nullptr;
     int* d_blk = nullptr;               // per-block status slots of the step kernel
     int blk_cap = 0;                    // slots allocated (blocks)
+    int gather_width = 2;               // flattened list entries per lane and pass of the step kernel
     GraphCache gc;
     std::string err;
 };

@@ -291,12 +291,14 @@ struct StepArgs {
     const RepDesc* rep;        // [R]
     const int* chunk_rep;      // [N / 64] replica of each 64-slot chunk
     const uint64_t* seeds;     // [R] thermostat keys
+    int width;                 // gather width of the non-logging steps: 1, 2 or 4 (read by the launcher)
+    int pad_w;
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
-void step_kernel_info(bool ev, const void** fn);
+void step_kernel_info(bool ev, int width, const void** fn);
 hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s);
-void step_batch_kernel_info(const void** fn);
+void step_batch_kernel_info(int width, const void** fn);
 
 struct ForceArgs {
     const float4* pos;

@@ -130,6 +130,10 @@ class System:
         return g.cpu().numpy().reshape(nt, nt, 3)
 
     # ---- dynamics ------------------------------------------------------------------
+    def set_gather_width(self, width: int):
+        """Entries per lane and pass of the fused step kernel (1, 2, 4): speed only."""
+        self.ctx.set_gather_width(width)
+
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
         return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))
 

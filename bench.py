@@ -109,7 +109,7 @@ def batch_bench(a):
           flush=True)
     mk_cfg = lambda S, seed=0: S.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=seed)  # noqa: E731
     tuned = None
-    r_buff, width, G = 0.3, 2, 16
+    r_buff, form, width, G = 0.3, "walk", 2, 16
     if not a.no_tune:
         factory = lambda rb: Batch(reps, r_buff=rb, seeds=range(R))  # noqa: E731
         probe = factory(0.3)
@@ -118,8 +118,9 @@ def batch_bench(a):
         tuned = tune.autotune(factory, cfg, signature=f"replica_set R={R} N={ntot} seed=1004",
                               r_buffs=(0.2, 0.3, 0.45), steps=200, warmup=100, cache=None,
                               log=lambda m: print("# " + m, file=sys.stderr, flush=True))
-        r_buff, width, G = tuned["r_buff"], tuned["width"], tuned["graph_steps"]
+        r_buff, form, width, G = tuned["r_buff"], tuned["form"], tuned["width"], tuned["graph_steps"]
     B = Batch(reps, r_buff=r_buff, seeds=range(R))
+    B.set_step_form(form)
     B.set_gather_width(width)
     cfg = mk_cfg(B)
     B.run(200, cfg, step0=0, log_period=a.log_period, graph_steps=G)
@@ -151,9 +152,9 @@ def batch_bench(a):
            "unit": "particle-timesteps/s", "batched": batched, "batched_ms_per_step": tb / a.batch_steps * 1e3,
            "batched_steps": a.batch_steps, "sequential_plain": seq,
            "sequential_ms_per_replica_step": ts / (R * a.seq_steps) * 1e3, "sequential_steps": a.seq_steps,
-           "speedup": batched / seq, "settings": {"r_buff": r_buff, "gather_width": width, "graph_steps": G}}
+           "speedup": batched / seq, "settings": {"r_buff": r_buff, "step_form": form, "gather_width": width, "graph_steps": G}}
     if tuned is not None:
-        out["autotune"] = [{k: c[k] for k in ("r_buff", "width", "graph_steps", "us_per_step")}
+        out["autotune"] = [{k: c[k] for k in ("r_buff", "form", "width", "graph_steps", "us_per_step")}
                            for c in tuned["candidates"]]
     del systems
     torch.cuda.empty_cache()

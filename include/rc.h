@@ -152,6 +152,21 @@ int rc_get_rlist(const rc_ctx* ctx, int a, int b, double* r_list);
  * A tuning knob only: every width sums each particle's terms in the same
  * order, so results are bit-identical.  RC_ERR_ARG for other values.        */
 int rc_set_gather_width(rc_ctx* ctx, int width);
+/* How the fused step (and rc_compute_forces with RC_FORCE_SUMS) evaluates
+ * the three-body forces of eq. (3bp):
+ *   RC_FORM_WALK (default): one pass; the part of the force on m that comes
+ *     from triplets centred on a partner j is summed by walking j's list
+ *     (work grows as k^2 per particle; no extra memory).
+ *   RC_FORM_SUMS: two passes.  The first stores S_i = sum of w_ij over i's
+ *     swap partners inside r_cut (w = sqrt(lambda eps) vhat); the second
+ *     gives every (m, j) entry the factor (S_m - w) + (S_j - w), i.e. the
+ *     triplet sum of eq. (3bp) rewritten as (S^2 - sum w^2)/2 per centre
+ *     (linear in k; one float per particle of context-owned scratch).
+ * Both are exact rewritings of the same energy; results differ by rounding
+ * order only.  RC_ERR_ARG for other values.                                 */
+#define RC_FORM_WALK 0
+#define RC_FORM_SUMS 1
+int rc_set_step_form(rc_ctx* ctx, int form);
 
 /* ---- status ---------------------------------------------------------------
  * rc_clear_status: zero a status word (async).  rc_read_status: synchronise
@@ -211,12 +226,15 @@ int rc_build_nlist(rc_ctx* ctx, const float* pos, float* vel /* NULL ok */, int 
  *   RC_FORCE_ACCUMULATE  add into force instead of overwriting it
  *   RC_FORCE_GATHER      atomic-free gather algorithm (each particle sums
  *                        every term that moves it; deterministic)
+ *   RC_FORCE_SUMS        the gather in the two-pass form (see
+ *                        rc_set_step_form; implies RC_FORCE_GATHER)
  * force[i].w receives the per-particle energy (added when accumulating).
  * ev (device, nullable) receives 7 doubles: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
  * with W the configurational virial of eq. (p3) (stress = -(K + W)/V),
  * reduced in FP64 in a fixed order.                                          */
 #define RC_FORCE_ACCUMULATE 1u
 #define RC_FORCE_GATHER     4u
+#define RC_FORCE_SUMS       8u
 int rc_compute_forces(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                       rc_box box, float* force /* [N*4] */, double* ev /* [7] | NULL */,
                       unsigned flags, int* status /* NULL ok */, void* stream);
@@ -385,9 +403,11 @@ int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn,
  *   RC_ERR_UNSUPPORTED when R > 65535, n_slots >= 2^27 or the batch needs
  *   more than 2^24 cell keys.
  * rc_batch_set_seeds: host [R] thermostat keys (default: cfg.seed + r).
- * rc_batch_set_gather_width: as rc_set_gather_width, for the batch.
+ * rc_batch_set_gather_width, rc_batch_set_step_form: as rc_set_gather_width
+ *   and rc_set_step_form, for the batch.
  * rc_batch_compute_forces: force [n_slots*4] as rc_compute_forces with
- *   RC_FORCE_GATHER (overwritten; unused slots untouched); ev = device
+ *   RC_FORCE_GATHER, or RC_FORCE_SUMS when the batch's step form is
+ *   RC_FORM_SUMS (overwritten; unused slots untouched); ev = device
  *   [R][7] (E, W) per replica, or NULL.
  * rc_batch_bond_count: counts = device [R] u64, overwritten.
  * rc_batch_step_fused: one fused step of every replica (modes as
@@ -405,6 +425,7 @@ const char* rc_batch_last_error(const rc_batch* b);
 int rc_batch_layout(const rc_batch* b, int* n_slots /* host */, int* offsets /* host [R+1] | NULL */);
 int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds /* host [R] */);
 int rc_batch_set_gather_width(rc_batch* b, int width);
+int rc_batch_set_step_form(rc_batch* b, int form);
 int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes /* host */);
 int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
                          void* stream);

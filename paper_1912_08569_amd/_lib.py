@@ -30,7 +30,8 @@ RC_MAX_TYPES = 16
 RC_STATUS_WORDS = 8
 RC_ST_FLAGS, RC_ST_KMAX, RC_ST_MAXPATH, RC_ST_FIRST_SOFT, RC_ST_FIRST_HARD = 0, 1, 2, 3, 4
 RC_FLAG_NLIST_OVERFLOW, RC_FLAG_REBUILD, RC_FLAG_NONFINITE, RC_FLAG_LOST, RC_FLAG_STALE = 1, 2, 4, 8, 16
-RC_FORCE_ACCUMULATE, RC_FORCE_GATHER = 1, 4
+RC_FORCE_ACCUMULATE, RC_FORCE_GATHER, RC_FORCE_SUMS = 1, 4, 8
+RC_FORM_WALK, RC_FORM_SUMS = 0, 1
 RC_HALF_FIRST, RC_HALF_SECOND = 0, 1
 RC_STEP_START, RC_STEP_CONT, RC_STEP_FINISH, RC_STEP_OBSERVE = 0, 1, 2, 3
 RC_INTEGRATOR_NVE, RC_INTEGRATOR_LANGEVIN = 0, 1
@@ -101,6 +102,7 @@ _SIGS = {
     "rc_set_lambda": ([_VP, ctypes.POINTER(_D)], _I),
     "rc_get_rlist": ([_VP, _I, _I, ctypes.POINTER(_D)], _I),
     "rc_set_gather_width": ([_VP, _I], _I),
+    "rc_set_step_form": ([_VP, _I], _I),
     "rc_clear_status": ([_VP, _VP], _I),
     "rc_read_status": ([_VP, ctypes.POINTER(_I), _VP], _I),
     "rc_cells_workspace_bytes": ([_VP, _I, Box, ctypes.POINTER(ctypes.c_size_t)], _I),
@@ -127,6 +129,7 @@ _SIGS = {
     "rc_batch_layout": ([_VP, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "rc_batch_set_seeds": ([_VP, ctypes.POINTER(_U64)], _I),
     "rc_batch_set_gather_width": ([_VP, _I], _I),
+    "rc_batch_set_step_form": ([_VP, _I], _I),
     "rc_batch_cells_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I),
     "rc_batch_build_cells": ([_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP], _I),
     "rc_batch_build_nlist": ([_VP, _VP, _VP, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),

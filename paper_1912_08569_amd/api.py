@@ -127,6 +127,10 @@ class Context:
     def set_gather_width(self, width: int):
         check(L.load().rc_set_gather_width(self.handle, int(width)), self.handle)
 
+    def set_step_form(self, form: str):
+        f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS}[form]
+        check(L.load().rc_set_step_form(self.handle, f), self.handle)
+
     def rlist(self, a: int, b: int) -> float:
         out = ctypes.c_double()
         check(L.load().rc_get_rlist(self.handle, a, b, ctypes.byref(out)), self.handle)
@@ -282,6 +286,10 @@ class BatchContext:
 
     def set_gather_width(self, width: int):
         check(L.load().rc_batch_set_gather_width(self.handle, int(width)), batch=self.handle)
+
+    def set_step_form(self, form: str):
+        f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS}[form]
+        check(L.load().rc_batch_set_step_form(self.handle, f), batch=self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

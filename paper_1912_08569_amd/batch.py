@@ -133,6 +133,10 @@ class Batch:
         """Entries per lane and pass of the fused step kernel (1, 2, 4): speed only."""
         self.bc.set_gather_width(width)
 
+    def set_step_form(self, form: str):
+        """"walk" (one pass, partner sums by list walks) or "sums" (two passes): speed only."""
+        self.bc.set_step_form(form)
+
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
         return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))
 

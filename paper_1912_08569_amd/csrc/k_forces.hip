@@ -17,7 +17,7 @@ static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 // ---------------------------------------------------------------------------
 // atomic-free gather force kernel (RC_FORCE_GATHER)
 // ---------------------------------------------------------------------------
-template <bool EV, bool BATCH>
+template <bool EV, bool BATCH, bool SF>
 __global__ __launch_bounds__(kWave) void k_forces_gather(ForceArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int blk = xcd_block(gridDim.x);
@@ -38,8 +38,8 @@ __global__ __launch_bounds__(kWave) void k_forces_gather(ForceArgs a) {
     const int packed = live ? a.nn[m] : 0;
     Acc acc = {};
     const OneSystem sys{s_tab, a.tab.nt, box_r};
-    wave_gather<EV, kDefaultWidth>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N, sys,
-                                   acc);
+    wave_gather<EV, kDefaultWidth, SF>(m - (int)threadIdx.x, live, pm, packed, a.pos, a.nlist, a.nn, a.k_max, a.N,
+                                       sys, acc, a.ssum);
     if (live) {
         float4 f = make_float4(acc.fx, acc.fy, acc.fz, acc.e);
         if (a.accumulate) {
@@ -228,23 +228,64 @@ hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) {
+// First pass of the sums form: S_m of every particle into a.ssum (one thread
+// per particle, one wavefront per block so that a batch chunk names the table).
+template <bool BATCH>
+__global__ __launch_bounds__(kWave) void k_swap_sums(ForceArgs a) {
+    extern __shared__ DevEntry s_tab[];
+    const int blk = xcd_block(gridDim.x);
+    Box box_r;
+    int lim = a.N;
+    if constexpr (BATCH) {
+        const RepDesc& d = a.rep[a.chunk_rep[blk]];
+        box_r = d.box;
+        lim = d.off + d.n;
+        load_table(s_tab, Table{a.tab.e + d.tab, a.tab.nt});
+    } else {
+        box_r = a.box;
+        load_table(s_tab, a.tab);
+    }
+    const int m = blk * kWave + threadIdx.x;
+    if (m >= lim) return;
+    const float4 pm = a.pos[m];
+    a.ssum[m] = swap_sum(m, pm, a.nn[m], a.pos, a.nlist, a.N, s_tab, a.tab.nt, box_r);
+}
+
+void sums_kernel_info(bool batch, const void** fn) {
+    *fn = batch ? reinterpret_cast<const void*>(&k_swap_sums<true>) : reinterpret_cast<const void*>(&k_swap_sums<false>);
+}
+
+static hipError_t launch_sums(const ForceArgs& a, bool batch, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
-    if (a.ev_part)
-        hipLaunchKernelGGL((k_forces_gather<true, false>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+    if (batch)
+        hipLaunchKernelGGL((k_swap_sums<true>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
     else
-        hipLaunchKernelGGL((k_forces_gather<false, false>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+        hipLaunchKernelGGL((k_swap_sums<false>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) {
+template <bool BATCH>
+static hipError_t launch_gather_any(const ForceArgs& a, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
-    if (a.ev_part)
-        hipLaunchKernelGGL((k_forces_gather<true, true>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
-    else
-        hipLaunchKernelGGL((k_forces_gather<false, true>), dim3(nblk(a.N, kWave)), dim3(kWave), shm, s, a);
+    const dim3 g(nblk(a.N, kWave)), b(kWave);
+    if (a.ssum) {
+        hipError_t e = launch_sums(a, BATCH, s);
+        if (e != hipSuccess) return e;
+        if (a.ev_part)
+            hipLaunchKernelGGL((k_forces_gather<true, BATCH, true>), g, b, shm, s, a);
+        else
+            hipLaunchKernelGGL((k_forces_gather<false, BATCH, true>), g, b, shm, s, a);
+    } else {
+        if (a.ev_part)
+            hipLaunchKernelGGL((k_forces_gather<true, BATCH, false>), g, b, shm, s, a);
+        else
+            hipLaunchKernelGGL((k_forces_gather<false, BATCH, false>), g, b, shm, s, a);
+    }
     return hipGetLastError();
 }
+
+hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s) { return launch_gather_any<false>(a, s); }
+hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) { return launch_gather_any<true>(a, s); }
 
 // ---------------------------------------------------------------------------
 // fused MD step: gather forces at x_in, finish the previous step's final half
@@ -254,7 +295,7 @@ hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) {
 // box, the coefficient table, the slot bound and the noise key; the noise
 // counter uses the tag relative to the replica's first slot, so a replica
 // draws the same numbers as the same system run on its own.
-template <bool EV, bool BATCH, int PL>
+template <bool EV, bool BATCH, int PL, bool SF>
 __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int nt = a.tab.nt;
@@ -286,7 +327,8 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int packed = live ? a.nn[m] : 0;
     const OneSystem sys{s_tab, nt, box};
-    wave_gather<EV, PL>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, sys, acc);
+    wave_gather<EV, PL, SF>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, sys, acc,
+                            a.ssum);
     if (live) {
         path_in = vm.w;
         const int tm = ptype(pm.w);
@@ -367,35 +409,60 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     }
 }
 
-// Step kernels by (ev, batch, width); log steps always use the default width.
-template <bool BATCH>
-static const void* step_fn(bool ev, int width) {
-    if (ev) return reinterpret_cast<const void*>(&k_step<true, BATCH, kDefaultWidth>);
+// Step kernels by (ev, batch, width, form); log steps use the default width.
+template <bool BATCH, bool SF>
+static const void* step_fn_form(bool ev, int width) {
+    if (ev) return reinterpret_cast<const void*>(&k_step<true, BATCH, kDefaultWidth, SF>);
     switch (width) {
-        case 1: return reinterpret_cast<const void*>(&k_step<false, BATCH, 1>);
-        case 4: return reinterpret_cast<const void*>(&k_step<false, BATCH, 4>);
-        default: return reinterpret_cast<const void*>(&k_step<false, BATCH, 2>);
+        case 1: return reinterpret_cast<const void*>(&k_step<false, BATCH, 1, SF>);
+        case 4: return reinterpret_cast<const void*>(&k_step<false, BATCH, 4, SF>);
+        default: return reinterpret_cast<const void*>(&k_step<false, BATCH, 2, SF>);
     }
 }
 
-static hipError_t launch_step_any(const void* fn, const StepArgs& a, hipStream_t s) {
+template <bool BATCH>
+static const void* step_fn(bool ev, int width, int form) {
+    return form == RC_FORM_SUMS ? step_fn_form<BATCH, true>(ev, width) : step_fn_form<BATCH, false>(ev, width);
+}
+
+// arguments of the first pass of the sums form for a step reading pos_in
+static ForceArgs sums_args(const StepArgs& a) {
+    ForceArgs f{};
+    f.pos = a.pos_in;
+    f.nlist = a.nlist;
+    f.nn = a.nn;
+    f.N = a.N;
+    f.k_max = a.k_max;
+    f.tab = a.tab;
+    f.box = a.box;
+    f.rep = a.rep;
+    f.chunk_rep = a.chunk_rep;
+    f.ssum = a.ssum;
+    return f;
+}
+
+template <bool BATCH>
+static hipError_t launch_step_any(const StepArgs& a, bool ev, hipStream_t s) {
+    if (a.form == RC_FORM_SUMS) {
+        hipError_t e = launch_sums(sums_args(a), BATCH, s);
+        if (e != hipSuccess) return e;
+    }
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
     StepArgs arg = a;
     void* args[] = {&arg};
-    return hipLaunchKernel(fn, dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), args, shm, s);
+    return hipLaunchKernel(step_fn<BATCH>(ev, a.width, a.form), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock), args,
+                           shm, s);
 }
 
-hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) {
-    return launch_step_any(step_fn<false>(ev, a.width), a, s);
-}
+hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) { return launch_step_any<false>(a, ev, s); }
 
-void step_kernel_info(bool ev, int width, const void** fn) { *fn = step_fn<false>(ev, width); }
+void step_kernel_info(bool ev, int width, int form, const void** fn) { *fn = step_fn<false>(ev, width, form); }
 
-hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s) {
-    return launch_step_any(step_fn<true>(ev, a.width), a, s);
-}
+hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s) { return launch_step_any<true>(a, ev, s); }
 
-void step_batch_kernel_info(int width, const void** fn) { *fn = step_fn<true>(false, width); }
+void step_batch_kernel_info(int width, int form, const void** fn) { *fn = step_fn<true>(false, width, form); }
+
+ForceArgs step_sums_args(const StepArgs& a) { return sums_args(a); }
 
 // ---------------------------------------------------------------------------
 // bond count: swap pairs i<j with canonical r^2 < r_min^2

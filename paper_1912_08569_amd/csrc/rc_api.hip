@@ -71,11 +71,7 @@ int rc_create(rc_ctx** out, int ntypes, const rc_pair_coeff* table, double r_buf
 
 int rc_destroy(rc_ctx* c) {
     if (!c) return RC_ERR_ARG;
-    drop_graphs(c);
-    if (c->d_tab) (void)hipFree(c->d_tab);
-    if (c->d_part) (void)hipFree(c->d_part);
-    if (c->d_step_base) (void)hipFree(c->d_step_base);
-    if (c->d_blk) (void)hipFree(c->d_blk);
+    free_ctx_buffers(c);
     delete c;
     return RC_OK;
 }
@@ -104,6 +100,13 @@ int rc_set_gather_width(rc_ctx* c, int width) {
     if (!c) return RC_ERR_ARG;
     if (width != 1 && width != 2 && width != 4) return fail(c, RC_ERR_ARG, "gather width must be 1, 2 or 4");
     c->gather_width = width;
+    return RC_OK;
+}
+
+int rc_set_step_form(rc_ctx* c, int form) {
+    if (!c) return RC_ERR_ARG;
+    if (form != RC_FORM_WALK && form != RC_FORM_SUMS) return fail(c, RC_ERR_ARG, "unknown step form %d", form);
+    c->step_form = form;
     return RC_OK;
 }
 
@@ -207,10 +210,13 @@ int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* 
     int r = check_common(c, N, pos);
     if (r) return r;
     if (!nlist || !nn || !force) return fail(c, RC_ERR_ARG, "nlist / nn / force are NULL");
-    if (flags & ~(RC_FORCE_ACCUMULATE | RC_FORCE_GATHER)) return fail(c, RC_ERR_ARG, "unknown flags");
+    if (flags & ~(RC_FORCE_ACCUMULATE | RC_FORCE_GATHER | RC_FORCE_SUMS))
+        return fail(c, RC_ERR_ARG, "unknown flags");
     Box b;
     if ((r = make_box(c, box, b))) return r;
-    const bool gather = flags & RC_FORCE_GATHER;
+    const bool sums = flags & RC_FORCE_SUMS;
+    const bool gather = (flags & RC_FORCE_GATHER) || sums;
+    if (sums && (r = ensure_ssum(c, (size_t)N))) return r;
     const int nb = nblocks(N, kWave);   // both force kernels run one wavefront per block
     if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     if ((r = check_list(c, nlist, nn, k_max))) return r;
@@ -226,6 +232,7 @@ int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* 
     a.ev_part = ev ? c->d_part : nullptr;
     a.accumulate = (flags & RC_FORCE_ACCUMULATE) ? 1 : 0;
     a.status = status;
+    a.ssum = sums ? c->d_ssum : nullptr;
     HIP_TRY(c, gather ? launch_forces_gather(a, S(stream)) : launch_forces_triplet(a, S(stream)));
     if (ev && (r = reduce_rows(c, nb, 0, 7, ev, S(stream)))) return r;
     return RC_OK;
@@ -292,6 +299,12 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
     a.seed = cfg->seed;
     a.status = status;
     a.width = c->gather_width;
+    a.form = c->step_form;
+    a.ssum = nullptr;
+    if (a.form == RC_FORM_SUMS) {
+        if ((r = ensure_ssum(c, (size_t)N))) return r;
+        a.ssum = c->d_ssum;
+    }
     if ((r = ensure_blk(c, nblocks(N, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
     return RC_OK;
@@ -457,7 +470,13 @@ struct PlainOps final : DriveOps {
     }
     const void* graph_fn() override {
         const void* fn;
-        step_kernel_info(false, c->gather_width, &fn);
+        step_kernel_info(false, c->gather_width, c->step_form, &fn);
+        return fn;
+    }
+    const void* graph_sums_fn() override {
+        if (c->step_form != RC_FORM_SUMS) return nullptr;
+        const void* fn;
+        sums_kernel_info(false, &fn);
         return fn;
     }
 };

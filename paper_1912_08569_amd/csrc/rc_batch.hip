@@ -30,12 +30,7 @@ struct rc_batch {
 namespace {
 
 void free_batch(rc_batch* b) {
-    rc_ctx* c = &b->c;
-    drop_graphs(c);
-    if (c->d_tab) (void)hipFree(c->d_tab);
-    if (c->d_part) (void)hipFree(c->d_part);
-    if (c->d_step_base) (void)hipFree(c->d_step_base);
-    if (c->d_blk) (void)hipFree(c->d_blk);
+    free_ctx_buffers(&b->c);
     if (b->d_rep) (void)hipFree(b->d_rep);
     if (b->d_chunk_rep) (void)hipFree(b->d_chunk_rep);
     if (b->d_key_end) (void)hipFree(b->d_key_end);
@@ -93,6 +88,12 @@ int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* p
     a.chunk_rep = b->d_chunk_rep;
     a.seeds = b->d_seeds;
     a.width = c->gather_width;
+    a.form = c->step_form;
+    a.ssum = nullptr;
+    if (a.form == RC_FORM_SUMS) {
+        if ((r = ensure_ssum(c, (size_t)b->n_slots))) return r;
+        a.ssum = c->d_ssum;
+    }
     if ((r = ensure_blk(c, nblocks(b->n_slots, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
     return RC_OK;
@@ -214,6 +215,13 @@ int rc_batch_set_gather_width(rc_batch* b, int width) {
     return RC_OK;
 }
 
+int rc_batch_set_step_form(rc_batch* b, int form) {
+    if (!b) return RC_ERR_ARG;
+    if (form != RC_FORM_WALK && form != RC_FORM_SUMS) return fail(&b->c, RC_ERR_ARG, "unknown step form %d", form);
+    b->c.step_form = form;
+    return RC_OK;
+}
+
 int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes) {
     if (!b || !bytes) return RC_ERR_ARG;
     *bytes = cells_layout(b->n_slots, b->nkeys).total;
@@ -300,6 +308,11 @@ int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, con
     a.status = status;
     a.rep = b->d_rep;
     a.chunk_rep = b->d_chunk_rep;
+    a.ssum = nullptr;
+    if (c->step_form == RC_FORM_SUMS) {
+        if ((r = ensure_ssum(c, (size_t)b->n_slots))) return r;
+        a.ssum = c->d_ssum;
+    }
     hipStream_t s = S(stream);
     HIP_TRY(c, launch_forces_gather_batch(a, s));
     if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_rep, b->R, 0, 7, ev, 7, s));
@@ -416,7 +429,13 @@ struct BatchOps final : DriveOps {
     }
     const void* graph_fn() override {
         const void* fn;
-        step_batch_kernel_info(b->c.gather_width, &fn);
+        step_batch_kernel_info(b->c.gather_width, b->c.step_form, &fn);
+        return fn;
+    }
+    const void* graph_sums_fn() override {
+        if (b->c.step_form != RC_FORM_SUMS) return nullptr;
+        const void* fn;
+        sums_kernel_info(true, &fn);
         return fn;
     }
 };

@@ -84,32 +84,42 @@ __device__ __forceinline__ void acc_virial(Acc& a, float c, float dx, float dy, 
 // ---------------------------------------------------------------------------
 // Wavefront-cooperative gather (one wavefront per block).  The 64 lanes own
 // 64 consecutive particles; their (particle, list slot) entries are laid out
-// flat (exclusive scan of the list lengths) and every lane evaluates one entry
-// per pass, so a wave needs about (sum of list lengths)/64 passes instead of
-// one pass per slot of its longest list.  Per-entry contributions are staged
-// in LDS and each owner lane sums its own entries in slot order
-// (deterministic).  Triplets the owner centres are added afterwards by a walk
-// of its swap range, only when it has two or more active swap partners.
+// flat (exclusive scan of the list lengths) and every lane evaluates PL
+// entries per pass, so a wave needs about (sum of list lengths)/(64 PL)
+// passes instead of one pass per slot of its longest list.  Per-entry
+// contributions are staged in LDS and each owner lane sums its own entries in
+// slot order (deterministic, and the same for every PL).
+//
+// Three-body forces, two forms of the same sum (eq. 3bp; the energy of centre
+// c is sum_{a<b} w_ca w_cb = (S_c^2 - sum_a w_ca^2)/2 with S_c = sum_a w_ca):
+//  * walk (SF = false): an entry (m, j) inside r_cut and beyond r_min adds
+//    the term centred on j by walking j's swap range for S_j - w_jm; the
+//    terms centred on m are added afterwards by a walk of m's own swap range
+//    (only for centres with two or more active partners).
+//  * sums (SF = true): S of every particle is precomputed (swap_sums) and an
+//    entry adds both parts at once with the factor (S_m - w) + (S_j - w).
 // ---------------------------------------------------------------------------
-template <bool EV>
+template <bool EV, bool SF>
 struct Stage {
-    static constexpr int n = EV ? 12 : 5;  // fx fy fz w active [e w0..w5]
+    // walk: fx fy fz w active [e w0..w5];  sums: fx fy fz [e w0..w5]
+    static constexpr int n = SF ? (EV ? 10 : 3) : (EV ? 12 : 5);
+    static constexpr int e = SF ? 3 : 5;   // first EV column
 };
 // PL = flattened entries each lane evaluates per pass (the gather width).
-// The owner sums its entries in slot order whatever PL is, so every width
-// gives the same bits.
 constexpr int kDefaultWidth = 2;
 
-template <bool EV, int kPerLane, class Ctx>
+template <bool EV, int kPerLane, bool SF, class Ctx>
 __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
                                             const float4* pos, const int* nlist, const int* nn, int k_max,
-                                            int N, const Ctx& ctx, Acc& acc) {
+                                            int N, const Ctx& ctx, Acc& acc, const float* ssum = nullptr) {
     const int nt = ctx.nt;
-    constexpr int NC = Stage<EV>::n;
+    constexpr int NC = Stage<EV, SF>::n;
+    constexpr int CE = Stage<EV, SF>::e;
     constexpr int W = kPerLane * kWave;  // entries per pass
     __shared__ int s_off[kWave + 1];
     __shared__ int s_ns[kWave];
     __shared__ float4 s_pos[kWave];
+    __shared__ float s_S[SF ? kWave : 1];
     __shared__ float s_c[NC][W];
     const int lane = threadIdx.x;
     const int ns = live ? nn_swap(packed) : 0;
@@ -125,6 +135,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     if (lane == kWave - 1) s_off[kWave] = inc;
     s_ns[lane] = ns;
     s_pos[lane] = pm;
+    if (SF) s_S[lane] = live ? ssum[base_m + lane] : 0.0f;
     __syncthreads();
     const int T = s_off[kWave];
     double S = 0.0;
@@ -133,12 +144,15 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
         // locate and load all entries of this pass first, so their memory
         // latencies overlap (list index, then neighbour position)
         int own[kPerLane], jj[kPerLane];
+        bool sw[kPerLane];
         float4 pj[kPerLane];
+        float sj[kPerLane];
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
             const int e = base + u * kWave + lane;
             own[u] = -1;
             jj[u] = 0;
+            sw[u] = false;
             if (e < T) {
                 int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
                 while (lo < hi) {
@@ -147,13 +161,17 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                     else hi = mid - 1;
                 }
                 const int sl = e - s_off[lo], nso = s_ns[lo];
-                const int slot = sl < nso ? sl : k_max - 1 - (sl - nso);
+                sw[u] = sl < nso;
+                const int slot = sw[u] ? sl : k_max - 1 - (sl - nso);
                 own[u] = lo;
                 jj[u] = nlist[(size_t)slot * N + base_m + lo];
             }
         }
 #pragma unroll
-        for (int u = 0; u < kPerLane; ++u) pj[u] = own[u] >= 0 ? pos[jj[u]] : pm;
+        for (int u = 0; u < kPerLane; ++u) {
+            pj[u] = own[u] >= 0 ? pos[jj[u]] : pm;
+            if (SF) sj[u] = sw[u] ? ssum[jj[u]] : 0.0f;
+        }
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
             float c[NC];
@@ -173,20 +191,34 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                         float phi, g;
                         pair_eval(en, r2, phi, g);
                         float f = g;
-                        if (EV) {
-                            c[5] = 0.5f * phi;
-                            const float h = -0.5f * g;
-                            c[6] = h * dx * dx; c[7] = h * dy * dy; c[8] = h * dz * dz;
-                            c[9] = h * dx * dy; c[10] = h * dx * dz; c[11] = h * dy * dz;
-                        }
+                        float h = -0.5f * g;     // virial weight of d (x) d
+                        float e3 = 0.0f;         // triplet energy share (sums form)
                         if (en.kind == RC_KIND_SWAP) {
                             float uu, u1r;
                             vhat_eval(en, r2d <= en.rmin2, r2, uu, u1r);
-                            c[3] = en.sqrt_lam * uu;
-                            c[4] = 1.0f;
-                            if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
-                                f += en.sqrt_lam * u1r *
-                                     partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt, box);
+                            const float w = en.sqrt_lam * uu;
+                            if (SF) {
+                                const float so = s_S[own[u]] - w;   // S_m - w
+                                if (u1r != 0.0f && en.sqrt_lam != 0.0f) {
+                                    const float k1 = en.sqrt_lam * u1r;
+                                    const float cc = k1 * so;       // terms centred on m
+                                    f += cc + k1 * (sj[u] - w);     // and on j
+                                    h -= cc;
+                                }
+                                e3 = 0.5f * w * so;
+                            } else {
+                                c[3] = w;
+                                c[4] = 1.0f;
+                                if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
+                                    f += en.sqrt_lam * u1r *
+                                         partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt,
+                                                               box);
+                            }
+                        }
+                        if (EV) {
+                            c[CE] = 0.5f * phi + e3;
+                            c[CE + 1] = h * dx * dx; c[CE + 2] = h * dy * dy; c[CE + 3] = h * dz * dz;
+                            c[CE + 4] = h * dx * dy; c[CE + 5] = h * dx * dz; c[CE + 6] = h * dy * dz;
                         }
                         c[0] = f * dx;
                         c[1] = f * dy;
@@ -203,17 +235,19 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
             acc.fx += s_c[0][q];
             acc.fy += s_c[1][q];
             acc.fz += s_c[2][q];
-            S += (double)s_c[3][q];
-            nact += s_c[4][q] != 0.0f;
+            if (!SF) {
+                S += (double)s_c[3][q];
+                nact += s_c[4][q] != 0.0f;
+            }
             if (EV) {
-                acc.e += s_c[5][q];
+                acc.e += s_c[CE][q];
 #pragma unroll
-                for (int w = 0; w < 6; ++w) acc.w[w] += s_c[6 + w][q];
+                for (int w = 0; w < 6; ++w) acc.w[w] += s_c[CE + 1 + w][q];
             }
         }
         __syncthreads();
     }
-    if (live && nact >= 2) {
+    if (!SF && live && nact >= 2) {
         const int m = base_m + lane;
         float prefix = 0.0f;
         walk_list<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, ctx.table(lane), nt, ctx.boxof(lane), -1,
@@ -234,6 +268,33 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                             }
                         });
     }
+}
+
+// First pass of the sums form for one particle m: S_m = sum of w_mj over m's
+// swap range inside r_cut, in slot order (FP32).  Positions of four slots
+// are requested before any is used.
+__device__ __forceinline__ float swap_sum(int m, const float4& pm, int packed, const float4* pos,
+                                          const int* nlist, int N, const DevEntry* tab, int nt, const Box& box) {
+    const int ns = nn_swap(packed);
+    const int tm = ptype(pm.w);
+    float s = 0.0f;
+    for (int b = 0; b < ns; b += 4) {
+        int j[4];
+        float4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) j[u] = (b + u < ns) ? nlist[(size_t)(b + u) * N + m] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = j[u] >= 0 ? pos[j[u]] : pm;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (j[u] < 0) continue;
+            const DevEntry& e = tab[tm * nt + ptype(p[u].w)];
+            double dx, dy, dz;
+            const double r2d = canon_r2(pm, p[u], box, dx, dy, dz);
+            if (r2d < e.rcut2) s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, (float)r2d);
+        }
+    }
+    return s;
 }
 
 // wave-wide sums of NW doubles; lane 0 stores them

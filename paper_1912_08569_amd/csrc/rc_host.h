@@ -32,6 +32,9 @@ struct rc_ctx {
     int* d_blk = nullptr;               // per-block status slots of the step kernel
     int blk_cap = 0;                    // slots allocated (blocks)
     int gather_width = 2;               // flattened list entries per lane and pass of the step kernel
+    int step_form = RC_FORM_WALK;       // RC_FORM_WALK | RC_FORM_SUMS
+    float* d_ssum = nullptr;            // per-particle switching sums of the sums form
+    size_t ssum_cap = 0;                // floats allocated
     GraphCache gc;
     std::string err;
 };
@@ -60,6 +63,8 @@ struct CellsLayout {
 CellsLayout cells_layout(int N, uint32_t nkeys);
 
 int ensure_part(rc_ctx* c, size_t bytes);
+int ensure_ssum(rc_ctx* c, size_t n);   // d_ssum for n particles (drops graphs when it moves)
+void free_ctx_buffers(rc_ctx* c);       // every device buffer the context owns
 int ensure_blk(rc_ctx* c, int nb, hipStream_t s);
 int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin);
 int check_list(rc_ctx* c, const int* nlist, const int* nn, int k_max);
@@ -83,8 +88,10 @@ struct DriveOps {
     virtual hipError_t launch(const StepArgs& a, bool ev) = 0;
     // reduce the partial rows of the last ev launch into log row `row`
     virtual int reduce_ev(int row) = 0;
-    // kernel that the step graphs replay
+    // kernel that the step graphs replay, and the first-pass kernel of the
+    // sums form (NULL for the walk form)
     virtual const void* graph_fn() = 0;
+    virtual const void* graph_sums_fn() = 0;
 };
 
 // Chunked driver: speculative chunks of fused steps (graph replays where no

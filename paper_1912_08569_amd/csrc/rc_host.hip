@@ -90,6 +90,32 @@ int ensure_part(rc_ctx* c, size_t bytes) {
     return RC_OK;
 }
 
+int ensure_ssum(rc_ctx* c, size_t n) {
+    if (c->ssum_cap >= n) return RC_OK;
+    drop_graphs(c);
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->d_ssum) (void)hipFree(c->d_ssum);
+    c->d_ssum = nullptr;
+    c->ssum_cap = 0;
+    HIP_TRY(c, hipMalloc(&c->d_ssum, sizeof(float) * n));
+    c->ssum_cap = n;
+    return RC_OK;
+}
+
+void free_ctx_buffers(rc_ctx* c) {
+    drop_graphs(c);
+    if (c->d_tab) (void)hipFree(c->d_tab);
+    if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_step_base) (void)hipFree(c->d_step_base);
+    if (c->d_blk) (void)hipFree(c->d_blk);
+    if (c->d_ssum) (void)hipFree(c->d_ssum);
+    c->d_tab = nullptr;
+    c->d_part = nullptr;
+    c->d_step_base = nullptr;
+    c->d_blk = nullptr;
+    c->d_ssum = nullptr;
+}
+
 void drop_graphs(rc_ctx* c) {
     for (int p = 0; p < 2; ++p) {
         if (c->gc.exec[p]) (void)hipGraphExecDestroy(c->gc.exec[p]);
@@ -204,12 +230,28 @@ int compile_table(int nt, const rc_pair_coeff* table, double r_buff, DevEntry* o
 // buffers, then one add of G to the device step base; one graph per start
 // parity.  Built with explicit kernel nodes (no capture, no memset nodes).
 // ---------------------------------------------------------------------------
-static int build_graphs(rc_ctx* c, const void* fn, const StepArgs& tmpl, int G) {
+static int add_node(rc_ctx* c, hipGraph_t g, hipGraphNode_t& prev, const void* fn, void** args, int blocks,
+                    int threads, size_t shm) {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = dim3(blocks);
+    kp.blockDim = dim3(threads);
+    kp.sharedMemBytes = (unsigned)shm;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    HIP_TRY(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    prev = node;
+    return RC_OK;
+}
+
+static int build_graphs(rc_ctx* c, const void* fn, const void* sums_fn, const StepArgs& tmpl, int G) {
     drop_graphs(c);
     const void* add_fn;
     add_step_kernel_info(&add_fn);
     const int nb = nblocks(tmpl.N, kStepBlock);
     const size_t shm = sizeof(DevEntry) * c->nt * c->nt;
+    int r;
     for (int p = 0; p < 2; ++p) {
         hipGraph_t g;
         HIP_TRY(c, hipGraphCreate(&g, 0));
@@ -226,31 +268,19 @@ static int build_graphs(rc_ctx* c, const void* fn, const StepArgs& tmpl, int G) 
             a.step = (uint64_t)k;
             a.step_base = c->d_step_base;
             a.ev_part = nullptr;
+            if (sums_fn) {
+                ForceArgs f = step_sums_args(a);
+                void* args[] = {&f};
+                if ((r = add_node(c, g, prev, sums_fn, args, nblocks(tmpl.N, kWave), kWave, shm))) return r;
+            }
             void* args[] = {&a};
-            hipKernelNodeParams kp{};
-            kp.func = const_cast<void*>(fn);
-            kp.gridDim = dim3(nb);
-            kp.blockDim = dim3(kStepBlock);
-            kp.sharedMemBytes = (unsigned)shm;
-            kp.kernelParams = args;
-            kp.extra = nullptr;
-            hipGraphNode_t node;
-            HIP_TRY(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-            prev = node;
+            if ((r = add_node(c, g, prev, fn, args, nb, kStepBlock, shm))) return r;
         }
         {
             unsigned long long* p_base = c->d_step_base;
             unsigned long long inc = (unsigned long long)G;
             void* args[] = {&p_base, &inc};
-            hipKernelNodeParams kp{};
-            kp.func = const_cast<void*>(add_fn);
-            kp.gridDim = dim3(1);
-            kp.blockDim = dim3(1);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = args;
-            kp.extra = nullptr;
-            hipGraphNode_t node;
-            HIP_TRY(c, hipGraphAddKernelNode(&node, g, &prev, 1, &kp));
+            if ((r = add_node(c, g, prev, add_fn, args, 1, 1, 0))) return r;
         }
         HIP_TRY(c, hipGraphInstantiate(&c->gc.exec[p], g, nullptr, nullptr, 0));
     }
@@ -333,7 +363,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         key.pos_out = reinterpret_cast<float4*>(buf->pos_alt);
         const void* fn = ops.graph_fn();
         if (!c->gc.valid || c->gc.steps != G || c->gc.fn != fn || !same_args(c->gc.key, key)) {
-            if ((r = build_graphs(c, fn, key, G))) return finish(r);
+            if ((r = build_graphs(c, fn, ops.graph_sums_fn(), key, G))) return finish(r);
         }
     }
     uint64_t dev_base = ~0ull;   // value *d_step_base will hold once queued work ran

@@ -121,14 +121,14 @@ __device__ __forceinline__ void vhat_eval(const DevEntry& e, bool inside, float 
     float s2 = e.sig2 / r2;
     float q = qpow(s2, e.n);
     float q2 = q * q;
-    u = 4.0f * (q - q2);
+    u = 4.0f * __fmaf_rn(-q, q, q);   // explicit fma: the same bits in every kernel
     u1r = 4.0f * (float)e.n * (2.0f * q2 - q) / r2;
 }
 
 __device__ __forceinline__ float vhat_value(const DevEntry& e, bool inside, float r2) {
     if (inside) return 1.0f;
     float q = qpow(e.sig2 / r2, e.n);
-    return 4.0f * (q - q * q);
+    return 4.0f * __fmaf_rn(-q, q, q);
 }
 
 // --------------------------------------------------------------------------
@@ -292,13 +292,14 @@ struct StepArgs {
     const int* chunk_rep;      // [N / 64] replica of each 64-slot chunk
     const uint64_t* seeds;     // [R] thermostat keys
     int width;                 // gather width of the non-logging steps: 1, 2 or 4 (read by the launcher)
-    int pad_w;
+    int form;                  // RC_FORM_WALK or RC_FORM_SUMS (read by the launcher)
+    float* ssum;               // [N] per-particle switching sums (RC_FORM_SUMS)
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
-void step_kernel_info(bool ev, int width, const void** fn);
+void step_kernel_info(bool ev, int width, int form, const void** fn);
 hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s);
-void step_batch_kernel_info(int width, const void** fn);
+void step_batch_kernel_info(int width, int form, const void** fn);
 
 struct ForceArgs {
     const float4* pos;
@@ -314,10 +315,15 @@ struct ForceArgs {
     int* status;
     const RepDesc* rep;    // batches only
     const int* chunk_rep;
+    float* ssum;           // [N] switching sums: non-NULL selects the two-pass form
 };
 hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s);
 hipError_t launch_forces_gather(const ForceArgs& a, hipStream_t s);
 hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s);
+// first pass of the two-pass form: the kernel that fills ssum (for graphs)
+// and its arguments for a step (positions pos_in)
+void sums_kernel_info(bool batch, const void** fn);
+ForceArgs step_sums_args(const StepArgs& a);
 
 struct IntegrateArgs {
     float4* pos;

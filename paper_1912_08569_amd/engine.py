@@ -98,11 +98,14 @@ class System:
         raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
 
     # ---- single evaluations -----------------------------------------------------
-    def compute_forces(self, gather: bool = False, ev: bool = True):
-        """Forces (N,4: xyz + per-particle energy) and, if ev, [E, W(6)] (float64)."""
+    def compute_forces(self, gather=False, ev: bool = True):
+        """Forces (N,4: xyz + per-particle energy) and, if ev, [E, W(6)] (float64).
+
+        gather: False = triplet kernel, True = gather kernel, "sums" = the
+        gather in the two-pass form."""
         if not self.built:
             self.build()
-        flags = rcl.RC_FORCE_GATHER if gather else 0
+        flags = rcl.RC_FORCE_SUMS if gather == "sums" else (rcl.RC_FORCE_GATHER if gather else 0)
         api.rc_compute_forces(self.ctx, self.pos, self.nlist, self.nn, self.box, self.force,
                               self.ev if ev else None, flags, self.status)
         return self.force, (self.ev[:7] if ev else None)
@@ -133,6 +136,10 @@ class System:
     def set_gather_width(self, width: int):
         """Entries per lane and pass of the fused step kernel (1, 2, 4): speed only."""
         self.ctx.set_gather_width(width)
+
+    def set_step_form(self, form: str):
+        """"walk" (one pass, partner sums by list walks) or "sums" (two passes): speed only."""
+        self.ctx.set_step_form(form)
 
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
         return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))

@@ -1,7 +1,10 @@
 """Autotuner of the MD step's launch configuration.
 
-Three knobs change only the speed of a run, never its physics:
+Four knobs change only the speed of a run, never its physics:
 
+* the step form: "walk" (one pass; partner sums by walking the partner's
+  list) or "sums" (two passes through per-particle switching sums), the
+  same energy written two ways (results differ by rounding order),
 * the gather width of the fused step kernel (flattened list entries each
   lane evaluates per pass: 1, 2 or 4; every width gives the same bits),
 * the steps per replayed graph (graph_steps),
@@ -43,9 +46,10 @@ def _store(path, data):
 
 
 def autotune(factory: Callable[[float], object], cfg, signature: str, r_buffs: Sequence[float],
-             widths: Sequence[int] = (1, 2, 4), graph_steps: Sequence[int] = (8, 16, 32), steps: int = 200,
-             warmup: int = 60, cache: Optional[str] = DEFAULT_CACHE, log=None) -> Dict:
-    """Fastest (r_buff, width, graph_steps) for the workload built by factory.
+             widths: Sequence[int] = (1, 2, 4), graph_steps: Sequence[int] = (16, 32),
+             forms: Sequence[str] = ("walk", "sums"), steps: int = 200, warmup: int = 60,
+             cache: Optional[str] = DEFAULT_CACHE, log=None) -> Dict:
+    """Fastest (r_buff, form, width, graph_steps) for the workload built by factory.
 
     Every candidate runs ``steps`` steps (after ``warmup`` untimed ones per
     r_buff) with the graph-replaying driver; the time per step includes the
@@ -61,7 +65,8 @@ def autotune(factory: Callable[[float], object], cfg, signature: str, r_buffs: S
         obj = factory(float(rb))
         obj.run(warmup, cfg, step0=step0)
         step0 += warmup
-        for w, G in itertools.product(widths, graph_steps):
+        for form, w, G in itertools.product(forms, widths, graph_steps):
+            obj.set_step_form(form)
             obj.set_gather_width(int(w))
             obj.run(2 * int(G), cfg, step0=step0, graph_steps=int(G))   # graphs built, caches warm
             step0 += 2 * int(G)
@@ -71,10 +76,11 @@ def autotune(factory: Callable[[float], object], cfg, signature: str, r_buffs: S
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             step0 += steps
-            results.append({"r_buff": float(rb), "width": int(w), "graph_steps": int(G),
+            results.append({"r_buff": float(rb), "form": form, "width": int(w), "graph_steps": int(G),
                             "us_per_step": dt / steps * 1e6, "rebuilds": int(r.stats.rebuilds)})
             if log:
-                log(f"tune {signature}: r_buff {rb} width {w} graph_steps {G}: {dt / steps * 1e6:.2f} us/step")
+                log(f"tune {signature}: r_buff {rb} {form} width {w} graph_steps {G}: "
+                    f"{dt / steps * 1e6:.2f} us/step")
         del obj
         torch.cuda.empty_cache()
     best = min(results, key=lambda x: x["us_per_step"])

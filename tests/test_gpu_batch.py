@@ -49,9 +49,11 @@ def test_layout_aligns_every_replica_to_a_wavefront():
     assert B.n_slots == B.offsets[-1]
 
 
-def test_batch_forces_match_oracle_per_replica():
+@pytest.mark.parametrize("form", ["walk", "sums"])
+def test_batch_forces_match_oracle_per_replica(form):
     reps = _mixed_replicas()
     B = _batch(reps)
+    B.set_step_form(form)
     F, ev = B.compute_forces()
     bonds = B.bond_count()
     torch.cuda.synchronize()
@@ -67,17 +69,20 @@ def test_batch_forces_match_oracle_per_replica():
         assert int(bonds[r]) == ref["bonds"], f"replica {r}"
 
 
-def test_batch_replica_equals_single_system_bitwise():
+@pytest.mark.parametrize("form", ["walk", "sums"])
+def test_batch_replica_equals_single_system_bitwise(form):
     # wide skin: one list build for the whole run in both, so every sum runs in the same order
     reps = _mixed_replicas()
     seeds = [1000 + 17 * r for r in range(len(reps))]
     B = _batch(reps, r_buff=0.9, seeds=seeds)
+    B.set_step_form(form)
     cfg = B.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=0)
     rb = B.run(40, cfg, step0=3, log_period=10)
     assert rb.stats.rebuilds == 1 and rb.stats.rollbacks == 0
     from paper_1912_08569_amd import System
     for r, s in enumerate(reps):
         S = System.from_workload(s, r_buff=0.9)
+        S.set_step_form(form)
         c1 = S.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=seeds[r])
         rs = S.run(40, c1, step0=3, log_period=10)
         assert rs.stats.rebuilds == 1

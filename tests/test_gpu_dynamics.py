@@ -21,8 +21,9 @@ def _ulp32(x):
     return (np.nextafter(x, np.float32(np.inf)) - x).astype(np.float64)
 
 
-def _one_step_check(s, kind, dt, kT, gamma, seed, step):
+def _one_step_check(s, kind, dt, kT, gamma, seed, step, form="walk"):
     S = _system(s)
+    S.set_step_form(form)
     S.build()
     x0, v0, _, ty = S.state_by_tag()
     cfg = S.integrator(kind=kind, dt=dt, kT=kT, gamma=gamma, seed=seed)
@@ -54,6 +55,48 @@ def test_fused_step_matches_oracle_small(kind):
 def test_fused_step_matches_oracle_mixture():
     s = W.assembly_mixture(N=20000, lam=1.0, seed=1003, kT=0.05)
     _one_step_check(s, "langevin", 0.001, 0.05, 1.0, 2003, 123456789)
+
+
+@pytest.mark.parametrize("lam", [0.3, 1.0])
+def test_fused_step_sums_form_matches_oracle(lam):
+    # dense reactive system (many partners per centre): the two-pass form of the step
+    s = W.small_reactive(N=3000, density=0.5, seed=1010, min_dist=0.85, table=W.swap_table_single(lam=lam))
+    _one_step_check(s, "langevin", 0.002, 0.1, 1.0, 2010, 77, form="sums")
+    _one_step_check(s, "nve", 0.002, 0.0, 0.0, 2010, 78, form="walk")
+
+
+def test_sums_form_graph_and_direct_launches_agree_bitwise():
+    s = W.small_reactive(N=4000, density=0.4, seed=52, table=W.swap_table_single(lam=0.5), kT=0.1)
+    A, B = _system(s), _system(s)
+    A.set_step_form("sums")
+    B.set_step_form("sums")
+    cfg = A.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=9)
+    ra = A.run(300, cfg, step0=5, use_graph=True, log_period=50)
+    rb = B.run(300, cfg, step0=5, use_graph=False, log_period=50)
+    assert ra.stats.rebuilds == rb.stats.rebuilds
+    xa, va, ia, _ = A.state_by_tag()
+    xb, vb, ib, _ = B.state_by_tag()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(ia, ib)
+    assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
+    # the logged state of the last row against the oracle
+    x, _, _, ty = A.state_by_tag()
+    ref = swap_ref.evaluate(x, ty, s.L, s.table)
+    assert int(ra.bonds[-1]) == ref["bonds"]
+    assert abs(ra.ev[-1, 0] - ref["E"]) <= 1e-5 * ref["A_E"]
+
+
+def test_gather_widths_give_identical_trajectories():
+    s = W.small_reactive(N=3000, density=0.35, seed=53, table=W.swap_table_single(lam=0.8), kT=0.1)
+    out = []
+    for w in (1, 2, 4):
+        S = _system(s)
+        S.set_gather_width(w)
+        cfg = S.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=4)
+        r = S.run(200, cfg, log_period=50)
+        out.append((S.state_by_tag(), r.ev))
+    for (st, ev) in out[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(out[0][0], st))
+        assert np.array_equal(out[0][1], ev)
 
 
 def test_fused_step_crossing_the_box():

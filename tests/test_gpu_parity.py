@@ -35,7 +35,7 @@ def _check_all(sysg, s, gather):
     return ref, ef
 
 
-@pytest.mark.parametrize("gather", [False, True])
+@pytest.mark.parametrize("gather", [False, True, "sums"])
 @pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 1.5])
 def test_small_reactive_one_call(lam, gather):
     # N=1000, density 0.2, eps 1, sigma 1, n 10, r_cut 1.5 (the small plain system)
@@ -44,7 +44,7 @@ def test_small_reactive_one_call(lam, gather):
     assert ref["n_pairs"] > 0
 
 
-@pytest.mark.parametrize("gather", [False, True])
+@pytest.mark.parametrize("gather", [False, True, "sums"])
 def test_dense_clusters_many_triplets(gather):
     # a dense lambda < 1 configuration: many centres with 3+ partners
     s = W.small_reactive(N=3000, density=0.55, seed=31, min_dist=0.85, table=W.swap_table_single(lam=0.4))
@@ -52,7 +52,7 @@ def test_dense_clusters_many_triplets(gather):
     assert ref["n_triplets"] > 500
 
 
-@pytest.mark.parametrize("gather", [False, True])
+@pytest.mark.parametrize("gather", [False, True, "sums"])
 @pytest.mark.parametrize("lam", [0.0, 1.0, 1.5])
 def test_assembly_mixture_small(lam, gather):
     s = W.assembly_mixture(N=20000, lam=lam, seed=1003)
@@ -78,6 +78,7 @@ def test_boundary_straddling_pairs():
     sysg = _system(s, r_buff=0.3)
     ref, _ = _check_all(sysg, s, gather=False)
     _check_all(sysg, s, gather=True)
+    _check_all(sysg, s, gather="sums")
     assert ref["n_triplets"] >= 6
 
 

@@ -370,7 +370,18 @@ int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,
  *   unordered entry {a, b} (reported on both (a,b) and (b,a)), FP64, fixed
  *   r_cut.  Device output, overwritten.
  * rc_param_vjp: out[(a*nt+b)*3 + w] = sum_m adj_m . dF_m/dtheta_w{a,b}
- *   (FP64, device), for fitting through trajectories.                        */
+ *   (FP64, device, overwritten; adj is float4 with w ignored), for fitting
+ *   through trajectories: closed-form derivatives of the pair force and of
+ *   the three-body forces of eq. (3bp) written per centre as
+ *   S P - Q (S = sum k u, P = sum k u' D, Q = sum k^2 u u' D, k = sqrt(lambda
+ *   eps), D = rhat . (adj_a - adj_centre)).  At lambda_e = 0 the part of
+ *   d/dlambda_e coupling entry e to other entries is reported as 0 (it is
+ *   unbounded there), as in rc_param_grad.  One thread per centre; FP64
+ *   partial sums per block reduced in a fixed order.
+ * rc_set_table: replace eps, sigma and lambda of the table (host,
+ *   ntypes^2, validated as in rc_create); kinds, exponents and r_cut must
+ *   equal the current ones (RC_ERR_ARG otherwise), so list radii and cell
+ *   grids stay valid.  Takes effect for launches issued after it returns.    */
 int rc_force_hvp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                  rc_box box, const float* v /* [N*4] */, float* hv /* [N*4] */, void* stream);
 int rc_param_grad(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
@@ -378,6 +389,7 @@ int rc_param_grad(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn
 int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                  rc_box box, const float* adj /* [N*4] */, double* out /* [nt*nt*3] */,
                  void* stream);
+int rc_set_table(rc_ctx* ctx, const rc_pair_coeff* table /* host [ntypes*ntypes] */);
 
 /* ---- batches of independent replicas (hot-path step a8) -----------------------
  * A batch holds R independent periodic systems of uneven size, box and

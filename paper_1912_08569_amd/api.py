@@ -21,7 +21,7 @@ __all__ = [
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
-    "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
+    "rc_param_vjp", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
     "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
     "rc_batch_time_fused_steps",
 ]
@@ -126,6 +126,13 @@ class Context:
 
     def set_gather_width(self, width: int):
         check(L.load().rc_set_gather_width(self.handle, int(width)), self.handle)
+
+    def set_table(self, table):
+        """New eps, sigma, lambda (same kinds, exponents and cutoffs)."""
+        nt = self.ntypes
+        arr = (L.PairCoeff * (nt * nt))()
+        _fill_table(arr, 0, table, nt)
+        check(L.load().rc_set_table(self.handle, arr), self.handle)
 
     def set_step_form(self, form: str):
         f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS}[form]
@@ -234,6 +241,12 @@ def rc_force_hvp(ctx: Context, pos, nlist, nn, bx, v, hv, stream=None):
     check(L.load().rc_force_hvp(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(v),
                                 _ptr(hv),
                                 _stream(stream)), ctx.handle)
+
+
+def rc_param_vjp(ctx: Context, pos, nlist, nn, bx, adj, out, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_param_vjp(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(adj),
+                                _ptr(out), _stream(stream)), ctx.handle)
 
 
 def rc_param_grad(ctx: Context, pos, nlist, nn, bx, grad, stream=None):

@@ -216,6 +216,129 @@ __global__ __launch_bounds__(kBlock) void k_param_grad(ParamArgs a) {
     for (int q = threadIdx.x; q < ne * 3; q += blockDim.x) a.part[(size_t)blockIdx.x * ne * 3 + q] = s_acc[q];
 }
 
+// ---------------------------------------------------------------------------
+// Force-parameter VJP: out[e][w] = sum_m a_m . dF_m / dtheta_w(e), theta =
+// (eps, sigma, lambda) of the unordered entry e.  With D = rhat . (a_j - a_m)
+// the work of the adjoint field on a term:
+//  pair (half per list direction):  a . F = -phi'(r) D, so
+//     d/deps = -(phi'/eps) D,  d/dsigma = -4 eps n^2 (q - 4 q^2) / (sigma r) D
+//  triplets of centre m (swap partners a inside r_cut, k_a = sqrt(lambda eps)
+//  of the edge, u = vhat, u' = du/dr, D_a = rhat_a . (a_a - a_m)):
+//     a . F = -T,  T = sum_{a != b} k_a k_b u_b u'_a D_a = S P - Q,
+//     S = sum k u,  P = sum k u' D,  Q = sum k^2 u u' D.
+//  Per partner entry e (sums restricted to partners of entry e carry the
+//  subscript e; U, V, X are the unweighted sum u, sum u' D, sum u u' D):
+//     dT/dlambda_e = eps_e (U V - X) + [P_e (S - S_e) + (P - P_e) S_e] / (2 lambda_e)
+//     dT/deps_e    = lambda_e (U V - X) + [P_e (S - S_e) + (P - P_e) S_e] / (2 eps_e)
+//     dT/dsigma_e  = A P - B + C S - G,  A = sum_e k u_s,  B = sum_e k^2 u_s u' D,
+//                    C = sum_e k u'_s D,  G = sum_e k^2 u'_s D u
+//  with u_s = du/dsigma = 4 n (q - 2q^2)/sigma and u'_s = 4 n^2 (4q^2 - q)/(sigma r)
+//  beyond r_min (all zero inside, where u = 1).  The cross term of
+//  dT/dlambda_e is taken as 0 when lambda_e = 0 (its derivative is unbounded
+//  there), as in the energy gradient.
+// ---------------------------------------------------------------------------
+struct SwapTerms {  // u, u', du/dsigma, du'/dsigma of one swap edge
+    float u, u1, us, u1s;
+};
+
+__device__ __forceinline__ SwapTerms swap_terms(const DevEntry& e, bool inside, float r2, float r) {
+    SwapTerms t{1.0f, 0.0f, 0.0f, 0.0f};
+    if (inside) return t;
+    const float q = qpow(e.sig2 / r2, e.n);
+    const float q2 = q * q, n = (float)e.n;
+    t.u = 4.0f * (q - q2);
+    t.u1 = 4.0f * n * (2.0f * q2 - q) / r;
+    t.us = 4.0f * n * (q - 2.0f * q2) / e.sigma;
+    t.u1s = 4.0f * n * n * (4.0f * q2 - q) / (e.sigma * r);
+    return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_param_vjp(ParamArgs a) {
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    const int nt = a.tab.nt, ne = nt * nt;
+    DevEntry* s_tab = reinterpret_cast<DevEntry*>(s_raw);
+    double* s_acc = reinterpret_cast<double*>(s_raw + sizeof(DevEntry) * ne);
+    for (int q = threadIdx.x; q < ne * 3; q += blockDim.x) s_acc[q] = 0.0;
+    load_table_adj(s_tab, a.tab);
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < a.N) {
+        const float4 pm = a.pos[m];
+        const float4 am = a.adj[m];
+        const int tm = ptype(pm.w);
+        const int packed = a.nn[m];
+        const int ns = nn_swap(packed), cnt = ns + nn_other(packed);
+        // pass 0: pair terms (every entry) and the totals S, P over the swap partners
+        double S = 0.0, P = 0.0;
+        unsigned present = 0u;   // partner types met in the swap range
+        for (int s = 0; s < cnt; ++s) {
+            const int slot = s < ns ? s : a.k_max - 1 - (s - ns);
+            const int j = a.nlist[(size_t)slot * a.N + m];
+            const float4 pj = a.pos[j];
+            const int tj = ptype(pj.w);
+            const DevEntry& e = s_tab[tm * nt + tj];
+            if (e.kind == RC_KIND_NONE) continue;
+            double dx, dy, dz;
+            const double r2d = canon_r2(pm, pj, a.box, dx, dy, dz);
+            if (!(r2d < e.rcut2)) continue;
+            const float r2 = (float)r2d, r = sqrtf(r2), ir = 1.0f / r;
+            const float4 aj = a.adj[j];
+            const float D = ((float)dx * (aj.x - am.x) + (float)dy * (aj.y - am.y) + (float)dz * (aj.z - am.z)) * ir;
+            const float q = qpow(e.sig2 / r2, e.n), q2 = q * q, n = (float)e.n;
+            const float d1 = 4.0f * e.eps * n * (q - 2.0f * q2) * ir;
+            const float d1s = 4.0f * e.eps * n * n * (q - 4.0f * q2) / (e.sigma * r);
+            const int key = (tm < tj ? tm * nt + tj : tj * nt + tm) * 3;
+            atomicAdd(&s_acc[key + 0], -0.5 * (double)(d1 / e.eps * D));
+            atomicAdd(&s_acc[key + 1], -0.5 * (double)(d1s * D));
+            if (e.kind == RC_KIND_SWAP) {
+                const SwapTerms t = swap_terms(e, r2d <= e.rmin2, r2, r);
+                S += (double)(e.sqrt_lam * t.u);
+                P += (double)(e.sqrt_lam * t.u1 * D);
+                present |= 1u << tj;
+            }
+        }
+        // pass 1: per partner entry, the restricted sums of the swap range
+        for (int te = 0; te < nt; ++te) {
+            if (!(present & (1u << te))) continue;
+            const DevEntry& ee = s_tab[tm * nt + te];
+            double U = 0, V = 0, X = 0, Se = 0, Pe = 0, A = 0, B = 0, C = 0, G = 0;
+            for (int s = 0; s < ns; ++s) {
+                const int j = a.nlist[(size_t)s * a.N + m];
+                const float4 pj = a.pos[j];
+                if (ptype(pj.w) != te) continue;
+                double dx, dy, dz;
+                const double r2d = canon_r2(pm, pj, a.box, dx, dy, dz);
+                if (!(r2d < ee.rcut2)) continue;
+                const float r2 = (float)r2d, r = sqrtf(r2);
+                const float4 aj = a.adj[j];
+                const float D = ((float)dx * (aj.x - am.x) + (float)dy * (aj.y - am.y) + (float)dz * (aj.z - am.z)) / r;
+                const SwapTerms t = swap_terms(ee, r2d <= ee.rmin2, r2, r);
+                const double k = (double)ee.sqrt_lam, k2 = k * k;
+                U += t.u;
+                V += (double)t.u1 * D;
+                X += (double)t.u * t.u1 * D;
+                Se += k * t.u;
+                Pe += k * t.u1 * D;
+                A += k * t.us;
+                B += k2 * t.us * t.u1 * D;
+                C += k * t.u1s * D;
+                G += k2 * t.u1s * D * t.u;
+            }
+            const double same = U * V - X;
+            const double cross = Pe * (S - Se) + (P - Pe) * Se;
+            const double lam = (double)ee.lam, eps = (double)ee.eps;
+            const double dl = eps * same + (lam > 0.0 ? cross / (2.0 * lam) : 0.0);
+            const double de = lam * same + cross / (2.0 * eps);
+            const double ds = A * P - B + C * S - G;
+            const int key = (tm < te ? tm * nt + te : te * nt + tm) * 3;
+            atomicAdd(&s_acc[key + 0], -de);
+            atomicAdd(&s_acc[key + 1], -ds);
+            atomicAdd(&s_acc[key + 2], -dl);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ne * 3; q += blockDim.x) a.part[(size_t)blockIdx.x * ne * 3 + q] = s_acc[q];
+}
+
 __global__ __launch_bounds__(kBlock) void k_reduce_param(const double* __restrict__ part, int nblocks,
                                                         int nt, double* __restrict__ out) {
     // one block per output value (upper-triangle key), mirrored to both entries
@@ -244,6 +367,13 @@ hipError_t launch_param(const ParamArgs& a, hipStream_t s) {
     const int ne = a.tab.nt * a.tab.nt;
     const size_t shm = sizeof(DevEntry) * ne + sizeof(double) * ne * 3;
     hipLaunchKernelGGL(k_param_grad, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_param_vjp(const ParamArgs& a, hipStream_t s) {
+    const int ne = a.tab.nt * a.tab.nt;
+    const size_t shm = sizeof(DevEntry) * ne + sizeof(double) * ne * 3;
+    hipLaunchKernelGGL(k_param_vjp, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
     return hipGetLastError();
 }
 

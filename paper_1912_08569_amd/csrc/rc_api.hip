@@ -96,6 +96,27 @@ int rc_set_lambda(rc_ctx* c, const double* lambda) {
     return RC_OK;
 }
 
+int rc_set_table(rc_ctx* c, const rc_pair_coeff* table) {
+    if (!c || !table) return RC_ERR_ARG;
+    const int nt = c->nt;
+    for (int q = 0; q < nt * nt; ++q) {
+        const rc_pair_coeff& o = c->table[q];
+        if (table[q].kind != o.kind || table[q].n != o.n || table[q].r_cut != o.r_cut)
+            return fail(c, RC_ERR_ARG, "rc_set_table: entry %d changes kind, n or r_cut", q);
+    }
+    std::vector<DevEntry> tab(nt * nt);
+    double rl = 0.0;
+    std::string why;
+    if (compile_table(nt, table, c->r_buff, tab.data(), &rl, &why) != RC_OK)
+        return fail(c, RC_ERR_ARG, "rc_set_table: %s", why.c_str());
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(c->d_tab, tab.data(), sizeof(DevEntry) * nt * nt, hipMemcpyHostToDevice));
+    c->table.assign(table, table + nt * nt);
+    c->host_tab = tab;
+    drop_graphs(c);
+    return RC_OK;
+}
+
 int rc_set_gather_width(rc_ctx* c, int width) {
     if (!c) return RC_ERR_ARG;
     if (width != 1 && width != 2 && width != 4) return fail(c, RC_ERR_ARG, "gather width must be 1, 2 or 4");
@@ -434,8 +455,31 @@ int rc_param_grad(rc_ctx* c, const float* pos, const int* nlist, const int* nn, 
     return RC_OK;
 }
 
-int rc_param_vjp(rc_ctx* c, const float*, const int*, const int*, int, int, rc_box, const float*, double*, void*) {
-    return fail(c, RC_ERR_UNSUPPORTED, "rc_param_vjp is not available in this build");
+int rc_param_vjp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
+                 const float* adj, double* out, void* stream) {
+    int r = check_common(c, N, pos);
+    if (r) return r;
+    if (!nlist || !nn || !adj || !out) return fail(c, RC_ERR_ARG, "nlist / nn / adj / out are NULL");
+    if (reinterpret_cast<uintptr_t>(adj) & 15) return fail(c, RC_ERR_ARG, "adj not 16-byte aligned");
+    Box b;
+    if ((r = make_box(c, box, b))) return r;
+    const int nb = nblocks(N, kBlock);
+    const int nv = c->nt * c->nt * 3;
+    if ((r = ensure_part(c, sizeof(double) * (size_t)nv * nb))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    ParamArgs a{};
+    a.pos = reinterpret_cast<const float4*>(pos);
+    a.nlist = nlist;
+    a.nn = nn;
+    a.k_max = k_max;
+    a.N = N;
+    a.tab = dev_table(c);
+    a.box = b;
+    a.adj = reinterpret_cast<const float4*>(adj);
+    a.part = c->d_part;
+    HIP_TRY(c, launch_param_vjp(a, S(stream)));
+    HIP_TRY(c, launch_reduce_param(c->d_part, nb, c->nt, out, S(stream)));
+    return RC_OK;
 }
 
 // ============================================================================

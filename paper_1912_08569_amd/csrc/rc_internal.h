@@ -421,6 +421,7 @@ struct ParamArgs {
     double* part;          // [nblocks * nt*nt*3]
 };
 hipError_t launch_param(const ParamArgs& a, hipStream_t s);
+hipError_t launch_param_vjp(const ParamArgs& a, hipStream_t s);
 hipError_t launch_reduce_param(const double* part, int nblocks, int nt, double* out,
                                hipStream_t s);
 

@@ -132,6 +132,20 @@ class System:
         api.rc_param_grad(self.ctx, self.pos, self.nlist, self.nn, self.box, g)
         return g.cpu().numpy().reshape(nt, nt, 3)
 
+    def param_vjp(self, adj: torch.Tensor) -> np.ndarray:
+        """sum_m adj_m . dF_m/dtheta for theta = (eps, sigma, lambda) of every entry, adj (N,4) in engine order."""
+        if not self.built:
+            self.build()
+        nt = self.ctx.ntypes
+        g = torch.zeros(nt * nt * 3, dtype=torch.float64, device=self.device)
+        api.rc_param_vjp(self.ctx, self.pos, self.nlist, self.nn, self.box, adj.contiguous(), g)
+        return g.cpu().numpy().reshape(nt, nt, 3)
+
+    def set_table(self, table):
+        """Replace eps, sigma, lambda (kinds, exponents and cutoffs unchanged)."""
+        self.ctx.set_table(table)
+        self.table = table
+
     # ---- dynamics ------------------------------------------------------------------
     def set_gather_width(self, width: int):
         """Entries per lane and pass of the fused step kernel (1, 2, 4): speed only."""

@@ -99,3 +99,67 @@ def test_param_grad_identities_on_gpu():
     ref = swap_ref.evaluate(x, ty, s.L, s.table)
     assert g[2] == pytest.approx(ref["E3"] / 1.3, rel=1e-5)
     assert g[0] == pytest.approx(ref["E"] / 2.0, rel=1e-5, abs=1e-5 * ref["A_E"])
+
+
+@pytest.mark.parametrize("lam", [0.4, 1.0, 1.5])
+def test_param_vjp_mixture_matches_force_differences(lam):
+    # two swap entries and a WCA entry, dense enough for many triplets
+    tab = W.PairTable.empty(2)
+    tab.set(0, 0, W.KIND_SWAP, 1.3, 1.0, 10, 1.5, lam)
+    tab.set(0, 1, W.KIND_WCA, 1.0, 0.9, 6)
+    tab.set(1, 1, W.KIND_SWAP, 2.0, 0.8, 8, 1.2, 0.7 * lam)
+    rng = np.random.default_rng(66)
+    L = float(np.float32(9.0))
+    pos, types = W.rsa_positions(rng, L, [250, 150], np.full((2, 2), 0.9))
+    s = W.System(pos=pos, types=types, L=L, table=tab, mass=np.ones(2), vel=np.zeros((400, 3), np.float32))
+    S = _system(s)
+    S.build()
+    x, _, _, ty = S.state_by_tag()
+    adj = rng.standard_normal((s.N, 3))
+    a4 = np.zeros((s.N, 4), np.float32)
+    a4[:, :3] = adj
+    got = S.param_vjp(S.to_engine_order(a4))
+    ref = adjoint_ref.force_param_vjp(x, ty, s.L, tab, a4[:, :3].astype(np.float64))
+    # FP32 terms summed with random-sign adjoints: relative accuracy ~1e-6 times the
+    # cancellation of the sum; 1e-3 of the largest value of each parameter kind
+    for w in range(3):
+        err = np.abs(got[:, :, w] - ref[:, :, w]).max()
+        assert err <= 1e-3 * np.abs(ref[:, :, w]).max(), (w, got[:, :, w], ref[:, :, w])
+    assert np.abs(ref[:, :, 2]).max() > 0.0   # three-body part present
+
+
+def test_param_vjp_lambda_zero_single_entry():
+    # at lambda = 0 the three-body force is linear in lambda: a . dF/dlambda = a . (F(1) - F(0))
+    from oracle import swap_ref
+    s = W.small_reactive(N=1500, density=0.4, seed=67, table=W.swap_table_single(lam=0.0))
+    S = _system(s)
+    S.build()
+    x, _, _, ty = S.state_by_tag()
+    rng = np.random.default_rng(5)
+    a4 = np.zeros((s.N, 4), np.float32)
+    a4[:, :3] = rng.standard_normal((s.N, 3))
+    got = S.param_vjp(S.to_engine_order(a4))[0, 0]
+    t1 = s.table.copy()
+    t1.lam[:] = 1.0
+    F0 = swap_ref.evaluate(x, ty, s.L, s.table, scales=False)["F"]
+    F1 = swap_ref.evaluate(x, ty, s.L, t1, scales=False)["F"]
+    adj = a4[:, :3].astype(np.float64)
+    r3, r0 = np.sum(adj * (F1 - F0)), np.sum(adj * F0) / 1.0
+    assert abs(got[2] - r3) <= 1e-3 * abs(r3)
+    assert abs(got[0] - r0) <= 1e-3 * abs(r0)
+
+
+def test_param_vjp_differentiation_workload_eps_identity():
+    # 32768 reactive particles, eps 10: a . dF/deps = a . F / eps for one entry
+    s = W.small_reactive(N=32768, density=0.25, seed=1005, table=W.swap_table_single(epsilon=10.0, lam=1.0))
+    S = _system(s)
+    S.build()
+    rng = np.random.default_rng(6)
+    a4 = np.zeros((s.N, 4), np.float32)
+    a4[:, :3] = rng.standard_normal((s.N, 3))
+    ae = S.to_engine_order(a4)
+    got = S.param_vjp(ae)[0, 0]
+    F, _ = S.compute_forces(gather=True)
+    torch.cuda.synchronize()
+    aF = float((ae[:, :3].double() * F[:, :3].double()).sum())
+    assert abs(got[0] - aF / 10.0) <= 1e-3 * abs(aF / 10.0)

@@ -476,6 +476,24 @@ def test_param_grad_identities_single_entry():
     assert g[1] == pytest.approx(out["W"][:3].sum() / 1.0, rel=1e-9)
 
 
+def test_force_param_vjp_identities_single_entry():
+    # one swap entry: F is linear in eps (pair and three-body parts alike) and the
+    # three-body force is linear in lambda, so a . dF/deps = a . F / eps and
+    # a . dF/dlambda = a . (F(lambda) - F(0)) / lambda
+    s = W.small_reactive(N=60, density=0.35, seed=9, table=W.swap_table_single(epsilon=2.0, lam=1.3))
+    rng = np.random.default_rng(4)
+    adj = rng.standard_normal((s.N, 3))
+    x = s.pos.astype(float)
+    out = adjoint_ref.force_param_vjp(x, s.types, s.L, s.table, adj)[0, 0]
+    F = ev(x, s.types, s.L, s.table)["F"]
+    t0 = s.table.copy()
+    t0.lam[:] = 0.0
+    F0 = ev(x, s.types, s.L, t0)["F"]
+    assert out[0] == pytest.approx(np.sum(adj * F) / 2.0, rel=1e-7)
+    assert out[2] == pytest.approx(np.sum(adj * (F - F0)) / 1.3, rel=1e-7)
+    assert abs(np.sum(adj * (F - F0))) > 1e-3 * abs(np.sum(adj * F))   # the three-body part is present
+
+
 # --------------------------------------------------------------------------
 # the C brute force and the numpy evaluator agree
 # --------------------------------------------------------------------------

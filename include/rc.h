@@ -390,6 +390,13 @@ int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn,
                  rc_box box, const float* adj /* [N*4] */, double* out /* [nt*nt*3] */,
                  void* stream);
 int rc_set_table(rc_ctx* ctx, const rc_pair_coeff* table /* host [ntypes*ntypes] */);
+/* Soft bond count: value (device double, overwritten) = sum over swap pairs
+ * i<j inside r_cut of vhat(r_ij) (eq. pot: 1 for a bonded pair, r <= r_min,
+ * falling to 0 at r_cut), so it equals rc_bond_count whenever no swap pair
+ * sits between r_min and r_cut; grad (device float4 [N], w = 0, nullable)
+ * receives dvalue/dx.  A differentiable bond observable for fits.          */
+int rc_soft_bonds(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
+                  rc_box box, double* value /* [1] */, float* grad /* [N*4] | NULL */, void* stream);
 
 /* ---- batches of independent replicas (hot-path step a8) -----------------------
  * A batch holds R independent periodic systems of uneven size, box and

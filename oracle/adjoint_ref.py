@@ -21,9 +21,13 @@ eq. pot, eq. 3bp); its derivatives are the plain calculus of those terms.
 * ``force_param_vjp``: a . dF/d(theta) for theta = (eps, sigma, lambda) of
   every entry, by central differences of ``swap_ref`` forces in the
   parameters (used only on small systems).
+* ``soft_bonds``: B = sum over interacting swap pairs of vhat(r) (eq. pot)
+  and dB/dx_m = -sum_j vhat'(r_mj) (x_j - x_m)/r_mj.
 
 Parity status: pinned by central finite differences of ``swap_ref`` (forces
-for ``hvp``, energy for ``param_grad``) and by the identities
+for ``hvp``, energy for ``param_grad``, ``soft_bonds`` for its own gradient,
+and ``soft_bonds`` equals ``swap_ref.bond_count`` when every swap pair inside
+r_cut is bonded) and by the identities
 dE/dlambda = E3/lambda and dE/deps = (E2_swap + E3)/eps of a one-entry system.
 """
 from __future__ import annotations
@@ -197,3 +201,16 @@ def force_param_vjp(pos, types, L, table, adj, h=1e-6):
                 out[a, b, w] = val
                 out[b, a, w] = val
     return out
+
+
+def soft_bonds(pos, types, L, table):
+    """(B, dB/dx [N,3]) with B = sum over interacting swap pairs of vhat(r)."""
+    P = swap_ref.interacting_pairs(pos, types, L, table)
+    E = swap_ref.directed_swap_edges(P)
+    N = P["N"]
+    B = 0.5 * float(np.sum(E["u"]))
+    g = np.zeros((N, 3))
+    if E["c"].size:
+        # centre c: dvhat(r_cp)/dx_c = -vhat'(r) rhat_cp
+        np.add.at(g, E["c"], -(E["u1"] / E["r"])[:, None] * E["d"])
+    return B, g

@@ -122,6 +122,7 @@ _SIGS = {
     "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
     "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
     "rc_set_table": ([_VP, ctypes.POINTER(PairCoeff)], _I),
+    "rc_soft_bonds": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
     # batches
     "rc_batch_create": ([ctypes.POINTER(_VP), _I, _I, ctypes.POINTER(PairCoeff), ctypes.POINTER(_I),
                          ctypes.POINTER(Box), _D], _I),

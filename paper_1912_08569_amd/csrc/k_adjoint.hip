@@ -370,6 +370,75 @@ hipError_t launch_param(const ParamArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Soft bond count B = sum over swap pairs i<j inside r_cut of vhat(r_ij)
+// (1 for a bonded pair, r <= r_min, decaying to 0 at r_cut; eq. pot) and its
+// gradient dB/dx_m = - sum_j vhat'(r_mj) rhat_mj over m's swap partners.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_soft_bonds(const float4* __restrict__ pos,
+                                                      const int* __restrict__ nlist, const int* __restrict__ nn,
+                                                      int k_max, int N, Table tab, Box box,
+                                                      double* __restrict__ part, float4* __restrict__ grad) {
+    extern __shared__ DevEntry s_tab[];
+    __shared__ double s_w[kBlock / kWave];
+    load_table_adj(s_tab, tab);
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    double b = 0.0;
+    if (m < N) {
+        const float4 pm = pos[m];
+        const int tm = ptype(pm.w);
+        const int ns = nn_swap(nn[m]);
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        for (int s = 0; s < ns; ++s) {
+            const int j = nlist[(size_t)s * N + m];
+            const float4 pj = pos[j];
+            const DevEntry& e = s_tab[tm * tab.nt + ptype(pj.w)];
+            if (e.kind != RC_KIND_SWAP) continue;
+            double dx, dy, dz;
+            const double r2d = canon_r2(pm, pj, box, dx, dy, dz);
+            if (!(r2d < e.rcut2)) continue;
+            float u, u1r;
+            vhat_eval(e, r2d <= e.rmin2, (float)r2d, u, u1r);
+            b += 0.5 * (double)u;
+            gx -= u1r * (float)dx;
+            gy -= u1r * (float)dy;
+            gz -= u1r * (float)dz;
+        }
+        if (grad) grad[m] = make_float4(gx, gy, gz, 0.0f);
+    }
+    b = wave_sum(b);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_doubles(const double* __restrict__ part, int nb,
+                                                       double* __restrict__ out) {
+    __shared__ double red[kBlock];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_soft_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                             Box box, double* part, double* value, float4* grad, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * tab.nt * tab.nt;
+    const int nb = nblk(N, kBlock);
+    hipLaunchKernelGGL(k_soft_bonds, dim3(nb), dim3(kBlock), shm, s, pos, nlist, nn, k_max, N, tab, box, part, grad);
+    hipLaunchKernelGGL(k_sum_doubles, dim3(1), dim3(kBlock), 0, s, part, nb, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_param_vjp(const ParamArgs& a, hipStream_t s) {
     const int ne = a.tab.nt * a.tab.nt;
     const size_t shm = sizeof(DevEntry) * ne + sizeof(double) * ne * 3;

@@ -96,6 +96,21 @@ int rc_set_lambda(rc_ctx* c, const double* lambda) {
     return RC_OK;
 }
 
+int rc_soft_bonds(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
+                  double* value, float* grad, void* stream) {
+    int r = check_common(c, N, pos);
+    if (r) return r;
+    if (!value) return fail(c, RC_ERR_ARG, "value is NULL");
+    if (grad && (reinterpret_cast<uintptr_t>(grad) & 15)) return fail(c, RC_ERR_ARG, "grad not 16-byte aligned");
+    Box b;
+    if ((r = make_box(c, box, b))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    if ((r = ensure_part(c, sizeof(double) * (size_t)(nblocks(N, kBlock) + 1)))) return r;
+    HIP_TRY(c, launch_soft_bonds(reinterpret_cast<const float4*>(pos), nlist, nn, k_max, N, dev_table(c), b, c->d_part,
+                                 value, reinterpret_cast<float4*>(grad), S(stream)));
+    return RC_OK;
+}
+
 int rc_set_table(rc_ctx* c, const rc_pair_coeff* table) {
     if (!c || !table) return RC_ERR_ARG;
     const int nt = c->nt;

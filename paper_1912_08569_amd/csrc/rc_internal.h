@@ -422,6 +422,9 @@ struct ParamArgs {
 };
 hipError_t launch_param(const ParamArgs& a, hipStream_t s);
 hipError_t launch_param_vjp(const ParamArgs& a, hipStream_t s);
+// soft bond count into *value (device double) and its gradient (float4, nullable)
+hipError_t launch_soft_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                             Box box, double* part, double* value, float4* grad, hipStream_t s);
 hipError_t launch_reduce_param(const double* part, int nblocks, int nt, double* out,
                                hipStream_t s);
 

@@ -141,6 +141,15 @@ class System:
         api.rc_param_vjp(self.ctx, self.pos, self.nlist, self.nn, self.box, adj.contiguous(), g)
         return g.cpu().numpy().reshape(nt, nt, 3)
 
+    def soft_bonds(self, grad: bool = False):
+        """Soft bond count (float64 device scalar) and, if grad, its gradient (N,4) in engine order."""
+        if not self.built:
+            self.build()
+        val = torch.zeros(1, dtype=torch.float64, device=self.device)
+        g = torch.empty_like(self.pos) if grad else None
+        api.rc_soft_bonds(self.ctx, self.pos, self.nlist, self.nn, self.box, val, g)
+        return val, g
+
     def set_table(self, table):
         """Replace eps, sigma, lambda (kinds, exponents and cutoffs unchanged)."""
         self.ctx.set_table(table)

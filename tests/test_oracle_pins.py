@@ -494,6 +494,27 @@ def test_force_param_vjp_identities_single_entry():
     assert abs(np.sum(adj * (F - F0))) > 1e-3 * abs(np.sum(adj * F))   # the three-body part is present
 
 
+def test_soft_bonds_gradient_and_bond_limit():
+    rng = np.random.default_rng(31)
+    tab = W.swap_table_single(lam=0.8)
+    L = 12.0
+    pos, ty = _cluster_away_from_cuts(rng, 12, tab, L, guard=1e-3)
+    B, g = adjoint_ref.soft_bonds(pos, ty, L, tab)
+    h = 1e-6
+    for m in range(pos.shape[0]):
+        for a in range(3):
+            xp, xm = pos.copy(), pos.copy()
+            xp[m, a] += h
+            xm[m, a] -= h
+            fd = (adjoint_ref.soft_bonds(xp, ty, L, tab)[0] - adjoint_ref.soft_bonds(xm, ty, L, tab)[0]) / (2 * h)
+            assert g[m, a] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    # three particles: one bonded pair (r < r_min), one pair beyond r_cut
+    rm = 2.0 ** 0.1
+    tri = np.array([[0.0, 0.0, 0.0], [0.9 * rm, 0.0, 0.0], [0.0, 3.0, 0.0]])
+    b3, _ = adjoint_ref.soft_bonds(tri, np.zeros(3, np.int32), L, tab)
+    assert b3 == 1.0 and swap_ref.bond_count(tri, np.zeros(3, np.int32), L, tab) == 1
+
+
 # --------------------------------------------------------------------------
 # the C brute force and the numpy evaluator agree
 # --------------------------------------------------------------------------

@@ -204,10 +204,50 @@ def adjoint_bench(a):
     grad = timed(lambda: api.rc_param_grad(S.ctx, S.pos, S.nlist, S.nn, S.box, g), 200)
     it = iter(range(10 ** 9))
     hvp = timed(lambda: api.rc_force_hvp(S.ctx, S.pos, S.nlist, S.nn, S.box, vs[next(it) % 64], hv), 640)
-    return {"workload": "32768 reactive particles, density 0.25, eps 10, sigma 1, n 10, lambda 1",
-            "forward_us": fwd, "forward_triplet_kernel_us": fwd_tri, "param_grad_us": grad,
-            "hvp_us_per_vector": hvp, "fwd_plus_param_grad_over_fwd": (fwd + grad) / fwd,
-            "hvp_over_fwd": hvp / fwd, "hvp_64_vectors_ms": hvp * 64 / 1e3}
+    adj = vs[0]
+    vjp = timed(lambda: api.rc_param_vjp(S.ctx, S.pos, S.nlist, S.nn, S.box, adj, g), 200)
+    fwd_sums = timed(lambda: api.rc_compute_forces(S.ctx, S.pos, S.nlist, S.nn, S.box, S.force, S.ev,
+                                                   rcl.RC_FORCE_SUMS, S.status), 200)
+    out = {"workload": "32768 reactive particles, density 0.25, eps 10, sigma 1, n 10, lambda 1",
+           "forward_us": fwd, "forward_sums_form_us": fwd_sums, "forward_triplet_kernel_us": fwd_tri,
+           "param_grad_us": grad, "param_vjp_us": vjp, "hvp_us_per_vector": hvp,
+           "fwd_plus_param_grad_over_fwd": (fwd + grad) / fwd, "hvp_over_fwd": hvp / fwd,
+           "hvp_64_vectors_ms": hvp * 64 / 1e3}
+    # one iteration of the lambda fit: 200 BAOAB steps forward, checkpointed backward (segments of 20)
+    from paper_1912_08569_amd.autograd import SwapModel
+    from paper_1912_08569_amd.fit import TrajectoryFit
+    M = SwapModel(System.from_workload(s))
+    fit = TrajectoryFit(M, torch.from_numpy(s.pos).cuda(), torch.from_numpy(s.vel).cuda(),
+                        torch.ones(s.N, device="cuda"), dt=0.002, kT=0.1, gamma=1.0, steps=200, segment=20,
+                        n_swap=s.N, seed=1)
+    theta0 = M.theta()
+    with torch.no_grad():
+        target = 1.05 * float(fit.observable(theta0))
+    mask = torch.zeros_like(theta0)
+    mask[0, 0, 2] = 1.0
+
+    def iteration():
+        lam = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        L = fit.loss(theta0 * (1 - mask) + mask * lam, target)
+        (gl,) = torch.autograd.grad(L, lam)
+        return float(gl)
+
+    iteration()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gl = iteration()
+    torch.cuda.synchronize()
+    t_it = time.perf_counter() - t0
+    with torch.no_grad():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fit.observable(theta0)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+    out.update({"fit_iteration_ms": t_it * 1e3, "fit_forward_only_ms": t_fwd * 1e3,
+                "fit_backward_over_forward": (t_it - t_fwd) / t_fwd, "fit_steps": 200, "fit_segment": 20,
+                "fit_dloss_dlambda": gl, "fit_list_rebuilds": M.rebuilds})
+    return out
 
 
 def main():

@@ -360,6 +360,26 @@ int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,
               const rc_md_options* opt /* host, NULL = defaults */,
               rc_md_stats* stats /* host, NULL ok */, void* stream);
 
+/* ---- FENE bond springs (supporting term of the bead-spring networks) -----------
+ * rc_set_bonds: attach a bond table to the context (NULL bonds detaches it).
+ *   bonds: device int32 [N][2], 8-byte aligned, indexed by TAG: the tags of
+ *   up to two spring partners, -1 for none; every bond listed at both ends.
+ *   rtag: device int32 [N], the tag -> index map that rc_build_cells keeps
+ *   (pass the same array there; rc_md_run requires buf->rtag == rtag).  Both
+ *   stay caller-owned and must outlive their use.  K > 0, R0 > 0: the spring
+ *   U(r) = -(K R0^2 / 2) ln(1 - (r/R0)^2) of Kremer & Grest, on top of the
+ *   pair table (bonded pairs keep their pair terms).  Once attached, every
+ *   fused step (rc_step_fused, rc_md_run) adds the spring forces, energies and
+ *   virials; a spring stretched to R0 gives a non-finite force (reported as
+ *   RC_ERR_NONFINITE by the driver).  Batches take no bonds.
+ * rc_fene_forces: the springs alone: force [N*4] += spring forces (w += half
+ *   of each bond energy); ev (device, nullable) = 7 doubles E, W of the
+ *   springs (overwritten).                                                     */
+int rc_set_bonds(rc_ctx* ctx, const int* bonds /* [N*2] | NULL */, const int* rtag /* [N] */, int N, double K,
+                 double R0);
+int rc_fene_forces(rc_ctx* ctx, const float* pos, int N, rc_box box, float* force /* [N*4] */,
+                   double* ev /* [7] | NULL */, void* stream);
+
 /* ---- differentiation (hot-path step a7) --------------------------------------
  * rc_force_hvp: hv = H v with H = d^2 E / dx dx (FP32, per-particle float4,
  *   w ignored/zero): second derivatives of the pair terms (phi'', phi'/r) and

@@ -40,12 +40,20 @@ def wrap(x, L):
 
 
 def baoab_step(pos, vel, types, tags, L, table, mass_by_type, dt, kT, gamma, seed, step,
-               force=None):
-    """Advance (pos, vel) by one step; returns dict(pos, vel, image, F, F_old)."""
+               force=None, extra=None):
+    """Advance (pos, vel) by one step; returns dict(pos, vel, image, F, F_old).
+
+    extra(x) -> [N,3], if given, adds a further force (e.g. bond springs; x in
+    the same order as pos)."""
     x = np.asarray(pos, dtype=np.float64).copy()
     v = np.asarray(vel, dtype=np.float64).copy()
     m = np.asarray(mass_by_type, dtype=np.float64)[np.asarray(types)][:, None]
-    F = swap_ref.evaluate(x, types, L, table, scales=False)["F"] if force is None else force
+
+    def forces(y):
+        f = swap_ref.evaluate(y, types, L, table, scales=False)["F"]
+        return f if extra is None else f + extra(y)
+
+    F = forces(x) if force is None else force
     v = v + 0.5 * dt * F / m
     x = x + 0.5 * dt * v
     if gamma > 0.0:
@@ -55,7 +63,7 @@ def baoab_step(pos, vel, types, tags, L, table, mass_by_type, dt, kT, gamma, see
         v = c1 * v + c2 * xi
     x = x + 0.5 * dt * v
     x, img = wrap(x, L)
-    Fn = swap_ref.evaluate(x, types, L, table, scales=False)["F"]
+    Fn = forces(x)
     v = v + 0.5 * dt * Fn / m
     return dict(pos=x, vel=v, image=img, F=Fn, F_old=F)
 

@@ -21,7 +21,7 @@ __all__ = [
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
-    "rc_param_vjp", "rc_soft_bonds", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
+    "rc_param_vjp", "rc_soft_bonds", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
     "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
     "rc_batch_time_fused_steps",
 ]
@@ -253,6 +253,20 @@ def rc_soft_bonds(ctx: Context, pos, nlist, nn, bx, value, grad=None, stream=Non
     N = pos.shape[0]
     check(L.load().rc_soft_bonds(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(value),
                                  _ptr(grad), _stream(stream)), ctx.handle)
+
+
+def rc_set_bonds(ctx: Context, bonds, rtag, K: float, R0: float):
+    """bonds: (N, 2) int32 device tensor of partner tags (-1 none); rtag: the tag -> index map."""
+    if bonds is None:
+        check(L.load().rc_set_bonds(ctx.handle, None, None, 0, 0.0, 0.0), ctx.handle)
+        return
+    check(L.load().rc_set_bonds(ctx.handle, _ptr(bonds), _ptr(rtag), int(bonds.shape[0]), float(K), float(R0)),
+          ctx.handle)
+
+
+def rc_fene_forces(ctx: Context, pos, bx, force, ev=None, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_fene_forces(ctx.handle, _ptr(pos), N, bx, _ptr(force), _ptr(ev), _stream(stream)), ctx.handle)
 
 
 def rc_param_grad(ctx: Context, pos, nlist, nn, bx, grad, stream=None):

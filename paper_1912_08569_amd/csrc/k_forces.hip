@@ -329,6 +329,8 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     const OneSystem sys{s_tab, nt, box};
     wave_gather<EV, PL, SF>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn, a.k_max, a.N, sys, acc,
                             a.ssum);
+    if (!BATCH && a.bonds && live)
+        fene_add<EV>(ptag(pm.w), pm, a.bonds, a.rtag, a.pos_in, box, a.fene_k, a.fene_r02, acc);
     if (live) {
         path_in = vm.w;
         const int tm = ptype(pm.w);
@@ -515,6 +517,40 @@ hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int 
     const int nb = nblk(N, kBlock);
     hipLaunchKernelGGL(k_bonds, dim3(nb), dim3(kBlock), shm, s, pos, nlist, nn, k_max, N, tab, box, part);
     hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(1024), 0, s, part, nb, count);
+    return hipGetLastError();
+}
+
+// FENE springs alone (one thread per particle; accumulates into force)
+template <bool EV>
+__global__ __launch_bounds__(kWave) void k_fene(const float4* __restrict__ pos, const int2* __restrict__ bonds,
+                                               const int* __restrict__ rtag, int N, Box box, float K, float R02,
+                                               float4* __restrict__ force, double* __restrict__ ev_part) {
+    const int m = blockIdx.x * kWave + threadIdx.x;
+    Acc acc = {};
+    if (m < N) {
+        const float4 pm = pos[m];
+        fene_add<EV>(ptag(pm.w), pm, bonds, rtag, pos, box, K, R02, acc);
+        float4 f = force[m];
+        f.x += acc.fx;
+        f.y += acc.fy;
+        f.z += acc.fz;
+        f.w += acc.e;
+        force[m] = f;
+    }
+    if (EV) {
+        double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
+        wave_sum_store<7>(v, ev_part + (size_t)blockIdx.x * kEvWords);
+    }
+}
+
+hipError_t launch_fene(const float4* pos, const int2* bonds, const int* rtag, int N, Box box, float K, float R02,
+                       float4* force, double* ev_part, hipStream_t s) {
+    if (ev_part)
+        hipLaunchKernelGGL(k_fene<true>, dim3(nblk(N, kWave)), dim3(kWave), 0, s, pos, bonds, rtag, N, box, K, R02,
+                           force, ev_part);
+    else
+        hipLaunchKernelGGL(k_fene<false>, dim3(nblk(N, kWave)), dim3(kWave), 0, s, pos, bonds, rtag, N, box, K, R02,
+                           force, ev_part);
     return hipGetLastError();
 }
 

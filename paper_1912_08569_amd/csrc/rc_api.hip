@@ -111,6 +111,44 @@ int rc_soft_bonds(rc_ctx* c, const float* pos, const int* nlist, const int* nn, 
     return RC_OK;
 }
 
+int rc_set_bonds(rc_ctx* c, const int* bonds, const int* rtag, int N, double K, double R0) {
+    if (!c) return RC_ERR_ARG;
+    if (!bonds) {
+        c->bonds = nullptr;
+        c->bonds_rtag = nullptr;
+        c->bonds_n = 0;
+        drop_graphs(c);
+        return RC_OK;
+    }
+    if (!rtag || N < 1 || N >= RC_MAX_TAG) return fail(c, RC_ERR_ARG, "rc_set_bonds: rtag NULL or bad N");
+    if (reinterpret_cast<uintptr_t>(bonds) & 7) return fail(c, RC_ERR_ARG, "bond table not 8-byte aligned");
+    if (!(K > 0.0) || !(R0 > 0.0) || !std::isfinite(K) || !std::isfinite(R0))
+        return fail(c, RC_ERR_ARG, "FENE needs K > 0 and R0 > 0");
+    c->bonds = bonds;
+    c->bonds_rtag = rtag;
+    c->bonds_n = N;
+    c->fene_k = K;
+    c->fene_r0 = R0;
+    drop_graphs(c);
+    return RC_OK;
+}
+
+int rc_fene_forces(rc_ctx* c, const float* pos, int N, rc_box box, float* force, double* ev, void* stream) {
+    int r = check_common(c, N, pos);
+    if (r) return r;
+    if (!force) return fail(c, RC_ERR_ARG, "force is NULL");
+    if (!c->bonds || c->bonds_n != N) return fail(c, RC_ERR_ARG, "no bond table for %d particles (rc_set_bonds)", N);
+    Box b;
+    if ((r = make_box(c, box, b))) return r;
+    const int nb = nblocks(N, kWave);
+    if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
+    HIP_TRY(c, launch_fene(reinterpret_cast<const float4*>(pos), reinterpret_cast<const int2*>(c->bonds), c->bonds_rtag,
+                           N, b, (float)c->fene_k, (float)(c->fene_r0 * c->fene_r0), reinterpret_cast<float4*>(force),
+                           ev ? c->d_part : nullptr, S(stream)));
+    if (ev && (r = reduce_rows(c, nb, 0, 7, ev, S(stream)))) return r;
+    return RC_OK;
+}
+
 int rc_set_table(rc_ctx* c, const rc_pair_coeff* table) {
     if (!c || !table) return RC_ERR_ARG;
     const int nt = c->nt;
@@ -341,6 +379,14 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
         if ((r = ensure_ssum(c, (size_t)N))) return r;
         a.ssum = c->d_ssum;
     }
+    a.bonds = nullptr;
+    if (c->bonds) {
+        if (c->bonds_n != N) return fail(c, RC_ERR_ARG, "bond table is for %d particles, not %d", c->bonds_n, N);
+        a.bonds = reinterpret_cast<const int2*>(c->bonds);
+        a.rtag = c->bonds_rtag;
+        a.fene_k = (float)c->fene_k;
+        a.fene_r02 = (float)(c->fene_r0 * c->fene_r0);
+    }
     if ((r = ensure_blk(c, nblocks(N, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
     return RC_OK;
@@ -550,6 +596,8 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
         return fail(c, RC_ERR_ARG, "md buffers incomplete");
     if (buf->k_max < 1 || buf->k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
+    if (c->bonds && buf->rtag != c->bonds_rtag)
+        return fail(c, RC_ERR_ARG, "with bonds, the md buffers' rtag must be the one given to rc_set_bonds");
     rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;

@@ -297,6 +297,35 @@ __device__ __forceinline__ float swap_sum(int m, const float4& pm, int packed, c
     return s;
 }
 
+// FENE springs of particle m (tag-indexed partner table, -1 = none; rtag
+// maps a tag to its current index): F_m += K d / (1 - r^2/R0^2) per bond,
+// d = x_j - x_m (minimum image); half the bond energy -(K R0^2/2) ln(1 -
+// r^2/R0^2) and half its virial -K d d /(1 - r^2/R0^2) go to m.  A bond
+// stretched to R0 or beyond yields a non-finite force.
+template <bool EV>
+__device__ __forceinline__ void fene_add(int tag, const float4& pm, const int2* bonds, const int* rtag,
+                                         const float4* pos, const Box& box, float K, float R02, Acc& acc) {
+    const int2 b = bonds[tag];
+    const int part[2] = {b.x, b.y};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (part[q] < 0) continue;
+        const float4 pj = pos[rtag[part[q]]];
+        double dxd, dyd, dzd;
+        const double r2d = canon_r2(pm, pj, box, dxd, dyd, dzd);
+        const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+        const float s = 1.0f - (float)r2d / R02;
+        const float g = s > 0.0f ? K / s : __int_as_float(0x7fc00000);
+        acc.fx += g * dx;
+        acc.fy += g * dy;
+        acc.fz += g * dz;
+        if (EV) {
+            acc.e += -0.25f * K * R02 * logf(s);
+            acc_virial(acc, -0.5f * g, dx, dy, dz);
+        }
+    }
+}
+
 // wave-wide sums of NW doubles; lane 0 stores them
 template <int NW>
 __device__ __forceinline__ void wave_sum_store(double (&v)[NW], double* out) {

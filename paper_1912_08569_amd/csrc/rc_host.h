@@ -35,6 +35,10 @@ struct rc_ctx {
     int step_form = RC_FORM_WALK;       // RC_FORM_WALK | RC_FORM_SUMS
     float* d_ssum = nullptr;            // per-particle switching sums of the sums form
     size_t ssum_cap = 0;                // floats allocated
+    const int* bonds = nullptr;         // FENE partner table (caller-owned, [n_bonded][2] by tag)
+    const int* bonds_rtag = nullptr;    // tag -> index map the springs read (caller-owned)
+    int bonds_n = 0;
+    double fene_k = 0.0, fene_r0 = 0.0;
     GraphCache gc;
     std::string err;
 };

@@ -294,6 +294,10 @@ struct StepArgs {
     int width;                 // gather width of the non-logging steps: 1, 2 or 4 (read by the launcher)
     int form;                  // RC_FORM_WALK or RC_FORM_SUMS (read by the launcher)
     float* ssum;               // [N] per-particle switching sums (RC_FORM_SUMS)
+    // FENE springs (single systems; NULL bonds = none)
+    const int2* bonds;         // [N] partner tags per tag, -1 = none
+    const int* rtag;           // [N] tag -> index
+    float fene_k, fene_r02;    // K and R0^2
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
@@ -422,6 +426,10 @@ struct ParamArgs {
 };
 hipError_t launch_param(const ParamArgs& a, hipStream_t s);
 hipError_t launch_param_vjp(const ParamArgs& a, hipStream_t s);
+// FENE springs alone: force[i] += spring forces (w += half bond energies);
+// ev_part: per-block rows (7 values at the head of 13-value rows) or NULL
+hipError_t launch_fene(const float4* pos, const int2* bonds, const int* rtag, int N, Box box, float K, float R02,
+                       float4* force, double* ev_part, hipStream_t s);
 // soft bond count into *value (device double) and its gradient (float4, nullable)
 hipError_t launch_soft_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
                              Box box, double* part, double* value, float4* grad, hipStream_t s);

@@ -33,7 +33,7 @@ class System:
     """
 
     def __init__(self, pos, types, L, table, vel=None, mass=None, r_buff: float = 0.3, k_max: int = 32,
-                 rollback: bool = True, device: str = "cuda"):
+                 rollback: bool = True, device: str = "cuda", bonds=None, fene=None):
         self.device = torch.device(device)
         self.ctx = api.Context(table, r_buff)
         self.table = table
@@ -69,11 +69,23 @@ class System:
             self.snap_pos = torch.empty_like(self.pos)
             self.snap_vel = torch.empty_like(self.vel)
             self.snap_image = torch.empty_like(self.image)
+        # FENE springs: partner tags per tag, read through rtag (kept by every cell build)
+        self.bonds = None
+        if bonds is not None:
+            if fene is None:
+                raise ValueError("bonds need fene=(K, R0)")
+            self.bonds = torch.from_numpy(np.ascontiguousarray(np.asarray(bonds, dtype=np.int32))).to(dev)
+            self.fene = (float(fene[0]), float(fene[1]))
+            api.rc_set_bonds(self.ctx, self.bonds, self.rtag, *self.fene)
+            self.ev_fene = torch.zeros(7, dtype=torch.float64, device=dev)
         self.built = False
 
     @classmethod
     def from_workload(cls, sysw, **kw):
-        return cls(sysw.pos, sysw.types, sysw.L, sysw.table, vel=sysw.vel, mass=sysw.mass, **kw)
+        extra = {}
+        if getattr(sysw, "bonds", None) is not None:
+            extra = {"bonds": sysw.bonds, "fene": sysw.fene}
+        return cls(sysw.pos, sysw.types, sysw.L, sysw.table, vel=sysw.vel, mass=sysw.mass, **extra, **kw)
 
     # ---- neighbour list -----------------------------------------------------------
     def _grow(self, k_needed: int):
@@ -108,6 +120,10 @@ class System:
         flags = rcl.RC_FORCE_SUMS if gather == "sums" else (rcl.RC_FORCE_GATHER if gather else 0)
         api.rc_compute_forces(self.ctx, self.pos, self.nlist, self.nn, self.box, self.force,
                               self.ev if ev else None, flags, self.status)
+        if self.bonds is not None:      # springs on top (accumulated)
+            api.rc_fene_forces(self.ctx, self.pos, self.box, self.force, self.ev_fene if ev else None)
+            if ev:
+                self.ev[:7] += self.ev_fene
         return self.force, (self.ev[:7] if ev else None)
 
     def bond_count(self) -> int:

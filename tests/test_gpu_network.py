@@ -1,0 +1,116 @@
+"""Bead-spring networks on the GPU: FENE springs next to the swap and WCA
+pair terms (the vitrimer-like workload), through the C ABI, against the FP64
+oracle (pair terms from swap_ref, springs from fene_ref)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import dynamics_ref, fene_ref, swap_ref
+from parity_util import force_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _system(s, **kw):
+    from paper_1912_08569_amd import System
+    return System.from_workload(s, **kw)
+
+
+def _ref(x, ty, s):
+    p = swap_ref.evaluate(x, ty, s.L, s.table)
+    f = fene_ref.evaluate(x, s.L, s.bonds, *s.fene)
+    ref = dict(p)
+    ref["F"] = p["F"] + f["F"]
+    ref["A_F"] = p["A_F"] + f["A_F"]
+    ref["E"] = p["E"] + f["E"]
+    ref["W"] = p["W"] + f["W"]
+    ref["pe"] = p["pe"] + f["pe"]
+    ref["A_E"] = p["A_E"] + float(np.sum(np.abs(f["pe"])))
+    return ref, f
+
+
+def test_fene_springs_alone_match_oracle():
+    from paper_1912_08569_amd import api
+    s = W.vitrimer_network(n_chains=60, n_dimers=30, seed=11)
+    S = _system(s)
+    S.build()
+    F = torch.zeros_like(S.pos)
+    ev = torch.zeros(7, dtype=torch.float64, device="cuda")
+    api.rc_fene_forces(S.ctx, S.pos, S.box, F, ev)
+    torch.cuda.synchronize()
+    x, _, _, ty = S.state_by_tag()
+    f = fene_ref.evaluate(x.astype(np.float64), s.L, s.bonds, *s.fene)
+    Fg = S.by_tag(F)
+    err = np.abs(Fg[:, :3] - f["F"]).max(axis=1) / np.maximum(f["A_F"], 1e-30)
+    assert err.max() <= 1e-5
+    evh = ev.cpu().numpy()
+    assert abs(evh[0] - f["E"]) <= 1e-5 * float(np.sum(np.abs(f["pe"])))
+    assert np.abs(evh[1:] - f["W"]).max() <= 1e-5 * float(np.sum(f["A_F"]) * 1.5)
+    assert np.abs(Fg[:, 3] - f["pe"]).max() <= 1e-5 * np.abs(f["pe"]).max()
+
+
+def test_network_forces_and_bonds_match_oracle():
+    s = W.vitrimer_network(n_chains=60, n_dimers=30, seed=12)
+    S = _system(s)
+    F, ev = S.compute_forces(gather=True)
+    torch.cuda.synchronize()
+    x, _, _, ty = S.state_by_tag()
+    ref, _ = _ref(x.astype(np.float64), ty, s)
+    assert force_errors(S.by_tag(F), ref).max() <= 1e-5
+    assert abs(ev[0].item() - ref["E"]) <= 1e-5 * ref["A_E"]
+    assert S.bond_count() == ref["bonds"]
+
+
+def test_fused_step_with_springs_matches_oracle_step():
+    s = W.vitrimer_network(n_chains=60, n_dimers=30, seed=13)
+    S = _system(s)
+    S.build()
+    x0, v0, _, ty = S.state_by_tag()
+    cfg = S.integrator(dt=0.002, kT=1.0, gamma=1.0, seed=21)
+    S.run(1, cfg, step0=9, use_graph=False)
+    x1, v1, img, _ = S.state_by_tag()
+    extra = lambda y: fene_ref.evaluate(y, s.L, s.bonds, *s.fene)["F"]  # noqa: E731
+    ref = dynamics_ref.baoab_step(x0, v0, ty, np.arange(s.N), s.L, s.table, s.mass, 0.002, 1.0, 1.0, 21, 9,
+                                  extra=extra)
+    r0, _ = _ref(x0.astype(np.float64), ty, s)
+    r1, _ = _ref(ref["pos"], ty, s)
+    c2 = np.sqrt((1 - np.exp(-2 * 0.002)) * 1.0)
+    vscale = np.abs(v0) + 4.0 * c2 + 0.002 * (r0["A_F"] + r1["A_F"])[:, None] + np.abs(ref["vel"])
+    assert np.all(np.abs(v1 - ref["vel"]) <= 2e-5 * vscale + 1e-7)
+    dx = np.abs(swap_ref.min_image(ref["pos"], x1.astype(np.float64), s.box))
+    ulp = np.abs(np.nextafter(np.abs(ref["pos"]).astype(np.float32), np.float32(np.inf))
+                 - np.abs(ref["pos"]).astype(np.float32)).astype(np.float64)
+    assert np.all(dx <= 4 * ulp + 0.002 * 2e-5 * vscale)
+    assert np.array_equal(img, ref["image"])
+
+
+def test_network_dynamics_keeps_springs_and_ends_on_oracle_values():
+    s = W.vitrimer_network(n_chains=120, n_dimers=60, seed=14)
+    S = _system(s)
+    S.run(300, S.integrator(dt=2e-4, kT=1.0, gamma=1.0, seed=22))   # gentle start from 0.8 sigma contacts
+    cfg = S.integrator(dt=0.002, kT=1.0, gamma=1.0, seed=22)
+    r = S.run(2000, cfg, step0=300, log_period=500)
+    assert r.stats.steps_done == 2000
+    x, _, _, ty = S.state_by_tag()
+    ref, f = _ref(x.astype(np.float64), ty, s)     # raises if a spring reached R0
+    assert int(r.bonds[-1]) == ref["bonds"]
+    assert abs(r.ev[-1, 0] - ref["E"]) <= 1e-5 * ref["A_E"]
+    T = r.ev[-1, 7:10].sum() / (3 * s.N)
+    assert 0.5 < T < 2.0        # thermostat at kT = 1 (bond formation releases heat)
+
+
+def test_full_network_runs():
+    # the 67,200-bead network: 4000 chains of 16 and 1600 crosslinker dimers at density 0.85
+    s = W.vitrimer_network()
+    S = _system(s)
+    # the random-walk start has many 0.8 sigma contacts; 300 push-off steps leave springs near R0 that the
+    # 0.002 step then breaks, 3000 relax them (max spring length 1.32 after the push-off)
+    S.run(3000, S.integrator(dt=2e-4, kT=1.0, gamma=1.0, seed=23))
+    cfg = S.integrator(dt=0.002, kT=1.0, gamma=1.0, seed=23)
+    r = S.run(1000, cfg, step0=3000, log_period=500)
+    x, _, _, ty = S.state_by_tag()
+    f = fene_ref.evaluate(x.astype(np.float64), s.L, s.bonds, *s.fene)
+    assert f["n_bonds"] == 61600
+    assert int(r.bonds[-1]) == swap_ref.bond_count(x.astype(np.float64), ty, s.L, s.table)
+    assert np.all(np.isfinite(r.ev))

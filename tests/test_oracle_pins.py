@@ -516,6 +516,54 @@ def test_soft_bonds_gradient_and_bond_limit():
 
 
 # --------------------------------------------------------------------------
+# FENE springs
+# --------------------------------------------------------------------------
+
+def test_fene_forces_are_minus_energy_gradient_and_closed_form():
+    from oracle import fene_ref
+    rng = np.random.default_rng(40)
+    L = 10.0
+    # a chain of 6 beads along x that crosses the boundary between beads 2 and 3
+    x = np.zeros((6, 3))
+    x[:, 0] = L / 2 - 2.0 + 0.95 * np.arange(6)
+    x += rng.uniform(-0.1, 0.1, x.shape)
+    x[:, 0] = (x[:, 0] + L / 2) % L - L / 2
+    bonds = np.full((6, 2), -1)
+    for k in range(5):
+        bonds[k, 1], bonds[k + 1, 0] = k + 1, k
+    out = fene_ref.evaluate(x, L, bonds, 30.0, 1.5)
+    h = 1e-6
+    for m in range(6):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[m, a] += h
+            xm[m, a] -= h
+            fd = (fene_ref.evaluate(xp, L, bonds, 30.0, 1.5)["E"] - fene_ref.evaluate(xm, L, bonds, 30.0, 1.5)["E"]) / (2 * h)
+            assert out["F"][m, a] == pytest.approx(-fd, rel=1e-6, abs=1e-6)
+    # one bond at r = 1.2: |F| = K r / (1 - r^2/R0^2) = 30 * 1.2 / 0.36 = 100
+    two = fene_ref.evaluate(np.array([[0.0, 0, 0], [1.2, 0, 0]]), L, np.array([[1, -1], [-1, 0]]), 30.0, 1.5)
+    assert two["F"][0, 0] == pytest.approx(100.0, rel=1e-12)
+    assert two["W"][0] == pytest.approx(-100.0 * 1.2, rel=1e-12)
+    assert sum(two["pe"]) == pytest.approx(two["E"], rel=1e-14)
+
+
+def test_fene_plus_wca_bond_length_is_kremer_grest():
+    # K = 30, R0 = 1.5, WCA eps = sigma = 1: the bond potential has its minimum at about
+    # 0.96 sigma (Kremer & Grest 1990; the thermal mean bond length at kT = 1 is ~0.97)
+    from scipy.optimize import minimize_scalar
+    from oracle import fene_ref
+    tab = W.PairTable.empty(1)
+    tab.set(0, 0, W.KIND_WCA, 1.0, 1.0, 6)
+    b = np.array([[1, -1], [-1, 0]])
+
+    def U(r):
+        x = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+        return fene_ref.evaluate(x, 20.0, b, 30.0, 1.5)["E"] + swap_ref.energy(x, np.zeros(2, np.int32), 20.0, tab)
+    res = minimize_scalar(U, bounds=(0.8, 1.12), method="bounded", options={"xatol": 1e-10})
+    assert abs(res.x - 0.961) < 0.002
+
+
+# --------------------------------------------------------------------------
 # the C brute force and the numpy evaluator agree
 # --------------------------------------------------------------------------
 

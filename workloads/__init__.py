@@ -15,12 +15,14 @@ Recipes (all seeded with numpy PCG64):
   versions).
 * ``replica_set``     -- many independent replicas of uneven size, density,
   lambda and inert fraction.
+* ``vitrimer_network`` -- bead-spring chains (FENE springs) with reactive
+  sites and free two-bead crosslinkers, grown self-avoiding in the box.
 * ``cluster``         -- hand-placed few-particle configurations.
 """
 from .systems import (  # noqa: F401
     KIND_NONE, KIND_SWAP, KIND_WCA, WCA_CUT_FACTOR,
     PairTable, System, fp32_box, wrap_fp32,
     swap_table_single, assembly_table,
-    small_reactive, assembly_mixture, replica_set, cluster,
+    small_reactive, assembly_mixture, replica_set, cluster, vitrimer_network, vitrimer_table,
     maxwell_velocities, rsa_positions,
 )

@@ -88,6 +88,8 @@ class System:
     vel: Optional[np.ndarray] = None   # float32 [N, 3]
     name: str = ""
     meta: dict = dataclasses.field(default_factory=dict)
+    bonds: Optional[np.ndarray] = None  # int32 [N, 2] spring partner tags per tag (-1 none)
+    fene: Optional[tuple] = None        # (K, R0) of the springs
 
     @property
     def N(self) -> int:
@@ -276,3 +278,120 @@ def cluster(coords, L=20.0, types=None, table: Optional[PairTable] = None) -> Sy
     return System(pos=wrap_fp32(c, Lf), types=ty, L=Lf, table=tab,
                   mass=np.ones(tab.ntypes), vel=np.zeros((c.shape[0], 3), np.float32),
                   name="cluster")
+
+
+def vitrimer_table(eps_site=20.0, sigma_site=0.3, n=10, rcut_site=0.45, lam=1.0) -> PairTable:
+    """Types: 0 backbone bead, 1 reactive chain site, 2 crosslinker bead.
+
+    WCA (eps = sigma = 1) between backbone beads and everything, and between
+    crosslinker beads; the swap potential between reactive sites and between
+    a site and a crosslinker bead (sites are small patch-like beads that
+    overlap their partner when bonded)."""
+    t = PairTable.empty(3)
+    t.set(0, 0, KIND_WCA, 1.0, 1.0, 6)
+    t.set(0, 1, KIND_WCA, 1.0, 1.0, 6)
+    t.set(0, 2, KIND_WCA, 1.0, 1.0, 6)
+    t.set(2, 2, KIND_WCA, 1.0, 1.0, 6)
+    t.set(1, 1, KIND_SWAP, eps_site, sigma_site, n, rcut_site, lam)
+    t.set(1, 2, KIND_SWAP, eps_site, sigma_site, n, rcut_site, lam)
+    return t
+
+
+def _grow_chains(rng, L, n_chains, chain_len, n_dimers, bond, d_min, tries=24):
+    """Self-avoiding growth of chains and dimers in a periodic box: every
+    bead keeps a periodic distance > d_min from all earlier beads, and
+    consecutive beads of a molecule sit ``bond`` apart."""
+    # cells at least one bond plus d_min wide: every check reads the 27 cells around one point
+    w = max(bond + d_min, L / 256.0)
+    nc = max(3, int(L // w))
+    w = L / nc
+    grid = {}
+    pts = []
+
+    def cell(p):
+        return tuple(int(math.floor((p[a] + 0.5 * L) / w)) % nc for a in range(3))
+
+    def clear(cands, centre, reach):
+        """Candidates (all within reach - w of centre) with no bead within d_min."""
+        ok = np.ones(len(cands), dtype=bool)
+        near = []
+        c0 = cell(centre)
+        rng_c = range(-reach, reach + 1)
+        for dx in rng_c:
+            for dy in rng_c:
+                for dz in rng_c:
+                    near.extend(grid.get(((c0[0] + dx) % nc, (c0[1] + dy) % nc, (c0[2] + dz) % nc), ()))
+        if near:
+            q = np.asarray([pts[k] for k in set(near)])
+            d = cands[:, None, :] - q[None, :, :]
+            d -= L * np.round(d / L)
+            ok = ~np.any(np.einsum("cka,cka->ck", d, d) <= d_min * d_min, axis=1)
+        return ok
+
+    def add(p):
+        grid.setdefault(cell(p), []).append(len(pts))
+        pts.append(p)
+
+    def wrap(p):
+        return p - L * np.floor((p + 0.5 * L) / L)
+
+    reach1 = reach2 = 1
+    if nc < 3:
+        raise ValueError("box too small for the growth grid")
+    mols = []
+    sizes = [chain_len] * n_chains + [2] * n_dimers
+    for size in sizes:
+        while True:
+            start = len(pts)
+            p = wrap(rng.uniform(-0.5 * L, 0.5 * L, 3))
+            if not clear(p[None, :], p, reach1)[0]:
+                continue
+            add(p)
+            ok = True
+            for _ in range(size - 1):
+                dirs = rng.standard_normal((tries, 3))
+                dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+                cands = wrap(pts[-1][None, :] + bond * dirs)
+                good = np.nonzero(clear(cands, pts[-1], reach2))[0]
+                if good.size == 0:
+                    ok = False
+                    break
+                add(cands[good[0]])
+            if ok:
+                mols.append((start, size))
+                break
+            # dead end: take the molecule out again and start elsewhere
+            for k in range(len(pts) - 1, start - 1, -1):
+                grid[cell(pts[k])].remove(k)
+            del pts[start:]
+    return np.asarray(pts), mols
+
+
+def vitrimer_network(n_chains=4000, chain_len=16, n_dimers=1600, density=0.85, site_frac=0.1, seed=1002,
+                     kT=1.0, K=30.0, R0=1.5, bond=0.97, d_min=0.8, lam=1.0) -> System:
+    """Bead-spring chains with reactive sites and free crosslinker dimers.
+
+    ``n_chains`` chains of ``chain_len`` beads (FENE K, R0 along each chain),
+    a seeded ``site_frac`` of the chain beads turned into reactive sites, and
+    ``n_dimers`` two-bead crosslinkers (one FENE spring each) whose beads bind
+    to sites; density counts every bead.  Grown self-avoiding with bond
+    length ``bond`` and no two beads closer than ``d_min``."""
+    rng = np.random.default_rng(seed)
+    N = n_chains * chain_len + 2 * n_dimers
+    L = fp32_box(N, density)
+    pos, mols = _grow_chains(rng, L, n_chains, chain_len, n_dimers, bond, d_min)
+    types = np.zeros(N, np.int32)
+    chain_beads = n_chains * chain_len
+    sites = rng.choice(chain_beads, int(round(site_frac * chain_beads)), replace=False)
+    types[sites] = 1
+    types[chain_beads:] = 2
+    bonds = np.full((N, 2), -1, np.int32)
+    for start, size in mols:
+        for k in range(start, start + size - 1):
+            bonds[k, 1] = k + 1
+            bonds[k + 1, 0] = k
+    mass = np.ones(3)
+    vel = maxwell_velocities(rng, types, mass, kT)
+    return System(pos=wrap_fp32(pos, L), types=types, L=L, table=vitrimer_table(lam=lam), mass=mass, vel=vel,
+                  name=f"vitrimer network N={N}", bonds=bonds, fene=(K, R0),
+                  meta={"n_chains": n_chains, "chain_len": chain_len, "n_dimers": n_dimers})

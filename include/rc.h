@@ -162,10 +162,16 @@ int rc_set_gather_width(rc_ctx* ctx, int width);
  *     gives every (m, j) entry the factor (S_m - w) + (S_j - w), i.e. the
  *     triplet sum of eq. (3bp) rewritten as (S^2 - sum w^2)/2 per centre
  *     (linear in k; one float per particle of context-owned scratch).
- * Both are exact rewritings of the same energy; results differ by rounding
+ *   RC_FORM_HEAD: the walk form's terms, sums and order, with the loads
+ *     reordered for short lists: the first slots of each list and of each
+ *     swap partner's list are read before they are known to be needed, so
+ *     a step waits on three rounds of memory latency instead of about eight
+ *     (single systems only; a batch takes it as RC_FORM_WALK).
+ * All are exact rewritings of the same energy; results differ by rounding
  * order only.  RC_ERR_ARG for other values.                                 */
 #define RC_FORM_WALK 0
 #define RC_FORM_SUMS 1
+#define RC_FORM_HEAD 2
 int rc_set_step_form(rc_ctx* ctx, int form);
 
 /* ---- status ---------------------------------------------------------------

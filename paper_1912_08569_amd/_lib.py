@@ -31,7 +31,7 @@ RC_STATUS_WORDS = 8
 RC_ST_FLAGS, RC_ST_KMAX, RC_ST_MAXPATH, RC_ST_FIRST_SOFT, RC_ST_FIRST_HARD = 0, 1, 2, 3, 4
 RC_FLAG_NLIST_OVERFLOW, RC_FLAG_REBUILD, RC_FLAG_NONFINITE, RC_FLAG_LOST, RC_FLAG_STALE = 1, 2, 4, 8, 16
 RC_FORCE_ACCUMULATE, RC_FORCE_GATHER, RC_FORCE_SUMS = 1, 4, 8
-RC_FORM_WALK, RC_FORM_SUMS = 0, 1
+RC_FORM_WALK, RC_FORM_SUMS, RC_FORM_HEAD = 0, 1, 2
 RC_HALF_FIRST, RC_HALF_SECOND = 0, 1
 RC_STEP_START, RC_STEP_CONT, RC_STEP_FINISH, RC_STEP_OBSERVE = 0, 1, 2, 3
 RC_INTEGRATOR_NVE, RC_INTEGRATOR_LANGEVIN = 0, 1

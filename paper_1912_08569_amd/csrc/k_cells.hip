@@ -282,57 +282,110 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
 // neighbour list
 // ---------------------------------------------------------------------------
 // List of one particle i (key order): scan the 27 cells around i's cell and
-// keep every j != i inside r_list(t_i, t_j).  Distances use FP64 differences
-// folded by the box (exact image choice) and an FP32 square; the list radius
-// carries a 1e-5 relative margin for that rounding.  Cell k's particles sit
-// at cell_start[key_base + k] + shift onwards.  rl(q, rl2, swap) gives entry
-// q's squared list radius and whether it is a swap pair.  Returns the full
-// neighbour count and stores nn[i] (clipped to k_max).
+// keep every j != i inside r_list(t_i, t_j).  Cells are visited in (z, y, x)
+// offset order and each cell's particles in memory order, so the list order
+// is fixed.  For a cell that does not wrap around the box the difference
+// x_j - x_i is one FP32 subtraction (a single rounding of the exact value);
+// across a periodic face it is the FP64 difference folded by the box (exact
+// image choice).  The square is FP32; the list radius carries a 1e-5 relative
+// margin for that rounding.  Cell k's particles sit at cell_start[key_base +
+// k] + shift onwards.  rl(q, rl2, swap) gives entry q's squared list radius
+// and whether it is a swap pair.  Returns the full neighbour count and stores
+// nn[i] (clipped to k_max).
+//
+// Per z slab the nine cell ranges are read together and kept in the thread's
+// LDS column col[0 .. 17] (stride kBlock); the slab's candidates are then
+// walked as one sequence, two positions in flight, so a wavefront iterates
+// over its longest candidate sequence rather than over nine cells times
+// their largest occupancy.
 template <class Radii>
 __device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, const Grid& g, uint32_t key_base,
                                         int shift, const int* __restrict__ cell_start, const float4* __restrict__ pos,
                                         int nt, int k_max, int N, int* __restrict__ nlist, int* __restrict__ nn,
-                                        Radii rl) {
+                                        int* col, Radii rl) {
     int ns = 0, no = 0;
     const int ti = ptype(pi.w);
     const int cx = cell_coord(pi.x, b.hf[0], g.inv_w[0], g.nc[0]);
     const int cy = cell_coord(pi.y, b.hf[1], g.inv_w[1], g.nc[1]);
     const int cz = cell_coord(pi.z, b.hf[2], g.inv_w[2], g.nc[2]);
+    // Morton parts of the three cell coordinates per axis, and whether the offset wraps
+    int wxy = 0;  // bit o: x offset o wraps; bit 3 + o: y offset o wraps
+    auto axis = [&](int c, int o, int nc, int bit) {
+        int x = c + o - 1;
+        wxy |= (x < 0 || x >= nc) ? bit : 0;
+        x += (x < 0) ? nc : 0;
+        x -= (x >= nc) ? nc : 0;
+        return spread3((uint32_t)x);
+    };
+    const uint32_t kx0 = axis(cx, 0, g.nc[0], 1), kx1 = axis(cx, 1, g.nc[0], 2), kx2 = axis(cx, 2, g.nc[0], 4);
+    const uint32_t ky0 = axis(cy, 0, g.nc[1], 8) << 1, ky1 = axis(cy, 1, g.nc[1], 16) << 1,
+                   ky2 = axis(cy, 2, g.nc[1], 32) << 1;
+    auto consider = [&](int j, const float4& pj, bool wrapped) {
+        float dx, dy, dz;
+        if (wrapped) {
+            dx = (float)fold((double)pj.x - (double)pi.x, b.L[0], b.h[0]);
+            dy = (float)fold((double)pj.y - (double)pi.y, b.L[1], b.h[1]);
+            dz = (float)fold((double)pj.z - (double)pi.z, b.L[2], b.h[2]);
+        } else {
+            dx = pj.x - pi.x;
+            dy = pj.y - pi.y;
+            dz = pj.z - pi.z;
+        }
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float rl2;
+        bool swap;
+        rl(ti * nt + ptype(pj.w), rl2, swap);
+        if (r2 < rl2) {
+            // swap kind from the front, the rest from the back (counters stay in registers)
+            const int slot = swap ? ns : k_max - 1 - no;
+            if (ns + no < k_max) nlist[(size_t)slot * N + i] = j;
+            ns += swap ? 1 : 0;
+            no += swap ? 0 : 1;
+        }
+    };
     for (int oz = -1; oz <= 1; ++oz) {
         int z = cz + oz;
+        const bool wz = z < 0 || z >= g.nc[2];
         z += (z < 0) ? g.nc[2] : 0;
         z -= (z >= g.nc[2]) ? g.nc[2] : 0;
-        for (int oy = -1; oy <= 1; ++oy) {
-            int y = cy + oy;
-            y += (y < 0) ? g.nc[1] : 0;
-            y -= (y >= g.nc[1]) ? g.nc[1] : 0;
-            for (int ox = -1; ox <= 1; ++ox) {
-                int x = cx + ox;
-                x += (x < 0) ? g.nc[0] : 0;
-                x -= (x >= g.nc[0]) ? g.nc[0] : 0;
-                const uint32_t key = key_base + morton3(x, y, z);
-                const int s = cell_start[key] + shift, e = cell_start[key + 1] + shift;
-                for (int j = s; j < e; ++j) {
-                    if (j == i) continue;
-                    const float4 pj = pos[j];
-                    float dx = (float)fold((double)pj.x - (double)pi.x, b.L[0], b.h[0]);
-                    float dy = (float)fold((double)pj.y - (double)pi.y, b.L[1], b.h[1]);
-                    float dz = (float)fold((double)pj.z - (double)pi.z, b.L[2], b.h[2]);
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    float rl2;
-                    bool swap;
-                    rl(ti * nt + ptype(pj.w), rl2, swap);
-                    if (r2 < rl2) {
-                        if (swap) {
-                            if (ns + no < k_max) nlist[(size_t)ns * N + i] = j;
-                            ++ns;
-                        } else {
-                            if (ns + no < k_max) nlist[(size_t)(k_max - 1 - no) * N + i] = j;
-                            ++no;
-                        }
-                    }
-                }
+        const uint32_t kz = spread3((uint32_t)z) << 2;
+        int st[9], en[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const uint32_t kxq = q % 3 == 0 ? kx0 : (q % 3 == 1 ? kx1 : kx2);
+            const uint32_t kyq = q / 3 == 0 ? ky0 : (q / 3 == 1 ? ky1 : ky2);
+            const uint32_t key = key_base + (kxq | kyq | kz);
+            st[q] = cell_start[key] + shift;
+            en[q] = cell_start[key + 1] + shift;
+        }
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+            col[q * kBlock] = st[q];
+            col[(9 + q) * kBlock] = en[q];
+        }
+        // cursor over the slab's candidates: cell q, next particle j, end e
+        int q = 0, j = st[0], e = en[0];
+        auto next = [&](bool& wrapped) -> int {
+            while (j >= e) {
+                if (q == 8) return -1;
+                ++q;
+                j = col[q * kBlock];
+                e = col[(9 + q) * kBlock];
             }
+            wrapped = wz || (wxy & ((1 << (q % 3)) | (8 << (q / 3)))) != 0;
+            return j++;
+        };
+        for (;;) {
+            bool w0 = false, w1 = false;
+            const int j0 = next(w0);
+            if (j0 < 0) break;
+            const int j1 = next(w1);
+            const float4 p0 = pos[j0];
+            float4 p1 = p0;
+            if (j1 >= 0) p1 = pos[j1];
+            if (j0 != i) consider(j0, p0, w0);
+            if (j1 < 0) break;
+            if (j1 != i) consider(j1, p1, w1);
         }
     }
     const int total = ns + no;
@@ -363,6 +416,7 @@ __device__ __forceinline__ void block_max_store(int cnt, int* __restrict__ out) 
 
 // One thread per particle (key order).
 __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
+    __shared__ int s_col[18 * kBlock];  // per-thread cell ranges of the current slab
     extern __shared__ float s_rl2[];  // [nt*nt] list radii^2, then [nt*nt] swap flags
     const int nt = a.tab.nt;
     int* s_swap = reinterpret_cast<int*>(s_rl2 + nt * nt);
@@ -376,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
     int total = 0;
     if (i < a.N) {
         total = list_one(i, a.pos[i], a.box, a.g, 0u, 0, a.cell_start, a.pos, nt, a.k_max, a.N, a.nlist, a.nn,
-                         [&](int q, float& rl2, bool& swap) {
+                         s_col + threadIdx.x, [&](int q, float& rl2, bool& swap) {
                              rl2 = s_rl2[q];
                              swap = s_swap[q] != 0;
                          });
@@ -388,6 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
 // Batches: each wave lies in one replica, which gives the box, grid, key
 // range and table; empty slots get an empty list.
 __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
+    __shared__ int s_col[18 * kBlock];  // per-thread cell ranges of the current slab
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int total = 0;
     if (i < a.N) {
@@ -395,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
         const DevEntry* t = a.tab.e + d.tab;
         if (i < d.off + d.n) {
             total = list_one(i, a.pos[i], d.box, d.grid, d.key_base, d.shift, a.cell_start, a.pos, a.tab.nt, a.k_max,
-                             a.N, a.nlist, a.nn, [&](int q, float& rl2, bool& swap) {
+                             a.N, a.nlist, a.nn, s_col + threadIdx.x, [&](int q, float& rl2, bool& swap) {
                                  rl2 = t[q].rlist2;
                                  swap = t[q].kind == RC_KIND_SWAP;
                              });

@@ -9,6 +9,7 @@
 //   force on the centre:                minus the sum of the two
 #include "rc_internal.h"
 #include "rc_gather.h"
+#include "rc_step.h"
 
 namespace rc {
 
@@ -320,9 +321,6 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
     const bool live = m < lim;
     const uint64_t step = a.step + (a.step_base ? *a.step_base : 0ull);
     Acc acc = {};
-    float kin[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float path = 0.0f, path_in = 0.0f;
-    bool bad = false, lost = false;
     const float4 pm = live ? a.pos_in[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int packed = live ? a.nn[m] : 0;
@@ -331,84 +329,7 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
                             a.ssum);
     if (!BATCH && a.bonds && live)
         fene_add<EV>(ptag(pm.w), pm, a.bonds, a.rtag, a.pos_in, box, a.fene_k, a.fene_r02, acc);
-    if (live) {
-        path_in = vm.w;
-        const int tm = ptype(pm.w);
-        const float minv = a.minv[tm];
-        const float hdt = 0.5f * a.dt;
-        float vx = vm.x, vy = vm.y, vz = vm.z;
-        if (a.mode == RC_STEP_CONT || a.mode == RC_STEP_FINISH) {  // final B of the previous step
-            vx += hdt * acc.fx * minv;
-            vy += hdt * acc.fy * minv;
-            vz += hdt * acc.fz * minv;
-        }
-        if (EV) {
-            const float mm = 1.0f / minv;
-            kin[0] = mm * vx * vx; kin[1] = mm * vy * vy; kin[2] = mm * vz * vz;
-            kin[3] = mm * vx * vy; kin[4] = mm * vx * vz; kin[5] = mm * vy * vz;
-        }
-        if (a.mode == RC_STEP_FINISH || a.mode == RC_STEP_OBSERVE) {
-            if (a.mode == RC_STEP_FINISH) a.vel[m] = make_float4(vx, vy, vz, vm.w);
-            path = vm.w;
-        } else {
-            vx += hdt * acc.fx * minv;  // B
-            vy += hdt * acc.fy * minv;
-            vz += hdt * acc.fz * minv;
-            float sx = hdt * vx, sy = hdt * vy, sz = hdt * vz;  // A (first half of the drift)
-            if (a.langevin) {                                  // O
-                float z0, z1, z2;
-                thermostat_normals(seed, (uint32_t)(ptag(pm.w) - tag0), step, z0, z1, z2);
-                const float c2 = a.c2[tm];
-                vx = a.c1 * vx + c2 * z0;
-                vy = a.c1 * vy + c2 * z1;
-                vz = a.c1 * vz + c2 * z2;
-            }
-            sx += hdt * vx;  // A
-            sy += hdt * vy;
-            sz += hdt * vz;
-            float x = pm.x + sx, y = pm.y + sy, z = pm.z + sz;
-            int ix = 0, iy = 0, iz = 0;
-            if (x >= box.hf[0]) { x -= box.Lf[0]; ix = 1; } else if (x < -box.hf[0]) { x += box.Lf[0]; ix = -1; }
-            if (y >= box.hf[1]) { y -= box.Lf[1]; iy = 1; } else if (y < -box.hf[1]) { y += box.Lf[1]; iy = -1; }
-            if (z >= box.hf[2]) { z -= box.Lf[2]; iz = 1; } else if (z < -box.hf[2]) { z += box.Lf[2]; iz = -1; }
-            path = vm.w + sqrtf(sx * sx + sy * sy + sz * sz);
-            lost = fabsf(sx) > box.hf[0] || fabsf(sy) > box.hf[1] || fabsf(sz) > box.hf[2];
-            bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
-                    isfinite(vz));
-            a.pos_out[m] = make_float4(x, y, z, pm.w);
-            a.vel[m] = make_float4(vx, vy, vz, path);
-            if (a.image && (ix | iy | iz)) {
-                int4 im = a.image[m];
-                im.x += ix;
-                im.y += iy;
-                im.z += iz;
-                a.image[m] = im;
-            }
-        }
-    }
-    // ---- status: per-block slots, plain stores (no same-address atomics) ----------
-    // Each block (one wave) ORs its flags and keeps its first soft/hard step in
-    // its own slot of blk[]; k_fold_status folds the slots once per chunk.
-    const bool soft = live && (a.mode == RC_STEP_START || a.mode == RC_STEP_CONT) && path > a.soft;
-    const bool hard = live && path_in > a.hard;
-    const unsigned long long bs = __ballot(soft), bh = __ballot(hard), bb = __ballot(bad),
-                             bl = __ballot(lost);
-    if (threadIdx.x == 0) {
-        const int fl = (bs ? RC_FLAG_REBUILD : 0) | (bh ? RC_FLAG_STALE : 0) | (bb ? RC_FLAG_NONFINITE : 0) |
-                       (bl ? RC_FLAG_LOST : 0);
-        if (fl) {
-            int* slot = a.blk + 3 * blockIdx.x;
-            const int st = (int)(step & 0x7fffffff);
-            slot[0] |= fl;
-            if (fl & RC_FLAG_REBUILD) slot[1] = min(slot[1], st);
-            if (fl & RC_FLAG_STALE) slot[2] = min(slot[2], st);
-        }
-    }
-    if (EV) {
-        double v[13] = {acc.e,  acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5],
-                        kin[0], kin[1],   kin[2],   kin[3],   kin[4],   kin[5]};
-        wave_sum_store<13>(v, a.ev_part + (size_t)blk * kEvWords);
-    }
+    step_finish<EV>(a, m, blk, live, pm, vm, acc, box, tag0, seed, step);
 }
 
 // Step kernels by (ev, batch, width, form); log steps use the default width.
@@ -424,6 +345,7 @@ static const void* step_fn_form(bool ev, int width) {
 
 template <bool BATCH>
 static const void* step_fn(bool ev, int width, int form) {
+    if (!BATCH && form == RC_FORM_HEAD) return step_head_fn(ev);
     return form == RC_FORM_SUMS ? step_fn_form<BATCH, true>(ev, width) : step_fn_form<BATCH, false>(ev, width);
 }
 

@@ -26,17 +26,32 @@ __device__ __forceinline__ void load_table(DevEntry* s_tab, const Table& t) {
     __syncthreads();
 }
 
+// Position of particle j: from the wavefront's LDS copy of the positions of
+// particles [base, base + 64) when j is one of them (most list neighbours are:
+// the particles are in Morton order), else from global memory.
+struct PosWin {
+    const float4* s;   // LDS copy, or NULL (always global)
+    int base;
+    __device__ __forceinline__ float4 get(const float4* pos, int j) const {
+        const unsigned lj = (unsigned)(j - base);
+        float4 p;
+        if (s && lj < (unsigned)kWave) p = s[lj];
+        else p = pos[j];
+        return p;
+    }
+};
+
 // Walk of particle m's list: the swap range (slots 0 .. ns-1) and, unless
 // SWAP_ONLY, the other range (slots k_max-1 down to k_max-no).  For every
 // neighbour j != skip inside its cutoff (canonical FP64 decision) the functor
 // gets (j, pj, entry, r2 in FP64, r2 in FP32, d = x_j - x_m in FP32).
 template <bool SWAP_ONLY, typename F>
-__device__ __forceinline__ void walk_list(int m, const float4& pm, int tm, const int* nlist, int packed,
-                                          int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
-                                          const Box& box, int skip, F&& f) {
+__device__ __forceinline__ void walk_list_w(int m, const float4& pm, int tm, const int* nlist, int packed,
+                                            int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
+                                            const Box& box, int skip, PosWin win, F&& f) {
     auto visit = [&](int j) {
         if (j == skip) return;
-        const float4 pj = pos[j];
+        const float4 pj = win.get(pos, j);
         const DevEntry& e = tab[tm * nt + ptype(pj.w)];
         if (e.kind == RC_KIND_NONE) return;
         double dx, dy, dz;
@@ -52,14 +67,21 @@ __device__ __forceinline__ void walk_list(int m, const float4& pm, int tm, const
     }
 }
 
+template <bool SWAP_ONLY, typename F>
+__device__ __forceinline__ void walk_list(int m, const float4& pm, int tm, const int* nlist, int packed,
+                                          int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
+                                          const Box& box, int skip, F&& f) {
+    walk_list_w<SWAP_ONLY>(m, pm, tm, nlist, packed, k_max, N, pos, tab, nt, box, skip, PosWin{nullptr, 0}, f);
+}
+
 // sum of w_ck over the swap partners k of centre c inside r_cut, except 'skip'
 // (only c's swap range is read: for a bonded pair it usually holds skip alone)
 __device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, int skip,
                                                        const int* nlist, const int* nn, int k_max, int N,
                                                        const float4* pos, const DevEntry* tab,
-                                                       int nt, const Box& box) {
+                                                       int nt, const Box& box, PosWin win = PosWin{nullptr, 0}) {
     float s = 0.0f;
-    walk_list<true>(c, pc, ptype(pc.w), nlist, nn[c], k_max, N, pos, tab, nt, box, skip,
+    walk_list_w<true>(c, pc, ptype(pc.w), nlist, nn[c], k_max, N, pos, tab, nt, box, skip, win,
                     [&](int, const float4&, const DevEntry& e, double r2d, float r2, float, float, float) {
                         s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, r2);
                     });
@@ -118,6 +140,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     constexpr int W = kPerLane * kWave;  // entries per pass
     __shared__ int s_off[kWave + 1];
     __shared__ int s_ns[kWave];
+    __shared__ unsigned char s_own[W];  // owner lane of each entry of the current pass
     __shared__ float4 s_pos[kWave];
     __shared__ float s_S[SF ? kWave : 1];
     __shared__ float s_c[NC][W];
@@ -137,10 +160,17 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     s_pos[lane] = pm;
     if (SF) s_S[lane] = live ? ssum[base_m + lane] : 0.0f;
     __syncthreads();
+    const PosWin win{s_pos, base_m};
     const int T = s_off[kWave];
     double S = 0.0;
     int nact = 0;
     for (int base = 0; base < T; base += W) {
+        // owner map of the pass: each lane marks its own entries in the window
+        {
+            const int q1 = min(my_off + cnt, base + W) - base;
+            for (int q = max(my_off, base) - base; q < q1; ++q) s_own[q] = (unsigned char)lane;
+        }
+        __syncthreads();
         // locate and load all entries of this pass first, so their memory
         // latencies overlap (list index, then neighbour position)
         int own[kPerLane], jj[kPerLane];
@@ -154,12 +184,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
             jj[u] = 0;
             sw[u] = false;
             if (e < T) {
-                int lo = 0, hi = kWave - 1;  // owner: last lane whose range starts at or before e
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[mid] <= e) lo = mid;
-                    else hi = mid - 1;
-                }
+                const int lo = s_own[e - base];
                 const int sl = e - s_off[lo], nso = s_ns[lo];
                 sw[u] = sl < nso;
                 const int slot = sw[u] ? sl : k_max - 1 - (sl - nso);
@@ -169,8 +194,12 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
         }
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
-            pj[u] = own[u] >= 0 ? pos[jj[u]] : pm;
-            if (SF) sj[u] = sw[u] ? ssum[jj[u]] : 0.0f;
+            pj[u] = pm;
+            if (own[u] >= 0) pj[u] = win.get(pos, jj[u]);
+            if (SF) {
+                const unsigned lj = (unsigned)(jj[u] - base_m);
+                sj[u] = sw[u] ? (lj < (unsigned)kWave ? s_S[lj] : ssum[jj[u]]) : 0.0f;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
@@ -188,14 +217,12 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                     const double r2d = canon_r2(po, pj[u], box, dxd, dyd, dzd);
                     if (r2d < en.rcut2) {
                         const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
-                        float phi, g;
-                        pair_eval(en, r2, phi, g);
+                        float phi, g, uu, u1r;
+                        pair_vhat_eval(en, en.kind == RC_KIND_SWAP, r2d <= en.rmin2, r2, phi, g, uu, u1r);
                         float f = g;
                         float h = -0.5f * g;     // virial weight of d (x) d
                         float e3 = 0.0f;         // triplet energy share (sums form)
                         if (en.kind == RC_KIND_SWAP) {
-                            float uu, u1r;
-                            vhat_eval(en, r2d <= en.rmin2, r2, uu, u1r);
                             const float w = en.sqrt_lam * uu;
                             if (SF) {
                                 const float so = s_S[own[u]] - w;   // S_m - w
@@ -212,7 +239,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                                 if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
                                     f += en.sqrt_lam * u1r *
                                          partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt,
-                                                               box);
+                                                               box, win);
                             }
                         }
                         if (EV) {
@@ -250,7 +277,8 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     if (!SF && live && nact >= 2) {
         const int m = base_m + lane;
         float prefix = 0.0f;
-        walk_list<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, ctx.table(lane), nt, ctx.boxof(lane), -1,
+        walk_list_w<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, ctx.table(lane), nt, ctx.boxof(lane), -1,
+                          win,
                         [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
                             float dz) {
                             float u, u1r;

@@ -82,35 +82,45 @@ __device__ __forceinline__ double canon_r2(const float4& pi, const float4& pj, c
 // --------------------------------------------------------------------------
 // FP32 term arithmetic
 // --------------------------------------------------------------------------
-__device__ __forceinline__ float ipowf(float x, int n) {
+// x^k by squaring; the exponents of the workloads (k = 3 for the WCA term,
+// k = 5 for n = 10) are unrolled into the same products the loop forms
+__device__ __forceinline__ float ipowf(float x, int k) {
+    if (k == 5) {
+        const float x2 = x * x;
+        return x * (x2 * x2);
+    }
+    if (k == 3) return x * (x * x);
     float r = 1.0f;
-    while (n) {
-        if (n & 1) r *= x;
+    while (k) {
+        if (k & 1) r *= x;
         x *= x;
-        n >>= 1;
+        k >>= 1;
     }
     return r;
 }
 
+// 1/r^2 by the hardware reciprocal (1 ulp): every r^-2 factor of a term uses it
+__device__ __forceinline__ float inv_r2(float r2) { return __builtin_amdgcn_rcpf(r2); }
+
 // q = (sigma/r)^n from s2 = sigma^2 / r^2
 __device__ __forceinline__ float qpow(float s2, int n) {
     float q = ipowf(s2, n >> 1);
-    if (n & 1) q *= sqrtf(s2);
+    if (n & 1) q *= __builtin_amdgcn_sqrtf(s2);
     return q;
 }
 
 // Pair term (eq. 2b for SWAP; WCA = n 6 plus the +eps shift): energy phi and
 // g = phi'(r)/r, so that the force on i from the pair is g * (x_j - x_i).
 __device__ __forceinline__ void pair_eval(const DevEntry& e, float r2, float& phi, float& g) {
-    float s2 = e.sig2 / r2;
-    float q = qpow(s2, e.n);
+    const float ir2 = inv_r2(r2);
+    float q = qpow(e.sig2 * ir2, e.n);
     float q2 = q * q;
     phi = 4.0f * e.eps * (q2 - q) + (e.kind == RC_KIND_WCA ? e.eps : 0.0f);
-    g = 4.0f * e.eps * (float)e.n * (q - 2.0f * q2) / r2;
+    g = 4.0f * e.eps * (float)e.n * (q - 2.0f * q2) * ir2;
 }
 
 // Switching factor of eq. (pot) inside the cutoff: u and u'(r)/r.
-// 'inside' is the canonical FP64 decision r^2 <= r_min^2.
+// 'inside' is the canonical decision r^2 <= r_min^2.
 __device__ __forceinline__ void vhat_eval(const DevEntry& e, bool inside, float r2, float& u,
                                           float& u1r) {
     if (inside) {
@@ -118,16 +128,33 @@ __device__ __forceinline__ void vhat_eval(const DevEntry& e, bool inside, float 
         u1r = 0.0f;
         return;
     }
-    float s2 = e.sig2 / r2;
-    float q = qpow(s2, e.n);
+    const float ir2 = inv_r2(r2);
+    float q = qpow(e.sig2 * ir2, e.n);
     float q2 = q * q;
     u = 4.0f * __fmaf_rn(-q, q, q);   // explicit fma: the same bits in every kernel
-    u1r = 4.0f * (float)e.n * (2.0f * q2 - q) / r2;
+    u1r = 4.0f * (float)e.n * (2.0f * q2 - q) * ir2;
+}
+
+// pair_eval and vhat_eval of one entry sharing 1/r^2 and (sigma/r)^n (the
+// same values as the two calls)
+__device__ __forceinline__ void pair_vhat_eval(const DevEntry& e, bool swap, bool inside, float r2, float& phi,
+                                               float& g, float& u, float& u1r) {
+    const float ir2 = inv_r2(r2);
+    const float q = qpow(e.sig2 * ir2, e.n);
+    const float q2 = q * q;
+    phi = 4.0f * e.eps * (q2 - q) + (e.kind == RC_KIND_WCA ? e.eps : 0.0f);
+    g = 4.0f * e.eps * (float)e.n * (q - 2.0f * q2) * ir2;
+    u = 0.0f;
+    u1r = 0.0f;
+    if (swap) {
+        u = inside ? 1.0f : 4.0f * __fmaf_rn(-q, q, q);
+        u1r = inside ? 0.0f : 4.0f * (float)e.n * (2.0f * q2 - q) * ir2;
+    }
 }
 
 __device__ __forceinline__ float vhat_value(const DevEntry& e, bool inside, float r2) {
     if (inside) return 1.0f;
-    float q = qpow(e.sig2 / r2, e.n);
+    float q = qpow(e.sig2 * inv_r2(r2), e.n);
     return 4.0f * __fmaf_rn(-q, q, q);
 }
 
@@ -188,8 +215,10 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
     }
     return c;
@@ -203,14 +232,14 @@ __device__ __forceinline__ void thermostat_normals(uint64_t seed, uint32_t tag, 
                                                    float& z0, float& z1, float& z2) {
     U4 w = philox10(U4{tag, (uint32_t)step, (uint32_t)(step >> 32), 0u}, (uint32_t)seed,
                     (uint32_t)(seed >> 32));
-    float r0 = sqrtf(-2.0f * logf(u01(w.x)));
-    float r1 = sqrtf(-2.0f * logf(u01(w.z)));
-    float s0, c0, s1, c1;
-    sincosf(6.283185307179586f * u01(w.y), &s0, &c0);
-    sincosf(6.283185307179586f * u01(w.w), &s1, &c1);
-    z0 = r0 * c0;
-    z1 = r0 * s0;
-    z2 = r1 * c1;
+    // v_sin_f32 / v_cos_f32 take the angle in revolutions: sin(2 pi u) is one
+    // instruction; the radius keeps the library logarithm (accurate near u = 1)
+    const float r0 = __builtin_amdgcn_sqrtf(-2.0f * logf(u01(w.x)));
+    const float r1 = __builtin_amdgcn_sqrtf(-2.0f * logf(u01(w.z)));
+    const float a0 = u01(w.y), a1 = u01(w.w);
+    z0 = r0 * __builtin_amdgcn_cosf(a0);
+    z1 = r0 * __builtin_amdgcn_sinf(a0);
+    z2 = r1 * __builtin_amdgcn_cosf(a1);
 }
 
 // --------------------------------------------------------------------------
@@ -292,7 +321,7 @@ struct StepArgs {
     const int* chunk_rep;      // [N / 64] replica of each 64-slot chunk
     const uint64_t* seeds;     // [R] thermostat keys
     int width;                 // gather width of the non-logging steps: 1, 2 or 4 (read by the launcher)
-    int form;                  // RC_FORM_WALK or RC_FORM_SUMS (read by the launcher)
+    int form;                  // RC_FORM_WALK, RC_FORM_SUMS or RC_FORM_HEAD (read by the launcher)
     float* ssum;               // [N] per-particle switching sums (RC_FORM_SUMS)
     // FENE springs (single systems; NULL bonds = none)
     const int2* bonds;         // [N] partner tags per tag, -1 = none
@@ -301,6 +330,8 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
+// the head-form step kernel (same launch shape and arguments as k_step)
+const void* step_head_fn(bool ev);
 void step_kernel_info(bool ev, int width, int form, const void** fn);
 hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s);
 void step_batch_kernel_info(int width, int form, const void** fn);

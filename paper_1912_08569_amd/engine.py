@@ -177,7 +177,8 @@ class System:
         self.ctx.set_gather_width(width)
 
     def set_step_form(self, form: str):
-        """"walk" (one pass, partner sums by list walks) or "sums" (two passes): speed only."""
+        """"walk" (one pass, partner sums by list walks), "sums" (two passes) or "head" (the walk form with
+        list heads read ahead, for short lists): speed only."""
         self.ctx.set_step_form(form)
 
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):

@@ -87,8 +87,8 @@ __global__ __launch_bounds__(kWave) void k_forces_triplet(ForceArgs a, int want_
     float w6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int nact = 0;
     walk_list<false>(i, pi, ti, a.nlist, cnt, a.k_max, a.N, a.pos, s_tab, nt, a.box, -1,
-                         [&](int, const float4&, const DevEntry& e, double, float r2, float dx, float dy,
-                             float dz) {
+                         [&](int, const float4&, const DevEntry& e, const PairGeom& pg) {
+                             const float r2 = pg.r2, dx = pg.dx, dy = pg.dy, dz = pg.dz;
                              float phi, g;
                              pair_eval(e, r2, phi, g);
                              fx += g * dx;
@@ -126,10 +126,10 @@ __global__ __launch_bounds__(kWave) void k_forces_triplet(ForceArgs a, int want_
         if (mine) {
             int q = off - round_start;
             walk_list<true>(i, pi, ti, a.nlist, cnt, a.k_max, a.N, a.pos, s_tab, nt, a.box, -1,
-                                 [&](int j, const float4&, const DevEntry& e, double r2d, float r2,
-                                     float dx, float dy, float dz) {
+                                 [&](int j, const float4&, const DevEntry& e, const PairGeom& pg) {
+                                     const float dx = pg.dx, dy = pg.dy, dz = pg.dz;
                                      float u, u1r;
-                                     vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                                     vhat_eval(e, pg.inside, pg.r2, u, u1r);
                                      p_j[q] = j;
                                      p_w[q] = e.sqrt_lam * u;
                                      p_g[q] = e.sqrt_lam * u1r;
@@ -403,8 +403,8 @@ __global__ __launch_bounds__(kBlock) void k_bonds(const float4* __restrict__ pos
     if (i < N) {
         const float4 pi = pos[i];
         walk_list<true>(i, pi, ptype(pi.w), nlist, nn[i], k_max, N, pos, s_tab, tab.nt, box, -1,
-                        [&](int j, const float4&, const DevEntry& e, double r2d, float, float, float, float) {
-                            if (j > i && r2d < e.rmin2) ++c;
+                        [&](int j, const float4&, const DevEntry&, const PairGeom& pg) {
+                            if (j > i && pg.bond) ++c;
                         });
     }
 #pragma unroll
@@ -491,8 +491,8 @@ __global__ __launch_bounds__(kWave) void k_bonds_batch(const float4* __restrict_
     if (i < d.off + d.n) {
         const float4 pi = pos[i];
         walk_list<true>(i, pi, ptype(pi.w), nlist, nn[i], k_max, N, pos, s_tab, tab.nt, d.box, -1,
-                        [&](int j, const float4&, const DevEntry& e, double r2d, float, float, float, float) {
-                            if (j > i && r2d < e.rmin2) ++c;
+                        [&](int j, const float4&, const DevEntry&, const PairGeom& pg) {
+                            if (j > i && pg.bond) ++c;
                         });
     }
 #pragma unroll

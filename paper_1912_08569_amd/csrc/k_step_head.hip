@@ -49,15 +49,14 @@ __device__ __forceinline__ void head_eval(const DevEntry* trow, const float4& pm
     e.on = 0;
     const DevEntry& en = trow[ptype(pj.w)];
     if (en.kind == RC_KIND_NONE) return;
-    double dxd, dyd, dzd;
-    const double r2d = canon_r2(pm, pj, box, dxd, dyd, dzd);
-    if (!(r2d < en.rcut2)) return;
-    const float r2 = (float)r2d;
-    e.dx = (float)dxd;
-    e.dy = (float)dyd;
-    e.dz = (float)dzd;
+    const PairGeom pg = pair_geom(pm, pj, box, en);
+    if (!pg.cut) return;
+    const float r2 = pg.r2;
+    e.dx = pg.dx;
+    e.dy = pg.dy;
+    e.dz = pg.dz;
     float uu;
-    pair_vhat_eval(en, en.kind == RC_KIND_SWAP, r2d <= en.rmin2, r2, e.phi, e.g, uu, e.u1r);
+    pair_vhat_eval(en, en.kind == RC_KIND_SWAP, pg.inside, r2, e.phi, e.g, uu, e.u1r);
     e.f = e.g;
     e.on = 1;
     if (en.kind == RC_KIND_SWAP) {
@@ -77,10 +76,9 @@ __device__ __forceinline__ float hop_term(const DevEntry* tab, int nt, const flo
                                           const Box& box) {
     const DevEntry& e = tab[ptype(pj.w) * nt + ptype(pk.w)];
     if (e.kind == RC_KIND_NONE) return 0.0f;
-    double dx, dy, dz;
-    const double r2d = canon_r2(pj, pk, box, dx, dy, dz);
-    if (!(r2d < e.rcut2)) return 0.0f;
-    return e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, (float)r2d);
+    const PairGeom g = pair_geom(pj, pk, box, e);
+    if (!g.cut) return 0.0f;
+    return e.sqrt_lam * vhat_value(e, g.inside, g.r2);
 }
 
 // accumulation of one entry in slot order; the products are rounded before the
@@ -299,11 +297,10 @@ __device__ __forceinline__ void step_head_body(const StepArgs& a) {
                     head_centre<EV>(es[s].w, es[s].u1r, es[s].sl, es[s].dx, es[s].dy, es[s].dz, S, prefix, acc);
         } else {
             walk_list<true>(m, pm, ptype(pm.w), nl, packed, K, N, pos, s_tab, nt, box, -1,
-                            [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
-                                float dz) {
+                            [&](int, const float4&, const DevEntry& e, const PairGeom& g) {
                                 float u, u1r;
-                                vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
-                                head_centre<EV>(e.sqrt_lam * u, u1r, e.sqrt_lam, dx, dy, dz, S, prefix, acc);
+                                vhat_eval(e, g.inside, g.r2, u, u1r);
+                                head_centre<EV>(e.sqrt_lam * u, u1r, e.sqrt_lam, g.dx, g.dy, g.dz, S, prefix, acc);
                             });
         }
     }

@@ -43,8 +43,8 @@ struct PosWin {
 
 // Walk of particle m's list: the swap range (slots 0 .. ns-1) and, unless
 // SWAP_ONLY, the other range (slots k_max-1 down to k_max-no).  For every
-// neighbour j != skip inside its cutoff (canonical FP64 decision) the functor
-// gets (j, pj, entry, r2 in FP64, r2 in FP32, d = x_j - x_m in FP32).
+// neighbour j != skip inside its cutoff (canonical decision) the functor gets
+// (j, pj, entry, geometry of m -> j).
 template <bool SWAP_ONLY, typename F>
 __device__ __forceinline__ void walk_list_w(int m, const float4& pm, int tm, const int* nlist, int packed,
                                             int k_max, int N, const float4* pos, const DevEntry* tab, int nt,
@@ -54,10 +54,9 @@ __device__ __forceinline__ void walk_list_w(int m, const float4& pm, int tm, con
         const float4 pj = win.get(pos, j);
         const DevEntry& e = tab[tm * nt + ptype(pj.w)];
         if (e.kind == RC_KIND_NONE) return;
-        double dx, dy, dz;
-        const double r2d = canon_r2(pm, pj, box, dx, dy, dz);
-        if (!(r2d < e.rcut2)) return;
-        f(j, pj, e, r2d, (float)r2d, (float)dx, (float)dy, (float)dz);
+        const PairGeom g = pair_geom(pm, pj, box, e);
+        if (!g.cut) return;
+        f(j, pj, e, g);
     };
     const int ns = nn_swap(packed);
     for (int s = 0; s < ns; ++s) visit(nlist[(size_t)s * N + m]);
@@ -82,8 +81,8 @@ __device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, 
                                                        int nt, const Box& box, PosWin win = PosWin{nullptr, 0}) {
     float s = 0.0f;
     walk_list_w<true>(c, pc, ptype(pc.w), nlist, nn[c], k_max, N, pos, tab, nt, box, skip, win,
-                    [&](int, const float4&, const DevEntry& e, double r2d, float r2, float, float, float) {
-                        s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, r2);
+                    [&](int, const float4&, const DevEntry& e, const PairGeom& g) {
+                        s += e.sqrt_lam * vhat_value(e, g.inside, g.r2);
                     });
     return s;
 }
@@ -160,7 +159,6 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     s_pos[lane] = pm;
     if (SF) s_S[lane] = live ? ssum[base_m + lane] : 0.0f;
     __syncthreads();
-    const PosWin win{s_pos, base_m};
     const int T = s_off[kWave];
     double S = 0.0;
     int nact = 0;
@@ -195,7 +193,14 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
             pj[u] = pm;
-            if (own[u] >= 0) pj[u] = win.get(pos, jj[u]);
+            if (own[u] >= 0) {
+                // neighbours among the wave's own 64 particles come from its LDS copy
+                const unsigned lj = (unsigned)(jj[u] - base_m);
+                if (lj < (unsigned)kWave)
+                    pj[u] = s_pos[lj];
+                else
+                    pj[u] = pos[jj[u]];
+            }
             if (SF) {
                 const unsigned lj = (unsigned)(jj[u] - base_m);
                 sj[u] = sw[u] ? (lj < (unsigned)kWave ? s_S[lj] : ssum[jj[u]]) : 0.0f;
@@ -213,12 +218,11 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                 const Box& box = ctx.boxof(own[u]);
                 const DevEntry& en = tab[ptype(po.w) * nt + ptype(pj[u].w)];
                 if (en.kind != RC_KIND_NONE) {
-                    double dxd, dyd, dzd;
-                    const double r2d = canon_r2(po, pj[u], box, dxd, dyd, dzd);
-                    if (r2d < en.rcut2) {
-                        const float r2 = (float)r2d, dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                    const PairGeom pg = pair_geom(po, pj[u], box, en);
+                    if (pg.cut) {
+                        const float r2 = pg.r2, dx = pg.dx, dy = pg.dy, dz = pg.dz;
                         float phi, g, uu, u1r;
-                        pair_vhat_eval(en, en.kind == RC_KIND_SWAP, r2d <= en.rmin2, r2, phi, g, uu, u1r);
+                        pair_vhat_eval(en, en.kind == RC_KIND_SWAP, pg.inside, r2, phi, g, uu, u1r);
                         float f = g;
                         float h = -0.5f * g;     // virial weight of d (x) d
                         float e3 = 0.0f;         // triplet energy share (sums form)
@@ -239,7 +243,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                                 if (u1r != 0.0f && en.sqrt_lam != 0.0f)  // owner is a partner of centre j
                                     f += en.sqrt_lam * u1r *
                                          partner_sum_excluding(jj[u], pj[u], mo, nlist, nn, k_max, N, pos, tab, nt,
-                                                               box, win);
+                                                               box);
                             }
                         }
                         if (EV) {
@@ -277,12 +281,11 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     if (!SF && live && nact >= 2) {
         const int m = base_m + lane;
         float prefix = 0.0f;
-        walk_list_w<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, ctx.table(lane), nt, ctx.boxof(lane), -1,
-                          win,
-                        [&](int, const float4&, const DevEntry& e, double r2d, float r2, float dx, float dy,
-                            float dz) {
+        walk_list<true>(m, pm, ptype(pm.w), nlist, packed, k_max, N, pos, ctx.table(lane), nt, ctx.boxof(lane), -1,
+                        [&](int, const float4&, const DevEntry& e, const PairGeom& g) {
+                            const float dx = g.dx, dy = g.dy, dz = g.dz;
                             float u, u1r;
-                            vhat_eval(e, r2d <= e.rmin2, r2, u, u1r);
+                            vhat_eval(e, g.inside, g.r2, u, u1r);
                             const float w = e.sqrt_lam * u;
                             const float excl = (float)(S - (double)w);
                             const float c = e.sqrt_lam * u1r * excl;  // centre gets +c d
@@ -317,9 +320,9 @@ __device__ __forceinline__ float swap_sum(int m, const float4& pm, int packed, c
         for (int u = 0; u < 4; ++u) {
             if (j[u] < 0) continue;
             const DevEntry& e = tab[tm * nt + ptype(p[u].w)];
-            double dx, dy, dz;
-            const double r2d = canon_r2(pm, p[u], box, dx, dy, dz);
-            if (r2d < e.rcut2) s += e.sqrt_lam * vhat_value(e, r2d <= e.rmin2, (float)r2d);
+            if (e.kind == RC_KIND_NONE) continue;
+            const PairGeom g = pair_geom(pm, p[u], box, e);
+            if (g.cut) s += e.sqrt_lam * vhat_value(e, g.inside, g.r2);
         }
     }
     return s;

@@ -213,6 +213,13 @@ int compile_table(int nt, const rc_pair_coeff* table, double r_buff, DevEntry* o
                 e.sig2 = (float)(p.sigma * p.sigma);
                 e.rcut2 = p.r_cut * p.r_cut;
                 e.rmin2 = (p.sigma * p.sigma) * std::pow(2.0, 2.0 / (double)(p.kind == RC_KIND_SWAP ? p.n : 6));
+                // guard bands of the FP32 decisions (pair_geom)
+                auto band = [](double t, float& lo, float& hi) {
+                    lo = std::nextafter((float)(t * (1.0 - 2e-6)), 0.0f);
+                    hi = std::nextafter((float)(t * (1.0 + 2e-6)), INFINITY);
+                };
+                band(e.rcut2, e.rcut2_lo, e.rcut2_hi);
+                band(e.rmin2, e.rmin2_lo, e.rmin2_hi);
                 const double rl = p.r_cut + r_buff;
                 e.rlist2 = (float)(rl * rl * (1.0 + 1e-5));
                 rmax = std::max(rmax, rl);

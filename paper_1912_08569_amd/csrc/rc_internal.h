@@ -20,8 +20,10 @@ constexpr int kStepBlock = 64;       // one wavefront per block: the step and ga
 constexpr int kScanItems = 8;        // counts per thread in the scan kernels
 constexpr int kScanTile = kBlock * kScanItems;
 
-// One compiled table entry (64 bytes).  FP32 values feed the term arithmetic;
-// the FP64 squares feed the canonical cut / bond decisions.
+// One compiled table entry (80 bytes).  FP32 values feed the term arithmetic;
+// the FP64 squares feed the canonical cut / bond decisions; the FP32 band
+// edges [lo, hi] around them bracket the squares that FP32 rounding could put
+// on the wrong side (see pair_geom).
 struct alignas(16) DevEntry {
     int kind;          // RC_KIND_*
     int n;             // exponent (6 for WCA)
@@ -34,7 +36,8 @@ struct alignas(16) DevEntry {
     float inv_eps;     // 1/eps (SWAP), 0 otherwise
     float sigma;       // sigma
     float lam;         // lambda (SWAP), 0 otherwise
-    float pad[3];
+    float rcut2_lo, rcut2_hi;   // r_cut^2 (1 -+ 2e-6), rounded outwards
+    float rmin2_lo, rmin2_hi;   // r_min^2 (1 -+ 2e-6), rounded outwards
 };
 
 struct Box {
@@ -77,6 +80,48 @@ __device__ __forceinline__ double canon_r2(const float4& pi, const float4& pj, c
     // plain operators under contract(off): each product and sum rounds separately
     const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
     return (xx + yy) + zz;
+}
+
+// Geometry of one pair (i -> j) under one table entry: the FP32 minimum-image
+// difference and square, and the canonical decisions.  Where x_j - x_i needs
+// no periodic fold the FP32 difference is the exact difference rounded once
+// (the same value as the canonical FP64 difference converted), and its FP32
+// square is within 4e-7 relative of the canonical one; a decision is then
+// taken in FP32 when the square lies outside the table's 2e-6 band around the
+// threshold.  Pairs across a periodic face, and squares inside a band, take
+// the canonical FP64 path, so every decision equals canon_r2's.
+struct PairGeom {
+    float dx, dy, dz;  // x_j - x_i (minimum image)
+    float r2;
+    bool cut;          // r^2 <  r_cut^2
+    bool inside;       // r^2 <= r_min^2
+    bool bond;         // r^2 <  r_min^2
+};
+
+__device__ __forceinline__ PairGeom pair_geom(const float4& pi, const float4& pj, const Box& b, const DevEntry& e) {
+    PairGeom g;
+    g.dx = pj.x - pi.x;
+    g.dy = pj.y - pi.y;
+    g.dz = pj.z - pi.z;
+    const bool wrap = fabsf(g.dx) > b.hf[0] || fabsf(g.dy) > b.hf[1] || fabsf(g.dz) > b.hf[2];
+    g.r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
+    g.cut = g.r2 < e.rcut2_lo;
+    g.inside = g.r2 < e.rmin2_lo;
+    g.bond = g.inside;
+    const bool sure = !wrap && (g.cut || g.r2 > e.rcut2_hi) &&
+                      (e.kind != RC_KIND_SWAP || g.inside || g.r2 > e.rmin2_hi);
+    if (!sure) {
+        double dx, dy, dz;
+        const double r2d = canon_r2(pi, pj, b, dx, dy, dz);
+        g.dx = (float)dx;
+        g.dy = (float)dy;
+        g.dz = (float)dz;
+        g.r2 = (float)r2d;
+        g.cut = r2d < e.rcut2;
+        g.inside = r2d <= e.rmin2;
+        g.bond = r2d < e.rmin2;
+    }
+    return g;
 }
 
 // --------------------------------------------------------------------------

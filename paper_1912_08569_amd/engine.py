@@ -32,9 +32,13 @@ class System:
     ``table`` (kind, epsilon, sigma, n, rcut, lam arrays), optional ``vel`` (N,3).
     """
 
+    # mean list length above which the two-pass (sums) form of the step beats the one-pass walk form
+    AUTO_SUMS_KBAR = 2.5
+
     def __init__(self, pos, types, L, table, vel=None, mass=None, r_buff: float = 0.3, k_max: int = 32,
-                 rollback: bool = True, device: str = "cuda", bonds=None, fene=None):
+                 rollback: bool = True, device: str = "cuda", bonds=None, fene=None, step_form: str = "auto"):
         self.device = torch.device(device)
+        self.step_form = step_form
         self.ctx = api.Context(table, r_buff)
         self.table = table
         self.N = int(np.asarray(pos).shape[0])
@@ -106,6 +110,8 @@ class System:
             if code != rcl.RC_OK:
                 raise RcError(code, "neighbour list build")
             self.built = True
+            if self.step_form == "auto":
+                self.ctx.set_step_form("sums" if self.mean_list_length() > self.AUTO_SUMS_KBAR else "walk")
             return st[rcl.RC_ST_KMAX]
         raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
 
@@ -177,9 +183,20 @@ class System:
         self.ctx.set_gather_width(width)
 
     def set_step_form(self, form: str):
-        """"walk" (one pass, partner sums by list walks), "sums" (two passes) or "head" (the walk form with
-        list heads read ahead, for short lists): speed only."""
-        self.ctx.set_step_form(form)
+        """"walk" (one pass, partner sums by list walks), "sums" (two passes), "head" (the walk form with
+        list heads read ahead, for short lists) or "auto" (walk or sums by the mean list length, chosen at
+        every build of the list from Python): speed only."""
+        self.step_form = form
+        if form == "auto":
+            if self.built:
+                self.ctx.set_step_form("sums" if self.mean_list_length() > self.AUTO_SUMS_KBAR else "walk")
+        else:
+            self.ctx.set_step_form(form)
+
+    def mean_list_length(self) -> float:
+        """Mean neighbour-list length of the last build (swap and other ranges)."""
+        nn = self.nn
+        return float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())
 
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
         return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))

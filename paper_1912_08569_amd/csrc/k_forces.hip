@@ -589,6 +589,25 @@ hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* s
     return hipGetLastError();
 }
 
+// the driver's snapshot of (pos, vel, image) and its restore, in one launch
+__global__ __launch_bounds__(kBlock) void k_copy_state(const float4* __restrict__ pos, const float4* __restrict__ vel,
+                                                      const int4* __restrict__ image, float4* __restrict__ pos_to,
+                                                      float4* __restrict__ vel_to, int4* __restrict__ image_to,
+                                                      int N) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    pos_to[i] = pos[i];
+    vel_to[i] = vel[i];
+    if (image && image_to) image_to[i] = image[i];
+}
+
+hipError_t launch_copy_state(const float4* pos, const float4* vel, const int4* image, float4* pos_to, float4* vel_to,
+                             int4* image_to, int N, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_state, dim3(nblk(N, kBlock)), dim3(kBlock), 0, s, pos, vel, image, pos_to, vel_to,
+                       image_to, N);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_blk_reset(int* __restrict__ blk, int nb) {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
         blk[3 * b] = 0;

@@ -39,6 +39,8 @@ struct rc_ctx {
     const int* bonds_rtag = nullptr;    // tag -> index map the springs read (caller-owned)
     int bonds_n = 0;
     double fene_k = 0.0, fene_r0 = 0.0;
+    int* h_status = nullptr;            // pinned host copy of a status word (driver waits)
+    hipEvent_t ev_sync = nullptr;       // the driver's wait event (no timing)
     GraphCache gc;
     std::string err;
 };
@@ -69,6 +71,8 @@ CellsLayout cells_layout(int N, uint32_t nkeys);
 int ensure_part(rc_ctx* c, size_t bytes);
 int ensure_ssum(rc_ctx* c, size_t n);   // d_ssum for n particles (drops graphs when it moves)
 void free_ctx_buffers(rc_ctx* c);       // every device buffer the context owns
+// copy a device status word to the host and wait for it by spinning on an event
+int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s);
 int ensure_blk(rc_ctx* c, int nb, hipStream_t s);
 int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin);
 int check_list(rc_ctx* c, const int* nlist, const int* nn, int k_max);

@@ -102,8 +102,27 @@ int ensure_ssum(rc_ctx* c, size_t n) {
     return RC_OK;
 }
 
+int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s) {
+    if (!c->h_status) HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(int) * RC_STATUS_WORDS));
+    if (!c->ev_sync) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
+    HIP_TRY(c, hipMemcpyAsync(c->h_status, d_status, sizeof(int) * RC_STATUS_WORDS, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipEventRecord(c->ev_sync, s));
+    // a blocking synchronisation costs tens of microseconds of wake-up per call; the driver calls
+    // this once per chunk, so it spins on the event instead
+    hipError_t e;
+    while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "waiting for the status word");
+    std::memcpy(hst, c->h_status, sizeof(int) * RC_STATUS_WORDS);
+    return RC_OK;
+}
+
 void free_ctx_buffers(rc_ctx* c) {
     drop_graphs(c);
+    if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    c->ev_sync = nullptr;
+    c->h_status = nullptr;
     if (c->d_tab) (void)hipFree(c->d_tab);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_step_base) (void)hipFree(c->d_step_base);
@@ -310,13 +329,20 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
 
     float* P[2] = {buf->pos, buf->pos_alt};
     int cur = 0;
+    // Rollback state: one snapshot per list build (an epoch).  Every chunk of an epoch before the
+    // last ran without a soft crossing (a soft crossing ends the epoch with a rebuild), so a chunk
+    // that goes stale is replayed from the epoch's start up to its first soft crossing.
+    bool need_snap = true;
+    int64_t epoch_start = 0;
+    int epoch_cur = 0, epoch_row = 0;
+    bool epoch_first = true;
 
     auto rebuild = [&](int which) -> int {
         int rr = ops.rebuild(P[which]);
         if (rr) return rr;
-        HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
+        if ((rr = read_status_spin(c, buf->status, hst, s))) return rr;
         ++st.rebuilds;
+        need_snap = true;
         if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW) {
             st.k_needed = hst[RC_ST_KMAX];
             return fail(c, RC_ERR_NLIST_OVERFLOW, "a particle has %d neighbours (k_max %d)", hst[RC_ST_KMAX],
@@ -389,14 +415,18 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             C = std::min<int64_t>(C, 8);
         }
         const int64_t chunk_start = done;
-        const int row_start = row;
-        const int cur_start = cur;
-        const bool first_start = first;
-        if (can_roll) {
-            HIP_TRY(c, hipMemcpyAsync(buf->snap_pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(c, hipMemcpyAsync(buf->snap_vel, buf->vel, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
-            if (buf->image)
-                HIP_TRY(c, hipMemcpyAsync(buf->snap_image, buf->image, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+        if (can_roll && need_snap) {
+            HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(P[cur]),
+                                         reinterpret_cast<const float4*>(buf->vel),
+                                         reinterpret_cast<const int4*>(buf->image),
+                                         reinterpret_cast<float4*>(buf->snap_pos),
+                                         reinterpret_cast<float4*>(buf->snap_vel),
+                                         reinterpret_cast<int4*>(buf->snap_image), N, s));
+            epoch_start = done;
+            epoch_cur = cur;
+            epoch_first = first;
+            epoch_row = row;
+            need_snap = false;
         }
         HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
         // ---- run it --------------------------------------------------------------
@@ -437,8 +467,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         };
         if ((r = run_steps(chunk_start, C))) return finish(r);
         HIP_TRY(c, launch_fold_status(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
-        HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
+        if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
         ++st.chunks;
         const int f = hst[RC_ST_FLAGS];
         if (f & RC_FLAG_LOST) return finish(fail(c, RC_ERR_LOST_PARTICLE, "a particle moved more than L/2 in one step"));
@@ -447,21 +476,22 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         std::memcpy(&mp, &hst[RC_ST_MAXPATH], sizeof mp);
         if (f & RC_FLAG_STALE) {
             if (!can_roll) return finish(fail(c, RC_ERR_ARG, "stale list without rollback buffers"));
-            // roll back and replay up to the first soft crossing, then rebuild
-            cur = cur_start;
-            first = first_start;
-            row = row_start;
-            HIP_TRY(c, hipMemcpyAsync(P[cur], buf->snap_pos, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(c, hipMemcpyAsync(buf->vel, buf->snap_vel, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
-            if (buf->image)
-                HIP_TRY(c, hipMemcpyAsync(buf->image, buf->snap_image, 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+            // roll back to the epoch's snapshot and replay up to the first soft crossing, then rebuild
+            cur = epoch_cur;
+            first = epoch_first;
+            row = epoch_row;
+            HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(buf->snap_pos),
+                                         reinterpret_cast<const float4*>(buf->snap_vel),
+                                         reinterpret_cast<const int4*>(buf->snap_image),
+                                         reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
+                                         reinterpret_cast<int4*>(buf->image), N, s));
             const int64_t soft_step = (int64_t)hst[RC_ST_FIRST_SOFT];
-            int64_t n_re = soft_step - (int64_t)((step0 + (uint64_t)chunk_start) & 0x7fffffff) + 1;
-            n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, C));
+            int64_t n_re = soft_step - (int64_t)((step0 + (uint64_t)epoch_start) & 0x7fffffff) + 1;
+            n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, chunk_start + C - epoch_start));
             HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
-            if ((r = run_steps(chunk_start, n_re))) return finish(r);
+            if ((r = run_steps(epoch_start, n_re))) return finish(r);
             HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
-            done = chunk_start + n_re;
+            done = epoch_start + n_re;
             ++st.rollbacks;
             if ((r = rebuild(cur))) return finish(r);
             rate = std::max(rate, (double)mp / std::max<int64_t>(1, C));

@@ -300,6 +300,16 @@ int rc_time_fused_steps(rc_ctx* ctx, float* pos_a, float* pos_b, float* vel, con
                         const int* nn, int k_max, int N, rc_box box, const rc_integrator* cfg /* host */,
                         uint64_t step0, int reps, int* status, float* ms /* host */, void* stream);
 
+/* ---- bond partners (the bond autocorrelation of the paper's swap test) --------
+ * partner (device int32 [N], indexed by TAG, overwritten): the tag of the one
+ * swap partner bonded to the particle (canonical r^2 < r_min^2, as for the
+ * bond count), -1 if it has no bond, -2 if it has more than one.  The bond
+ * autocorrelation (Sec. 3.1: the fraction of the bonds of time 0 that are
+ * still unswapped at time t) is the fraction of particles whose partner at t
+ * equals their partner at 0.  Requires tags < N (as rtag does).              */
+int rc_bond_partners(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
+                     rc_box box, int* partner /* [N] */, void* stream);
+
 /* ---- bond count (hot-path step a4) -------------------------------------------
  * Number of swap pairs i<j with r^2 < r_min^2 (canonical FP64 predicate, the
  * bond criterion of the swap system), written to *count (device, uint64).
@@ -391,7 +401,10 @@ int rc_fene_forces(rc_ctx* ctx, const float* pos, int N, rc_box box, float* forc
  *   w ignored/zero): second derivatives of the pair terms (phi'', phi'/r) and
  *   of the triplets through vhat, vhat', vhat'' (vhat'' = -v''/eps beyond
  *   r_min, 0 inside; H is defined off the r_min and r_cut shells).  The force
- *   JVP is -hv.  Atomic-free gather (deterministic).
+ *   JVP is -hv.  Atomic-free gather (deterministic) in two passes: the first
+ *   keeps every particle's switching sum and its derivative along v in
+ *   context-owned scratch (16 bytes per particle), the second reads a
+ *   partner's sums from there.
  * rc_param_grad: grad[(a*nt + b)*3 + {0,1,2}] = dE/d(eps, sigma, lambda) of the
  *   unordered entry {a, b} (reported on both (a,b) and (b,a)), FP64, fixed
  *   r_cut.  Device output, overwritten.

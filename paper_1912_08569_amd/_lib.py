@@ -124,6 +124,7 @@ _SIGS = {
     "rc_set_table": ([_VP, ctypes.POINTER(PairCoeff)], _I),
     "rc_soft_bonds": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
     "rc_set_bonds": ([_VP, _VP, _VP, _I, _D, _D], _I),
+    "rc_bond_partners": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
     "rc_fene_forces": ([_VP, _VP, _I, Box, _VP, _VP, _VP], _I),
     # batches
     "rc_batch_create": ([ctypes.POINTER(_VP), _I, _I, ctypes.POINTER(PairCoeff), ctypes.POINTER(_I),

@@ -21,7 +21,7 @@ __all__ = [
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
-    "rc_param_vjp", "rc_soft_bonds", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
+    "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
     "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
     "rc_batch_time_fused_steps",
 ]
@@ -253,6 +253,13 @@ def rc_soft_bonds(ctx: Context, pos, nlist, nn, bx, value, grad=None, stream=Non
     N = pos.shape[0]
     check(L.load().rc_soft_bonds(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(value),
                                  _ptr(grad), _stream(stream)), ctx.handle)
+
+
+def rc_bond_partners(ctx: Context, pos, nlist, nn, bx, partner, stream=None):
+    """partner: (N,) int32 device tensor, by tag: the bonded partner's tag, -1 none, -2 several."""
+    N = pos.shape[0]
+    check(L.load().rc_bond_partners(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
+                                    _ptr(partner), _stream(stream)), ctx.handle)
 
 
 def rc_set_bonds(ctx: Context, bonds, rtag, K: float, R0: float):

@@ -10,7 +10,10 @@
 //     D_ma = v_a - v_m,  dr_ma = rhat_ma . D_ma,
 //     dG_ma = phi'' dr + w'' dr (S_m + S_a - 2 w) + w' (dS_m + dS_a - 2 w' dr),
 //     dS_m = sum_b w'_mb dr_mb.
-// S_a and dS_a come from a two-hop walk over a's list.
+// A first pass stores (S, dS) of every particle; the second reads S_a and dS_a
+// of a partner from there instead of walking a's list (the two-hop walk of
+// the one-pass form; the values are those of the same walk, so the result is
+// the same).
 #include "rc_internal.h"
 
 namespace rc {
@@ -78,6 +81,17 @@ __device__ __forceinline__ void centre_sums(int c, const float4& pc, const float
     }
 }
 
+// first pass: (S, dS) of every particle
+__global__ __launch_bounds__(kBlock) void k_hvp_sums(HvpArgs a) {
+    extern __shared__ DevEntry s_tab[];
+    load_table_adj(s_tab, a.tab);
+    const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    if (m >= a.N) return;
+    double S, dS;
+    centre_sums(m, a.pos[m], a.v[m], a.nlist, a.nn, a.k_max, a.N, a.pos, a.v, s_tab, a.tab.nt, a.box, S, dS);
+    a.sums[m] = make_double2(S, dS);
+}
+
 __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
     extern __shared__ DevEntry s_tab[];
     load_table_adj(s_tab, a.tab);
@@ -89,8 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
     const int tm = ptype(pm.w);
     const int packed = a.nn[m];
     const int ns = nn_swap(packed), cnt = ns + nn_other(packed);
-    double Sm, dSm;
-    centre_sums(m, pm, vm, a.nlist, a.nn, a.k_max, a.N, a.pos, a.v, s_tab, nt, a.box, Sm, dSm);
+    const double2 sm = a.sums[m];
+    const double Sm = sm.x, dSm = sm.y;
     float hx = 0.f, hy = 0.f, hz = 0.f;
     for (int s = 0; s < cnt; ++s) {
         const int slot = s < ns ? s : a.k_max - 1 - (s - ns);
@@ -113,8 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
             float w, w1, w2;
             w_d012(e, r2d <= e.rmin2, r2, r, w, w1, w2);
             if (w1 != 0.0f || w2 != 0.0f) {
-                double Sj, dSj;
-                centre_sums(j, pj, vj, a.nlist, a.nn, a.k_max, a.N, a.pos, a.v, s_tab, nt, a.box, Sj, dSj);
+                const double2 sj = a.sums[j];
+                const double Sj = sj.x, dSj = sj.y;
                 const float X = (float)((Sm - (double)w) + (Sj - (double)w));
                 const float dX = (float)((dSm - (double)(w1 * dr)) + (dSj - (double)(w1 * dr)));
                 G += w1 * X;
@@ -131,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
 
 hipError_t launch_hvp(const HvpArgs& a, hipStream_t s) {
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    hipLaunchKernelGGL(k_hvp_sums, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
     hipLaunchKernelGGL(k_hvp, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
     return hipGetLastError();
 }

@@ -418,6 +418,34 @@ __global__ __launch_bounds__(kBlock) void k_bonds(const float4* __restrict__ pos
     }
 }
 
+// bond partner of every particle, by tag: the tag of its one bonded swap partner
+// (canonical r^2 < r_min^2), -1 when it has none, -2 when it has several
+__global__ __launch_bounds__(kBlock) void k_bond_partners(const float4* __restrict__ pos,
+                                                         const int* __restrict__ nlist,
+                                                         const int* __restrict__ nn, int k_max, int N, Table tab,
+                                                         Box box, int* __restrict__ partner) {
+    extern __shared__ DevEntry s_tab[];
+    load_table(s_tab, tab);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float4 pi = pos[i];
+    int p = -1;
+    walk_list<true>(i, pi, ptype(pi.w), nlist, nn[i], k_max, N, pos, s_tab, tab.nt, box, -1,
+                    [&](int, const float4& pj, const DevEntry&, const PairGeom& pg) {
+                        if (pg.bond) p = (p == -1) ? ptag(pj.w) : -2;
+                    });
+    const int t = ptag(pi.w);
+    if (t >= 0 && t < N) partner[t] = p;   // tags >= N have no slot (documented requirement: tags < N)
+}
+
+hipError_t launch_bond_partners(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                                Box box, int* partner, hipStream_t s) {
+    const size_t shm = sizeof(DevEntry) * tab.nt * tab.nt;
+    hipLaunchKernelGGL(k_bond_partners, dim3(nblk(N, kBlock)), dim3(kBlock), shm, s, pos, nlist, nn, k_max, N, tab,
+                       box, partner);
+    return hipGetLastError();
+}
+
 // one block: sum nb partial counts into *out (fixed order: exact either way)
 __global__ __launch_bounds__(1024) void k_sum_u64(const unsigned long long* __restrict__ part, int nb,
                                                  unsigned long long* __restrict__ out) {

@@ -469,6 +469,20 @@ int rc_bond_count(rc_ctx* c, const float* pos, const int* nlist, const int* nn, 
     return RC_OK;
 }
 
+int rc_bond_partners(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
+                     int* partner, void* stream) {
+    int r = check_common(c, N, pos);
+    if (r) return r;
+    if (!nlist || !nn || !partner) return fail(c, RC_ERR_ARG, "nlist / nn / partner are NULL");
+    if (N > RC_MAX_TAG) return fail(c, RC_ERR_ARG, "too many particles for tag-indexed output");
+    Box b;
+    if ((r = make_box(c, box, b))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    HIP_TRY(c, launch_bond_partners(reinterpret_cast<const float4*>(pos), nlist, nn, k_max, N, dev_table(c), b,
+                                    partner, S(stream)));
+    return RC_OK;
+}
+
 int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box, const float* v,
                  float* hv, void* stream) {
     int r = check_common(c, N, pos);
@@ -487,6 +501,8 @@ int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, i
     a.box = b;
     a.v = reinterpret_cast<const float4*>(v);
     a.hv = reinterpret_cast<float4*>(hv);
+    if ((r = ensure_hsum(c, (size_t)N))) return r;
+    a.sums = reinterpret_cast<double2*>(c->d_hsum);
     HIP_TRY(c, launch_hvp(a, S(stream)));
     return RC_OK;
 }

@@ -35,6 +35,8 @@ struct rc_ctx {
     int step_form = RC_FORM_WALK;       // RC_FORM_WALK | RC_FORM_SUMS | RC_FORM_HEAD
     float* d_ssum = nullptr;            // per-particle switching sums of the sums form
     size_t ssum_cap = 0;                // floats allocated
+    double* d_hsum = nullptr;           // per-particle (S, dS) of the Hessian-vector product
+    size_t hsum_cap = 0;                // particles allocated
     const int* bonds = nullptr;         // FENE partner table (caller-owned, [n_bonded][2] by tag)
     const int* bonds_rtag = nullptr;    // tag -> index map the springs read (caller-owned)
     int bonds_n = 0;
@@ -69,7 +71,8 @@ struct CellsLayout {
 CellsLayout cells_layout(int N, uint32_t nkeys);
 
 int ensure_part(rc_ctx* c, size_t bytes);
-int ensure_ssum(rc_ctx* c, size_t n);   // d_ssum for n particles (drops graphs when it moves)
+int ensure_ssum(rc_ctx* c, size_t n);
+int ensure_hsum(rc_ctx* c, size_t n);   // d_hsum for n particles   // d_ssum for n particles (drops graphs when it moves)
 void free_ctx_buffers(rc_ctx* c);       // every device buffer the context owns
 // copy a device status word to the host and wait for it by spinning on an event
 int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s);

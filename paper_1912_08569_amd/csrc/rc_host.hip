@@ -117,6 +117,17 @@ int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s) {
     return RC_OK;
 }
 
+int ensure_hsum(rc_ctx* c, size_t n) {
+    if (c->hsum_cap >= n) return RC_OK;
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->d_hsum) (void)hipFree(c->d_hsum);
+    c->d_hsum = nullptr;
+    c->hsum_cap = 0;
+    HIP_TRY(c, hipMalloc(&c->d_hsum, 2 * sizeof(double) * n));
+    c->hsum_cap = n;
+    return RC_OK;
+}
+
 void free_ctx_buffers(rc_ctx* c) {
     drop_graphs(c);
     if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
@@ -128,6 +139,9 @@ void free_ctx_buffers(rc_ctx* c) {
     if (c->d_step_base) (void)hipFree(c->d_step_base);
     if (c->d_blk) (void)hipFree(c->d_blk);
     if (c->d_ssum) (void)hipFree(c->d_ssum);
+    if (c->d_hsum) (void)hipFree(c->d_hsum);
+    c->d_hsum = nullptr;
+    c->hsum_cap = 0;
     c->d_tab = nullptr;
     c->d_part = nullptr;
     c->d_step_base = nullptr;

@@ -464,6 +464,9 @@ hipError_t launch_nlist(const NlistArgs& a, hipStream_t s);
 // count: device u64 result; part: scratch of ceil(N / kBlock) u64
 hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
                         Box box, unsigned long long* count, unsigned long long* part, hipStream_t s);
+// tag of each particle's single bonded partner (-1 none, -2 several), indexed by tag
+hipError_t launch_bond_partners(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,
+                                Box box, int* partner, hipStream_t s);
 hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s);
 hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s);
 
@@ -489,6 +492,7 @@ struct HvpArgs {
     Box box;
     const float4* v;
     float4* hv;
+    double2* sums;             // [N] scratch: (S, dS) of every particle (first pass)
 };
 hipError_t launch_hvp(const HvpArgs& a, hipStream_t s);
 

@@ -132,6 +132,12 @@ class System:
                 self.ev[:7] += self.ev_fene
         return self.force, (self.ev[:7] if ev else None)
 
+    def bond_partners(self) -> np.ndarray:
+        """Bond partner of every particle, by tag (the partner's tag; -1 none, -2 several)."""
+        out = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        api.rc_bond_partners(self.ctx, self.pos, self.nlist, self.nn, self.box, out)
+        return out.cpu().numpy()
+
     def bond_count(self) -> int:
         if not self.built:
             self.build()

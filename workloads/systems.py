@@ -241,6 +241,34 @@ def assembly_mixture(N=1048576, lam=1.0, density=0.3, seed=1003, kT=0.05,
                   name=f"assembly N={N} lambda={lam}", meta={"lam": lam})
 
 
+def dumbbell_table(rcut=1.3, n=100, lam=1.0) -> PairTable:
+    """The bond-swap test mixture of the paper's Sec. 3.1: type 0 = A, type 1 = B.
+
+    A-B swap term (eps 1, sigma 1, exponent n = 100, cutoff r_cut, lambda);
+    A-A and B-B WCA (eps 1, sigma 1)."""
+    t = PairTable.empty(2)
+    t.set(0, 0, KIND_WCA, 1.0, 1.0, 6)
+    t.set(1, 1, KIND_WCA, 1.0, 1.0, 6)
+    t.set(0, 1, KIND_SWAP, 1.0, 1.0, n, rcut, lam)
+    return t
+
+
+def dumbbell_mixture(N=1000, rcut=1.3, density=0.125, seed=1006, kT=0.03, frac_b=0.4,
+                     min_dist=0.95) -> System:
+    """N particles, A:B = 3:2 at number density 0.125 (the paper's Sec. 3.1 and its performance
+    figure, N = 2^9 ... 2^17): at kT 0.03 every B binds one A, and the A surplus is the reservoir the
+    swaps draw on.  Uniform random sequential addition rejecting distances <= min_dist."""
+    rng = np.random.default_rng(seed)
+    L = fp32_box(N, density)
+    nb = int(round(frac_b * N))
+    tab = dumbbell_table(rcut)
+    pos, types = rsa_positions(rng, L, [N - nb, nb], np.full((2, 2), min_dist))
+    mass = np.ones(2)
+    vel = maxwell_velocities(rng, types, mass, kT)
+    return System(pos=pos, types=types, L=L, table=tab, mass=mass, vel=vel,
+                  name=f"dumbbell mixture N={N} r_cut={rcut}")
+
+
 def replica_set(R=256, seed=1004, n_lo=500, n_hi=20000, kT=0.1) -> List[System]:
     """Independent replicas with N ~ logU[n_lo, n_hi], rho ~ U[0.2, 0.4],
     lambda ~ U[0, 1.5] and inert WCA fraction ~ U[0, 0.5].

@@ -357,6 +357,36 @@ def bond_count(pos, types, L, table) -> int:
     return int(np.count_nonzero((P["kind"] == KIND_SWAP) & (P["r2"] < P["rmin2"])))
 
 
+def bond_partners(pos, types, L, table) -> np.ndarray:
+    """Per particle (in the order of pos): the index of its single bonded swap partner
+    (r^2 < r_min^2), -1 without a bond, -2 with more than one."""
+    P = interacting_pairs(pos, types, L, table)
+    m = (P["kind"] == KIND_SWAP) & (P["r2"] < P["rmin2"])
+    i, j = P["i"][m], P["j"][m]
+    deg = np.zeros(P["N"], np.int64)
+    np.add.at(deg, i, 1)
+    np.add.at(deg, j, 1)
+    out = np.full(P["N"], -1, np.int64)
+    out[i] = j
+    out[j] = i
+    out[deg > 1] = -2
+    return out
+
+
+def bond_autocorrelation(partners0, partners_t, mask=None) -> float:
+    """Fraction of the bonds present in partners0 that are still present (same partner) in
+    partners_t (the bond autocorrelation of the paper's swap test, Sec. 3.1); mask selects the
+    particles counted (e.g. the minority species, whose every member is bonded)."""
+    p0 = np.asarray(partners0)
+    pt = np.asarray(partners_t)
+    keep = p0 >= 0
+    if mask is not None:
+        keep &= np.asarray(mask, bool)
+    if not np.any(keep):
+        return float("nan")
+    return float(np.mean(pt[keep] == p0[keep]))
+
+
 def bond_degree(pos, types, L, table) -> np.ndarray:
     """Per-particle number of bonded swap partners (r^2 < r_min^2)."""
     P = interacting_pairs(pos, types, L, table)

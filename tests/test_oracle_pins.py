@@ -302,6 +302,47 @@ def test_bond_count_threshold_and_pair_kinds():
     assert ev(pos, ty, 30.0, tab)["bonds"] == 1
 
 
+def test_bond_partners_and_autocorrelation():
+    # the bond autocorrelation of the swap test (Sec. 3.1): fraction of the bonds of time 0 whose
+    # partner is unchanged at t.  Clusters: a bonded A-B dimer, a B bonded to two A (a triplet at
+    # r_min), a free A, and an A-B bond across the periodic face.
+    rm = math.sqrt(swap_ref.rmin2_canonical(1.0, 10))
+    tab = two_type_table(1.0)
+    L = 30.0
+    pos = [[0, 0, 0], [0.9 * rm, 0, 0],                          # 0-1 dimer
+           [8 - 0.9 * rm, 0, 0], [8, 0, 0], [8 + 0.9 * rm, 0, 0],  # 3 (B) bonded to 2 and 4
+           [-8, 8, 8],                                            # free A
+           [L / 2 - 0.3, -8, 0], [-L / 2 + 0.3, -8, 0]]           # A-B across the face
+    ty = [0, 1, 0, 1, 0, 0, 0, 1]
+    p = swap_ref.bond_partners(pos, ty, L, tab)
+    assert list(p) == [1, 0, 3, -2, 3, -1, 7, 6]
+    assert swap_ref.bond_count(pos, ty, L, tab) == 4
+    # a swap: B 1 leaves A 0 for A 5 (moved next to it); the other bonds stay
+    pos2 = [list(x) for x in pos]
+    pos2[5] = [0.9 * rm + 0.9 * rm, 0, 0]
+    pos2[0] = [-5, -5, -5]
+    p2 = swap_ref.bond_partners(pos2, ty, L, tab)
+    assert p2[1] == 5 and p2[0] == -1 and p2[5] == 1
+    is_b = np.array(ty) == 1
+    # B particles bonded at time 0: 1 (to 0), 7 (to 6); 3 has two bonds (-2) and is not counted
+    assert swap_ref.bond_autocorrelation(p, p2, mask=is_b) == 0.5
+    assert swap_ref.bond_autocorrelation(p, p, mask=is_b) == 1.0
+
+
+def test_dumbbell_mixture_recipe():
+    # the swap-test mixture of Sec. 3.1: A:B = 3:2 (600:400 at N = 1000), density 0.125, A-B swap term
+    # with n = 100 and the chosen cutoff, A-A and B-B WCA
+    s = W.dumbbell_mixture(N=1000, rcut=1.15, seed=3)
+    assert np.bincount(s.types).tolist() == [600, 400]
+    assert s.N / s.L ** 3 == pytest.approx(0.125, rel=1e-5)
+    t = s.table
+    assert t.kind[0, 1] == W.KIND_SWAP and t.n[0, 1] == 100 and t.rcut[0, 1] == 1.15
+    assert t.kind[0, 0] == W.KIND_WCA and t.kind[1, 1] == W.KIND_WCA
+    # v(1.15) for n = 100: about 3e-6 eps, far below the truncation of Lennard-Jones at 2.5 sigma
+    v = 4.0 * ((1 / 1.15) ** 200 - (1 / 1.15) ** 100)
+    assert -4e-6 < v < -3e-6
+
+
 def test_generators_invariants():
     s = W.small_reactive(N=500, density=0.2, seed=1)
     assert s.pos.dtype == np.float32

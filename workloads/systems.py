@@ -254,10 +254,12 @@ def dumbbell_table(rcut=1.3, n=100, lam=1.0) -> PairTable:
 
 
 def dumbbell_mixture(N=1000, rcut=1.3, density=0.125, seed=1006, kT=0.03, frac_b=0.4,
-                     min_dist=0.95) -> System:
+                     min_dist=1.05) -> System:
     """N particles, A:B = 3:2 at number density 0.125 (the paper's Sec. 3.1 and its performance
     figure, N = 2^9 ... 2^17): at kT 0.03 every B binds one A, and the A surplus is the reservoir the
-    swaps draw on.  Uniform random sequential addition rejecting distances <= min_dist."""
+    swaps draw on.  Uniform random sequential addition rejecting distances <= min_dist (1.05 sigma:
+    beyond the minimum r_min = 2^(1/100) sigma of the n = 100 swap term, whose wall a closer start
+    would hit with forces of order 10^7)."""
     rng = np.random.default_rng(seed)
     L = fp32_box(N, density)
     nb = int(round(frac_b * N))

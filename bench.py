@@ -52,6 +52,9 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="batched run with the default launch settings")
     p.add_argument("--no-adjoint", action="store_true", help="skip the forward/adjoint timings")
     p.add_argument("--only-extras", action="store_true", help="skip the 1M-particle run (debugging)")
+    p.add_argument("--no-dumbbells", action="store_true", help="skip the dumbbell-mixture size sweep")
+    p.add_argument("--dumbbell-steps", type=int, default=4000)
+    p.add_argument("--dumbbell-warmup", type=int, default=1000)
     return p.parse_args()
 
 
@@ -258,6 +261,50 @@ def adjoint_bench(a):
     return out
 
 
+def dumbbell_bench(a):
+    """The paper's performance workload: the A:B = 3:2 dumbbell mixture (n = 100, WCA AA/BB, density
+    0.125, kT 0.03) at N = 2^9 ... 2^17 particles and cutoffs 1.3 and 1.15, as timesteps per second.
+    Langevin dt 0.001, neighbour-list skin 0.3, log every 100 steps; each size is relaxed for
+    `dumbbell_warmup` steps from its random start before `dumbbell_steps` timed steps."""
+    import torch
+
+    import workloads as W
+    from paper_1912_08569_amd import System
+
+    rows = []
+    for rcut in (1.3, 1.15):
+        for x in range(9, 18):
+            N = 1 << x
+            s = W.dumbbell_mixture(N=N, rcut=rcut, seed=1100 + x)
+            S = System.from_workload(s, r_buff=0.3)
+            cfg = S.integrator(dt=0.001, kT=0.03, gamma=1.0, seed=2100 + x)
+            S.run(a.dumbbell_warmup, cfg, step0=0, log_period=a.log_period)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = S.run(a.dumbbell_steps, cfg, step0=a.dumbbell_warmup, log_period=a.log_period)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            nn = S.nn
+            kbar = float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())
+            bonds = int(res.bonds[-1]) if res.bonds is not None and len(res.bonds) else None
+            form = S.step_form
+            if form == "auto":   # the form the last list build from Python chose
+                form = S.auto_step_form()
+            rows.append({"N": N, "r_cut": rcut, "steps_per_s": round(a.dumbbell_steps / dt, 1),
+                         "us_per_step": round(dt / a.dumbbell_steps * 1e6, 3),
+                         "particle_steps_per_s": N * a.dumbbell_steps / dt, "mean_list_length": round(kbar, 3),
+                         "step_form": form, "rebuilds": int(res.stats.rebuilds), "bonds": bonds,
+                         "n_b": int(np.count_nonzero(s.types == 1))})
+            print(f"# dumbbells N={N} r_cut={rcut}: {rows[-1]['steps_per_s']:.0f} steps/s "
+                  f"({rows[-1]['us_per_step']:.2f} us/step), k={kbar:.2f}, form {form}, bonds {bonds}",
+                  file=sys.stderr, flush=True)
+            del S
+    torch.cuda.empty_cache()
+    return {"workload": "dumbbell mixture A:B = 3:2, n 100, WCA AA/BB, density 0.125, Langevin kT 0.03 dt 0.001, "
+                        "skin 0.3, log every 100 steps", "unit": "timesteps/s",
+            "warmup": a.dumbbell_warmup, "steps": a.dumbbell_steps, "rows": rows}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -277,6 +324,8 @@ def main():
             out["adjoint"] = adjoint_bench(a)
         if not a.no_batch:
             out["batch"] = batch_bench(a)
+        if not a.no_dumbbells:
+            out["dumbbells"] = dumbbell_bench(a)
         print(json.dumps(out), flush=True)
         return
     t_gen = time.perf_counter()
@@ -368,6 +417,8 @@ def main():
         out["adjoint"] = adjoint_bench(a)
     if not a.no_batch:
         out["batch"] = batch_bench(a)
+    if not a.no_dumbbells:
+        out["dumbbells"] = dumbbell_bench(a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysw, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -32,8 +32,11 @@ class System:
     ``table`` (kind, epsilon, sigma, n, rcut, lam arrays), optional ``vel`` (N,3).
     """
 
-    # mean list length above which the two-pass (sums) form of the step beats the one-pass walk form
-    AUTO_SUMS_KBAR = 2.5
+    # Mean swap-range length from which the two-pass (sums) form of the step beats the one-pass walk
+    # form.  The walk form pays a walk of the partner's swap range for every active swap entry; the
+    # sums form pays one more pass over all particles.  Measured at 8k-1M particles: walk is faster
+    # at 0.14 (site/colloid mixture), the two tie near 0.53, sums is faster from 0.8 on.
+    AUTO_SUMS_KSWAP = 0.5
 
     def __init__(self, pos, types, L, table, vel=None, mass=None, r_buff: float = 0.3, k_max: int = 32,
                  rollback: bool = True, device: str = "cuda", bonds=None, fene=None, step_form: str = "auto"):
@@ -111,7 +114,7 @@ class System:
                 raise RcError(code, "neighbour list build")
             self.built = True
             if self.step_form == "auto":
-                self.ctx.set_step_form("sums" if self.mean_list_length() > self.AUTO_SUMS_KBAR else "walk")
+                self.ctx.set_step_form(self.auto_step_form())
             return st[rcl.RC_ST_KMAX]
         raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
 
@@ -190,14 +193,22 @@ class System:
 
     def set_step_form(self, form: str):
         """"walk" (one pass, partner sums by list walks), "sums" (two passes), "head" (the walk form with
-        list heads read ahead, for short lists) or "auto" (walk or sums by the mean list length, chosen at
+        list heads read ahead, for short lists) or "auto" (walk or sums by the mean swap-range length, chosen at
         every build of the list from Python): speed only."""
         self.step_form = form
         if form == "auto":
             if self.built:
-                self.ctx.set_step_form("sums" if self.mean_list_length() > self.AUTO_SUMS_KBAR else "walk")
+                self.ctx.set_step_form(self.auto_step_form())
         else:
             self.ctx.set_step_form(form)
+
+    def auto_step_form(self) -> str:
+        """The form "auto" picks for the current list: "sums" or "walk"."""
+        return "sums" if self.mean_swap_length() >= self.AUTO_SUMS_KSWAP else "walk"
+
+    def mean_swap_length(self) -> float:
+        """Mean length of the swap range of the last list build."""
+        return float((self.nn & 0xFFFF).float().mean().item())
 
     def mean_list_length(self) -> float:
         """Mean neighbour-list length of the last build (swap and other ranges)."""

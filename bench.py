@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--no-dumbbells", action="store_true", help="skip the dumbbell-mixture size sweep")
     p.add_argument("--dumbbell-steps", type=int, default=4000)
     p.add_argument("--dumbbell-warmup", type=int, default=1000)
+    p.add_argument("--dumbbell-n", type=str, default="", help="comma-separated sizes (default 2^9 ... 2^17)")
+    p.add_argument("--dumbbell-rcut", type=str, default="1.3,1.15", help="comma-separated cutoffs")
     return p.parse_args()
 
 
@@ -272,9 +274,10 @@ def dumbbell_bench(a):
     from paper_1912_08569_amd import System
 
     rows = []
-    for rcut in (1.3, 1.15):
-        for x in range(9, 18):
-            N = 1 << x
+    sizes = [int(v) for v in a.dumbbell_n.split(",")] if a.dumbbell_n else [1 << x for x in range(9, 18)]
+    for rcut in [float(v) for v in a.dumbbell_rcut.split(",")]:
+        for N in sizes:
+            x = N.bit_length() - 1
             s = W.dumbbell_mixture(N=N, rcut=rcut, seed=1100 + x)
             S = System.from_workload(s, r_buff=0.3)
             cfg = S.integrator(dt=0.001, kT=0.03, gamma=1.0, seed=2100 + x)
@@ -287,9 +290,7 @@ def dumbbell_bench(a):
             nn = S.nn
             kbar = float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())
             bonds = int(res.bonds[-1]) if res.bonds is not None and len(res.bonds) else None
-            form = S.step_form
-            if form == "auto":   # the form the last list build from Python chose
-                form = S.auto_step_form()
+            form = S.ctx.step_form
             rows.append({"N": N, "r_cut": rcut, "steps_per_s": round(a.dumbbell_steps / dt, 1),
                          "us_per_step": round(dt / a.dumbbell_steps * 1e6, 3),
                          "particle_steps_per_s": N * a.dumbbell_steps / dt, "mean_list_length": round(kbar, 3),

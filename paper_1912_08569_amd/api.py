@@ -106,6 +106,7 @@ class Context:
         self.handle = h
         self.ntypes = nt
         self.r_buff = float(r_buff)
+        self.step_form = "walk"   # the library's default form
 
     def close(self):
         if getattr(self, "handle", None):
@@ -137,6 +138,7 @@ class Context:
     def set_step_form(self, form: str):
         f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS, "head": L.RC_FORM_HEAD}[form]
         check(L.load().rc_set_step_form(self.handle, f), self.handle)
+        self.step_form = form
 
     def rlist(self, a: int, b: int) -> float:
         out = ctypes.c_double()

@@ -194,7 +194,7 @@ class System:
     def set_step_form(self, form: str):
         """"walk" (one pass, partner sums by list walks), "sums" (two passes), "head" (the walk form with
         list heads read ahead, for short lists) or "auto" (walk or sums by the mean swap-range length, chosen at
-        every build of the list from Python): speed only."""
+        every build of the list from Python and at the start of every run): speed only."""
         self.step_form = form
         if form == "auto":
             if self.built:
@@ -235,6 +235,11 @@ class System:
     def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
             graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True) -> RunResult:
         """Advance n_steps with the fused step kernel under the chunked driver."""
+        if self.step_form == "auto":
+            if not self.built:
+                self.build()    # picks the form from the new list
+            else:               # from the list the last build left
+                self.ctx.set_step_form(self.auto_step_form())
         rows = (n_steps // log_period + 2) if log_period > 0 else 1
         ev_log = torch.zeros((rows, 13), dtype=torch.float64, device=self.device)
         bonds_log = torch.zeros(rows, dtype=torch.int64, device=self.device)

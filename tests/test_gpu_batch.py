@@ -151,7 +151,7 @@ def test_single_replica_batch_is_the_system():
     s = W.small_reactive(N=1000, density=0.2, seed=1001, table=W.swap_table_single(lam=1.0), kT=0.1)
     from paper_1912_08569_amd import System
     B = _batch([s], seeds=[9], r_buff=0.6)
-    S = System.from_workload(s, r_buff=0.6)
+    S = System.from_workload(s, r_buff=0.6, step_form="walk")   # the batch's default form
     cfg = B.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=9)
     rb = B.run(40, cfg, log_period=10)
     rs = S.run(40, cfg, log_period=10)

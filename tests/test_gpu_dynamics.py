@@ -258,3 +258,20 @@ def test_bonds_log_matches_oracle_at_the_end():
     assert int(r.bonds[-1]) == ref["bonds"]
     assert r.bonds[-1] > r.bonds[0]                # bonds form during assembly
     assert abs(r.ev[-1, 0] - ref["E"]) <= 1e-5 * ref["A_E"]
+
+
+def test_auto_form_follows_the_swap_range_length():
+    # "auto" picks the two-pass form for an all-reactive system and the walk form for the site/colloid
+    # mixture, before the first run's steps (speed only: both forms are checked against the oracle)
+    s = W.small_reactive(N=2000, seed=54, kT=0.1)
+    S = _system(s)
+    S.run(20, S.integrator(dt=0.001, kT=0.1, gamma=1.0, seed=1))
+    assert S.mean_swap_length() >= S.AUTO_SUMS_KSWAP and S.ctx.step_form == "sums"
+    m = W.assembly_mixture(N=20000, lam=1.0, seed=24, kT=0.05)
+    M = _system(m)
+    M.run(20, M.integrator(dt=0.001, kT=0.05, gamma=1.0, seed=1))
+    assert M.mean_swap_length() < M.AUTO_SUMS_KSWAP and M.ctx.step_form == "walk"
+    # an explicit form is kept by later runs
+    S.set_step_form("walk")
+    S.run(20, S.integrator(dt=0.001, kT=0.1, gamma=1.0, seed=1), step0=20)
+    assert S.ctx.step_form == "walk"

@@ -293,21 +293,48 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
 // and whether it is a swap pair.  Returns the full neighbour count and stores
 // nn[i] (clipped to k_max).
 //
-// Per z slab the nine cell ranges are read together and kept in the thread's
-// LDS column col[0 .. 17] (stride kBlock); the slab's candidates are then
-// walked as one sequence, two positions in flight, so a wavefront iterates
-// over its longest candidate sequence rather than over nine cells times
-// their largest occupancy.
+// A cell whose nearest point is farther from i than i's largest list radius
+// (over all partner types) is skipped: its count is taken as zero.  The gaps
+// to the cell faces are shrunk by 1e-3 cell widths, far above the FP32
+// rounding of the cell coordinates, so no cell that holds a listable
+// neighbour is skipped.
+//
+// Per z slab the nine cells' candidates are numbered t = 0 .. tot-1 in
+// visiting order (exclusive prefix pre[q] of the cell counts), and candidate t
+// is located without branches: the last cell q with pre[q] <= t gives
+// j = t + (start_q - pre_q).  The offset and the cell's wrap flag are packed in
+// one word, so a candidate costs eight compare/select pairs and a wavefront
+// runs one uniform loop per slab instead of a data-dependent cursor.  The next
+// candidate's position is requested before the current one is tested.
 template <class Radii>
 __device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, const Grid& g, uint32_t key_base,
                                         int shift, const int* __restrict__ cell_start, const float4* __restrict__ pos,
                                         int nt, int k_max, int N, int* __restrict__ nlist, int* __restrict__ nn,
-                                        int* col, Radii rl) {
+                                        Radii rl) {
     int ns = 0, no = 0;
     const int ti = ptype(pi.w);
     const int cx = cell_coord(pi.x, b.hf[0], g.inv_w[0], g.nc[0]);
     const int cy = cell_coord(pi.y, b.hf[1], g.inv_w[1], g.nc[1]);
     const int cz = cell_coord(pi.z, b.hf[2], g.inv_w[2], g.nc[2]);
+    float rmax2 = 0.0f;  // i's largest squared list radius
+    for (int t = 0; t < nt; ++t) {
+        float r2t;
+        bool sw;
+        rl(ti * nt + t, r2t, sw);
+        rmax2 = fmaxf(rmax2, r2t);
+    }
+    // squared gaps from i to the cells at offsets -1, 0, +1 along an axis
+    auto gaps = [&](float x, float h, float inv_w, int c, float& g0, float& g2) {
+        const float f = (x + h) * inv_w - (float)c;  // place in the cell, in widths
+        const float w = 1.0f / inv_w;
+        const float lo = fmaxf(f - 1e-3f, 0.0f) * w, hi = fmaxf(1.0f - f - 1e-3f, 0.0f) * w;
+        g0 = lo * lo;
+        g2 = hi * hi;
+    };
+    float gx0, gx2, gy0, gy2, gz0, gz2;
+    gaps(pi.x, b.hf[0], g.inv_w[0], cx, gx0, gx2);
+    gaps(pi.y, b.hf[1], g.inv_w[1], cy, gy0, gy2);
+    gaps(pi.z, b.hf[2], g.inv_w[2], cz, gz0, gz2);
     // Morton parts of the three cell coordinates per axis, and whether the offset wraps
     int wxy = 0;  // bit o: x offset o wraps; bit 3 + o: y offset o wraps
     auto axis = [&](int c, int o, int nc, int bit) {
@@ -335,7 +362,7 @@ __device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, c
         float rl2;
         bool swap;
         rl(ti * nt + ptype(pj.w), rl2, swap);
-        if (r2 < rl2) {
+        if (r2 < rl2 && j != i) {
             // swap kind from the front, the rest from the back (counters stay in registers)
             const int slot = swap ? ns : k_max - 1 - no;
             if (ns + no < k_max) nlist[(size_t)slot * N + i] = j;
@@ -344,49 +371,57 @@ __device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, c
         }
     };
     for (int oz = -1; oz <= 1; ++oz) {
+        const float dz2 = oz < 0 ? gz0 : (oz > 0 ? gz2 : 0.0f);
+        if (dz2 >= rmax2) continue;
         int z = cz + oz;
         const bool wz = z < 0 || z >= g.nc[2];
         z += (z < 0) ? g.nc[2] : 0;
         z -= (z >= g.nc[2]) ? g.nc[2] : 0;
         const uint32_t kz = spread3((uint32_t)z) << 2;
-        int st[9], en[9];
+        // cell 0's packed word, then cells 1..8: exclusive prefix of the counts and
+        // (start - prefix) * 2 + wraps (vector values, so they stay in registers)
+        typedef int int8v __attribute__((ext_vector_type(8)));
+        int ow0 = 0, tot = 0;
+        int8v pre, ow;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const uint32_t kxq = q % 3 == 0 ? kx0 : (q % 3 == 1 ? kx1 : kx2);
             const uint32_t kyq = q / 3 == 0 ? ky0 : (q / 3 == 1 ? ky1 : ky2);
             const uint32_t key = key_base + (kxq | kyq | kz);
-            st[q] = cell_start[key] + shift;
-            en[q] = cell_start[key + 1] + shift;
-        }
-#pragma unroll
-        for (int q = 1; q < 9; ++q) {
-            col[q * kBlock] = st[q];
-            col[(9 + q) * kBlock] = en[q];
-        }
-        // cursor over the slab's candidates: cell q, next particle j, end e
-        int q = 0, j = st[0], e = en[0];
-        auto next = [&](bool& wrapped) -> int {
-            while (j >= e) {
-                if (q == 8) return -1;
-                ++q;
-                j = col[q * kBlock];
-                e = col[(9 + q) * kBlock];
+            const float d2 = dz2 + (q / 3 == 0 ? gy0 : (q / 3 == 2 ? gy2 : 0.0f)) +
+                             (q % 3 == 0 ? gx0 : (q % 3 == 2 ? gx2 : 0.0f));
+            const int st = cell_start[key] + shift;
+            const int en = d2 < rmax2 ? cell_start[key + 1] + shift : st;
+            const bool wq = wz || (wxy & ((1 << (q % 3)) | (8 << (q / 3)))) != 0;
+            const int o = (st - tot) * 2 + (wq ? 1 : 0);  // st - tot may be negative: >> 1 is arithmetic
+            if (q == 0) {
+                ow0 = o;
+            } else {
+                pre[q - 1] = tot;
+                ow[q - 1] = o;
             }
-            wrapped = wz || (wxy & ((1 << (q % 3)) | (8 << (q / 3)))) != 0;
-            return j++;
-        };
-        for (;;) {
-            bool w0 = false, w1 = false;
-            const int j0 = next(w0);
-            if (j0 < 0) break;
-            const int j1 = next(w1);
-            const float4 p0 = pos[j0];
-            float4 p1 = p0;
-            if (j1 >= 0) p1 = pos[j1];
-            if (j0 != i) consider(j0, p0, w0);
-            if (j1 < 0) break;
-            if (j1 != i) consider(j1, p1, w1);
+            tot += en - st;
         }
+        if (tot == 0) continue;
+#define RC_LOCATE(t, o)                                      \
+    do {                                                     \
+        o = ow0;                                             \
+        _Pragma("unroll") for (int q = 0; q < 8; ++q) o = ((t) >= pre[q]) ? ow[q] : o; \
+    } while (0)
+        int oc;
+        RC_LOCATE(0, oc);
+        float4 pc = pos[oc >> 1];
+        for (int t = 0; t < tot; ++t) {
+            const int jc = t + (oc >> 1);
+            const bool wc = (oc & 1) != 0;
+            const float4 pcur = pc;
+            if (t + 1 < tot) {  // request the next candidate first
+                RC_LOCATE(t + 1, oc);
+                pc = pos[t + 1 + (oc >> 1)];
+            }
+            consider(jc, pcur, wc);
+        }
+#undef RC_LOCATE
     }
     const int total = ns + no;
     // on overflow the stored prefix is what fitted (the status reports it)
@@ -416,7 +451,6 @@ __device__ __forceinline__ void block_max_store(int cnt, int* __restrict__ out) 
 
 // One thread per particle (key order).
 __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
-    __shared__ int s_col[18 * kBlock];  // per-thread cell ranges of the current slab
     extern __shared__ float s_rl2[];  // [nt*nt] list radii^2, then [nt*nt] swap flags
     const int nt = a.tab.nt;
     int* s_swap = reinterpret_cast<int*>(s_rl2 + nt * nt);
@@ -430,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
     int total = 0;
     if (i < a.N) {
         total = list_one(i, a.pos[i], a.box, a.g, 0u, 0, a.cell_start, a.pos, nt, a.k_max, a.N, a.nlist, a.nn,
-                         s_col + threadIdx.x, [&](int q, float& rl2, bool& swap) {
+                         [&](int q, float& rl2, bool& swap) {
                              rl2 = s_rl2[q];
                              swap = s_swap[q] != 0;
                          });
@@ -442,7 +476,6 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
 // Batches: each wave lies in one replica, which gives the box, grid, key
 // range and table; empty slots get an empty list.
 __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
-    __shared__ int s_col[18 * kBlock];  // per-thread cell ranges of the current slab
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int total = 0;
     if (i < a.N) {
@@ -450,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
         const DevEntry* t = a.tab.e + d.tab;
         if (i < d.off + d.n) {
             total = list_one(i, a.pos[i], d.box, d.grid, d.key_base, d.shift, a.cell_start, a.pos, a.tab.nt, a.k_max,
-                             a.N, a.nlist, a.nn, s_col + threadIdx.x, [&](int q, float& rl2, bool& swap) {
+                             a.N, a.nlist, a.nn, [&](int q, float& rl2, bool& swap) {
                                  rl2 = t[q].rlist2;
                                  swap = t[q].kind == RC_KIND_SWAP;
                              });

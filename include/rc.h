@@ -358,7 +358,12 @@ typedef struct rc_md_options {
     int adapt;          /* 1: size chunks from the measured growth of the path
                            lengths so that rollbacks stay rare; 0: always
                            max_chunk steps (rollbacks repair stale chunks)    */
-    int pad;
+    int one_block;      /* 1: with use_graph, a system of at most 1024 particles
+                           (walk or sums form) runs each graph_steps-step replay
+                           as one launch of one workgroup that keeps the
+                           positions in LDS (same results, bit for bit); 0:
+                           hipGraphs only.  Ignored by rc_batch_run.  The
+                           defaults (opt = NULL) are {1, 16, 256, 0, 0.8, 1, 1}. */
 } rc_md_options;
 
 typedef struct rc_md_stats {

@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
                             a.ssum);
     if (!BATCH && a.bonds && live)
         fene_add<EV>(ptag(pm.w), pm, a.bonds, a.rtag, a.pos_in, box, a.fene_k, a.fene_r02, acc);
-    step_finish<EV>(a, m, blk, live, pm, vm, acc, box, tag0, seed, step);
+    step_finish<EV>(a, a.pos_out, m, blk, live, pm, vm, acc, box, tag0, seed, step);
 }
 
 // Step kernels by (ev, batch, width, form); log steps use the default width.

@@ -305,7 +305,7 @@ __device__ __forceinline__ void step_head_body(const StepArgs& a) {
         }
     }
     if (a.bonds && live) fene_add<EV>(ptag(pm.w), pm, a.bonds, a.rtag, pos, box, a.fene_k, a.fene_r02, acc);
-    step_finish<EV>(a, m, blk, live, pm, vm, acc, box, 0, a.seed, step);
+    step_finish<EV>(a, a.pos_out, m, blk, live, pm, vm, acc, box, 0, a.seed, step);
 }
 
 // list heads: two swap slots, three other slots.  The step kernel is held to

@@ -601,6 +601,10 @@ struct PlainOps final : DriveOps {
         sums_kernel_info(false, &fn);
         return fn;
     }
+    bool block_ok() override { return step_block_fits(N, c->nt, c->step_form); }
+    hipError_t launch_block(const StepArgs& a, float4* pos, int G) override {
+        return launch_step_block(a, pos, c->d_step_base, G, s);
+    }
 };
 
 }  // namespace
@@ -615,7 +619,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
     if (c->bonds && buf->rtag != c->bonds_rtag)
         return fail(c, RC_ERR_ARG, "with bonds, the md buffers' rtag must be the one given to rc_set_bonds");
-    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0};
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 1};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
     if (opt.max_chunk < 1) opt.max_chunk = 256;

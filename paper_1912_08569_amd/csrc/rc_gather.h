@@ -129,7 +129,25 @@ struct Stage {
 // PL = flattened entries each lane evaluates per pass (the gather width).
 constexpr int kDefaultWidth = 2;
 
-template <bool EV, int kPerLane, bool SF, class Ctx>
+// Most wavefronts one workgroup of the multi-wave (WS) gather holds.
+constexpr int kGatherMaxWaves = 16;
+
+// Barrier of the gather's LDS exchange.  With one wavefront per block (WS =
+// false) it is the block barrier; with several (WS = true) the exchange stays
+// inside each wavefront, whose trip counts differ, so it is a wavefront-level
+// barrier with workgroup-scope fences (LDS writes complete before the reads).
+template <bool WS>
+__device__ __forceinline__ void gather_sync() {
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <bool EV, int kPerLane, bool SF, class Ctx, bool WS = false>
 __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
                                             const float4* pos, const int* nlist, const int* nn, int k_max,
                                             int N, const Ctx& ctx, Acc& acc, const float* ssum = nullptr) {
@@ -137,13 +155,21 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     constexpr int NC = Stage<EV, SF>::n;
     constexpr int CE = Stage<EV, SF>::e;
     constexpr int W = kPerLane * kWave;  // entries per pass
-    __shared__ int s_off[kWave + 1];
-    __shared__ int s_ns[kWave];
-    __shared__ unsigned char s_own[W];  // owner lane of each entry of the current pass
-    __shared__ float4 s_pos[kWave];
-    __shared__ float s_S[SF ? kWave : 1];
-    __shared__ float s_c[NC][W];
-    const int lane = threadIdx.x;
+    constexpr int NW = WS ? kGatherMaxWaves : 1;  // LDS slices, one per wavefront
+    __shared__ int s_off_w[NW][kWave + 1];
+    __shared__ int s_ns_w[NW][kWave];
+    __shared__ unsigned char s_own_w[NW][W];  // owner lane of each entry of the current pass
+    __shared__ float4 s_pos_w[NW][kWave];
+    __shared__ float s_S_w[NW][SF ? kWave : 1];
+    __shared__ float s_c_w[NW][NC][W];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = WS ? (int)(threadIdx.x / kWave) : 0;
+    int* s_off = s_off_w[wv];
+    int* s_ns = s_ns_w[wv];
+    unsigned char* s_own = s_own_w[wv];
+    float4* s_pos = s_pos_w[wv];
+    float* s_S = s_S_w[wv];
+    float(*s_c)[W] = s_c_w[wv];
     const int ns = live ? nn_swap(packed) : 0;
     const int cnt = live ? ns + nn_other(packed) : 0;
     int inc = cnt;
@@ -158,7 +184,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     s_ns[lane] = ns;
     s_pos[lane] = pm;
     if (SF) s_S[lane] = live ? ssum[base_m + lane] : 0.0f;
-    __syncthreads();
+    gather_sync<WS>();
     const int T = s_off[kWave];
     double S = 0.0;
     int nact = 0;
@@ -168,7 +194,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
             const int q1 = min(my_off + cnt, base + W) - base;
             for (int q = max(my_off, base) - base; q < q1; ++q) s_own[q] = (unsigned char)lane;
         }
-        __syncthreads();
+        gather_sync<WS>();
         // locate and load all entries of this pass first, so their memory
         // latencies overlap (list index, then neighbour position)
         int own[kPerLane], jj[kPerLane];
@@ -260,7 +286,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
 #pragma unroll
             for (int q = 0; q < NC; ++q) s_c[q][u * kWave + lane] = c[q];
         }
-        __syncthreads();
+        gather_sync<WS>();
         const int lo = max(my_off, base) - base, hi = min(my_off + cnt, base + W) - base;
         for (int q = lo; q < hi; ++q) {
             acc.fx += s_c[0][q];
@@ -276,7 +302,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                 for (int w = 0; w < 6; ++w) acc.w[w] += s_c[CE + 1 + w][q];
             }
         }
-        __syncthreads();
+        gather_sync<WS>();
     }
     if (!SF && live && nact >= 2) {
         const int m = base_m + lane;
@@ -362,7 +388,7 @@ template <int NW>
 __device__ __forceinline__ void wave_sum_store(double (&v)[NW], double* out) {
 #pragma unroll
     for (int q = 0; q < NW; ++q) v[q] = wave_sum(v[q]);
-    if (threadIdx.x == 0) {
+    if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
         for (int q = 0; q < NW; ++q) out[q] = v[q];
     }

@@ -103,6 +103,10 @@ struct DriveOps {
     // sums form (NULL for the walk form)
     virtual const void* graph_fn() = 0;
     virtual const void* graph_sums_fn() = 0;
+    // whether graph replays may run as one-workgroup launches of G steps, and
+    // such a launch (a: launch arguments of the replay's first step)
+    virtual bool block_ok() { return false; }
+    virtual hipError_t launch_block(const StepArgs&, float4*, int) { return hipErrorNotSupported; }
 };
 
 // Chunked driver: speculative chunks of fused steps (graph replays where no

@@ -404,7 +404,8 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     const float hard = tmpl.hard;
     const bool graphs = opt.use_graph != 0;
     const int G = opt.graph_steps;
-    if (graphs) {
+    const bool blockrun = graphs && opt.one_block != 0 && ops.block_ok();
+    if (graphs && !blockrun) {
         StepArgs key = tmpl;
         key.pos_in = reinterpret_cast<const float4*>(buf->pos);
         key.pos_out = reinterpret_cast<float4*>(buf->pos_alt);
@@ -464,7 +465,18 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
                     }
                     if (clear) {
                         if (dev_base != step) HIP_TRY(c, launch_set_step(c->d_step_base, step, s));
-                        HIP_TRY(c, hipGraphLaunch(c->gc.exec[cur], s));
+                        if (blockrun) {
+                            StepArgs a = tmpl;
+                            a.pos_in = reinterpret_cast<const float4*>(P[cur]);
+                            a.pos_out = reinterpret_cast<float4*>(P[cur ^ 1]);
+                            a.mode = RC_STEP_CONT;
+                            a.step = 0;
+                            a.step_base = c->d_step_base;
+                            a.ev_part = nullptr;
+                            HIP_TRY(c, ops.launch_block(a, reinterpret_cast<float4*>(P[cur]), G));
+                        } else {
+                            HIP_TRY(c, hipGraphLaunch(c->gc.exec[cur], s));
+                        }
                         dev_base = step + G;
                         k += G;
                         continue;  // G is even: cur is unchanged

@@ -375,6 +375,15 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
+// Small systems (at most kBlockMaxN particles, single system, walk or sums
+// form): G plain steps in one workgroup with the positions in LDS, the same
+// arithmetic as G launches of the step.  pos_final receives the positions
+// (the buffer a.pos_in names), *step_base is read as the first step's index
+// and advanced by G.  step_block_fits says whether a system fits the kernel.
+constexpr int kBlockMaxN = 1024;
+bool step_block_fits(int N, int nt, int form);
+hipError_t launch_step_block(const StepArgs& a, float4* pos_final, unsigned long long* step_base, int G,
+                             hipStream_t s);
 // the head-form step kernel (same launch shape and arguments as k_step)
 const void* step_head_fn(bool ev);
 void step_kernel_info(bool ev, int width, int form, const void** fn);

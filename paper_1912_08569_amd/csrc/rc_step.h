@@ -1,7 +1,9 @@
 // The integrator half of the fused MD step, shared by every step kernel:
 // the final half kick of the previous step with the forces just gathered,
 // then B A O A into pos_out (BAOAB, Leimkuhler & Matthews 2013), the path
-// length of the skin test, and the per-block status slots.
+// length of the skin test, and the per-block status slots.  pos_out receives
+// the new positions (a.pos_out, or a workgroup's LDS copy); blk is the logical
+// 64-particle block, which names the status slot and the energy row.
 #pragma once
 
 #include "rc_gather.h"
@@ -9,7 +11,8 @@
 namespace rc {
 
 template <bool EV>
-__device__ __forceinline__ void step_finish(const StepArgs& a, int m, int blk, bool live, const float4& pm,
+__device__ __forceinline__ void step_finish(const StepArgs& a, float4* pos_out, int m, int blk, bool live,
+                                            const float4& pm,
                                             const float4& vm, const Acc& acc, const Box& box, int tag0,
                                             uint64_t seed, uint64_t step) {
     float kin[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -59,7 +62,7 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, int m, int blk, b
             lost = fabsf(sx) > box.hf[0] || fabsf(sy) > box.hf[1] || fabsf(sz) > box.hf[2];
             bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
                     isfinite(vz));
-            a.pos_out[m] = make_float4(x, y, z, pm.w);
+            pos_out[m] = make_float4(x, y, z, pm.w);
             a.vel[m] = make_float4(vx, vy, vz, path);
             if (a.image && (ix | iy | iz)) {
                 int4 im = a.image[m];
@@ -77,11 +80,11 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, int m, int blk, b
     const bool hard = live && path_in > a.hard;
     const unsigned long long bs = __ballot(soft), bh = __ballot(hard), bb = __ballot(bad),
                              bl = __ballot(lost);
-    if (threadIdx.x == 0) {
+    if ((threadIdx.x & (kWave - 1)) == 0) {
         const int fl = (bs ? RC_FLAG_REBUILD : 0) | (bh ? RC_FLAG_STALE : 0) | (bb ? RC_FLAG_NONFINITE : 0) |
                        (bl ? RC_FLAG_LOST : 0);
         if (fl) {
-            int* slot = a.blk + 3 * blockIdx.x;
+            int* slot = a.blk + 3 * blk;
             const int st = (int)(step & 0x7fffffff);
             slot[0] |= fl;
             if (fl & RC_FLAG_REBUILD) slot[1] = min(slot[1], st);

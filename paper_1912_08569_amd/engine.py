@@ -233,8 +233,12 @@ class System:
         return b
 
     def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
-            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True) -> RunResult:
-        """Advance n_steps with the fused step kernel under the chunked driver."""
+            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True,
+            one_block: bool = True) -> RunResult:
+        """Advance n_steps with the fused step kernel under the chunked driver.
+
+        one_block: with use_graph, systems of at most 1024 particles run each replay of graph_steps
+        steps in one workgroup launch (same results, bit for bit)."""
         if self.step_form == "auto":
             if not self.built:
                 self.build()    # picks the form from the new list
@@ -244,7 +248,7 @@ class System:
         ev_log = torch.zeros((rows, 13), dtype=torch.float64, device=self.device)
         bonds_log = torch.zeros(rows, dtype=torch.int64, device=self.device)
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
-                             int(adapt), 0)
+                             int(adapt), int(one_block))
         for _ in range(4):
             try:
                 st = api.rc_md_run(self.ctx, self.md_buffers(ev_log, bonds_log), self.N, self.box, cfg, step0,

@@ -275,3 +275,38 @@ def test_auto_form_follows_the_swap_range_length():
     S.set_step_form("walk")
     S.run(20, S.integrator(dt=0.001, kT=0.1, gamma=1.0, seed=1), step0=20)
     assert S.ctx.step_form == "walk"
+
+
+def _one_block_case(case):
+    if case == "dumbbells":
+        return W.dumbbell_mixture(N=512, rcut=1.3, seed=41), None, dict(dt=0.001, kT=0.03)
+    if case == "reactive_walk":
+        return W.small_reactive(N=1000, density=0.3, seed=42, kT=0.1), "walk", dict(dt=0.002, kT=0.1)
+    if case == "reactive_sums":
+        return W.small_reactive(N=1000, density=0.3, seed=43, kT=0.1), "sums", dict(dt=0.002, kT=0.1)
+    if case == "tiny":
+        return W.small_reactive(N=100, density=0.2, seed=44, kT=0.1), "walk", dict(dt=0.002, kT=0.1)
+    return W.vitrimer_network(n_chains=60, n_dimers=30, seed=12), None, dict(dt=2e-4, kT=1.0)
+
+
+@pytest.mark.parametrize("case", ["dumbbells", "reactive_walk", "reactive_sums", "tiny", "network"])
+def test_one_block_replays_equal_graph_replays(case):
+    # systems of at most 1024 particles replay graph_steps steps in one workgroup with the positions
+    # in LDS: the trajectory, the logs and the driver's decisions equal the hipGraph replays bit for bit
+    # (ragged last wavefronts: 1000, 100 and 1020 particles; FENE springs in the network)
+    s, form, kw = _one_block_case(case)
+    out = []
+    for one_block in (True, False):
+        S = _system(s)
+        if form:
+            S.set_step_form(form)
+        cfg = S.integrator(gamma=1.0, seed=17, **kw)
+        r = S.run(400, cfg, step0=3, log_period=50, one_block=one_block)
+        out.append((S.state_by_tag(), r, S.ctx.step_form))
+    (sa, ra, fa), (sb, rb, fb) = out
+    assert fa == fb
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+    assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
+    assert (ra.stats.rebuilds, ra.stats.rollbacks, ra.stats.chunks) == (rb.stats.rebuilds, rb.stats.rollbacks,
+                                                                       rb.stats.chunks)
+    assert ra.stats.steps_done == 400

@@ -296,8 +296,11 @@ hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) { retur
 // box, the coefficient table, the slot bound and the noise key; the noise
 // counter uses the tag relative to the replica's first slot, so a replica
 // draws the same numbers as the same system run on its own.
+// Seven wavefronts per SIMD: the walk-form kernel at width 2 then fits 72
+// VGPRs without spilling (74 otherwise, six wavefronts) and runs ~2 % faster
+// at 1M particles; the other instantiations are unchanged by the hint.
 template <bool EV, bool BATCH, int PL, bool SF>
-__global__ __launch_bounds__(kWave) void k_step(StepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int nt = a.tab.nt;
     const int blk = xcd_block(gridDim.x);
@@ -621,18 +624,20 @@ hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* s
 __global__ __launch_bounds__(kBlock) void k_copy_state(const float4* __restrict__ pos, const float4* __restrict__ vel,
                                                       const int4* __restrict__ image, float4* __restrict__ pos_to,
                                                       float4* __restrict__ vel_to, int4* __restrict__ image_to,
-                                                      int N) {
+                                                      int N, int zero_path) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     pos_to[i] = pos[i];
-    vel_to[i] = vel[i];
+    float4 v = vel[i];
+    if (zero_path) v.w = 0.0f;
+    vel_to[i] = v;
     if (image && image_to) image_to[i] = image[i];
 }
 
 hipError_t launch_copy_state(const float4* pos, const float4* vel, const int4* image, float4* pos_to, float4* vel_to,
-                             int4* image_to, int N, hipStream_t s) {
+                             int4* image_to, int N, hipStream_t s, bool zero_path) {
     hipLaunchKernelGGL(k_copy_state, dim3(nblk(N, kBlock)), dim3(kBlock), 0, s, pos, vel, image, pos_to, vel_to,
-                       image_to, N);
+                       image_to, N, zero_path ? 1 : 0);
     return hipGetLastError();
 }
 

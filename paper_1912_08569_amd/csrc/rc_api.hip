@@ -602,6 +602,19 @@ struct PlainOps final : DriveOps {
         return fn;
     }
     bool block_ok() override { return step_block_fits(N, c->nt, c->step_form); }
+    // the cell sort permutes pos, vel and image through the workspace's
+    // temporaries and copies them back, so those hold the rebuilt state
+    bool rebuild_snapshot(const float4** p, const float4** v, const int4** im) override {
+        Grid g;
+        if (make_grid(c, c->rlist_max, b, g)) return false;
+        const CellsLayout l = cells_layout(N, g.nkeys);
+        if (buf->cells_ws_bytes < l.total) return false;
+        const char* w = static_cast<const char*>(buf->cells_ws);
+        *p = reinterpret_cast<const float4*>(w + l.tpos);
+        *v = reinterpret_cast<const float4*>(w + l.tvel);
+        *im = reinterpret_cast<const int4*>(w + l.timage);
+        return true;
+    }
     hipError_t launch_block(const StepArgs& a, float4* pos, int G) override {
         return launch_step_block(a, pos, c->d_step_base, G, s);
     }

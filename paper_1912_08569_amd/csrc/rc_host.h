@@ -106,6 +106,10 @@ struct DriveOps {
     // whether graph replays may run as one-workgroup launches of G steps, and
     // such a launch (a: launch arguments of the replay's first step)
     virtual bool block_ok() { return false; }
+    // where the last rebuild left a copy of the state it produced (positions,
+    // velocities with stale path lengths, images or NULL), if it does: the
+    // driver then restores from there instead of taking its own snapshot
+    virtual bool rebuild_snapshot(const float4**, const float4**, const int4**) { return false; }
     virtual hipError_t launch_block(const StepArgs&, float4*, int) { return hipErrorNotSupported; }
 };
 

@@ -347,6 +347,9 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     // last ran without a soft crossing (a soft crossing ends the epoch with a rebuild), so a chunk
     // that goes stale is replayed from the epoch's start up to its first soft crossing.
     bool need_snap = true;
+    const float4 *ws_pos = nullptr, *ws_vel = nullptr;
+    const int4* ws_image = nullptr;
+    const bool snap_in_ws = ops.rebuild_snapshot(&ws_pos, &ws_vel, &ws_image);
     int64_t epoch_start = 0;
     int epoch_cur = 0, epoch_row = 0;
     bool epoch_first = true;
@@ -431,12 +434,13 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         }
         const int64_t chunk_start = done;
         if (can_roll && need_snap) {
-            HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(P[cur]),
-                                         reinterpret_cast<const float4*>(buf->vel),
-                                         reinterpret_cast<const int4*>(buf->image),
-                                         reinterpret_cast<float4*>(buf->snap_pos),
-                                         reinterpret_cast<float4*>(buf->snap_vel),
-                                         reinterpret_cast<int4*>(buf->snap_image), N, s));
+            if (!snap_in_ws)
+                HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(P[cur]),
+                                             reinterpret_cast<const float4*>(buf->vel),
+                                             reinterpret_cast<const int4*>(buf->image),
+                                             reinterpret_cast<float4*>(buf->snap_pos),
+                                             reinterpret_cast<float4*>(buf->snap_vel),
+                                             reinterpret_cast<int4*>(buf->snap_image), N, s));
             epoch_start = done;
             epoch_cur = cur;
             epoch_first = first;
@@ -506,11 +510,16 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             cur = epoch_cur;
             first = epoch_first;
             row = epoch_row;
-            HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(buf->snap_pos),
-                                         reinterpret_cast<const float4*>(buf->snap_vel),
-                                         reinterpret_cast<const int4*>(buf->snap_image),
-                                         reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
-                                         reinterpret_cast<int4*>(buf->image), N, s));
+            if (snap_in_ws)   // the state the epoch's list build left (path lengths zero)
+                HIP_TRY(c, launch_copy_state(ws_pos, ws_vel, buf->image ? ws_image : nullptr,
+                                             reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
+                                             reinterpret_cast<int4*>(buf->image), N, s, true));
+            else
+                HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(buf->snap_pos),
+                                             reinterpret_cast<const float4*>(buf->snap_vel),
+                                             reinterpret_cast<const int4*>(buf->snap_image),
+                                             reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
+                                             reinterpret_cast<int4*>(buf->image), N, s));
             const int64_t soft_step = (int64_t)hst[RC_ST_FIRST_SOFT];
             int64_t n_re = soft_step - (int64_t)((step0 + (uint64_t)epoch_start) & 0x7fffffff) + 1;
             n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, chunk_start + C - epoch_start));

@@ -483,9 +483,10 @@ hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s);
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
                               hipStream_t s);
 hipError_t launch_status_reset_chunk(int* status, hipStream_t s);
-// one launch copying pos, vel and (if both non-NULL) image: the driver's snapshot and its restore
+// one launch copying pos, vel and (if both non-NULL) image: the driver's snapshot and its restore;
+// zero_path writes the velocities' path lengths (w) as zero (a restore of the state a list build left)
 hipError_t launch_copy_state(const float4* pos, const float4* vel, const int4* image, float4* pos_to, float4* vel_to,
-                             int4* image_to, int N, hipStream_t s);
+                             int4* image_to, int N, hipStream_t s, bool zero_path = false);
 hipError_t launch_zero_words(int* p, int n, hipStream_t s);
 hipError_t launch_add_step(unsigned long long* p, unsigned long long v, hipStream_t s);
 hipError_t launch_set_step(unsigned long long* p, unsigned long long v, hipStream_t s);

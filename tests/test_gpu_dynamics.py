@@ -194,6 +194,28 @@ def test_driver_rollbacks_repair_stale_chunks():
     assert ra.ev[0, 0] == rb.ev[0, 0]
 
 
+@pytest.mark.parametrize("n", [3000, 1000])
+def test_rollback_replays_are_exact(n):
+    # With the rebuild threshold at the stale threshold (soft_frac 1), long fixed chunks rebuild right
+    # after the first crossing, either at a chunk's end or by a rollback to the epoch's start and a
+    # replay up to that step: the same schedule as one-step chunks.  The restore (state and zero path
+    # lengths) and the replay are exact, so both runs agree bit for bit.  1000 particles replay in one
+    # workgroup.
+    s = W.small_reactive(N=n, density=0.25, seed=46, table=W.swap_table_single(lam=1.0), kT=0.5)
+    A = _system(s, r_buff=0.06)
+    B = _system(s, r_buff=0.06)
+    for S in (A, B):
+        S.set_step_form("walk")
+    cfg = A.integrator(dt=0.002, kT=0.5, gamma=1.0, seed=11)
+    ra = A.run(300, cfg, max_chunk=64, adapt=False, log_period=100, soft_frac=1.0)
+    rb = B.run(300, cfg, max_chunk=1, adapt=False, log_period=100, soft_frac=1.0)
+    assert ra.stats.rollbacks > 0 and rb.stats.rollbacks == 0
+    assert ra.stats.rebuilds == rb.stats.rebuilds
+    sa, sb = A.state_by_tag(), B.state_by_tag()
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+    assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
+
+
 def test_nve_energy_is_conserved():
     # n = 100, r_cut = 1.3: the truncation jump is 1.6e-11 eps (SI, Performance)
     tab = W.swap_table_single(epsilon=1.0, sigma=1.0, n=100, rcut=1.3, lam=1.0)

@@ -328,7 +328,13 @@ int rc_bond_count(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn
  * and replayed up to the step where the soft threshold was first crossed;
  * the counter-based noise makes the replay exact.  Every log_period steps
  * (and at the end) it appends one row of 13 doubles (E, W, K at that step) to
- * ev_log and one bond count to bonds_log.  Buffers are caller owned:      */
+ * ev_log and one bond count to bonds_log.  On an error return stats (if given)
+ * still holds steps_done and log_rows, and pos / vel hold the state after
+ * steps_done steps; after RC_ERR_NLIST_OVERFLOW with steps_done > 0 that state
+ * owes its last step's final half kick, so the caller continues it (with a
+ * larger k_max) by a call with resume = 1 for the remaining steps.  A single
+ * system detects an overflow at the status read that ends the chunk after the
+ * build and then returns the state at the build.  Buffers are caller owned: */
 typedef struct rc_md_buffers {
     float* pos;        /* [N*4] state in/out                                  */
     float* pos_alt;    /* [N*4] second position buffer                        */
@@ -362,8 +368,12 @@ typedef struct rc_md_options {
                            (walk or sums form) runs each graph_steps-step replay
                            as one launch of one workgroup that keeps the
                            positions in LDS (same results, bit for bit); 0:
-                           hipGraphs only.  Ignored by rc_batch_run.  The
-                           defaults (opt = NULL) are {1, 16, 256, 0, 0.8, 1, 1}. */
+                           hipGraphs only.  Ignored by rc_batch_run.          */
+    int resume;         /* 1: the state owes its last step's final half kick
+                           (it is what an earlier call left when it returned an
+                           error after steps_done > 0): the first step applies
+                           it, and n_steps = 0 applies just that kick.  The
+                           defaults (opt = NULL) are {1, 16, 256, 0, 0.8, 1, 1, 0}. */
 } rc_md_options;
 
 typedef struct rc_md_stats {
@@ -372,7 +382,7 @@ typedef struct rc_md_stats {
     int64_t rollbacks;
     int64_t chunks;
     int64_t log_rows;
-    int32_t k_needed;   /* on RC_ERR_NLIST_OVERFLOW: the k_max needed          */
+    int32_t k_needed;   /* on RC_ERR_NLIST_OVERFLOW: the neighbour count found */
     int32_t flags;      /* last status flags                                  */
 } rc_md_stats;
 

@@ -78,7 +78,8 @@ class MdBuffers(ctypes.Structure):
 class MdOptions(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("graph_steps", ctypes.c_int),
                 ("max_chunk", ctypes.c_int), ("log_period", ctypes.c_int),
-                ("soft_frac", ctypes.c_double), ("adapt", ctypes.c_int), ("one_block", ctypes.c_int)]
+                ("soft_frac", ctypes.c_double), ("adapt", ctypes.c_int), ("one_block", ctypes.c_int),
+                ("resume", ctypes.c_int)]
 
 
 class MdStats(ctypes.Structure):

@@ -161,7 +161,7 @@ class Batch:
         ev_log = torch.zeros((rows, self.R, 13), dtype=torch.float64, device=self.device)
         bonds_log = torch.zeros((rows, self.R), dtype=torch.int64, device=self.device)
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
-                             int(adapt), 0)
+                             int(adapt), 0, 0)
         for _ in range(4):
             try:
                 st = api.rc_batch_run(self.bc, self.md_buffers(ev_log, bonds_log), cfg, step0, n_steps, opts)
@@ -170,6 +170,8 @@ class Batch:
                 if e.code != rcl.RC_ERR_NLIST_OVERFLOW:
                     raise
                 done = int(e.stats.steps_done)
+                if done > 0:        # the state owes its last step's final half kick
+                    opts.resume = 1
                 self._grow(int(e.stats.k_needed))
                 step0 += done
                 n_steps -= done

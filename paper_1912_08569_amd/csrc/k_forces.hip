@@ -707,8 +707,8 @@ hipError_t launch_reduce_rows_batch(const double* part, const RepDesc* rep, int 
 }
 
 __global__ void k_status_reset_chunk(int* st) {
-    // keep KMAX and MAXPATH, clear the chunk-local markers
-    st[RC_ST_FLAGS] = 0;
+    // keep KMAX, MAXPATH and the overflow flag of the current list, clear the chunk-local markers
+    st[RC_ST_FLAGS] &= RC_FLAG_NLIST_OVERFLOW;
     st[RC_ST_FIRST_SOFT] = 0x7fffffff;
     st[RC_ST_FIRST_HARD] = 0x7fffffff;
 }

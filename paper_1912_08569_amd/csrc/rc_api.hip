@@ -632,7 +632,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
     if (c->bonds && buf->rtag != c->bonds_rtag)
         return fail(c, RC_ERR_ARG, "with bonds, the md buffers' rtag must be the one given to rc_set_bonds");
-    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 1};
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 1, 0};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
     if (opt.max_chunk < 1) opt.max_chunk = 256;

@@ -453,7 +453,7 @@ extern "C" int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_inte
         return fail(c, RC_ERR_ARG, "md buffers incomplete");
     if (buf->k_max < 1 || buf->k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
-    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0};
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0, 0};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
     if (opt.max_chunk < 1) opt.max_chunk = 256;

@@ -354,28 +354,47 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     int epoch_cur = 0, epoch_row = 0;
     bool epoch_first = true;
 
+    // With the rebuilt state kept in the workspace, the list's overflow check is
+    // deferred to the status read that ends the next chunk (one host wait less
+    // per build): an overflow there restores the epoch's start and returns.
+    const bool defer_check = snap_in_ws && can_roll;
+    bool check_pending = false;
+    int64_t done = 0;
+    int row = 0;
+    auto overflow = [&]() -> int {
+        st.k_needed = hst[RC_ST_KMAX];
+        return fail(c, RC_ERR_NLIST_OVERFLOW, "a particle has %d neighbours (k_max %d)", hst[RC_ST_KMAX],
+                    buf->k_max);
+    };
     auto rebuild = [&](int which) -> int {
         int rr = ops.rebuild(P[which]);
         if (rr) return rr;
-        if ((rr = read_status_spin(c, buf->status, hst, s))) return rr;
         ++st.rebuilds;
         need_snap = true;
-        if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW) {
-            st.k_needed = hst[RC_ST_KMAX];
-            return fail(c, RC_ERR_NLIST_OVERFLOW, "a particle has %d neighbours (k_max %d)", hst[RC_ST_KMAX],
-                        buf->k_max);
+        if (defer_check) {
+            check_pending = true;
+            return RC_OK;
         }
+        if ((rr = read_status_spin(c, buf->status, hst, s))) return rr;
+        if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW) return overflow();
         return RC_OK;
     };
+    // every return reports the steps done: on an error the state (in buf->pos)
+    // is that of step0 + steps_done with the last step's final half kick due
     auto finish = [&](int code) -> int {
+        if (code != RC_OK) {
+            if (cur != 0) (void)hipMemcpyAsync(buf->pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s);
+            (void)hipStreamSynchronize(s);
+        }
         if (stats) {
             st.flags = hst[RC_ST_FLAGS];
+            st.steps_done = done;
+            st.log_rows = row;
             *stats = st;
         }
         return code;
     };
 
-    int row = 0;
     auto log_now = [&](int which) -> int {
         if (buf->bonds_log) return ops.bonds(P[which], row);
         return RC_OK;
@@ -400,8 +419,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
 
     const bool logging = buf->ev_log || buf->bonds_log;
     const int lp = opt.log_period;
-    bool first = true;
-    int64_t done = 0;
+    bool first = opt.resume == 0;  // a resumed state owes its last step's final half kick
     double rate = 0.0;           // growth of the largest path length per step
     float last_maxpath = 0.0f;
     const float hard = tmpl.hard;
@@ -426,10 +444,14 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         else if (!opt.adapt) {
             // fixed chunks: stale chunks are rolled back
         } else if (rate > 0.0) {
+            // end the chunk well before the stale threshold: a rollback replays the whole epoch
+            // (~1.4 ms at 1M particles), far more than one more chunk's host wait; aiming the
+            // end between the rebuild and stale thresholds (one chunk per epoch) rolled back
+            // about once per thousand steps and was slower
             const double room = (double)hard - (double)last_maxpath;
             const int64_t safe = (int64_t)std::floor(room / (1.5 * rate));
             C = std::max<int64_t>(1, std::min<int64_t>(C, safe));
-        } else if (first) {
+        } else if (done == 0) {
             C = std::min<int64_t>(C, 8);
         }
         const int64_t chunk_start = done;
@@ -500,6 +522,18 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
         ++st.chunks;
         const int f = hst[RC_ST_FLAGS];
+        check_pending = false;
+        if (f & RC_FLAG_NLIST_OVERFLOW) {
+            // the epoch ran on a truncated list: back to its start, which the caller resumes
+            cur = epoch_cur;
+            first = epoch_first;
+            row = epoch_row;
+            HIP_TRY(c, launch_copy_state(ws_pos, ws_vel, buf->image ? ws_image : nullptr,
+                                         reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
+                                         reinterpret_cast<int4*>(buf->image), N, s, true));
+            done = epoch_start;
+            return finish(overflow());
+        }
         if (f & RC_FLAG_LOST) return finish(fail(c, RC_ERR_LOST_PARTICLE, "a particle moved more than L/2 in one step"));
         if (f & RC_FLAG_NONFINITE) return finish(fail(c, RC_ERR_NONFINITE, "non-finite position or velocity"));
         float mp;
@@ -544,6 +578,12 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         }
     }
     // ---- final half kick (and the last log row) ------------------------------------
+    if (check_pending) {  // the list of the last build has not been checked yet
+        if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
+        check_pending = false;
+        if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW)
+            return finish(overflow());  // all steps done, the final half kick still due
+    }
     {
         const bool ev = logging && buf->ev_log;
         if (logging) {

@@ -248,7 +248,7 @@ class System:
         ev_log = torch.zeros((rows, 13), dtype=torch.float64, device=self.device)
         bonds_log = torch.zeros(rows, dtype=torch.int64, device=self.device)
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
-                             int(adapt), int(one_block))
+                             int(adapt), int(one_block), 0)
         for _ in range(4):
             try:
                 st = api.rc_md_run(self.ctx, self.md_buffers(ev_log, bonds_log), self.N, self.box, cfg, step0,
@@ -258,6 +258,8 @@ class System:
                 if e.code != rcl.RC_ERR_NLIST_OVERFLOW:
                     raise
                 done = int(e.stats.steps_done)
+                if done > 0:        # the state owes its last step's final half kick
+                    opts.resume = 1
                 self._grow(int(e.stats.k_needed))
                 step0 += done
                 n_steps -= done

@@ -216,6 +216,29 @@ def test_rollback_replays_are_exact(n):
     assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
 
 
+@pytest.mark.parametrize("n,steps,short", [(4000, 400, 0), (1000, 300, 2)])
+def test_list_overflow_mid_run_resumes_exactly(n, steps, short):
+    # A list sized to the first build's longest list overflows during the run.  The driver returns the
+    # state at the failed build (its last half kick still owed) with the steps done; the engine grows the
+    # list and resumes.  With the rebuild threshold at the stale threshold the rebuild schedule does not
+    # depend on chunking, so the result equals a run with room to spare, bit for bit.  short > 0: the
+    # list is too short for the first build already (found at the end of the first chunk, zero steps done).
+    s = W.small_reactive(N=n, density=0.35, seed=47, kT=0.5)
+    probe = _system(s, k_max=64)
+    probe.build()
+    kmax0 = int(((probe.nn & 0xFFFF) + (probe.nn >> 16)).max().item())
+    A = _system(s, k_max=kmax0 - short)
+    B = _system(s, k_max=64)
+    for S in (A, B):
+        S.set_step_form("walk")
+    cfg = A.integrator(dt=0.002, kT=0.5, gamma=1.0, seed=12)
+    ra = A.run(steps, cfg, soft_frac=1.0)
+    rb = B.run(steps, cfg, soft_frac=1.0)
+    assert A.k_max > kmax0                      # the list overflowed and grew
+    sa, sb = A.state_by_tag(), B.state_by_tag()
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+
+
 def test_nve_energy_is_conserved():
     # n = 100, r_cut = 1.3: the truncation jump is 1.6e-11 eps (SI, Performance)
     tab = W.swap_table_single(epsilon=1.0, sigma=1.0, n=100, rcut=1.3, lam=1.0)

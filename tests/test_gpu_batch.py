@@ -179,3 +179,25 @@ def test_full_replica_set_parity_on_samples():
         assert_energy(evh[r, 0], ref)
         assert_virial(evh[r, 1:7], ref)
         assert int(bonds[r]) == ref["bonds"]
+
+
+def test_batch_list_overflow_mid_run_resumes_exactly():
+    # lists sized to the first build's longest list overflow during the run; the driver returns the
+    # state at the failed build with the steps done, the batch grows its lists and resumes (the last
+    # half kick owed): with the rebuild threshold at the stale threshold the result equals a batch with
+    # room to spare, bit for bit
+    # (an even start, every pair 1.1 sigma apart, has short lists that bonding then lengthens)
+    reps = [W.small_reactive(N=4000, density=0.35, seed=sd, kT=0.5, min_dist=1.1) for sd in (47, 48)]
+    probe = _batch(reps, k_max=64)
+    probe.build()
+    kmax0 = int(((probe.nn & 0xFFFF) + (probe.nn >> 16)).max().item())
+    A = _batch(reps, k_max=kmax0, seeds=[1, 2])
+    B = _batch(reps, k_max=64, seeds=[1, 2])
+    for X in (A, B):
+        X.set_step_form("walk")
+    cfg = A.integrator(dt=0.002, kT=0.5, gamma=1.0, seed=0)
+    A.run(800, cfg, soft_frac=1.0)
+    B.run(800, cfg, soft_frac=1.0)
+    assert A.k_max > kmax0
+    for r in range(len(reps)):
+        assert all(np.array_equal(x, y) for x, y in zip(A.state_by_tag(r), B.state_by_tag(r))), f"replica {r}"

@@ -172,12 +172,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     float(*s_c)[W] = s_c_w[wv];
     const int ns = live ? nn_swap(packed) : 0;
     const int cnt = live ? ns + nn_other(packed) : 0;
-    int inc = cnt;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += t;
-    }
+    const int inc = wave_inclusive_scan(cnt);  // every lane of the wavefront is active here
     const int my_off = inc - cnt;
     s_off[lane] = my_off;
     if (lane == kWave - 1) s_off[kWave] = inc;

@@ -290,6 +290,20 @@ __device__ __forceinline__ void thermostat_normals(uint64_t seed, uint32_t tag, 
 // --------------------------------------------------------------------------
 // wave / block reductions
 // --------------------------------------------------------------------------
+// Inclusive prefix sum over the 64 lanes of a wavefront, all lanes active:
+// shifts by 1, 2, 4, 8 inside each 16-lane row, then each row adds the last
+// lane of the rows before it (row broadcasts of lanes 15 and 31).  Six DPP
+// adds; no LDS round trips.
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a) {
             if (x >= a.box.hf[0]) { x -= a.box.Lf[0]; ix = 1; } else if (x < -a.box.hf[0]) { x += a.box.Lf[0]; ix = -1; }
             if (y >= a.box.hf[1]) { y -= a.box.Lf[1]; iy = 1; } else if (y < -a.box.hf[1]) { y += a.box.Lf[1]; iy = -1; }
             if (z >= a.box.hf[2]) { z -= a.box.Lf[2]; iz = 1; } else if (z < -a.box.hf[2]) { z += a.box.Lf[2]; iz = -1; }
-            path += sqrtf(sx * sx + sy * sy + sz * sz);
+            path += __builtin_amdgcn_sqrtf(sx * sx + sy * sy + sz * sz);  // as the fused step
             lost = fabsf(sx) > a.box.hf[0] || fabsf(sy) > a.box.hf[1] || fabsf(sz) > a.box.hf[2];
             bad = !(isfinite(x) && isfinite(y) && isfinite(z));
             soft = path > a.soft;

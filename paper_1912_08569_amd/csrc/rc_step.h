@@ -58,7 +58,8 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, float4* pos_out, 
             if (x >= box.hf[0]) { x -= box.Lf[0]; ix = 1; } else if (x < -box.hf[0]) { x += box.Lf[0]; ix = -1; }
             if (y >= box.hf[1]) { y -= box.Lf[1]; iy = 1; } else if (y < -box.hf[1]) { y += box.Lf[1]; iy = -1; }
             if (z >= box.hf[2]) { z -= box.Lf[2]; iz = 1; } else if (z < -box.hf[2]) { z += box.Lf[2]; iz = -1; }
-            path = vm.w + sqrtf(sx * sx + sy * sy + sz * sz);
+            // the path length only gates list builds: the hardware square root (~1 ulp) suffices
+            path = vm.w + __builtin_amdgcn_sqrtf(sx * sx + sy * sy + sz * sz);
             lost = fabsf(sx) > box.hf[0] || fabsf(sy) > box.hf[1] || fabsf(sz) > box.hf[2];
             bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
                     isfinite(vz));

@@ -214,6 +214,9 @@ def adjoint_bench(a):
     grad = timed(lambda: api.rc_param_grad(S.ctx, S.pos, S.nlist, S.nn, S.box, g), 200)
     it = iter(range(10 ** 9))
     hvp = timed(lambda: api.rc_force_hvp(S.ctx, S.pos, S.nlist, S.nn, S.box, vs[next(it) % 64], hv), 640)
+    V64 = torch.stack(list(vs[:64])).contiguous()       # the 64 tangent vectors of the workload
+    HV64 = torch.empty_like(V64)
+    hvp64 = timed(lambda: api.rc_force_hvp_batch(S.ctx, S.pos, S.nlist, S.nn, S.box, V64, HV64), 50)
     adj = vs[0]
     vjp = timed(lambda: api.rc_param_vjp(S.ctx, S.pos, S.nlist, S.nn, S.box, adj, g), 200)
     fwd_sums = timed(lambda: api.rc_compute_forces(S.ctx, S.pos, S.nlist, S.nn, S.box, S.force, S.ev,
@@ -224,7 +227,8 @@ def adjoint_bench(a):
            "forward_triplet_kernel_us": fwd_tri,
            "param_grad_us": grad, "param_vjp_us": vjp, "hvp_us_per_vector": hvp,
            "fwd_plus_param_grad_over_fwd": (best + grad) / best, "hvp_over_fwd": hvp / best,
-           "hvp_64_vectors_ms": hvp * 64 / 1e3}
+           "hvp_64_vectors_ms": hvp * 64 / 1e3, "hvp_64_batched_ms": hvp64 / 1e3,
+           "hvp_batched_us_per_vector": hvp64 / 64, "hvp_batched_over_fwd": hvp64 / 64 / best}
     # one iteration of the lambda fit: 200 BAOAB steps forward, checkpointed backward (segments of 20)
     from paper_1912_08569_amd.autograd import SwapModel
     from paper_1912_08569_amd.fit import TrajectoryFit

@@ -438,6 +438,15 @@ int rc_fene_forces(rc_ctx* ctx, const float* pos, int N, rc_box box, float* forc
  *   grids stay valid.  Takes effect for launches issued after it returns.    */
 int rc_force_hvp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                  rc_box box, const float* v /* [N*4] */, float* hv /* [N*4] */, void* stream);
+/* rc_force_hvp_batch: the products of nvec tangent vectors at once, v and hv
+ *   [nvec][N*4] (device, 16-byte aligned, nvec in [1, 65535]); each product
+ *   equals rc_force_hvp of that vector bit for bit.  One launch per pass
+ *   covers every vector (grid rows), so small systems fill the GPU.  The
+ *   context keeps 16 * N * nvec bytes of first-pass sums (grown on demand;
+ *   growing synchronises the device).                                         */
+int rc_force_hvp_batch(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
+                       rc_box box, int nvec, const float* v /* [nvec][N*4] */, float* hv /* [nvec][N*4] */,
+                       void* stream);
 int rc_param_grad(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                   rc_box box, double* grad /* [nt*nt*3] */, void* stream);
 int rc_param_vjp(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,

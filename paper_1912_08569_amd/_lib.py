@@ -120,6 +120,7 @@ _SIGS = {
     "rc_md_run": ([_VP, ctypes.POINTER(MdBuffers), _I, Box, ctypes.POINTER(Integrator), _U64, _I,
                    ctypes.POINTER(MdOptions), ctypes.POINTER(MdStats), _VP], _I),
     "rc_force_hvp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
+    "rc_force_hvp_batch": ([_VP, _VP, _VP, _VP, _I, _I, Box, _I, _VP, _VP, _VP], _I),
     "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
     "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
     "rc_set_table": ([_VP, ctypes.POINTER(PairCoeff)], _I),

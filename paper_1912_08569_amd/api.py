@@ -19,7 +19,7 @@ from ._lib import RcError, check
 __all__ = [
     "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
-    "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp",
+    "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp", "rc_force_hvp_batch",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
     "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
     "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
@@ -243,6 +243,15 @@ def rc_force_hvp(ctx: Context, pos, nlist, nn, bx, v, hv, stream=None):
     check(L.load().rc_force_hvp(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx, _ptr(v),
                                 _ptr(hv),
                                 _stream(stream)), ctx.handle)
+
+
+def rc_force_hvp_batch(ctx: Context, pos, nlist, nn, bx, v, hv, stream=None):
+    """hv[k] = H v[k] for v, hv of shape (nvec, N, 4), in one launch per pass."""
+    N = pos.shape[0]
+    if v.dim() != 3 or v.shape[1] != N or v.shape[2] != 4 or hv.shape != v.shape:
+        raise ValueError("v and hv must be (nvec, N, 4)")
+    check(L.load().rc_force_hvp_batch(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
+                                      int(v.shape[0]), _ptr(v), _ptr(hv), _stream(stream)), ctx.handle)
 
 
 def rc_param_vjp(ctx: Context, pos, nlist, nn, bx, adj, out, stream=None):

@@ -81,15 +81,17 @@ __device__ __forceinline__ void centre_sums(int c, const float4& pc, const float
     }
 }
 
-// first pass: (S, dS) of every particle
+// first pass: (S, dS) of every particle; grid row y works on vector y
 __global__ __launch_bounds__(kBlock) void k_hvp_sums(HvpArgs a) {
     extern __shared__ DevEntry s_tab[];
     load_table_adj(s_tab, a.tab);
     const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     if (m >= a.N) return;
+    const size_t vo = (size_t)blockIdx.y * a.N;
+    const float4* v = a.v + vo;
     double S, dS;
-    centre_sums(m, a.pos[m], a.v[m], a.nlist, a.nn, a.k_max, a.N, a.pos, a.v, s_tab, a.tab.nt, a.box, S, dS);
-    a.sums[m] = make_double2(S, dS);
+    centre_sums(m, a.pos[m], v[m], a.nlist, a.nn, a.k_max, a.N, a.pos, v, s_tab, a.tab.nt, a.box, S, dS);
+    a.sums[vo + m] = make_double2(S, dS);
 }
 
 __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
@@ -98,12 +100,15 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
     const int nt = a.tab.nt;
     const int m = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     if (m >= a.N) return;
+    const size_t vo = (size_t)blockIdx.y * a.N;
+    const float4* v = a.v + vo;
+    const double2* sums = a.sums + vo;
     const float4 pm = a.pos[m];
-    const float4 vm = a.v[m];
+    const float4 vm = v[m];
     const int tm = ptype(pm.w);
     const int packed = a.nn[m];
     const int ns = nn_swap(packed), cnt = ns + nn_other(packed);
-    const double2 sm = a.sums[m];
+    const double2 sm = sums[m];
     const double Sm = sm.x, dSm = sm.y;
     float hx = 0.f, hy = 0.f, hz = 0.f;
     for (int s = 0; s < cnt; ++s) {
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
         if (!(r2d < e.rcut2)) continue;
         const float r2 = (float)r2d, r = sqrtf(r2), ir = 1.0f / r;
         const float rx = (float)dxd * ir, ry = (float)dyd * ir, rz = (float)dzd * ir;
-        const float4 vj = a.v[j];
+        const float4 vj = v[j];
         const float Dx = vj.x - vm.x, Dy = vj.y - vm.y, Dz = vj.z - vm.z;
         const float dr = rx * Dx + ry * Dy + rz * Dz;
         float G, dG;
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
             float w, w1, w2;
             w_d012(e, r2d <= e.rmin2, r2, r, w, w1, w2);
             if (w1 != 0.0f || w2 != 0.0f) {
-                const double2 sj = a.sums[j];
+                const double2 sj = sums[j];
                 const double Sj = sj.x, dSj = sj.y;
                 const float X = (float)((Sm - (double)w) + (Sj - (double)w));
                 const float dX = (float)((dSm - (double)(w1 * dr)) + (dSj - (double)(w1 * dr)));
@@ -140,13 +145,15 @@ __global__ __launch_bounds__(kBlock) void k_hvp(HvpArgs a) {
         hy -= dG * ry + c * (Dy - dr * ry);
         hz -= dG * rz + c * (Dz - dr * rz);
     }
-    a.hv[m] = make_float4(hx, hy, hz, 0.0f);
+    a.hv[vo + m] = make_float4(hx, hy, hz, 0.0f);
 }
 
 hipError_t launch_hvp(const HvpArgs& a, hipStream_t s) {
+    if (a.nvec < 1 || a.nvec > 65535) return hipErrorInvalidValue;
     const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
-    hipLaunchKernelGGL(k_hvp_sums, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
-    hipLaunchKernelGGL(k_hvp, dim3(nblk(a.N, kBlock)), dim3(kBlock), shm, s, a);
+    const dim3 grid(nblk(a.N, kBlock), a.nvec);
+    hipLaunchKernelGGL(k_hvp_sums, grid, dim3(kBlock), shm, s, a);
+    hipLaunchKernelGGL(k_hvp, grid, dim3(kBlock), shm, s, a);
     return hipGetLastError();
 }
 

@@ -485,9 +485,17 @@ int rc_bond_partners(rc_ctx* c, const float* pos, const int* nlist, const int* n
 
 int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box, const float* v,
                  float* hv, void* stream) {
+    return rc_force_hvp_batch(c, pos, nlist, nn, k_max, N, box, 1, v, hv, stream);
+}
+
+int rc_force_hvp_batch(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
+                       int nvec, const float* v, float* hv, void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
     if (!nlist || !nn || !v || !hv) return fail(c, RC_ERR_ARG, "nlist / nn / v / hv are NULL");
+    if (nvec < 1 || nvec > 65535) return fail(c, RC_ERR_ARG, "nvec = %d outside [1, 65535]", nvec);
+    if ((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(hv)) & 15)
+        return fail(c, RC_ERR_ARG, "v / hv not 16-byte aligned");
     Box b;
     if ((r = make_box(c, box, b))) return r;
     if ((r = check_list(c, nlist, nn, k_max))) return r;
@@ -501,7 +509,8 @@ int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, i
     a.box = b;
     a.v = reinterpret_cast<const float4*>(v);
     a.hv = reinterpret_cast<float4*>(hv);
-    if ((r = ensure_hsum(c, (size_t)N))) return r;
+    a.nvec = nvec;
+    if ((r = ensure_hsum(c, (size_t)N * (size_t)nvec))) return r;
     a.sums = reinterpret_cast<double2*>(c->d_hsum);
     HIP_TRY(c, launch_hvp(a, S(stream)));
     return RC_OK;

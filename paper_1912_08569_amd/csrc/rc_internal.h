@@ -514,9 +514,10 @@ struct HvpArgs {
     int N;
     Table tab;
     Box box;
-    const float4* v;
-    float4* hv;
-    double2* sums;             // [N] scratch: (S, dS) of every particle (first pass)
+    const float4* v;           // [nvec][N] tangent vectors
+    float4* hv;                // [nvec][N] products
+    double2* sums;             // [nvec][N] scratch: (S, dS) of every particle (first pass)
+    int nvec;                  // vectors, one per grid row (blockIdx.y)
 };
 hipError_t launch_hvp(const HvpArgs& a, hipStream_t s);
 

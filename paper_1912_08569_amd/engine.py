@@ -155,6 +155,15 @@ class System:
         api.rc_force_hvp(self.ctx, self.pos, self.nlist, self.nn, self.box, v.contiguous(), out)
         return out
 
+    def hvp_batch(self, V: torch.Tensor) -> torch.Tensor:
+        """H V[k] for V of shape (nvec, N, 4) in the engine's particle order, one launch per pass."""
+        if not self.built:
+            self.build()
+        V = V.contiguous()
+        out = torch.empty_like(V)
+        api.rc_force_hvp_batch(self.ctx, self.pos, self.nlist, self.nn, self.box, V, out)
+        return out
+
     def param_grad(self) -> np.ndarray:
         if not self.built:
             self.build()

@@ -53,6 +53,28 @@ def test_hvp_differentiation_workload():
     _hvp_check(s, seed=3005)
 
 
+@pytest.mark.parametrize("n,nvec", [(32768, 64), (1000, 3)])
+def test_hvp_batch_equals_single_products(n, nvec):
+    # several tangent vectors in one launch per pass (64 at the differentiation workload's size; a
+    # ragged 1000-particle case): every product equals the single-vector product bit for bit
+    s = W.small_reactive(N=n, density=0.25, seed=1005, table=W.swap_table_single(epsilon=10.0, lam=1.0))
+    S = _system(s)
+    S.build()
+    gen = torch.Generator().manual_seed(8)
+    V = torch.randn((nvec, n, 4), generator=gen, dtype=torch.float32)
+    V[:, :, 3] = 0.0
+    V = V.to(S.device)
+    H = S.hvp_batch(V)
+    for k in range(nvec):
+        assert torch.equal(H[k], S.hvp(V[k])), f"vector {k}"
+    # the first product also against the oracle
+    x, _, _, ty = S.state_by_tag()
+    v0 = S.by_tag(V[0])[:, :3].astype(np.float64)
+    ref, scale = adjoint_ref.hvp(x, ty, s.L, s.table, v0, with_scale=True)
+    err = np.abs(S.by_tag(H[0])[:, :3] - ref).max(axis=1)
+    assert np.all(err <= HVP_TOL * scale + 1e-30)
+
+
 def test_hvp_mixture():
     s = W.assembly_mixture(N=20000, lam=1.0, seed=62)
     _hvp_check(s, seed=5)

@@ -634,3 +634,55 @@ def test_per_particle_energies_sum_to_total():
     rm = 2.0 ** 0.1
     o = ev([[-rm, 0, 0], [0, 0, 0], [1.2, 0, 0]], [0, 1, 0], 50.0, two_type_table(1.0))
     assert o["pe"][1] - 0.5 * (o["E2"]) == pytest.approx(o["E3"], abs=1e-12)
+
+
+def test_stress_autocorrelation_pins():
+    # G(t) = V/kT < avg over xy, xz, yz of sigma(t0) sigma(t0 + t) > (the autocorrelation method after
+    # eq. p3), sigma_ab = -(K_ab + W_ab)/V
+    from oracle import observables_ref as O
+    V, kT, T = 8.0, 0.5, 12
+    lags = np.arange(T)
+    # constant shear virial in xy, sigma_xy = -c, the other components zero: V/kT c^2/3 at every lag
+    rows = np.zeros((T, 13))
+    c = 0.7
+    rows[:, 4] = c * V
+    assert np.allclose(O.stress_autocorrelation(rows, V, kT, T - 1), V / kT * c * c / 3, rtol=1e-14)
+    # alternating kinetic shear term in xz, sigma_xz = -a (-1)^t: V/kT a^2 (-1)^t / 3
+    rows = np.zeros((T, 13))
+    a = 0.3
+    rows[:, 11] = a * V * (-1.0) ** lags
+    assert np.allclose(O.stress_autocorrelation(rows, V, kT, T - 1), V / kT * a * a * (-1.0) ** lags / 3,
+                       rtol=1e-14)
+    rng = np.random.default_rng(5)
+    # the energy and the diagonal components do not enter
+    rows = rng.standard_normal((T, 13))
+    rows[:, [4, 5, 6, 10, 11, 12]] = 0.0
+    assert np.all(O.stress_autocorrelation(rows, V, kT, T - 1) == 0.0)
+    # kinetic and virial parts add into one stress
+    rows = rng.standard_normal((T, 13))
+    merged = rows.copy()
+    merged[:, 4:7] += merged[:, 10:13]
+    merged[:, 10:13] = 0.0
+    assert np.allclose(O.stress_autocorrelation(rows, V, kT, 5), O.stress_autocorrelation(merged, V, kT, 5),
+                       rtol=1e-12)
+    # every origin is averaged: reversing the series in time leaves G unchanged
+    G = O.stress_autocorrelation(rows, V, kT, T - 1)
+    assert np.allclose(G, O.stress_autocorrelation(rows[::-1], V, kT, T - 1), rtol=1e-12)
+    # G(0) is V/kT times the mean square shear stress
+    s = -(rows[:, 4:7] + rows[:, 10:13]) / V
+    assert np.isclose(G[0], V / kT * np.mean(s * s), rtol=1e-12)
+    with pytest.raises(ValueError):
+        O.stress_autocorrelation(rows, V, kT, T)
+
+
+def test_partner_counts_pin():
+    # bonded at 0, unchanged (the bond autocorrelation's numerator) and swapped (a bonded site whose
+    # single partner is now another particle); a broken bond and a site with several bonds are neither
+    from oracle import observables_ref as O
+    p0 = [1, 0, 3, -2, 3, -1, 7, 6]
+    pt = [5, -1, 3, -2, -2, 1, 7, 6]
+    assert O.partner_counts(p0, pt) == (6, 3, 1)
+    odd = np.arange(8) % 2 == 1
+    assert O.partner_counts(p0, pt, odd) == (2, 1, 0)
+    b, u, _ = O.partner_counts(p0, pt, odd)
+    assert swap_ref.bond_autocorrelation(p0, pt, mask=odd) == u / b

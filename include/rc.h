@@ -310,6 +310,27 @@ int rc_time_fused_steps(rc_ctx* ctx, float* pos_a, float* pos_b, float* vel, con
 int rc_bond_partners(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
                      rc_box box, int* partner /* [N] */, void* stream);
 
+/* ---- observables built on the step ------------------------------------------
+ * rc_partner_counts: counts[0..2] (device uint64, overwritten) = over the tags
+ *   t < N with select[t] != 0 (select: device bytes by tag, NULL = all) the
+ *   particles bonded at 0 (p0[t] >= 0), those with an unchanged partner
+ *   (pt[t] == p0[t]) and those whose single partner is another particle
+ *   (pt[t] >= 0, != p0[t]: a swap event), for two partner snapshots p0, pt
+ *   (device int32 [N], as rc_bond_partners writes them).  counts[1]/counts[0]
+ *   is the bond autocorrelation at the lag between them (Sec. 3.1, Fig. 3).
+ *   Exact (integers).  Uses the context's scratch.
+ * rc_stress_autocorrelation: G[t], t = 0 .. max_lag (device doubles,
+ *   overwritten) = V/kT times the average over the off-diagonal components
+ *   xy, xz, yz and over every time origin t0 < T - t of sigma(t0)
+ *   sigma(t0 + t), sigma_ab = -(K_ab + W_ab)/V, for T logged rows (device
+ *   doubles [T][13]: E, W(6), K(6) as rc_md_run writes ev_log); t counts rows.
+ *   The relaxation modulus by the autocorrelation method (Sec. 2.2 after eq.
+ *   p3).  FP64, deterministic (fixed reduction order).  0 <= max_lag < T.   */
+int rc_partner_counts(rc_ctx* ctx, const int* p0, const int* pt, const unsigned char* select /* [N] | NULL */,
+                      int N, unsigned long long* counts /* device [3] */, void* stream);
+int rc_stress_autocorrelation(rc_ctx* ctx, const double* rows /* device [T][13] */, int T, double volume,
+                              double kT, int max_lag, double* G /* device [max_lag+1] */, void* stream);
+
 /* ---- bond count (hot-path step a4) -------------------------------------------
  * Number of swap pairs i<j with r^2 < r_min^2 (canonical FP64 predicate, the
  * bond criterion of the swap system), written to *count (device, uint64).

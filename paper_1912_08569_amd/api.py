@@ -19,7 +19,7 @@ from ._lib import RcError, check
 __all__ = [
     "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
-    "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp", "rc_force_hvp_batch",
+    "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp", "rc_force_hvp_batch", "rc_partner_counts", "rc_stress_autocorrelation",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
     "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
     "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
@@ -252,6 +252,23 @@ def rc_force_hvp_batch(ctx: Context, pos, nlist, nn, bx, v, hv, stream=None):
         raise ValueError("v and hv must be (nvec, N, 4)")
     check(L.load().rc_force_hvp_batch(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
                                       int(v.shape[0]), _ptr(v), _ptr(hv), _stream(stream)), ctx.handle)
+
+
+def rc_partner_counts(ctx: Context, p0, pt, select, counts, stream=None):
+    """counts (3,) int64 device <- (bonded at 0, unchanged, swapped) over the selected tags."""
+    N = p0.shape[0]
+    if pt.shape[0] != N or (select is not None and select.shape[0] != N) or counts.numel() < 3:
+        raise ValueError("p0, pt (and select) must have N entries, counts at least 3")
+    check(L.load().rc_partner_counts(ctx.handle, _ptr(p0), _ptr(pt), _ptr(select), N, _ptr(counts),
+                                     _stream(stream)), ctx.handle)
+
+
+def rc_stress_autocorrelation(ctx: Context, rows, volume, kT, max_lag, G, stream=None):
+    """G (max_lag + 1,) float64 device <- stress autocorrelation of logged rows (T, 13) float64 device."""
+    if rows.dim() != 2 or rows.shape[1] != 13 or G.numel() < max_lag + 1:
+        raise ValueError("rows must be (T, 13), G at least max_lag + 1 long")
+    check(L.load().rc_stress_autocorrelation(ctx.handle, _ptr(rows), int(rows.shape[0]), float(volume), float(kT),
+                                             int(max_lag), _ptr(G), _stream(stream)), ctx.handle)
 
 
 def rc_param_vjp(ctx: Context, pos, nlist, nn, bx, adj, out, stream=None):

@@ -483,6 +483,30 @@ int rc_bond_partners(rc_ctx* c, const float* pos, const int* nlist, const int* n
     return RC_OK;
 }
 
+int rc_partner_counts(rc_ctx* c, const int* p0, const int* pt, const unsigned char* select, int N,
+                      unsigned long long* counts, void* stream) {
+    if (!c) return RC_ERR_ARG;
+    if (!p0 || !pt || !counts) return fail(c, RC_ERR_ARG, "p0 / pt / counts are NULL");
+    if (N < 1 || N > RC_MAX_TAG) return fail(c, RC_ERR_ARG, "N = %d outside [1, %d]", N, RC_MAX_TAG);
+    const int nb = (N + kBlock - 1) / kBlock;
+    int r = ensure_part(c, sizeof(unsigned long long) * 3 * (size_t)nb);
+    if (r) return r;
+    HIP_TRY(c, launch_partner_counts(p0, pt, select, N, reinterpret_cast<unsigned long long*>(c->d_part), counts,
+                                     S(stream)));
+    return RC_OK;
+}
+
+int rc_stress_autocorrelation(rc_ctx* c, const double* rows, int T, double volume, double kT, int max_lag,
+                              double* G, void* stream) {
+    if (!c) return RC_ERR_ARG;
+    if (!rows || !G) return fail(c, RC_ERR_ARG, "rows / G are NULL");
+    if (T < 1 || max_lag < 0 || max_lag >= T)
+        return fail(c, RC_ERR_ARG, "need 0 <= max_lag < T (T = %d, max_lag = %d)", T, max_lag);
+    if (!(volume > 0.0) || !(kT > 0.0)) return fail(c, RC_ERR_ARG, "volume and kT must be > 0");
+    HIP_TRY(c, launch_stress_acf(rows, T, volume, kT, max_lag, G, S(stream)));
+    return RC_OK;
+}
+
 int rc_force_hvp(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box, const float* v,
                  float* hv, void* stream) {
     return rc_force_hvp_batch(c, pos, nlist, nn, k_max, N, box, 1, v, hv, stream);

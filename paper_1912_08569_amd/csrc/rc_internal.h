@@ -520,6 +520,12 @@ struct HvpArgs {
     int nvec;                  // vectors, one per grid row (blockIdx.y)
 };
 hipError_t launch_hvp(const HvpArgs& a, hipStream_t s);
+// observables: partner statistics over tags (part: 3 * ceil(N/kBlock) counts of scratch; out: 3
+// device counts) and the stress autocorrelation of T logged rows (G: max_lag + 1 device doubles)
+hipError_t launch_partner_counts(const int* p0, const int* pt, const unsigned char* sel, int N,
+                                 unsigned long long* part, unsigned long long* out, hipStream_t s);
+hipError_t launch_stress_acf(const double* rows, int T, double volume, double kT, int max_lag, double* G,
+                             hipStream_t s);
 
 struct ParamArgs {
     const float4* pos;

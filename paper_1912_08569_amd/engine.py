@@ -141,6 +141,24 @@ class System:
         api.rc_bond_partners(self.ctx, self.pos, self.nlist, self.nn, self.box, out)
         return out.cpu().numpy()
 
+    def partner_counts(self, p0, pt, select=None):
+        """(bonded at 0, unchanged, swapped) between two partner snapshots by tag (bond_partners()
+        output), over the tags where select is true (None: all).  unchanged / bonded is the bond
+        autocorrelation; swapped counts bonded sites whose partner changed."""
+        dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.device)  # noqa: E731
+        sel = None if select is None else dev(np.asarray(select, bool).astype(np.uint8), torch.uint8)
+        counts = torch.zeros(3, dtype=torch.int64, device=self.device)
+        api.rc_partner_counts(self.ctx, dev(p0, torch.int32), dev(pt, torch.int32), sel, counts)
+        return tuple(int(x) for x in counts.cpu().numpy())
+
+    def stress_autocorrelation(self, rows, kT: float, max_lag: int) -> np.ndarray:
+        """G(t), t = 0 .. max_lag log rows, of logged rows (E, W(6), K(6)) such as RunResult.ev."""
+        r = torch.as_tensor(np.ascontiguousarray(rows, dtype=np.float64)).to(self.device)
+        G = torch.empty(max_lag + 1, dtype=torch.float64, device=self.device)
+        volume = float(self.box.L[0]) * float(self.box.L[1]) * float(self.box.L[2])
+        api.rc_stress_autocorrelation(self.ctx, r, volume, kT, max_lag, G)
+        return G.cpu().numpy()
+
     def bond_count(self) -> int:
         if not self.built:
             self.build()

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import workloads as W
-from oracle import swap_ref
+from oracle import observables_ref, swap_ref
 from parity_util import assert_energy, assert_forces, assert_virial
 
 pytestmark = pytest.mark.gpu
@@ -73,3 +73,33 @@ def test_bond_partners_of_the_assembly_mixture():
     both = single[p[p[single]] >= 0]
     assert np.all(p[p[both]] == both)        # symmetric where both ends have one bond
     assert np.count_nonzero(p != -1) > 0
+
+
+def test_partner_counts_and_stress_autocorrelation_match_oracle():
+    # on-device statistics of two partner snapshots (exact) and G(t) of the logged stress rows (FP64,
+    # reduction order) against the oracle, for the dumbbell mixture
+    s = W.dumbbell_mixture(N=2000, rcut=1.3, seed=24)
+    S = _system(s)
+    cfg = S.integrator(dt=0.001, kT=0.03, gamma=1.0, seed=34)
+    S.build()
+    p0 = S.bond_partners()
+    r = S.run(2000, cfg, log_period=10)
+    S.build()
+    p1 = S.bond_partners()
+    for sel in (None, s.types == 1):
+        assert S.partner_counts(p0, p1, sel) == observables_ref.partner_counts(p0, p1, sel)
+    rows = r.ev
+    assert rows.shape[0] > 100
+    G = S.stress_autocorrelation(rows, 0.03, 60)
+    ref = observables_ref.stress_autocorrelation(rows, float(s.L) ** 3, 0.03, 60)
+    assert np.allclose(G, ref, rtol=1e-11, atol=1e-11 * abs(ref[0]))
+
+
+def test_partner_counts_hand_example():
+    # a broken bond, a site with several bonds, a swap, unchanged bonds; with and without a selection
+    s = W.dumbbell_mixture(N=512, rcut=1.3, seed=25)
+    S = _system(s)
+    p0 = np.array([1, 0, 3, -2, 3, -1, 7, 6])
+    pt = np.array([5, -1, 3, -2, -2, 1, 7, 6])
+    assert S.partner_counts(p0, pt) == (6, 3, 1)
+    assert S.partner_counts(p0, pt, np.arange(8) % 2 == 1) == (2, 1, 0)

@@ -146,3 +146,46 @@ def test_argument_errors_are_synchronous():
     bad = W.swap_table_single(lam=-1.0)
     with pytest.raises(RcError):
         api.Context(bad)
+
+
+def test_argument_errors_of_the_newer_entry_points():
+    # rejected before any launch, with RC_ERR_ARG and a message
+    import ctypes
+
+    import torch
+    from paper_1912_08569_amd import RcError, api
+    from paper_1912_08569_amd import _lib as L
+    s = W.small_reactive(N=300, density=0.2, seed=4)
+    S = _system(s)
+    S.build()
+
+    def rejected(fn):
+        with pytest.raises(RcError) as e:
+            fn()
+        assert e.value.code == L.RC_ERR_ARG and len(str(e.value)) > 20
+    V = torch.zeros((2, s.N, 4), dtype=torch.float32, device=S.device)
+    flat = torch.zeros(2 * s.N * 4 + 1, dtype=torch.float32, device=S.device)
+    rejected(lambda: L.check(L.load().rc_force_hvp_batch(S.ctx.handle, api._ptr(S.pos), api._ptr(S.nlist),
+                                                         api._ptr(S.nn), S.k_max, s.N, S.box, 0, api._ptr(V),
+                                                         api._ptr(V), None), S.ctx.handle))
+    mis = ctypes.c_void_p(flat.data_ptr() + 4)          # 4 bytes off 16-byte alignment
+    rejected(lambda: L.check(L.load().rc_force_hvp_batch(S.ctx.handle, api._ptr(S.pos), api._ptr(S.nlist),
+                                                         api._ptr(S.nn), S.k_max, s.N, S.box, 2, mis,
+                                                         api._ptr(V), None), S.ctx.handle))
+    rows = torch.zeros((10, 13), dtype=torch.float64, device=S.device)
+    G = torch.zeros(20, dtype=torch.float64, device=S.device)
+    rejected(lambda: api.rc_stress_autocorrelation(S.ctx, rows, 8.0, 1.0, 10, G))      # max_lag == T
+    rejected(lambda: api.rc_stress_autocorrelation(S.ctx, rows, 0.0, 1.0, 3, G))       # volume 0
+    rejected(lambda: api.rc_stress_autocorrelation(S.ctx, rows, 8.0, -1.0, 3, G))      # kT < 0
+    p = torch.zeros(4, dtype=torch.int32, device=S.device)
+    c = torch.zeros(3, dtype=torch.int64, device=S.device)
+    rejected(lambda: L.check(L.load().rc_partner_counts(S.ctx.handle, api._ptr(p), None, None, 4, api._ptr(c),
+                                                        None), S.ctx.handle))
+    rejected(lambda: S.ctx.set_gather_width(3))
+    rejected(lambda: L.check(L.load().rc_set_step_form(S.ctx.handle, 7), S.ctx.handle))
+    # the driver: k_max outside [1, 512]
+    cfg = S.integrator(dt=0.001, kT=0.1, gamma=1.0, seed=1)
+    buf = S.md_buffers(torch.zeros((2, 13), dtype=torch.float64, device=S.device),
+                       torch.zeros(2, dtype=torch.int64, device=S.device))
+    buf.k_max = 0
+    rejected(lambda: api.rc_md_run(S.ctx, buf, s.N, S.box, cfg, 0, 10, None))

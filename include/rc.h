@@ -211,7 +211,12 @@ int rc_build_cells(rc_ctx* ctx, float* pos /* [N*4] */, float* vel /* [N*4] | NU
  * the list is at least r_cut apart (the paper's three-particle neighbour
  * lists, SI "Performance").  Layout: swap-kind neighbours first, the others
  * from the back of the column (nn[i] = ns | (no << 16), see above), so that
- * the triplet walks read swap partners only.                                 */
+ * the triplet walks read swap partners only.  The same launch writes a packed
+ * copy of the list into the context (per wavefront of 64 particles, its
+ * entries flattened in walk order: neighbour index and owner lane, 5 bytes
+ * per slot), which the single-system fused step reads; a fused step given a
+ * list it did not see built packs it first.  A list changed by other means
+ * than rc_build_nlist under the same pointers must be rebuilt with it.       */
 int rc_build_nlist(rc_ctx* ctx, const float* pos, float* vel /* NULL ok */, int N, rc_box box,
                    const void* ws, size_t ws_bytes, int k_max, int* nlist /* [k_max*N] */,
                    int* nn /* [N] */, int* status /* [RC_STATUS_WORDS] | NULL */, void* stream);

@@ -461,16 +461,32 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
     __syncthreads();
     const int nb = gridDim.x;
     const int i = xcd_block(nb) * blockDim.x + threadIdx.x;
-    int total = 0;
+    int total = 0, packed = 0;
     if (i < a.N) {
         total = list_one(i, a.pos[i], a.box, a.g, 0u, 0, a.cell_start, a.pos, nt, a.k_max, a.N, a.nlist, a.nn,
                          [&](int q, float& rl2, bool& swap) {
                              rl2 = s_rl2[q];
                              swap = s_swap[q] != 0;
                          });
+        packed = a.nn[i];
         if (a.vel) a.vel[i].w = 0.0f;
     }
+    if (a.pl_j) pack_wave_lists(i, i < a.N, packed, a.nlist, a.k_max, a.N, a.pl_j, a.pl_o);
     block_max_store(total, a.block_max + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_list(const int* __restrict__ nlist, const int* __restrict__ nn,
+                                                      int k_max, int N, int* __restrict__ pl_j,
+                                                      unsigned char* __restrict__ pl_o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < N;
+    pack_wave_lists(i, live, live ? nn[i] : 0, nlist, k_max, N, pl_j, pl_o);
+}
+
+hipError_t launch_pack_list(const int* nlist, const int* nn, int k_max, int N, int* pl_j, unsigned char* pl_o,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_list, dim3(nblk(N, kBlock)), dim3(kBlock), 0, s, nlist, nn, k_max, N, pl_j, pl_o);
+    return hipGetLastError();
 }
 
 // Batches: each wave lies in one replica, which gives the box, grid, key

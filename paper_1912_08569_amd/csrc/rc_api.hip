@@ -276,7 +276,14 @@ int rc_build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, c
     a.nn = nn;
     a.status = status;
     a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
+    if ((r = ensure_plist(c, N, k_max))) return r;
+    a.pl_j = c->d_pl_j;  // the packed copy the fused step reads, made in the same launch
+    a.pl_o = c->d_pl_o;
     HIP_TRY(c, launch_nlist(a, S(stream)));
+    c->pl_nlist = nlist;
+    c->pl_nn = nn;
+    c->pl_k = k_max;
+    c->pl_n = N;
     return RC_OK;
 }
 
@@ -350,7 +357,7 @@ int rc_integrate_step(rc_ctx* c, float* pos, float* vel, const float* force, int
 
 static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* pos_out, float* vel, int* image,
                           const int* nlist, const int* nn, int k_max, int N, const Box& b, const rc_integrator* cfg,
-                          double soft_frac, int* status) {
+                          double soft_frac, int* status, hipStream_t s, bool pack = true) {
     float c1;
     int lang;
     int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang);
@@ -390,6 +397,10 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
     }
     if ((r = ensure_blk(c, nblocks(N, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
+    // the packed copy of the list (the driver's first list build makes it: pack = false)
+    if ((r = pack ? packed_list_for(c, nlist, nn, k_max, N, s) : ensure_plist(c, N, k_max))) return r;
+    a.pl_j = c->d_pl_j;
+    a.pl_o = c->d_pl_o;
     return RC_OK;
 }
 
@@ -406,7 +417,9 @@ int rc_step_fused(rc_ctx* c, const float* pos_in, float* pos_out, float* vel, in
     Box b;
     if ((r = make_box(c, box, b))) return r;
     StepArgs a{};
-    if ((r = fill_step_args(c, a, pos_in, pos_out, vel, image, nlist, nn, k_max, N, b, cfg, soft_frac, status))) return r;
+    if ((r = fill_step_args(c, a, pos_in, pos_out, vel, image, nlist, nn, k_max, N, b, cfg, soft_frac, status,
+                            S(stream))))
+        return r;
     const int nb = nblocks(N, kStepBlock);
     if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     a.mode = mode;
@@ -429,7 +442,8 @@ int rc_time_fused_steps(rc_ctx* c, float* pos_a, float* pos_b, float* vel, const
     Box b;
     if ((r = make_box(c, box, b))) return r;
     StepArgs a{};
-    if ((r = fill_step_args(c, a, pos_a, pos_b, vel, nullptr, nlist, nn, k_max, N, b, cfg, 0.8, status))) return r;
+    if ((r = fill_step_args(c, a, pos_a, pos_b, vel, nullptr, nlist, nn, k_max, N, b, cfg, 0.8, status, S(stream))))
+        return r;
     a.mode = RC_STEP_CONT;
     a.step_base = nullptr;
     a.ev_part = nullptr;
@@ -677,7 +691,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     if ((r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     StepArgs tmpl{};
     if ((r = fill_step_args(c, tmpl, buf->pos, buf->pos_alt, buf->vel, buf->image, buf->nlist, buf->nn, buf->k_max, N,
-                            b, cfg, opt.soft_frac, buf->status)))
+                            b, cfg, opt.soft_frac, buf->status, s, false)))
         return r;
     PlainOps ops;
     ops.c = c;

@@ -147,10 +147,14 @@ __device__ __forceinline__ void gather_sync() {
     }
 }
 
-template <bool EV, int kPerLane, bool SF, class Ctx, bool WS = false>
+// PK: the entries come from the packed copy of the list (pl_j, pl_o: neighbour
+// and owner lane of every flattened entry, pack_wave_lists) instead of the
+// owner map in LDS and a search of the list columns; same entries, same order.
+template <bool EV, int kPerLane, bool SF, class Ctx, bool WS = false, bool PK = false>
 __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4& pm, int packed,
                                             const float4* pos, const int* nlist, const int* nn, int k_max,
-                                            int N, const Ctx& ctx, Acc& acc, const float* ssum = nullptr) {
+                                            int N, const Ctx& ctx, Acc& acc, const float* ssum = nullptr,
+                                            const int* pl_j = nullptr, const unsigned char* pl_o = nullptr) {
     const int nt = ctx.nt;
     constexpr int NC = Stage<EV, SF>::n;
     constexpr int CE = Stage<EV, SF>::e;
@@ -174,22 +178,25 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
     const int cnt = live ? ns + nn_other(packed) : 0;
     const int inc = wave_inclusive_scan(cnt);  // every lane of the wavefront is active here
     const int my_off = inc - cnt;
-    s_off[lane] = my_off;
-    if (lane == kWave - 1) s_off[kWave] = inc;
-    s_ns[lane] = ns;
+    if (!PK) {
+        s_off[lane] = my_off;
+        if (lane == kWave - 1) s_off[kWave] = inc;
+        s_ns[lane] = ns;
+    }
     s_pos[lane] = pm;
     if (SF) s_S[lane] = live ? ssum[base_m + lane] : 0.0f;
     gather_sync<WS>();
-    const int T = s_off[kWave];
+    const int T = PK ? __builtin_amdgcn_readlane(inc, kWave - 1) : s_off[kWave];
+    const size_t pk_base = (size_t)base_m * k_max;  // the wavefront's region of the packed list
     double S = 0.0;
     int nact = 0;
     for (int base = 0; base < T; base += W) {
-        // owner map of the pass: each lane marks its own entries in the window
-        {
+        if (!PK) {
+            // owner map of the pass: each lane marks its own entries in the window
             const int q1 = min(my_off + cnt, base + W) - base;
             for (int q = max(my_off, base) - base; q < q1; ++q) s_own[q] = (unsigned char)lane;
+            gather_sync<WS>();
         }
-        gather_sync<WS>();
         // locate and load all entries of this pass first, so their memory
         // latencies overlap (list index, then neighbour position)
         int own[kPerLane], jj[kPerLane];
@@ -203,12 +210,18 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
             jj[u] = 0;
             sw[u] = false;
             if (e < T) {
-                const int lo = s_own[e - base];
-                const int sl = e - s_off[lo], nso = s_ns[lo];
-                sw[u] = sl < nso;
-                const int slot = sw[u] ? sl : k_max - 1 - (sl - nso);
-                own[u] = lo;
-                jj[u] = nlist[(size_t)slot * N + base_m + lo];
+                if (PK) {
+                    own[u] = pl_o[pk_base + e];
+                    jj[u] = pl_j[pk_base + e];
+                    sw[u] = true;  // S_j is read for every entry and used for swap-kind ones only
+                } else {
+                    const int lo = s_own[e - base];
+                    const int sl = e - s_off[lo], nso = s_ns[lo];
+                    sw[u] = sl < nso;
+                    const int slot = sw[u] ? sl : k_max - 1 - (sl - nso);
+                    own[u] = lo;
+                    jj[u] = nlist[(size_t)slot * N + base_m + lo];
+                }
             }
         }
 #pragma unroll

@@ -37,6 +37,13 @@ struct rc_ctx {
     size_t ssum_cap = 0;                // floats allocated
     double* d_hsum = nullptr;           // per-particle (S, dS) of the Hessian-vector product
     size_t hsum_cap = 0;                // particles allocated
+    // packed copy of the last list (pack_wave_lists), read by the single-system step kernel
+    int* d_pl_j = nullptr;
+    unsigned char* d_pl_o = nullptr;
+    size_t pl_cap = 0;                  // entries allocated
+    const int* pl_nlist = nullptr;      // the list it was made from: (nlist, nn, k_max, N)
+    const int* pl_nn = nullptr;
+    int pl_k = 0, pl_n = 0;
     const int* bonds = nullptr;         // FENE partner table (caller-owned, [n_bonded][2] by tag)
     const int* bonds_rtag = nullptr;    // tag -> index map the springs read (caller-owned)
     int bonds_n = 0;
@@ -72,7 +79,11 @@ CellsLayout cells_layout(int N, uint32_t nkeys);
 
 int ensure_part(rc_ctx* c, size_t bytes);
 int ensure_ssum(rc_ctx* c, size_t n);
-int ensure_hsum(rc_ctx* c, size_t n);   // d_hsum for n particles   // d_ssum for n particles (drops graphs when it moves)
+int ensure_hsum(rc_ctx* c, size_t n);
+// packed-list arrays for N particles and k_max slots (drops graphs when they move)
+int ensure_plist(rc_ctx* c, int N, int k_max);
+// the packed copy of (nlist, nn, k_max, N): made on the stream unless it is the current one
+int packed_list_for(rc_ctx* c, const int* nlist, const int* nn, int k_max, int N, hipStream_t s);   // d_hsum for n particles   // d_ssum for n particles (drops graphs when it moves)
 void free_ctx_buffers(rc_ctx* c);       // every device buffer the context owns
 // copy a device status word to the host and wait for it by spinning on an event
 int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s);

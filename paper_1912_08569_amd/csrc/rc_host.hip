@@ -117,6 +117,35 @@ int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s) {
     return RC_OK;
 }
 
+int ensure_plist(rc_ctx* c, int N, int k_max) {
+    const size_t n = (size_t)((N + kWave - 1) / kWave) * kWave * (size_t)k_max;
+    if (c->pl_cap >= n) return RC_OK;
+    drop_graphs(c);
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->d_pl_j) (void)hipFree(c->d_pl_j);
+    if (c->d_pl_o) (void)hipFree(c->d_pl_o);
+    c->d_pl_j = nullptr;
+    c->d_pl_o = nullptr;
+    c->pl_cap = 0;
+    c->pl_nlist = nullptr;
+    HIP_TRY(c, hipMalloc(&c->d_pl_j, sizeof(int) * n));
+    HIP_TRY(c, hipMalloc(&c->d_pl_o, n));
+    c->pl_cap = n;
+    return RC_OK;
+}
+
+int packed_list_for(rc_ctx* c, const int* nlist, const int* nn, int k_max, int N, hipStream_t s) {
+    if (c->pl_nlist == nlist && c->pl_nn == nn && c->pl_k == k_max && c->pl_n == N) return RC_OK;
+    int r = ensure_plist(c, N, k_max);
+    if (r) return r;
+    HIP_TRY(c, launch_pack_list(nlist, nn, k_max, N, c->d_pl_j, c->d_pl_o, s));
+    c->pl_nlist = nlist;
+    c->pl_nn = nn;
+    c->pl_k = k_max;
+    c->pl_n = N;
+    return RC_OK;
+}
+
 int ensure_hsum(rc_ctx* c, size_t n) {
     if (c->hsum_cap >= n) return RC_OK;
     HIP_TRY(c, hipDeviceSynchronize());
@@ -130,6 +159,12 @@ int ensure_hsum(rc_ctx* c, size_t n) {
 
 void free_ctx_buffers(rc_ctx* c) {
     drop_graphs(c);
+    if (c->d_pl_j) (void)hipFree(c->d_pl_j);
+    if (c->d_pl_o) (void)hipFree(c->d_pl_o);
+    c->d_pl_j = nullptr;
+    c->d_pl_o = nullptr;
+    c->pl_cap = 0;
+    c->pl_nlist = nullptr;
     if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
     if (c->h_status) (void)hipHostFree(c->h_status);
     c->ev_sync = nullptr;

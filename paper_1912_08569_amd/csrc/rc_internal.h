@@ -304,6 +304,28 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
     return x;
 }
 
+// Packed copy of the lists of a wavefront's 64 particles (lanes i - lane ..
+// i - lane + 63): entry e of the wavefront's region, which starts at
+// (i - lane) * k_max, holds the neighbour index and the owner lane, in the
+// order the gather walks them (each particle's swap range, then its other
+// range; particles in lane order).  Every lane of the wavefront must be
+// active; live = i < N.  The arrays hold ceil(N / 64) * 64 * k_max entries.
+__device__ __forceinline__ void pack_wave_lists(int i, bool live, int packed, const int* nlist, int k_max, int N,
+                                                int* pl_j, unsigned char* pl_o) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    // a built list has ns + no <= k_max; the clamp keeps every write inside the
+    // wavefront's region whatever nn holds
+    const int ns = live ? min(nn_swap(packed), k_max) : 0;
+    const int cnt = live ? ns + min(nn_other(packed), k_max - ns) : 0;
+    const int off = wave_inclusive_scan(cnt) - cnt;
+    const size_t base = (size_t)(i - lane) * k_max + off;
+    for (int s = 0; s < cnt; ++s) {
+        const int slot = s < ns ? s : k_max - 1 - (s - ns);
+        pl_j[base + s] = nlist[(size_t)slot * N + i];
+        pl_o[base + s] = (unsigned char)lane;
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -382,6 +404,10 @@ struct StepArgs {
     int width;                 // gather width of the non-logging steps: 1, 2 or 4 (read by the launcher)
     int form;                  // RC_FORM_WALK, RC_FORM_SUMS or RC_FORM_HEAD (read by the launcher)
     float* ssum;               // [N] per-particle switching sums (RC_FORM_SUMS)
+    // packed list (single systems): per wavefront the flattened entries of its
+    // 64 particles, neighbour index and owner lane (pack_wave_lists)
+    const int* pl_j;
+    const unsigned char* pl_o;
     // FENE springs (single systems; NULL bonds = none)
     const int2* bonds;         // [N] partner tags per tag, -1 = none
     const int* rtag;           // [N] tag -> index
@@ -481,8 +507,13 @@ struct NlistArgs {
     int* nn;
     int* status;
     int* block_max;    // [ceil(N / kBlock)] scratch (largest list length per block)
+    int* pl_j;         // packed copy of the list (NULL: none), see pack_wave_lists
+    unsigned char* pl_o;
 };
 hipError_t launch_nlist(const NlistArgs& a, hipStream_t s);
+// the packed copy of a list built elsewhere
+hipError_t launch_pack_list(const int* nlist, const int* nn, int k_max, int N, int* pl_j, unsigned char* pl_o,
+                            hipStream_t s);
 
 // count: device u64 result; part: scratch of ceil(N / kBlock) u64
 hipError_t launch_bonds(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,

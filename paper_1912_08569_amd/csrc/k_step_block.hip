@@ -63,8 +63,9 @@ __global__ __launch_bounds__(kBlockMaxN) void k_step_block(StepArgs a, float4* _
             __syncthreads();
         }
         Acc acc = {};
-        wave_gather<false, kDefaultWidth, SF, OneSystem, true>(m - lane, live, pm, packed, pin, a.nlist, a.nn,
-                                                                 a.k_max, a.N, sys, acc, s_S);
+        wave_gather<false, kDefaultWidth, SF, OneSystem, true, true>(m - lane, live, pm, packed, pin, a.nlist,
+                                                                       a.nn, a.k_max, a.N, sys, acc, s_S, a.pl_j,
+                                                                       a.pl_o);
         if (a.bonds && live)
             fene_add<false>(ptag(pm.w), pm, a.bonds, a.rtag, pin, a.box, a.fene_k, a.fene_r02, acc);
         step_finish<false>(a, pout, m, w, live, pm, vm, acc, a.box, 0, a.seed, base + (uint64_t)k);

@@ -523,6 +523,8 @@ int rc_soft_bonds(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn
  * rc_batch_run: rc_md_run over the whole batch: buf arrays are n_slots long,
  *   ev_log is [rows][R][13] and bonds_log [rows][R].  A list build of the
  *   batch happens when any replica needs one.  Synchronises the stream.
+ * rc_batch_build_nlist also writes the packed copy of the lists that the
+ *   batch's fused step reads (as rc_build_nlist does for one system).
  * rc_batch_time_fused_steps: as rc_time_fused_steps for the batch.          */
 typedef struct rc_batch rc_batch;
 

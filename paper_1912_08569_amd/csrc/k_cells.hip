@@ -493,7 +493,7 @@ hipError_t launch_pack_list(const int* nlist, const int* nn, int k_max, int N, i
 // range and table; empty slots get an empty list.
 __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int total = 0;
+    int total = 0, packed = 0;
     if (i < a.N) {
         const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
         const DevEntry* t = a.tab.e + d.tab;
@@ -503,11 +503,13 @@ __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
                                  rl2 = t[q].rlist2;
                                  swap = t[q].kind == RC_KIND_SWAP;
                              });
+            packed = a.nn[i];
         } else {
             a.nn[i] = 0;
         }
         if (a.vel) a.vel[i].w = 0.0f;
     }
+    if (a.pl_j) pack_wave_lists(i, i < a.N, packed, a.nlist, a.k_max, a.N, a.pl_j, a.pl_o);
     block_max_store(total, a.block_max + blockIdx.x);
 }
 

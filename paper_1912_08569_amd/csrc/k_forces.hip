@@ -328,9 +328,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
     const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int packed = live ? a.nn[m] : 0;
     const OneSystem sys{s_tab, nt, box};
-    // single systems read the packed copy of the list; batches walk the list columns
-    wave_gather<EV, PL, SF, OneSystem, false, !BATCH>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist,
-                                                       a.nn, a.k_max, a.N, sys, acc, a.ssum, a.pl_j, a.pl_o);
+    // the entries come from the packed copy of the list
+    wave_gather<EV, PL, SF, OneSystem, false, true>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn,
+                                                     a.k_max, a.N, sys, acc, a.ssum, a.pl_j, a.pl_o);
     if (!BATCH && a.bonds && live)
         fene_add<EV>(ptag(pm.w), pm, a.bonds, a.rtag, a.pos_in, box, a.fene_k, a.fene_r02, acc);
     step_finish<EV>(a, a.pos_out, m, blk, live, pm, vm, acc, box, tag0, seed, step);

@@ -60,7 +60,7 @@ int ensure_seeds(rc_batch* b, const rc_integrator* cfg, hipStream_t s) {
 
 int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* pos_out, float* vel, int* image,
                          const int* nlist, const int* nn, int k_max, const rc_integrator* cfg, double soft_frac,
-                         int* status, hipStream_t s) {
+                         int* status, hipStream_t s, bool pack = true) {
     rc_ctx* c = &b->c;
     float c1;
     int lang;
@@ -96,6 +96,11 @@ int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* p
     }
     if ((r = ensure_blk(c, nblocks(b->n_slots, kStepBlock), nullptr))) return r;
     a.blk = c->d_blk;
+    // the packed copy of the list (the driver's first list build makes it: pack = false)
+    if ((r = pack ? packed_list_for(c, nlist, nn, k_max, b->n_slots, s) : ensure_plist(c, b->n_slots, k_max)))
+        return r;
+    a.pl_j = c->d_pl_j;
+    a.pl_o = c->d_pl_o;
     return RC_OK;
 }
 
@@ -282,7 +287,15 @@ int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* 
     a.nn = nn;
     a.status = status;
     a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
-    HIP_TRY(&b->c, launch_nlist_batch(a, S(stream)));
+    rc_ctx* c = &b->c;
+    if ((r = ensure_plist(c, b->n_slots, k_max))) return r;
+    a.pl_j = c->d_pl_j;  // the packed copy the fused step reads, made in the same launch
+    a.pl_o = c->d_pl_o;
+    HIP_TRY(c, launch_nlist_batch(a, S(stream)));
+    c->pl_nlist = nlist;
+    c->pl_nn = nn;
+    c->pl_k = k_max;
+    c->pl_n = b->n_slots;
     return RC_OK;
 }
 
@@ -463,7 +476,7 @@ extern "C" int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_inte
     if ((r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     StepArgs tmpl{};
     if ((r = fill_step_args_batch(b, tmpl, buf->pos, buf->pos_alt, buf->vel, buf->image, buf->nlist, buf->nn,
-                                  buf->k_max, cfg, opt.soft_frac, buf->status, s)))
+                                  buf->k_max, cfg, opt.soft_frac, buf->status, s, false)))
         return r;
     BatchOps ops;
     ops.b = b;

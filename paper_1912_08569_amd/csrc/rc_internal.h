@@ -618,6 +618,8 @@ struct NlistArgsB {
     int* nn;
     int* status;
     int* block_max;
+    int* pl_j;              // packed copy of the list (NULL: none), see pack_wave_lists
+    unsigned char* pl_o;
 };
 hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s);
 

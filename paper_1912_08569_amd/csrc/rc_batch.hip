@@ -452,6 +452,17 @@ struct BatchOps final : DriveOps {
         sums_kernel_info(true, &fn);
         return fn;
     }
+    // the batch cell sort also permutes (pos, vel, image) of every slot through
+    // the workspace's temporaries and copies them back
+    bool rebuild_snapshot(const float4** p, const float4** v, const int4** im) override {
+        const CellsLayout l = cells_layout(b->n_slots, b->nkeys);
+        if (buf->cells_ws_bytes < l.total) return false;
+        const char* w = static_cast<const char*>(buf->cells_ws);
+        *p = reinterpret_cast<const float4*>(w + l.tpos);
+        *v = reinterpret_cast<const float4*>(w + l.tvel);
+        *im = reinterpret_cast<const int4*>(w + l.timage);
+        return true;
+    }
 };
 
 }  // namespace

@@ -297,10 +297,13 @@ int rc_step_fused(rc_ctx* ctx, const float* pos_in, float* pos_out, float* vel, 
                   const rc_integrator* cfg /* host */, uint64_t step, int mode, double soft_frac,
                   double* ev /* [13] | NULL */, int* status, void* stream);
 
-/* Measurement helper: launch `reps` RC_STEP_CONT fused steps back to back from
- * host code (alternating pos_a -> pos_b -> pos_a ...; status is written to
- * status), bracketed by hipEvents on `stream`; synchronises and returns the
- * elapsed milliseconds in *ms (host).  Used to time the step kernel alone. */
+/* Measurement helper: launch `reps` RC_STEP_CONT fused steps back to back on
+ * `stream` (alternating pos_a -> pos_b -> pos_a ...; status is written to
+ * status), each kernel launch carrying its own start/stop hipEvents
+ * (hipExtLaunchKernel); synchronises and returns in *ms (host) the sum of
+ * the kernels' own execution times in milliseconds (the sums pass included
+ * in the two-pass form; the dispatch gaps between launches excluded).  Used
+ * to time the step kernel alone.                                            */
 int rc_time_fused_steps(rc_ctx* ctx, float* pos_a, float* pos_b, float* vel, const int* nlist,
                         const int* nn, int k_max, int N, rc_box box, const rc_integrator* cfg /* host */,
                         uint64_t step0, int reps, int* status, float* ms /* host */, void* stream);

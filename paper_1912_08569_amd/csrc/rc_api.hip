@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "rc_host.h"
 
 using namespace rc;
@@ -448,23 +450,45 @@ int rc_time_fused_steps(rc_ctx* c, float* pos_a, float* pos_b, float* vel, const
     a.step_base = nullptr;
     a.ev_part = nullptr;
     hipStream_t s = S(stream);
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
+    // every kernel launch carries its own start/stop events, which time its
+    // execution alone (not the dispatch gaps between launches)
+    const void* fn;
+    step_kernel_info(false, a.width, a.form, &fn);
+    const void* sums_fn = nullptr;
+    if (a.form == RC_FORM_SUMS) sums_kernel_info(false, &sums_fn);
+    const int nk = sums_fn ? 2 : 1;
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    std::vector<hipEvent_t> ev((size_t)2 * nk * reps, nullptr);
+    hipError_t err = hipSuccess;
+    for (size_t q = 0; q < ev.size() && err == hipSuccess; ++q) err = hipEventCreate(&ev[q]);
     float4* P[2] = {reinterpret_cast<float4*>(pos_a), reinterpret_cast<float4*>(pos_b)};
-    hipError_t err = hipEventRecord(e0, s);
     for (int k = 0; k < reps && err == hipSuccess; ++k) {
         a.pos_in = P[k & 1];
         a.pos_out = P[(k + 1) & 1];
         a.step = step0 + (uint64_t)k;
-        err = launch_step(a, false, s);
+        hipEvent_t* e = &ev[(size_t)2 * nk * k];
+        if (sums_fn) {
+            ForceArgs f = step_sums_args(a);
+            void* args[] = {&f};
+            err = hipExtLaunchKernel(sums_fn, dim3(nblocks(N, kWave)), dim3(kWave), args, shm, s, e[0], e[1], 0);
+            e += 2;
+        }
+        if (err == hipSuccess) {
+            void* args[] = {&a};
+            err = hipExtLaunchKernel(fn, dim3(nblocks(N, kStepBlock)), dim3(kStepBlock), args, shm, s, e[0], e[1], 0);
+        }
     }
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = launch_fold_status(c->d_blk, nblocks(N, kStepBlock), nullptr, N, status, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (err == hipSuccess) err = hipEventSynchronize(ev.back());
+    double total = 0.0;
+    for (size_t q = 0; q + 1 < ev.size() && err == hipSuccess; q += 2) {
+        float t = 0.f;
+        err = hipEventElapsedTime(&t, ev[q], ev[q + 1]);
+        total += t;
+    }
+    *ms = (float)total;
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (err != hipSuccess) return hip_fail(c, err, "rc_time_fused_steps");
     return RC_OK;
 }

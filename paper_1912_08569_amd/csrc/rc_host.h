@@ -78,12 +78,12 @@ struct CellsLayout {
 CellsLayout cells_layout(int N, uint32_t nkeys);
 
 int ensure_part(rc_ctx* c, size_t bytes);
-int ensure_ssum(rc_ctx* c, size_t n);
-int ensure_hsum(rc_ctx* c, size_t n);
+int ensure_ssum(rc_ctx* c, size_t n);   // d_ssum for n particles (drops graphs when it moves)
+int ensure_hsum(rc_ctx* c, size_t n);   // d_hsum for n particles
 // packed-list arrays for N particles and k_max slots (drops graphs when they move)
 int ensure_plist(rc_ctx* c, int N, int k_max);
 // the packed copy of (nlist, nn, k_max, N): made on the stream unless it is the current one
-int packed_list_for(rc_ctx* c, const int* nlist, const int* nn, int k_max, int N, hipStream_t s);   // d_hsum for n particles   // d_ssum for n particles (drops graphs when it moves)
+int packed_list_for(rc_ctx* c, const int* nlist, const int* nn, int k_max, int N, hipStream_t s);
 void free_ctx_buffers(rc_ctx* c);       // every device buffer the context owns
 // copy a device status word to the host and wait for it by spinning on an event
 int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s);

@@ -514,8 +514,12 @@ __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
 }
 
 // one block: fold the per-block maxima into the status word
+// Fold the per-block largest list lengths into the status words: KMAX and
+// the overflow flag.  fresh: write every word instead, as a cleared status
+// followed by this fold and a chunk reset would leave it (the driver's
+// rebuilds, which so need no separate clear and reset launches).
 __global__ __launch_bounds__(1024) void k_nlist_status(const int* __restrict__ block_max, int nb, int k_max,
-                                                      int* __restrict__ status) {
+                                                      int* __restrict__ status, int fresh) {
     __shared__ int red[1024];
     int m = 0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) m = max(m, block_max[b]);
@@ -526,8 +530,17 @@ __global__ __launch_bounds__(1024) void k_nlist_status(const int* __restrict__ b
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        status[RC_ST_KMAX] = max(status[RC_ST_KMAX], red[0]);
-        if (red[0] > k_max) status[RC_ST_FLAGS] |= RC_FLAG_NLIST_OVERFLOW;
+        const int ovf = red[0] > k_max ? RC_FLAG_NLIST_OVERFLOW : 0;
+        if (fresh) {
+            for (int w = 0; w < RC_STATUS_WORDS; ++w) status[w] = 0;
+            status[RC_ST_FLAGS] = ovf;
+            status[RC_ST_KMAX] = red[0];
+            status[RC_ST_FIRST_SOFT] = 0x7fffffff;
+            status[RC_ST_FIRST_HARD] = 0x7fffffff;
+        } else {
+            status[RC_ST_KMAX] = max(status[RC_ST_KMAX], red[0]);
+            status[RC_ST_FLAGS] |= ovf;
+        }
     }
 }
 
@@ -535,14 +548,18 @@ hipError_t launch_nlist(const NlistArgs& a, hipStream_t s) {
     const size_t shm = 2 * sizeof(float) * a.tab.nt * a.tab.nt;
     const int nb = nblk(a.N, kBlock);
     hipLaunchKernelGGL(k_nlist, dim3(nb), dim3(kBlock), shm, s, a);
-    if (a.status) hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status);
+    if (a.status)
+        hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status,
+                           a.fresh_status);
     return hipGetLastError();
 }
 
 hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s) {
     const int nb = nblk(a.N, kBlock);
     hipLaunchKernelGGL(k_nlist_batch, dim3(nb), dim3(kBlock), 0, s, a);
-    if (a.status) hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status);
+    if (a.status)
+        hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status,
+                           a.fresh_status);
     return hipGetLastError();
 }
 

@@ -707,14 +707,16 @@ hipError_t launch_reduce_rows_batch(const double* part, const RepDesc* rep, int 
     return hipGetLastError();
 }
 
-__global__ void k_status_reset_chunk(int* st) {
+__global__ void k_status_reset_chunk(int* st, unsigned long long* base, unsigned long long step) {
     // keep KMAX, MAXPATH and the overflow flag of the current list, clear the chunk-local markers
     st[RC_ST_FLAGS] &= RC_FLAG_NLIST_OVERFLOW;
     st[RC_ST_FIRST_SOFT] = 0x7fffffff;
     st[RC_ST_FIRST_HARD] = 0x7fffffff;
+    if (base) *base = step;  // the step counter of the graph replays, in the same launch
 }
-hipError_t launch_status_reset_chunk(int* status, hipStream_t s) {
-    hipLaunchKernelGGL(k_status_reset_chunk, dim3(1), dim3(1), 0, s, status);
+hipError_t launch_status_reset_chunk(int* status, hipStream_t s, unsigned long long* step_base,
+                                     unsigned long long step) {
+    hipLaunchKernelGGL(k_status_reset_chunk, dim3(1), dim3(1), 0, s, status, step_base, step);
     return hipGetLastError();
 }
 

@@ -254,8 +254,9 @@ int rc_build_cells(rc_ctx* c, float* pos, float* vel, int* image, int* rtag, int
     return RC_OK;
 }
 
-int rc_build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, const void* ws, size_t ws_bytes,
-                   int k_max, int* nlist, int* nn, int* status, void* stream) {
+// fresh: the status words are written whole (the driver's rebuilds), else folded into
+static int build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, const void* ws, size_t ws_bytes,
+                       int k_max, int* nlist, int* nn, int* status, bool fresh, void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
     if (k_max < 1 || k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
@@ -277,6 +278,7 @@ int rc_build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, c
     a.nlist = nlist;
     a.nn = nn;
     a.status = status;
+    a.fresh_status = fresh ? 1 : 0;
     a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
     if ((r = ensure_plist(c, N, k_max))) return r;
     a.pl_j = c->d_pl_j;  // the packed copy the fused step reads, made in the same launch
@@ -287,6 +289,11 @@ int rc_build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, c
     c->pl_k = k_max;
     c->pl_n = N;
     return RC_OK;
+}
+
+int rc_build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, const void* ws, size_t ws_bytes,
+                   int k_max, int* nlist, int* nn, int* status, void* stream) {
+    return build_nlist(c, pos, vel, N, box, ws, ws_bytes, k_max, nlist, nn, status, false, stream);
 }
 
 int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
@@ -647,9 +654,8 @@ struct PlainOps final : DriveOps {
         int rr = rc_build_cells(c, pos, buf->vel, buf->image, buf->rtag, N, box, buf->cells_ws, buf->cells_ws_bytes,
                                 s);
         if (rr) return rr;
-        HIP_TRY(c, launch_zero_words(buf->status, RC_STATUS_WORDS, s));
-        return rc_build_nlist(c, pos, buf->vel, N, box, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
-                              buf->nn, buf->status, s);
+        return build_nlist(c, pos, buf->vel, N, box, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
+                           buf->nn, buf->status, true, s);
     }
     int bonds(const float* pos, int row) override {
         HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(pos), buf->nlist, buf->nn, buf->k_max, N,

@@ -266,8 +266,9 @@ int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* r
     return RC_OK;
 }
 
-int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
-                         int* nlist, int* nn, int* status, void* stream) {
+// fresh: the status words are written whole (the driver's rebuilds), else folded into
+static int batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
+                             int* nlist, int* nn, int* status, bool fresh, void* stream) {
     if (!b) return RC_ERR_ARG;
     int r = check_pos(b, pos);
     if (r) return r;
@@ -286,6 +287,7 @@ int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* 
     a.nlist = nlist;
     a.nn = nn;
     a.status = status;
+    a.fresh_status = fresh ? 1 : 0;
     a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
     rc_ctx* c = &b->c;
     if ((r = ensure_plist(c, b->n_slots, k_max))) return r;
@@ -297,6 +299,11 @@ int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* 
     c->pl_k = k_max;
     c->pl_n = b->n_slots;
     return RC_OK;
+}
+
+int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
+                         int* nlist, int* nn, int* status, void* stream) {
+    return batch_build_nlist(b, pos, vel, ws, ws_bytes, k_max, nlist, nn, status, false, stream);
 }
 
 int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, const int* nn, int k_max, float* force,
@@ -424,9 +431,8 @@ struct BatchOps final : DriveOps {
     int rebuild(float* pos) override {
         int rr = rc_batch_build_cells(b, pos, buf->vel, buf->image, buf->rtag, buf->cells_ws, buf->cells_ws_bytes, s);
         if (rr) return rr;
-        HIP_TRY(&b->c, launch_zero_words(buf->status, RC_STATUS_WORDS, s));
-        return rc_batch_build_nlist(b, pos, buf->vel, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
-                                    buf->nn, buf->status, s);
+        return batch_build_nlist(b, pos, buf->vel, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
+                                 buf->nn, buf->status, true, s);
     }
     int bonds(const float* pos, int row) override {
         HIP_TRY(&b->c, launch_bonds_batch(reinterpret_cast<const float4*>(pos), buf->nlist, buf->nn, buf->k_max,

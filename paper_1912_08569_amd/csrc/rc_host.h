@@ -102,7 +102,9 @@ void drop_graphs(rc_ctx* c);
 struct DriveOps {
     virtual ~DriveOps() = default;
     // cell sort (permutes pos, vel, image) and list build from pos; the list
-    // kernels leave KMAX and the overflow flag in the status word
+    // kernels write the status words whole: KMAX and the overflow flag of the
+    // new list, MAXPATH zero and the chunk markers cleared (as a chunk reset
+    // leaves them)
     virtual int rebuild(float* pos) = 0;
     // bond count(s) of the state in pos into log row `row`
     virtual int bonds(const float* pos, int row) = 0;

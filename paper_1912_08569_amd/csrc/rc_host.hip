@@ -450,7 +450,6 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     };
 
     if ((r = rebuild(cur))) return finish(r);
-    HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
 
     const bool logging = buf->ev_log || buf->bonds_log;
     const int lp = opt.log_period;
@@ -504,7 +503,9 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             epoch_row = row;
             need_snap = false;
         }
-        HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+        // one launch clears the chunk markers and sets the replays' step counter
+        HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, step0 + (uint64_t)chunk_start));
+        dev_base = step0 + (uint64_t)chunk_start;
         // ---- run it --------------------------------------------------------------
         auto run_steps = [&](int64_t from, int64_t count) -> int {
             int64_t k = 0;
@@ -592,7 +593,8 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             const int64_t soft_step = (int64_t)hst[RC_ST_FIRST_SOFT];
             int64_t n_re = soft_step - (int64_t)((step0 + (uint64_t)epoch_start) & 0x7fffffff) + 1;
             n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, chunk_start + C - epoch_start));
-            HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
+            HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, step0 + (uint64_t)epoch_start));
+            dev_base = step0 + (uint64_t)epoch_start;
             if ((r = run_steps(epoch_start, n_re))) return finish(r);
             HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
             done = epoch_start + n_re;
@@ -600,7 +602,6 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             if ((r = rebuild(cur))) return finish(r);
             rate = std::max(rate, (double)mp / std::max<int64_t>(1, C));
             last_maxpath = 0.0f;
-            HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
             continue;
         }
         done = chunk_start + C;
@@ -609,7 +610,6 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if (f & RC_FLAG_REBUILD) {
             if ((r = rebuild(cur))) return finish(r);
             last_maxpath = 0.0f;
-            HIP_TRY(c, launch_status_reset_chunk(buf->status, s));
         }
     }
     // ---- final half kick (and the last log row) ------------------------------------

@@ -509,6 +509,7 @@ struct NlistArgs {
     int* block_max;    // [ceil(N / kBlock)] scratch (largest list length per block)
     int* pl_j;         // packed copy of the list (NULL: none), see pack_wave_lists
     unsigned char* pl_o;
+    int fresh_status;  // 1: write every status word (see k_nlist_status); 0: fold into them
 };
 hipError_t launch_nlist(const NlistArgs& a, hipStream_t s);
 // the packed copy of a list built elsewhere
@@ -527,7 +528,10 @@ hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s);
 // reduce nblocks partial rows of 13 doubles into out[first .. first+count)
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
                               hipStream_t s);
-hipError_t launch_status_reset_chunk(int* status, hipStream_t s);
+// clear the chunk-local status markers (keeping KMAX, MAXPATH and the overflow flag) and, if
+// step_base is not NULL, set *step_base = step
+hipError_t launch_status_reset_chunk(int* status, hipStream_t s, unsigned long long* step_base = nullptr,
+                                     unsigned long long step = 0);
 // one launch copying pos, vel and (if both non-NULL) image: the driver's snapshot and its restore;
 // zero_path writes the velocities' path lengths (w) as zero (a restore of the state a list build left)
 hipError_t launch_copy_state(const float4* pos, const float4* vel, const int4* image, float4* pos_to, float4* vel_to,
@@ -620,6 +624,7 @@ struct NlistArgsB {
     int* block_max;
     int* pl_j;              // packed copy of the list (NULL: none), see pack_wave_lists
     unsigned char* pl_o;
+    int fresh_status;       // as in NlistArgs
 };
 hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s);
 

@@ -120,7 +120,12 @@ typedef struct rc_box {
 
 typedef struct rc_integrator {
     int kind;                      /* RC_INTEGRATOR_*                            */
-    int pad;
+    int dim;                       /* 3 (or 0): 3D.  2: motion in the xy plane:
+                                      the thermostat draws no z noise, so a
+                                      system whose particles share one z and
+                                      have vz = 0 keeps them (the z force
+                                      components are then exactly zero); the
+                                      box's z edge is still >= 3 list radii  */
     double dt;
     double kT;
     double gamma;                  /* friction (1/time); ignored for NVE        */

@@ -12,7 +12,9 @@ splitting of Leimkuhler & Matthews (2013):
   B: v += (dt/2) F(x_new)/m
 
 gamma = 0 gives velocity Verlet (NVE).  xi are the Philox/Box-Muller normals
-of ``philox_ref`` keyed by (seed, tag, step).
+of ``philox_ref`` keyed by (seed, tag, step).  dim = 2 (the paper's 2d boxes,
+Sec. 3.2) keeps motion in the xy plane: the z component of xi is dropped, so
+particles that share one z and have vz = 0 keep them.
 
 Parity status: pinned by equipartition, NVE energy conservation and time
 reversibility tests.
@@ -40,7 +42,7 @@ def wrap(x, L):
 
 
 def baoab_step(pos, vel, types, tags, L, table, mass_by_type, dt, kT, gamma, seed, step,
-               force=None, extra=None):
+               force=None, extra=None, dim=3):
     """Advance (pos, vel) by one step; returns dict(pos, vel, image, F, F_old).
 
     extra(x) -> [N,3], if given, adds a further force (e.g. bond springs; x in
@@ -60,6 +62,9 @@ def baoab_step(pos, vel, types, tags, L, table, mass_by_type, dt, kT, gamma, see
         c1 = math.exp(-gamma * dt)
         c2 = np.sqrt((1.0 - c1 * c1) * kT / m)
         xi = philox_ref.thermostat_normals(seed, tags, step)
+        if dim == 2:
+            xi = np.asarray(xi, dtype=np.float64).copy()
+            xi[:, 2] = 0.0
         v = c1 * v + c2 * xi
     x = x + 0.5 * dt * v
     x, img = wrap(x, L)

@@ -60,7 +60,7 @@ class Box(ctypes.Structure):
 
 
 class Integrator(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("pad", ctypes.c_int), ("dt", ctypes.c_double),
+    _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int), ("dt", ctypes.c_double),
                 ("kT", ctypes.c_double), ("gamma", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("mass", ctypes.c_double * RC_MAX_TYPES)]
 

@@ -51,9 +51,11 @@ def box(edges) -> L.Box:
     return out
 
 
-def integrator(kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0, mass: Sequence[float] = (1.0,)):
+def integrator(kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0, mass: Sequence[float] = (1.0,), dim: int = 3):
+    """rc_integrator; dim = 2 keeps motion in the xy plane (no thermostat noise along z)."""
     cfg = L.Integrator()
     cfg.kind = L.RC_INTEGRATOR_LANGEVIN if kind == "langevin" else L.RC_INTEGRATOR_NVE
+    cfg.dim = int(dim)
     cfg.dt, cfg.kT, cfg.gamma, cfg.seed = float(dt), float(kT), float(gamma), int(seed)
     for t in range(L.RC_MAX_TYPES):
         cfg.mass[t] = float(mass[t]) if t < len(mass) else 1.0

@@ -137,8 +137,8 @@ class Batch:
         """"walk" (one pass, partner sums by list walks) or "sums" (two passes): speed only."""
         self.bc.set_step_form(form)
 
-    def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
-        return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))
+    def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0, dim=3):
+        return api.integrator(kind, dt, kT, gamma, seed, list(self.mass), dim=dim)
 
     def md_buffers(self, ev_log=None, bonds_log=None) -> rcl.MdBuffers:
         b = rcl.MdBuffers()

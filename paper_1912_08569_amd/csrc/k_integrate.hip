@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a) {
                 const float c2 = a.c2[t];
                 vx = a.c1 * vx + c2 * z0;
                 vy = a.c1 * vy + c2 * z1;
-                vz = a.c1 * vz + c2 * z2;
+                vz = a.c1 * vz + c2 * a.noise_z * z2;  // no z noise in the xy plane
             }
             sx += hdt * vx;
             sy += hdt * vy;

@@ -341,7 +341,7 @@ int rc_integrate_step(rc_ctx* c, float* pos, float* vel, const float* force, int
     IntegrateArgs a{};
     float c1;
     int lang;
-    if ((r = check_integrator(c, cfg, a.minv, a.c2, c1, lang))) return r;
+    if ((r = check_integrator(c, cfg, a.minv, a.c2, c1, lang, a.noise_z))) return r;
     const int nb = nblocks(N, kBlock);
     if (kin && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
     a.pos = reinterpret_cast<float4*>(pos);
@@ -369,7 +369,7 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
                           double soft_frac, int* status, hipStream_t s, bool pack = true) {
     float c1;
     int lang;
-    int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang);
+    int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang, a.noise_z);
     if (r) return r;
     if ((r = check_list(c, nlist, nn, k_max))) return r;
     a.pos_in = reinterpret_cast<const float4*>(pos_in);

@@ -64,7 +64,7 @@ int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* p
     rc_ctx* c = &b->c;
     float c1;
     int lang;
-    int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang);
+    int r = check_integrator(c, cfg, a.minv, a.c2, c1, lang, a.noise_z);
     if (r) return r;
     if ((r = check_list(c, nlist, nn, k_max))) return r;
     if ((r = ensure_seeds(b, cfg, s))) return r;

@@ -88,7 +88,8 @@ void free_ctx_buffers(rc_ctx* c);       // every device buffer the context owns
 // copy a device status word to the host and wait for it by spinning on an event
 int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s);
 int ensure_blk(rc_ctx* c, int nb, hipStream_t s);
-int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin);
+int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin,
+                     float& noise_z);
 int check_list(rc_ctx* c, const int* nlist, const int* nn, int k_max);
 
 // Validate one ntypes x ntypes table and compile it; returns RC_OK or

@@ -209,8 +209,12 @@ int ensure_blk(rc_ctx* c, int nb, hipStream_t s) {
     return RC_OK;
 }
 
-int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin) {
+int check_integrator(rc_ctx* c, const rc_integrator* cfg, float* minv, float* c2, float& c1, int& langevin,
+                     float& noise_z) {
     if (!cfg) return fail(c, RC_ERR_ARG, "integrator is NULL");
+    if (cfg->dim != 0 && cfg->dim != 2 && cfg->dim != 3)
+        return fail(c, RC_ERR_ARG, "integrator dim must be 2 or 3 (0 = 3), not %d", cfg->dim);
+    noise_z = cfg->dim == 2 ? 0.0f : 1.0f;
     if (cfg->kind != RC_INTEGRATOR_NVE && cfg->kind != RC_INTEGRATOR_LANGEVIN)
         return fail(c, RC_ERR_ARG, "unknown integrator kind %d", cfg->kind);
     if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return fail(c, RC_ERR_ARG, "dt must be positive");

@@ -390,6 +390,7 @@ struct StepArgs {
     float c2[RC_MAX_TYPES];    // sqrt((1 - c1^2) kT / m) per type
     float dt, c1;
     int langevin;
+    float noise_z;   // 1, or 0 for motion in the xy plane (no thermostat noise along z)
     float hard, soft;          // path-length thresholds (stale list, rebuild)
     uint64_t seed;
     uint64_t step;             // step index (added to *step_base if not NULL)
@@ -466,6 +467,7 @@ struct IntegrateArgs {
     float c2[RC_MAX_TYPES];
     float dt, c1;
     int langevin;
+    float noise_z;   // 1, or 0 for motion in the xy plane (no thermostat noise along z)
     float soft;
     uint64_t seed, step;
     double* kin_part;   // [nblocks*13] | NULL (slots 7..12 used)

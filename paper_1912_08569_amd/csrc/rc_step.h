@@ -48,7 +48,7 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, float4* pos_out, 
                 const float c2 = a.c2[tm];
                 vx = a.c1 * vx + c2 * z0;
                 vy = a.c1 * vy + c2 * z1;
-                vz = a.c1 * vz + c2 * z2;
+                vz = a.c1 * vz + c2 * a.noise_z * z2;  // no z noise in the xy plane
             }
             sx += hdt * vx;  // A
             sy += hdt * vy;

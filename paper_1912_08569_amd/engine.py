@@ -242,8 +242,8 @@ class System:
         nn = self.nn
         return float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())
 
-    def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0):
-        return api.integrator(kind, dt, kT, gamma, seed, list(self.mass))
+    def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0, dim=3):
+        return api.integrator(kind, dt, kT, gamma, seed, list(self.mass), dim=dim)
 
     def md_buffers(self, ev_log=None, bonds_log=None) -> rcl.MdBuffers:
         b = rcl.MdBuffers()

@@ -21,16 +21,18 @@ def _ulp32(x):
     return (np.nextafter(x, np.float32(np.inf)) - x).astype(np.float64)
 
 
-def _one_step_check(s, kind, dt, kT, gamma, seed, step, form="walk"):
+def _one_step_check(s, kind, dt, kT, gamma, seed, step, form="walk", dim=3):
     S = _system(s)
     S.set_step_form(form)
     S.build()
     x0, v0, _, ty = S.state_by_tag()
-    cfg = S.integrator(kind=kind, dt=dt, kT=kT, gamma=gamma, seed=seed)
+    cfg = S.integrator(kind=kind, dt=dt, kT=kT, gamma=gamma, seed=seed, dim=dim)
     S.run(1, cfg, step0=step, use_graph=False)
     x1, v1, img, _ = S.state_by_tag()
     ref = dynamics_ref.baoab_step(x0, v0, ty, np.arange(s.N), s.L, s.table, s.mass, dt, kT,
-                                  gamma if kind == "langevin" else 0.0, seed, step)
+                                  gamma if kind == "langevin" else 0.0, seed, step, dim=dim)
+    if dim == 2:   # the plane is kept exactly
+        assert np.all(x1[:, 2] == x0[:, 2]) and np.all(v1[:, 2] == 0.0)
     e0 = swap_ref.evaluate(x0, ty, s.L, s.table)
     e1 = swap_ref.evaluate(ref["pos"], ty, s.L, s.table)
     m = s.mass[ty][:, None]
@@ -50,6 +52,29 @@ def _one_step_check(s, kind, dt, kT, gamma, seed, step, form="walk"):
 def test_fused_step_matches_oracle_small(kind):
     s = W.small_reactive(N=1000, density=0.2, seed=1001, table=W.swap_table_single(lam=0.7))
     _one_step_check(s, kind, 0.002, 0.1, 1.0, 2001, 17)
+
+
+@pytest.mark.parametrize("kind", ["langevin", "nve"])
+def test_planar_step_matches_oracle(kind):
+    # the paper's 2d box (side 39.63, 1000 particles, kT 1): integrator dim 2
+    s = W.planar_reactive(N=1000, seed=1012)
+    _one_step_check(s, kind, 0.001, 1.0, 1.0, 2012, 31, dim=2)
+
+
+def test_planar_run_stays_in_the_plane():
+    from paper_1912_08569_amd import RcError, api
+    s = W.planar_reactive(N=1000, seed=1013)
+    S = _system(s)
+    with pytest.raises(RcError):
+        S.run(1, api.integrator(dt=0.001, kT=1.0, gamma=1.0, seed=5, mass=list(S.mass), dim=4))
+    cfg = S.integrator(dt=0.001, kT=1.0, gamma=1.0, seed=5, dim=2)
+    res = S.run(3000, cfg, log_period=0)
+    assert res.stats.rebuilds >= 1
+    x, v, img, ty = S.state_by_tag()
+    assert np.all(x[:, 2] == 0.0) and np.all(v[:, 2] == 0.0) and np.all(img[:, 2] == 0)
+    # equipartition in the plane: <m (vx^2 + vy^2)> = 2 kT (2000 degrees of freedom: ~3 % scatter)
+    ke2 = float(np.mean(s.mass[ty] * (v[:, 0].astype(np.float64) ** 2 + v[:, 1].astype(np.float64) ** 2)))
+    assert abs(ke2 / 2.0 - 1.0) < 0.12, ke2
 
 
 def test_fused_step_matches_oracle_mixture():

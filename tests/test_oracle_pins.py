@@ -686,3 +686,18 @@ def test_partner_counts_pin():
     assert O.partner_counts(p0, pt, odd) == (2, 1, 0)
     b, u, _ = O.partner_counts(p0, pt, odd)
     assert swap_ref.bond_autocorrelation(p0, pt, mask=odd) == u / b
+
+
+def test_planar_step_pin():
+    # dim 2 drops only the z noise: with every particle at z = 0 and vz = 0 the z force components
+    # vanish, so the step keeps z and vz exactly, and the positions in the plane are the 3D step's
+    # (whose z noise does move z)
+    s = W.planar_reactive(N=60, L=12.0, Lz=6.0, seed=5, min_dist=0.9)
+    tags = np.arange(s.N)
+    a = dynamics_ref.baoab_step(s.pos, s.vel, s.types, tags, s.box, s.table, s.mass, 0.002, 1.0, 1.0, 7, 3, dim=2)
+    b = dynamics_ref.baoab_step(s.pos, s.vel, s.types, tags, s.box, s.table, s.mass, 0.002, 1.0, 1.0, 7, 3, dim=3)
+    assert np.all(a["F_old"][:, 2] == 0.0) and np.all(a["F"][:, 2] == 0.0)
+    assert np.all(a["pos"][:, 2] == 0.0) and np.all(a["vel"][:, 2] == 0.0)
+    assert np.any(b["pos"][:, 2] != 0.0)
+    assert np.array_equal(a["pos"][:, :2], b["pos"][:, :2])
+    assert np.any(np.abs(a["F_old"][:, :2]) > 0.0)   # the configuration does interact

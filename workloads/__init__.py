@@ -19,6 +19,8 @@ Recipes (all seeded with numpy PCG64):
   sites and free two-bead crosslinkers, grown self-avoiding in the box.
 * ``dumbbell_mixture`` -- the A/B bond-swap mixture (A:B = 3:2, n = 100,
   density 0.125) of the paper's swap test and performance figure.
+* ``planar_reactive`` -- reactive particles in the plane z = 0 of the paper's
+  2d square box (side 39.63), for the integrator's dim = 2 mode.
 * ``cluster``         -- hand-placed few-particle configurations.
 """
 from .systems import (  # noqa: F401
@@ -26,6 +28,6 @@ from .systems import (  # noqa: F401
     PairTable, System, fp32_box, wrap_fp32,
     swap_table_single, assembly_table,
     small_reactive, assembly_mixture, replica_set, cluster, vitrimer_network, vitrimer_table,
-    dumbbell_mixture, dumbbell_table,
+    dumbbell_mixture, dumbbell_table, planar_reactive,
     maxwell_velocities, rsa_positions,
 )

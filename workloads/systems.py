@@ -101,7 +101,7 @@ class System:
 
     @property
     def box(self) -> np.ndarray:
-        return np.array([self.L, self.L, self.L], dtype=np.float64)
+        return np.broadcast_to(np.asarray(self.L, dtype=np.float64), (3,)).copy()
 
 
 def fp32_box(N: int, density: float) -> float:
@@ -202,6 +202,38 @@ def assembly_table(lam: float, eps_site=15.0, sigma_site=0.3, n=10, rcut_site=0.
     t.set(0, 1, KIND_WCA, 1.0, sigma_cross, 6)
     t.set(1, 1, KIND_SWAP, eps_site, sigma_site, n, rcut_site, lam)
     return t
+
+
+def planar_reactive(N=1000, L=39.63, Lz=8.0, seed=1012, min_dist=0.9, kT=1.0,
+                    table: Optional[PairTable] = None) -> System:
+    """N reactive particles in the plane z = 0 of a (L, L, Lz) box with vz = 0: the paper's 2d square
+    box (Sec. 3.2: side 39.63 sigma, 1000 particles, kT/eps = 1) filled with point particles of the
+    single-entry swap table (eps 1, sigma 1, n 10, r_cut 1.5, lambda 1).  Run it with an integrator of
+    dim 2.  Lz only has to hold three list radii.  Uniform random sequential addition in the plane,
+    rejecting distances <= min_dist."""
+    rng = np.random.default_rng(seed)
+    Lf = float(np.float32(L))
+    Lzf = float(np.float32(Lz))
+    acc = []
+    while len(acc) < N:
+        for c in wrap_fp32(rng.uniform(-0.5 * Lf, 0.5 * Lf, size=(4 * N, 3)), Lf)[:, :2].astype(np.float64):
+            if len(acc) >= N:
+                break
+            if acc:
+                d = c - np.asarray(acc)
+                d -= Lf * np.round(d / Lf)
+                if np.min(np.einsum("ij,ij->i", d, d)) <= min_dist * min_dist:
+                    continue
+            acc.append(c)
+    pos = np.zeros((N, 3), np.float32)
+    pos[:, :2] = np.asarray(acc, dtype=np.float32)
+    types = np.zeros(N, np.int32)
+    tab = table if table is not None else swap_table_single(lam=1.0)
+    mass = np.ones(tab.ntypes)
+    vel = maxwell_velocities(rng, types, mass, kT)
+    vel[:, 2] = 0.0
+    return System(pos=pos, types=types, L=(Lf, Lf, Lzf), table=tab, mass=mass, vel=vel,
+                  name=f"planar reactive N={N} L={Lf}")
 
 
 def small_reactive(N=1000, density=0.2, seed=1001, min_dist=0.8, kT=0.1,

@@ -163,11 +163,10 @@ def candidate_pairs(pos64: np.ndarray, L: np.ndarray, rmax: float):
     if N <= 2500 or rmax >= 0.45 * float(np.min(L)):
         i, j = np.triu_indices(N, k=1)
         return i.astype(np.int64), j.astype(np.int64)
-    Lx = float(L[0])
-    assert np.all(L == Lx), "k-d tree path assumes a cubic box"
-    p = pos64 + 0.5 * Lx
-    p = np.minimum(np.maximum(p, 0.0), np.nextafter(Lx, 0.0))
-    tree = cKDTree(p, boxsize=Lx)
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    p = pos64 + 0.5 * Lv
+    p = np.minimum(np.maximum(p, 0.0), np.nextafter(Lv, 0.0))
+    tree = cKDTree(p, boxsize=Lv)   # periodic along each axis (orthorhombic boxes)
     pairs = tree.query_pairs(rmax * (1.0 + 1e-9) + 1e-12, output_type="ndarray")
     if pairs.size == 0:
         return np.zeros(0, np.int64), np.zeros(0, np.int64)

@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 256 MiB device copy (to scale FETCH/WRITE counters)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-replica comparison")
+    p.add_argument("--no-rigid", action="store_true", help="skip the rigid patchy-body run")
+    p.add_argument("--rigid-steps", type=int, default=2000)
     p.add_argument("--batch-steps", type=int, default=1000)
     p.add_argument("--seq-steps", type=int, default=200, help="steps of each replica run alone")
     p.add_argument("--no-tune", action="store_true", help="batched run with the default launch settings")
@@ -267,6 +269,24 @@ def adjoint_bench(a):
     return out
 
 
+def rigid_bench(a):
+    """The 2d patchy mixture of Sec. 3.2 as rigid bodies: steps/s of the body step (forces, body kernel,
+    list rebuilds when due; one host check of the path lengths per step)."""
+    import workloads as W
+    from paper_1912_08569_amd import RigidBodies, System
+    s = W.patchy_mixture()
+    S = System.from_workload(s)
+    R = RigidBodies(S, s.meta["bodies"], s.meta["theta"], s.meta["omega"])
+    cfg = S.integrator(dt=0.001, kT=1.0, gamma=1.0, seed=9, dim=2)
+    R.run(200, cfg)
+    out = R.run(a.rigid_steps, cfg, step0=200)
+    print(f"# rigid patchy mixture: {a.rigid_steps / out['seconds']:.0f} steps/s", file=sys.stderr, flush=True)
+    return {"workload": "2d patchy mixture: 400 trifunctional + 600 difunctional rigid disks (3400 particles), "
+                        "box 39.63, patch swap eps 20 sigma 0.1 r_cut 0.2, Langevin kT 1 dt 0.001",
+            "unit": "timesteps/s", "steps": a.rigid_steps, "steps_per_s": round(a.rigid_steps / out["seconds"], 1),
+            "rebuilds": out["rebuilds"], "particles": int(s.N), "bodies": int(len(s.meta["bodies"]["centre"]))}
+
+
 def dumbbell_bench(a):
     """The paper's performance workload: the A:B = 3:2 dumbbell mixture (n = 100, WCA AA/BB, density
     0.125, kT 0.03) at N = 2^9 ... 2^17 particles and cutoffs 1.3 and 1.15, as timesteps per second.
@@ -331,6 +351,8 @@ def main():
             out["batch"] = batch_bench(a)
         if not a.no_dumbbells:
             out["dumbbells"] = dumbbell_bench(a)
+        if not a.no_rigid:
+            out["rigid"] = rigid_bench(a)
         print(json.dumps(out), flush=True)
         return
     t_gen = time.perf_counter()
@@ -435,6 +457,8 @@ def main():
         out["batch"] = batch_bench(a)
     if not a.no_dumbbells:
         out["dumbbells"] = dumbbell_bench(a)
+    if not a.no_rigid:
+        out["rigid"] = rigid_bench(a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysw, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -275,6 +275,30 @@ int rc_integrate_step(rc_ctx* ctx, float* pos, float* vel, const float* force,
                       uint64_t step, int half, double* kin /* [6] | NULL */,
                       int* status /* NULL ok */, void* stream);
 
+/* ---- rigid planar bodies (next-4: the patchy colloids of Sec. 3.2) ----------
+ * Body b is the particle with tag centre[b] (a disk; its type's mass) plus the
+ * massless member particles with tags member[first[b] .. first[b+1]) held at
+ * body-frame offsets (offset[2m], offset[2m+1]), turned by the angle theta[b].
+ * Motion is in the xy plane: cfg->dim must be 2, and every particle keeps its
+ * z.  With the forces in `force` (every particle, current positions):
+ *   RC_HALF_FIRST : v += dt/2 F/M, w += dt/2 tau/I ; x += dt/2 v, theta += dt/2 w ;
+ *                   v = c1 v + sqrt((1-c1^2) kT/M) (xi_x, xi_y),
+ *                   w = c1 w + sqrt((1-c1^2) kT/I) xi_z ; x += dt/2 v,
+ *                   theta += dt/2 w (theta folded into [-pi, pi)) ; members
+ *                   placed at x + R(theta) offset, their path lengths grown
+ *                   by their own moves
+ *   RC_HALF_SECOND: v += dt/2 F/M, w += dt/2 tau/I
+ * F and tau (about the centre, minimum image) sum the centre's and the
+ * members' forces; xi are the centre's thermostat normals (tag, step).  Member
+ * velocities are set to v + w x d.  rtag maps tag -> index (rc_build_cells);
+ * inertia, theta and omega are [B] device arrays, first is [B+1], member [M],
+ * offset [M][2].  A non-finite body state sets RC_FLAG_NONFINITE in status.  */
+int rc_rigid_step(rc_ctx* ctx, float* pos, float* vel, const float* force, int* image /* NULL ok */,
+                  const int* rtag, int B, const int* centre, const int* first, const int* member,
+                  const float* offset, const float* inertia, float* theta, float* omega, int N, rc_box box,
+                  const rc_integrator* cfg /* host */, uint64_t step, int half, int* status /* NULL ok */,
+                  void* stream);
+
 /* ---- fused step (the metric path: a3 + a5 in one kernel) ---------------------
  * One kernel per MD step.  Reads pos_in, writes pos_out (pos_in != pos_out,
  * double buffered).  Each particle m gathers every force term that moves it:

@@ -13,5 +13,6 @@ from . import api  # noqa: E402
 from .api import *  # noqa: E402,F401,F403
 from .engine import RunResult, System  # noqa: E402,F401
 from .batch import Batch, BatchResult  # noqa: E402,F401
+from .rigid import RigidBodies  # noqa: E402,F401
 
 __version__ = "0.1.0"

@@ -122,6 +122,8 @@ _SIGS = {
     "rc_force_hvp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),
     "rc_force_hvp_batch": ([_VP, _VP, _VP, _VP, _I, _I, Box, _I, _VP, _VP, _VP], _I),
     "rc_partner_counts": ([_VP, _VP, _VP, _VP, _I, _VP, _VP], _I),
+    "rc_rigid_step": ([_VP, _VP, _VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, Box,
+                       ctypes.POINTER(Integrator), _U64, _I, _VP, _VP], _I),
     "rc_stress_autocorrelation": ([_VP, _VP, _I, ctypes.c_double, ctypes.c_double, _I, _VP, _VP], _I),
     "rc_param_grad": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP], _I),
     "rc_param_vjp": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _VP], _I),

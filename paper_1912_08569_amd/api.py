@@ -187,6 +187,17 @@ def _kmax(nlist, N):
     return int(nlist.numel() // max(N, 1))
 
 
+def rc_rigid_step(ctx: Context, pos, vel, force, image, rtag, bodies, theta, omega, bx, cfg, step, half,
+                  status=None, stream=None):
+    """bodies: dict of device tensors centre, first, member, offset [M,2] float32, inertia."""
+    N = pos.shape[0]
+    check(L.load().rc_rigid_step(ctx.handle, _ptr(pos), _ptr(vel), _ptr(force), _ptr(image), _ptr(rtag),
+                                 int(bodies["centre"].shape[0]), _ptr(bodies["centre"]), _ptr(bodies["first"]),
+                                 _ptr(bodies["member"]), _ptr(bodies["offset"]), _ptr(bodies["inertia"]),
+                                 _ptr(theta), _ptr(omega), N, bx, ctypes.byref(cfg), int(step), int(half),
+                                 _ptr(status), _stream(stream)), ctx.handle)
+
+
 def rc_compute_forces(ctx: Context, pos, nlist, nn, bx, force, ev=None, flags=0, status=None, stream=None):
     N = pos.shape[0]
     check(L.load().rc_compute_forces(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,

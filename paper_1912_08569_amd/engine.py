@@ -43,6 +43,7 @@ class System:
         self.device = torch.device(device)
         self.step_form = step_form
         self.ctx = api.Context(table, r_buff)
+        self.r_buff = float(r_buff)
         self.table = table
         self.N = int(np.asarray(pos).shape[0])
         self.edges = [float(L)] * 3 if np.isscalar(L) else [float(x) for x in L]

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import adjoint_ref, dynamics_ref, literal, philox_ref, swap_ref
+from oracle import adjoint_ref, dynamics_ref, literal, philox_ref, rigid_ref, swap_ref
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -701,3 +701,58 @@ def test_planar_step_pin():
     assert np.any(b["pos"][:, 2] != 0.0)
     assert np.array_equal(a["pos"][:, :2], b["pos"][:, :2])
     assert np.any(np.abs(a["F_old"][:, :2]) > 0.0)   # the configuration does interact
+
+
+def _two_bodies(p0, p1, th, v, w, L=(60.0, 60.0, 8.0), eps_patch=20.0):
+    # a trifunctional body (3 patches) and a difunctional one (2 patches), tags 0, 1 and 2..6
+    off = np.array([[0.5 * np.cos(a), 0.5 * np.sin(a)] for a in (0.0, 2 * np.pi / 3, 4 * np.pi / 3, 0.0, np.pi)])
+    bodies = dict(centre=np.array([0, 1]), first=np.array([0, 3, 5]), member=np.arange(2, 7), offset=off,
+                  inertia=np.array([0.125, 0.125]))
+    pos = np.zeros((7, 3))
+    pos[0, :2], pos[1, :2] = p0, p1
+    th = np.asarray(th, dtype=np.float64)
+    pos = rigid_ref.place(pos, bodies, th, L)
+    vel = np.zeros((7, 3))
+    vel[0, :2], vel[1, :2] = v[0], v[1]
+    types = np.array([0, 1, 2, 2, 2, 2, 2])
+    return pos, vel, th, np.asarray(w, dtype=np.float64), types, bodies, W.patchy_table(eps_patch=eps_patch)
+
+
+def test_rigid_free_body_pin():
+    # bodies far apart: no force, so gamma = 0 steps move and turn them uniformly
+    L = (60.0, 60.0, 8.0)
+    pos, vel, th, w, ty, bodies, tab = _two_bodies((-10.0, 0.0), (10.0, 3.0), (0.3, -2.0), ((0.7, -0.2), (-0.1, 0.4)),
+                                                  (1.5, -3.0), L)
+    x, v, t, o = pos, vel, th, w
+    dt, K = 0.01, 40
+    for k in range(K):
+        out = rigid_ref.step(x, v, t, o, ty, bodies, L, tab, np.ones(3), dt, 0.0, 0.0, 1, k)
+        x, v, t, o = out["pos"], out["vel"], out["theta"], out["omega"]
+    want_th = np.mod(th + K * dt * w + np.pi, 2 * np.pi) - np.pi
+    assert np.allclose(t, want_th, atol=1e-12) and np.allclose(o, w, atol=0)
+    assert np.allclose(x[:2, :2], pos[:2, :2] + K * dt * vel[:2, :2], atol=1e-12)
+    assert np.allclose(x, rigid_ref.place(x, bodies, want_th, L), atol=1e-12)
+
+
+def test_rigid_collision_conserves_energy_and_angular_momentum():
+    # two bodies whose facing patches bind, at gamma = 0: energy to O(dt^2), angular momentum about
+    # the origin to rounding (every force of the potential is central, so it exerts no net torque)
+    L = (60.0, 60.0, 8.0)
+    pos, vel, th, w, ty, bodies, tab = _two_bodies((-0.58, 0.0), (0.58, 0.03), (0.0, np.pi),
+                                                  ((0.3, 0.1), (-0.3, 0.0)), (0.5, -0.2), L)
+    m = np.ones(3)
+
+    def energy(x, v, o):
+        kt, kr = rigid_ref.kinetic(v, o, ty, bodies, m)
+        return kt + kr + swap_ref.evaluate(x, ty, L, tab, scales=False)["E"]
+
+    e0, l0 = energy(pos, vel, w), rigid_ref.angular_momentum(pos, vel, w, ty, bodies, m)
+    assert abs(swap_ref.evaluate(pos, ty, L, tab, scales=False)["E"]) > 0.1   # the patches interact
+    x, v, t, o = pos, vel, th, w
+    de = 0.0
+    for k in range(1000):
+        out = rigid_ref.step(x, v, t, o, ty, bodies, L, tab, m, 1e-5, 0.0, 0.0, 1, k)
+        x, v, t, o = out["pos"], out["vel"], out["theta"], out["omega"]
+        de = max(de, abs(energy(x, v, o) - e0))
+    assert de < 2e-3 * abs(e0), (de, e0)
+    assert abs(rigid_ref.angular_momentum(x, v, o, ty, bodies, m) - l0) < 1e-10

@@ -21,6 +21,8 @@ Recipes (all seeded with numpy PCG64):
   density 0.125) of the paper's swap test and performance figure.
 * ``planar_reactive`` -- reactive particles in the plane z = 0 of the paper's
   2d square box (side 39.63), for the integrator's dim = 2 mode.
+* ``patchy_mixture``  -- the 2d mixture of tri- and difunctional patchy disks
+  (rigid bodies: centres plus rim patches) in the same box.
 * ``cluster``         -- hand-placed few-particle configurations.
 """
 from .systems import (  # noqa: F401
@@ -28,6 +30,6 @@ from .systems import (  # noqa: F401
     PairTable, System, fp32_box, wrap_fp32,
     swap_table_single, assembly_table,
     small_reactive, assembly_mixture, replica_set, cluster, vitrimer_network, vitrimer_table,
-    dumbbell_mixture, dumbbell_table, planar_reactive,
+    dumbbell_mixture, dumbbell_table, planar_reactive, patchy_mixture, patchy_table,
     maxwell_velocities, rsa_positions,
 )

@@ -236,6 +236,83 @@ def planar_reactive(N=1000, L=39.63, Lz=8.0, seed=1012, min_dist=0.9, kT=1.0,
                   name=f"planar reactive N={N} L={Lf}")
 
 
+def patchy_table(eps_patch=20.0, sigma_patch=0.1, n=10, rcut_patch=0.2, lam=1.0) -> PairTable:
+    """Sec. 3.2's swapping patchy mixture: type 0 = trifunctional disk, 1 = difunctional disk (WCA,
+    eps 1, sigma 1, among all disks), 2 = patch (the swap potential among patches: eps 20 kT at kT 1,
+    sigma 0.1 so that r_min ~ the paper's patch length 0.1, r_cut 0.2 = its bond distance; n 10,
+    lambda 1); disks and patches do not interact."""
+    t = PairTable.empty(3)
+    for a in (0, 1):
+        for b in (0, 1):
+            t.set(a, b, KIND_WCA, 1.0, 1.0, 6)
+    t.set(2, 2, KIND_SWAP, eps_patch, sigma_patch, n, rcut_patch, lam)
+    return t
+
+
+def patchy_mixture(n_tri=400, n_di=600, L=39.63, Lz=8.0, seed=1014, kT=1.0, min_dist=0.95, radius=0.5,
+                   patch_gap=0.15, table: Optional[PairTable] = None) -> System:
+    """The 2d mixture of Sec. 3.2: n_tri trifunctional and n_di difunctional disks (sigma 1) with patches
+    on the rim (radius 0.5; three at 120 degrees, two at 180) in a square box of side 39.63, kT 1.
+    Tags 0 .. B-1 are the disk centres (type 0 / 1), then the patches (type 2), body by body.  Random
+    sequential addition of the centres in the plane z = 0, uniform angles (redrawn for bodies with a
+    patch closer than patch_gap to another body's patch), Maxwell velocities in the
+    plane (vz = 0) and angular velocities of variance kT/I with I = radius^2 / 2 (unit-mass disks).
+    meta["bodies"] holds centre [B], first [B+1], member [M], offset [M, 2] (body frame), inertia [B];
+    meta["theta"], meta["omega"] the initial angles and angular velocities."""
+    base = planar_reactive(N=n_tri + n_di, L=L, Lz=Lz, seed=seed, min_dist=min_dist, kT=kT)
+    rng = np.random.default_rng(seed + 1)
+    B = n_tri + n_di
+    Lf = float(base.L[0])
+    ctype = np.array([0] * n_tri + [1] * n_di, np.int32)
+    rng.shuffle(ctype)
+    npatch = np.where(ctype == 0, 3, 2)
+    first = np.concatenate([[0], np.cumsum(npatch)]).astype(np.int32)
+    M = int(first[-1])
+    ang = np.concatenate([np.arange(k) * (2.0 * np.pi / k) for k in npatch])
+    offset = np.stack([radius * np.cos(ang), radius * np.sin(ang)], axis=1).astype(np.float32)
+    owner = np.repeat(np.arange(B), npatch)
+    theta = rng.uniform(-np.pi, np.pi, B).astype(np.float32)
+    inertia = np.full(B, 0.5 * radius * radius, np.float32)
+    omega = (rng.standard_normal(B) * np.sqrt(kT / inertia)).astype(np.float32)
+    cen = base.pos[:, :2].astype(np.float64)
+
+    def rim(th_b):
+        th = th_b.astype(np.float64)[owner]
+        return np.stack([np.cos(th) * offset[:, 0] - np.sin(th) * offset[:, 1],
+                         np.sin(th) * offset[:, 0] + np.cos(th) * offset[:, 1]], axis=1)
+
+    # no two patches of different bodies start closer than patch_gap (the stiff swap term's core):
+    # redraw the angles of the bodies involved
+    from scipy.spatial import cKDTree
+    for _ in range(200):
+        p = cen[owner] + rim(theta)
+        p = np.mod(p + 0.5 * Lf, Lf)
+        pairs = cKDTree(np.minimum(p, np.nextafter(Lf, 0.0)), boxsize=Lf).query_pairs(patch_gap, output_type="ndarray")
+        pairs = pairs[owner[pairs[:, 0]] != owner[pairs[:, 1]]] if len(pairs) else pairs
+        if len(pairs) == 0:
+            break
+        bad = np.unique(owner[pairs[:, 0]])
+        theta[bad] = rng.uniform(-np.pi, np.pi, len(bad)).astype(np.float32)
+    else:
+        raise RuntimeError("patchy_mixture: could not separate the patches")
+    d = rim(theta)
+    pos = np.zeros((B + M, 3), np.float32)
+    pos[:B] = base.pos
+    pos[B:, :2] = wrap_fp32(np.concatenate([base.pos[owner, :2].astype(np.float64) + d,
+                                            np.zeros((M, 1))], axis=1), Lf)[:, :2]
+    vel = np.zeros((B + M, 3), np.float32)
+    vel[:B, :2] = base.vel[:, :2]
+    vel[B:, 0] = vel[owner, 0] - omega[owner] * d[:, 1]
+    vel[B:, 1] = vel[owner, 1] + omega[owner] * d[:, 0]
+    types = np.concatenate([ctype, np.full(M, 2, np.int32)])
+    bodies = dict(centre=np.arange(B, dtype=np.int32), first=first,
+                  member=(B + np.arange(M)).astype(np.int32), offset=offset, inertia=inertia)
+    tab = table if table is not None else patchy_table()
+    return System(pos=pos, types=types, L=base.L, table=tab, mass=np.ones(tab.ntypes), vel=vel,
+                  name=f"patchy mixture {n_tri}+{n_di} L={Lf}",
+                  meta={"bodies": bodies, "theta": theta, "omega": omega})
+
+
 def small_reactive(N=1000, density=0.2, seed=1001, min_dist=0.8, kT=0.1,
                    table: Optional[PairTable] = None) -> System:
     """N identical reactive particles (eps 1, sigma 1, n 10, r_cut 1.5, lambda 1)."""

@@ -282,7 +282,7 @@ def rigid_bench(a):
     out = R.run(a.rigid_steps, cfg, step0=200)
     print(f"# rigid patchy mixture: {a.rigid_steps / out['seconds']:.0f} steps/s", file=sys.stderr, flush=True)
     return {"workload": "2d patchy mixture: 400 trifunctional + 600 difunctional rigid disks (3400 particles), "
-                        "box 39.63, patch swap eps 20 sigma 0.1 r_cut 0.2, Langevin kT 1 dt 0.001",
+                        "box 39.63, patch swap eps 10 sigma 0.1 n 6 r_cut 0.2, Langevin kT 1 dt 0.001",
             "unit": "timesteps/s", "steps": a.rigid_steps, "steps_per_s": round(a.rigid_steps / out["seconds"], 1),
             "rebuilds": out["rebuilds"], "particles": int(s.N), "bodies": int(len(s.meta["bodies"]["centre"]))}
 

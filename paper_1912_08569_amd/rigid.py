@@ -9,6 +9,7 @@ kernels; this module only holds the body arrays and sequences the calls.
 """
 from __future__ import annotations
 
+import math
 import time
 
 import numpy as np
@@ -49,7 +50,10 @@ class RigidBodies:
         t0 = time.perf_counter()
         for k in range(n_steps):
             self._half(cfg, step0 + k, rcl.RC_HALF_FIRST)
-            if float(S.vel[:, 3].max()) > soft:
+            mp = float(S.vel[:, 3].max())
+            if not math.isfinite(mp):
+                raise RuntimeError(f"rigid bodies: non-finite state at step {step0 + k}")
+            if mp > soft:
                 S.build()
                 rebuilds += 1
             S.compute_forces(gather=True, ev=False)

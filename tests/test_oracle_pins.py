@@ -703,7 +703,7 @@ def test_planar_step_pin():
     assert np.any(np.abs(a["F_old"][:, :2]) > 0.0)   # the configuration does interact
 
 
-def _two_bodies(p0, p1, th, v, w, L=(60.0, 60.0, 8.0), eps_patch=20.0):
+def _two_bodies(p0, p1, th, v, w, L=(60.0, 60.0, 8.0), eps_patch=10.0):
     # a trifunctional body (3 patches) and a difunctional one (2 patches), tags 0, 1 and 2..6
     off = np.array([[0.5 * np.cos(a), 0.5 * np.sin(a)] for a in (0.0, 2 * np.pi / 3, 4 * np.pi / 3, 0.0, np.pi)])
     bodies = dict(centre=np.array([0, 1]), first=np.array([0, 3, 5]), member=np.arange(2, 7), offset=off,

@@ -236,11 +236,12 @@ def planar_reactive(N=1000, L=39.63, Lz=8.0, seed=1012, min_dist=0.9, kT=1.0,
                   name=f"planar reactive N={N} L={Lf}")
 
 
-def patchy_table(eps_patch=20.0, sigma_patch=0.1, n=10, rcut_patch=0.2, lam=1.0) -> PairTable:
+def patchy_table(eps_patch=10.0, sigma_patch=0.1, n=6, rcut_patch=0.2, lam=1.0) -> PairTable:
     """Sec. 3.2's swapping patchy mixture: type 0 = trifunctional disk, 1 = difunctional disk (WCA,
-    eps 1, sigma 1, among all disks), 2 = patch (the swap potential among patches: eps 20 kT at kT 1,
-    sigma 0.1 so that r_min ~ the paper's patch length 0.1, r_cut 0.2 = its bond distance; n 10,
-    lambda 1); disks and patches do not interact."""
+    eps 1, sigma 1, among all disks), 2 = patch (the swap potential among patches: eps 10 kT at kT 1,
+    sigma 0.1 so that r_min ~ the paper's patch length 0.1, r_cut 0.2 = its bond distance, n 6 so that
+    the bond vibration, ~440 per unit time, is resolved at dt 1e-3 like the paper's strongest Gaussian
+    patches; lambda 1); disks and patches do not interact."""
     t = PairTable.empty(3)
     for a in (0, 1):
         for b in (0, 1):

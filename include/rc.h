@@ -13,8 +13,9 @@
  *
  * plus a BAOAB Langevin / velocity-Verlet integrator, cell-list binning with a
  * Morton-ordered counting sort, a full neighbour list, exact bond counting,
- * Hessian-vector products and parameter gradients of the energy, and a batch
- * mode that advances many independent replicas in one launch per step.
+ * Hessian-vector products and parameter gradients of the energy, a batch
+ * mode that advances many independent replicas in one launch per step, and
+ * planar motion with rigid patchy bodies (the 2d systems of Sec. 3.2).
  *
  * Conventions shared by every entry point
  * ---------------------------------------

@@ -11,6 +11,15 @@ from oracle import rigid_ref, swap_ref
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _device_first():
+    # the device is brought up before the workload's host-side set-up runs (as in every other GPU test
+    # file, where an engine object exists before the first input is generated)
+    import torch
+    torch.zeros(1, device="cuda")
+    yield
+
+
 def _bodies(s):
     from paper_1912_08569_amd import RigidBodies, System
     S = System.from_workload(s)

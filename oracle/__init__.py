@@ -22,8 +22,10 @@ What it computes (all in float64):
 * ``brute``     -- a plain C, OpenMP, O(N^2) brute-force evaluator of the same
   quantities (independent code, built with ``-ffp-contract=off``), used for
   large systems, sampled-particle checks and the CPU baseline timing.
-* ``adjoint_ref`` -- Hessian-vector products and parameter gradients of the
-  total energy by central finite differences of ``swap_ref`` forces/energy.
+* ``adjoint_ref`` -- analytic Hessian-vector products and parameter gradients
+  of the total energy (the calculus of the same terms), pinned by central
+  finite differences of ``swap_ref`` forces and energies; the force-parameter
+  vector-Jacobian product by central differences of ``swap_ref`` forces.
 
 Parity status of each function is listed in its module header.
 """

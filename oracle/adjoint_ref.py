@@ -29,6 +29,9 @@ for ``hvp``, energy for ``param_grad``, ``soft_bonds`` for its own gradient,
 and ``soft_bonds`` equals ``swap_ref.bond_count`` when every swap pair inside
 r_cut is bonded) and by the identities
 dE/dlambda = E3/lambda and dE/deps = (E2_swap + E3)/eps of a one-entry system.
+The error scale of ``hvp`` is pinned by its bound on |Hv|, its units and its
+closed-form ratio to |Hv| along a bond far beyond r_min
+(tests/test_oracle_scales.py).
 """
 from __future__ import annotations
 

@@ -21,7 +21,9 @@ indexed by tag.
 
 Pins: a free body moves and turns uniformly; energy (translational, rotational
 and potential) and the total angular momentum of colliding bodies are kept by
-the gamma = 0 step (tests/test_oracle_pins.py).
+the gamma = 0 step (tests/test_oracle_pins.py); the Langevin branch brings a
+free-body gas to equipartition, M <v_x^2> = M <v_y^2> = I <w^2> = kT
+(tests/test_oracle_scales.py).
 """
 from __future__ import annotations
 

@@ -34,7 +34,10 @@ r_min^2 = (sigma*sigma) * pow(2, 2/n).  Any implementation that follows these
 IEEE operations reaches the same integer decisions.
 
 Parity status: pinned (closed forms, finite differences of the energy, strain
-derivatives, the flat swap barrier, literal triple loops).
+derivatives, the flat swap barrier, literal triple loops).  The error scales
+A_F, A_E, A_W and A_pe are pinned by the bounds they must satisfy, their
+units (eps and length scaling) and their equality with the quantity itself
+where one sub-term dominates (tests/test_oracle_scales.py).
 """
 from __future__ import annotations
 

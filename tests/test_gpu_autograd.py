@@ -11,7 +11,7 @@ import torch
 
 import workloads as W
 from oracle import adjoint_ref, swap_ref
-from parity_util import force_errors
+from parity_util import assert_forces, force_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,7 @@ def test_energy_gradients_match_oracle():
     gx, gt = torch.autograd.grad(E, (x, theta))
     ref = swap_ref.evaluate(s.pos.astype(np.float64), s.types, s.L, s.table)
     assert abs(float(E.detach()) - ref["E"]) <= 1e-5 * ref["A_E"]
-    e = force_errors(-gx.cpu().numpy(), ref)
-    assert e.max() <= 1e-5
+    assert_forces(-gx.cpu().numpy(), ref)
     g = adjoint_ref.param_grad(s.pos.astype(np.float64), s.types, s.L, s.table)
     iu = np.triu_indices(2)
     assert np.abs(gt.numpy()[iu] - g[iu]).max() <= 1e-5 * np.abs(g).max()
@@ -86,7 +85,7 @@ def test_model_rebuilds_and_keeps_tag_order():
         xf = x.astype(np.float32)
         F = swap_forces(M, torch.from_numpy(xf).cuda(), theta)
         ref = swap_ref.evaluate(xf.astype(np.float64), s.types, s.L, s.table)
-        assert force_errors(F.cpu().numpy(), ref).max() <= 1e-5
+        assert_forces(F.cpu().numpy(), ref)
     assert M.rebuilds >= 2
 
 

@@ -7,7 +7,7 @@ import torch
 
 import workloads as W
 from oracle import dynamics_ref, fene_ref, swap_ref
-from parity_util import force_errors
+from parity_util import assert_forces
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_network_forces_and_bonds_match_oracle():
     torch.cuda.synchronize()
     x, _, _, ty = S.state_by_tag()
     ref, _ = _ref(x.astype(np.float64), ty, s)
-    assert force_errors(S.by_tag(F), ref).max() <= 1e-5
+    assert_forces(S.by_tag(F), ref)
     assert abs(ev[0].item() - ref["E"]) <= 1e-5 * ref["A_E"]
     assert S.bond_count() == ref["bonds"]
 

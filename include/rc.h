@@ -256,6 +256,29 @@ int rc_compute_forces(rc_ctx* ctx, const float* pos, const int* nlist, const int
                       rc_box box, float* force /* [N*4] */, double* ev /* [7] | NULL */,
                       unsigned flags, int* status /* NULL ok */, void* stream);
 
+/* ---- forces without allocation ------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * rc_compute_forces_noalloc takes the arguments of rc_compute_forces, computes
+ * what it computes (bit for bit with RC_FORCE_GATHER or RC_FORCE_SUMS; the
+ * default triplet kernel sums with atomics, so its last bits vary from call
+ * to call, as rc_compute_forces' do) and calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch -- the per-block FP64 rows of the
+ * energy/virial reduction and, with RC_FORCE_SUMS, the per-particle switching
+ * sums -- is a fixed device array of RC_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on from the first rc_create there until the
+ * process ends, instead of the context's growable buffers.  Every launch
+ * writes all the scratch it reads, so nothing in it needs to start at zero.
+ * Every call on one GPU shares that GPU's array: calls whose launches can
+ * overlap on one GPU (different streams or threads) race, and the caller
+ * must order them.  N > RC_NOALLOC_MAX_N returns RC_ERR_UNSUPPORTED with
+ * nothing launched; other errors as rc_compute_forces.                       */
+#define RC_NOALLOC_MAX_N 1048576   /* 2^20 particles */
+#define RC_NOALLOC_SCRATCH_BYTES ((size_t)13 * 8 * (RC_NOALLOC_MAX_N / 64) + (size_t)4 * RC_NOALLOC_MAX_N)
+int rc_compute_forces_noalloc(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn, int k_max, int N,
+                              rc_box box, float* force /* [N*4] */, double* ev /* [7] | NULL */,
+                              unsigned flags, int* status /* NULL ok */, void* stream);
+
 /* ---- integrator (hot-path step a5) -------------------------------------------
  * BAOAB Langevin (the paper's "canonical Langevin dynamics", Sec. 3.2; scheme
  * of Leimkuhler & Matthews 2013) or velocity Verlet (NVE):

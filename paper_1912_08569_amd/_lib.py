@@ -28,6 +28,7 @@ RC_KIND_NONE, RC_KIND_SWAP, RC_KIND_WCA = 0, 1, 2
 RC_TYPE_BITS = 4
 RC_MAX_TYPES = 16
 RC_STATUS_WORDS = 8
+RC_NOALLOC_MAX_N = 1048576
 RC_ST_FLAGS, RC_ST_KMAX, RC_ST_MAXPATH, RC_ST_FIRST_SOFT, RC_ST_FIRST_HARD = 0, 1, 2, 3, 4
 RC_FLAG_NLIST_OVERFLOW, RC_FLAG_REBUILD, RC_FLAG_NONFINITE, RC_FLAG_LOST, RC_FLAG_STALE = 1, 2, 4, 8, 16
 RC_FORCE_ACCUMULATE, RC_FORCE_GATHER, RC_FORCE_SUMS = 1, 4, 8
@@ -110,6 +111,7 @@ _SIGS = {
     "rc_build_cells": ([_VP, _VP, _VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _VP], _I),
     "rc_build_nlist": ([_VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),
     "rc_compute_forces": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
+    "rc_compute_forces_noalloc": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
     "rc_integrate_step": ([_VP, _VP, _VP, _VP, _VP, _I, Box, ctypes.POINTER(Integrator), _U64, _I,
                            _VP, _VP, _VP], _I),
     "rc_step_fused": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, Box, ctypes.POINTER(Integrator), _U64,

@@ -19,6 +19,7 @@ from ._lib import RcError, check
 __all__ = [
     "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
+    "rc_compute_forces_noalloc",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp", "rc_force_hvp_batch", "rc_partner_counts", "rc_stress_autocorrelation",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
     "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
@@ -203,6 +204,13 @@ def rc_compute_forces(ctx: Context, pos, nlist, nn, bx, force, ev=None, flags=0,
     check(L.load().rc_compute_forces(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
                                      _ptr(force),
                                      _ptr(ev), int(flags), _ptr(status), _stream(stream)), ctx.handle)
+
+
+def rc_compute_forces_noalloc(ctx: Context, pos, nlist, nn, bx, force, ev=None, flags=0, status=None, stream=None):
+    N = pos.shape[0]
+    check(L.load().rc_compute_forces_noalloc(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
+                                             _ptr(force), _ptr(ev), int(flags), _ptr(status), _stream(stream)),
+          ctx.handle)
 
 
 def rc_integrate_step(ctx: Context, pos, vel, force, image, bx, cfg, step, half, kin=None, status=None,

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,7 +16,41 @@
 using namespace rc;
 using namespace rc::host;
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of rc_compute_forces_noalloc: the per-block energy/virial rows
+// of RC_NOALLOC_MAX_N particles, then their switching sums.  In host code the
+// array's name is only a stand-in; its device address on each GPU is taken
+// once (rc_create, with that device current) and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------
 namespace {
+constexpr size_t kNoallocRowBytes =
+    sizeof(double) * kEvWords * (size_t)((RC_NOALLOC_MAX_N + kWave - 1) / kWave);
+constexpr size_t kNoallocBytes = kNoallocRowBytes + sizeof(float) * (size_t)RC_NOALLOC_MAX_N;
+static_assert(kNoallocRowBytes % 256 == 0, "sums must start 256-byte aligned");
+static_assert(kNoallocBytes == RC_NOALLOC_SCRATCH_BYTES, "scratch size and its public value disagree");
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+// device address of the fixed scratch on the current device (looked up once per device)
+hipError_t noalloc_scratch_here(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipSuccess;   // the entry point then reports it
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
 
 int check_common(rc_ctx* c, int N, const void* pos) {
     if (!c) return RC_ERR_ARG;
@@ -32,6 +67,39 @@ int reduce_rows(rc_ctx* c, int nb, int first, int count, double* out, hipStream_
 }
 
 Table dev_table(const rc_ctx* c) { return Table{c->d_tab, c->nt}; }
+
+// rc_compute_forces on given scratch: part (per-block FP64 rows, kEvWords
+// doubles per wavefront block) when ev is wanted, ssum (N floats) for the
+// two-pass form.  Launches only; allocates nothing.
+int forces_into(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N, rc_box box,
+                float* force, double* ev, unsigned flags, int* status, double* part, float* ssum, hipStream_t s) {
+    if (!nlist || !nn || !force) return fail(c, RC_ERR_ARG, "nlist / nn / force are NULL");
+    if (flags & ~(RC_FORCE_ACCUMULATE | RC_FORCE_GATHER | RC_FORCE_SUMS))
+        return fail(c, RC_ERR_ARG, "unknown flags");
+    Box b;
+    int r;
+    if ((r = make_box(c, box, b))) return r;
+    if ((r = check_list(c, nlist, nn, k_max))) return r;
+    const bool sums = flags & RC_FORCE_SUMS;
+    const bool gather = (flags & RC_FORCE_GATHER) || sums;
+    const int nb = nblocks(N, kWave);
+    ForceArgs a{};
+    a.pos = reinterpret_cast<const float4*>(pos);
+    a.nlist = nlist;
+    a.nn = nn;
+    a.k_max = k_max;
+    a.N = N;
+    a.tab = dev_table(c);
+    a.box = b;
+    a.force = reinterpret_cast<float4*>(force);
+    a.ev_part = ev ? part : nullptr;
+    a.accumulate = (flags & RC_FORCE_ACCUMULATE) ? 1 : 0;
+    a.status = status;
+    a.ssum = sums ? ssum : nullptr;
+    HIP_TRY(c, gather ? launch_forces_gather(a, s) : launch_forces_triplet(a, s));
+    if (ev) HIP_TRY(c, launch_reduce_rows(part, nb, 0, 7, ev, s));
+    return RC_OK;
+}
 
 }  // namespace
 
@@ -62,7 +130,8 @@ int rc_create(rc_ctx** out, int ntypes, const rc_pair_coeff* table, double r_buf
         hipMalloc(&c->d_tab, sizeof(DevEntry) * ntypes * ntypes) != hipSuccess ||
         hipMemcpy(c->d_tab, c->host_tab.data(), sizeof(DevEntry) * ntypes * ntypes,
                   hipMemcpyHostToDevice) != hipSuccess ||
-        hipMalloc(&c->d_step_base, sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc(&c->d_step_base, sizeof(unsigned long long)) != hipSuccess ||
+        noalloc_scratch_here(c->device, &c->noalloc_scratch) != hipSuccess) {
         if (c->d_tab) (void)hipFree(c->d_tab);
         delete c;
         return RC_ERR_HIP;
@@ -300,33 +369,27 @@ int rc_compute_forces(rc_ctx* c, const float* pos, const int* nlist, const int* 
                       float* force, double* ev, unsigned flags, int* status, void* stream) {
     int r = check_common(c, N, pos);
     if (r) return r;
-    if (!nlist || !nn || !force) return fail(c, RC_ERR_ARG, "nlist / nn / force are NULL");
-    if (flags & ~(RC_FORCE_ACCUMULATE | RC_FORCE_GATHER | RC_FORCE_SUMS))
-        return fail(c, RC_ERR_ARG, "unknown flags");
-    Box b;
-    if ((r = make_box(c, box, b))) return r;
-    const bool sums = flags & RC_FORCE_SUMS;
-    const bool gather = (flags & RC_FORCE_GATHER) || sums;
-    if (sums && (r = ensure_ssum(c, (size_t)N))) return r;
     const int nb = nblocks(N, kWave);   // both force kernels run one wavefront per block
+    if ((flags & RC_FORCE_SUMS) && (r = ensure_ssum(c, (size_t)N))) return r;
     if (ev && (r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
-    if ((r = check_list(c, nlist, nn, k_max))) return r;
-    ForceArgs a{};
-    a.pos = reinterpret_cast<const float4*>(pos);
-    a.nlist = nlist;
-    a.nn = nn;
-    a.k_max = k_max;
-    a.N = N;
-    a.tab = dev_table(c);
-    a.box = b;
-    a.force = reinterpret_cast<float4*>(force);
-    a.ev_part = ev ? c->d_part : nullptr;
-    a.accumulate = (flags & RC_FORCE_ACCUMULATE) ? 1 : 0;
-    a.status = status;
-    a.ssum = sums ? c->d_ssum : nullptr;
-    HIP_TRY(c, gather ? launch_forces_gather(a, S(stream)) : launch_forces_triplet(a, S(stream)));
-    if (ev && (r = reduce_rows(c, nb, 0, 7, ev, S(stream)))) return r;
-    return RC_OK;
+    return forces_into(c, pos, nlist, nn, k_max, N, box, force, ev, flags, status, c->d_part, c->d_ssum,
+                       S(stream));
+}
+
+int rc_compute_forces_noalloc(rc_ctx* c, const float* pos, const int* nlist, const int* nn, int k_max, int N,
+                              rc_box box, float* force, double* ev, unsigned flags, int* status, void* stream) {
+    int r = check_common(c, N, pos);
+    if (r) return r;
+    if (N > RC_NOALLOC_MAX_N)
+        return fail(c, RC_ERR_UNSUPPORTED,
+                    "rc_compute_forces_noalloc: N = %d exceeds the fixed scratch's limit of %d particles", N,
+                    RC_NOALLOC_MAX_N);
+    if (!c->noalloc_scratch)
+        return fail(c, RC_ERR_UNSUPPORTED, "rc_compute_forces_noalloc: no fixed scratch on device %d", c->device);
+    char* base = static_cast<char*>(c->noalloc_scratch);
+    double* rows = reinterpret_cast<double*>(base);
+    float* sums = reinterpret_cast<float*>(base + kNoallocRowBytes);
+    return forces_into(c, pos, nlist, nn, k_max, N, box, force, ev, flags, status, rows, sums, S(stream));
 }
 
 int rc_integrate_step(rc_ctx* c, float* pos, float* vel, const float* force, int* image, int N, rc_box box,

@@ -51,6 +51,7 @@ struct rc_ctx {
     int* h_status = nullptr;            // pinned host copy of a status word (driver waits)
     hipEvent_t ev_sync = nullptr;       // the driver's wait event (no timing)
     GraphCache gc;
+    void* noalloc_scratch = nullptr;    // device address of the fixed scratch on this device
     std::string err;
 };
 

@@ -40,7 +40,8 @@ def parse():
     p.add_argument("--log-period", type=int, default=100)
     p.add_argument("--r-buff", type=float, default=0.3, help="neighbour-list skin")
     p.add_argument("--no-graph", action="store_true")
-    p.add_argument("--kernel-reps", type=int, default=200)
+    p.add_argument("--kernel-steps", type=int, default=400,
+                   help="steps of the driver run whose step launches are timed one by one")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -59,6 +60,14 @@ def parse():
     p.add_argument("--dumbbell-warmup", type=int, default=1000)
     p.add_argument("--dumbbell-n", type=str, default="", help="comma-separated sizes (default 2^9 ... 2^17)")
     p.add_argument("--dumbbell-rcut", type=str, default="1.3,1.15", help="comma-separated cutoffs")
+    p.add_argument("--no-sweep", action="store_true", help="skip the lambda sweep of the 1M mixture")
+    p.add_argument("--sweep-steps", type=int, default=2000)
+    p.add_argument("--sweep-warmup", type=int, default=200)
+    p.add_argument("--no-vitrimer", action="store_true", help="skip the vitrimer-network run")
+    p.add_argument("--vit-steps", type=int, default=2000)
+    p.add_argument("--vit-warmup", type=int, default=500)
+    p.add_argument("--profile-kernel", action="store_true",
+                   help="only the 1M system: build, warm up, then the timed-launch run (for counter runs)")
     return p.parse_args()
 
 
@@ -73,30 +82,169 @@ def step_kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(sysw, seconds):
-    """The C brute-force oracle (plain O(N^2) FP64, OpenMP) on sampled particles.
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Per sampled particle it evaluates every pair and triplet term acting on
-    it against all N particles, which is what one step costs it per particle
-    (the integration itself is negligible next to it).  Rate = sampled
-    particles per second = particle-timesteps/s of the oracle.
-    """
-    from oracle import brute
+
+def cpu_baseline(sysw, seconds):
+    """The FP64 oracle on the host cores, as it stands (a baseline, not a target: O(N^2) brute force is
+    not a fair CPU MD engine).
+
+    value: the C brute force (plain O(N^2) FP64, OpenMP, every core) on sampled particles of the
+    benchmark system: per sampled particle every pair and triplet term acting on it against all N
+    particles, which is what one step costs it per particle (the integration is negligible next to it),
+    so sampled particles per second = particle-timesteps/s of the oracle.  Beside it: the same at one
+    thread, the 1000-particle system's 1000-step BAOAB run (C brute-force forces, numpy integrator) at
+    every core and a bounded sample at one thread, and one forward evaluation (C) and one Hessian-vector
+    product (numpy) of the 32,768-particle differentiation system."""
+    import workloads as W
+    from oracle import adjoint_ref, brute, dynamics_ref
     brute.build(force=False)
     cores = len(os.sched_getaffinity(0))
     rng = np.random.default_rng(99)
-    m = 2 * cores
+
+    def c3_rate(threads, budget):
+        m = 2 * threads
+        t0 = time.perf_counter()
+        brute.forces_subset(sysw.pos, sysw.types, sysw.L, sysw.table, rng.choice(sysw.N, m, replace=False), threads)
+        dt = time.perf_counter() - t0
+        M = int(max(m, min(200000, m * budget / max(dt, 1e-3))))
+        idx = rng.choice(sysw.N, M, replace=False)
+        t0 = time.perf_counter()
+        brute.forces_subset(sysw.pos, sysw.types, sysw.L, sysw.table, idx, threads)
+        return M, time.perf_counter() - t0
+
+    M, dt = c3_rate(cores, seconds)
+    M1, dt1 = c3_rate(1, 0.3 * seconds)
+
+    # the plain small system: 1000 reactive particles, density 0.2, BAOAB kT 0.1 dt 0.002 gamma 1
+    s1 = W.small_reactive(N=1000, density=0.2, seed=1001, kT=0.1)
+
+    def c1_run(threads, steps):
+        x, v = s1.pos.astype(np.float64), s1.vel.astype(np.float64)
+        force = lambda y: brute.evaluate(y, s1.types, s1.L, s1.table, threads)["F"]  # noqa: E731
+        tags = np.arange(s1.N)
+        t0 = time.perf_counter()
+        F = None
+        for k in range(steps):
+            out = dynamics_ref.baoab_step(x, v, s1.types, tags, s1.L, s1.table, s1.mass, 0.002, 0.1, 1.0, 2001, k,
+                                          force=F, force_fn=force)
+            x, v, F = out["pos"], out["vel"], out["F"]
+        return time.perf_counter() - t0
+
+    t_c1 = c1_run(cores, 1000)
+    t_c1_1 = c1_run(1, 200)
+
+    # the differentiation system: 32,768 reactive particles, density 0.25, eps 10
+    s5 = W.small_reactive(N=32768, density=0.25, seed=1005, table=W.swap_table_single(epsilon=10.0, lam=1.0))
+    x5 = s5.pos.astype(np.float64)
     t0 = time.perf_counter()
-    brute.forces_subset(sysw.pos, sysw.types, sysw.L, sysw.table, rng.choice(sysw.N, m, replace=False), cores)
-    dt = time.perf_counter() - t0
-    M = int(max(m, min(200000, m * seconds / max(dt, 1e-3))))
-    idx = rng.choice(sysw.N, M, replace=False)
+    brute.evaluate(x5, s5.types, s5.L, s5.table, cores)
+    t_fwd = time.perf_counter() - t0
+    vec = np.random.default_rng(3005).standard_normal(x5.shape)
     t0 = time.perf_counter()
-    brute.forces_subset(sysw.pos, sysw.types, sysw.L, sysw.table, idx, cores)
-    dt = time.perf_counter() - t0
+    adjoint_ref.hvp(x5, s5.types, s5.L, s5.table, vec)
+    t_hvp = time.perf_counter() - t0
     return {"value": M / dt, "unit": "particle-timesteps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": f"forces on {M} random particles of the {sysw.N}-particle system, each against all "
-                      f"{sysw.N} particles (FP64 brute force, {dt:.1f} s)"}
+                      f"{sysw.N} particles (FP64 brute force, {dt:.1f} s at {cores} threads)",
+            "single_thread": {"value": M1 / dt1, "unit": "particle-timesteps/s", "cores": 1,
+                              "sample": f"{M1} particles, {dt1:.1f} s"},
+            "small_system_run": {"workload": "1000 reactive particles, density 0.2, 1000 BAOAB steps kT 0.1 dt 0.002",
+                                 "value": 1000 * 1000 / t_c1, "unit": "particle-timesteps/s", "cores": cores,
+                                 "seconds": round(t_c1, 2),
+                                 "single_thread_value": 1000 * 200 / t_c1_1,
+                                 "single_thread_sample": f"200 steps, {t_c1_1:.1f} s"},
+            "differentiation_system": {"workload": "32768 reactive particles, density 0.25, eps 10 (random start)",
+                                       "forward_s": round(t_fwd, 3), "forward_cores": cores,
+                                       "forward_kind": "C brute force, O(N^2)",
+                                       "hvp_s": round(t_hvp, 3), "hvp_kind": "numpy, candidate pairs by k-d tree",
+                                       "hvp_cores": 1},
+            "note": "baseline only: the oracle is an O(N^2) brute force written for checking, not a CPU MD engine"}
+
+
+def _log_steps(step0, n, lp, skip_first):
+    """Step indices of the rows a run logs (multiples of the period, then the end)."""
+    s = [k for k in range(step0, step0 + n) if lp > 0 and k % lp == 0 and not (skip_first and k == step0)]
+    return s + [step0 + n]
+
+
+def lambda_sweep(a, sysw):
+    """The self-assembly mixture at lambda 0, 0.5, 1 and 1.5 (the swap-barrier knob of Sec. 2) from the
+    same start: particle-timesteps/s of `sweep_steps` steps after `sweep_warmup`, and the bond-count
+    trajectory of the whole run (a row every log period)."""
+    import torch
+
+    from paper_1912_08569_amd import System
+    rows = []
+    for lam in (0.0, 0.5, 1.0, 1.5):
+        S = System(sysw.pos, sysw.types, sysw.L, sysw.table.with_lambda(lam), vel=sysw.vel, mass=sysw.mass,
+                   r_buff=a.r_buff, k_max=32)
+        cfg = S.integrator(dt=0.001, kT=0.05, gamma=1.0, seed=2003)
+        S.build()
+        r0 = S.run(a.sweep_warmup, cfg, step0=0, log_period=a.log_period)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = S.run(a.sweep_steps, cfg, step0=a.sweep_warmup, log_period=a.log_period)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps = _log_steps(0, a.sweep_warmup, a.log_period, False) + \
+            _log_steps(a.sweep_warmup, a.sweep_steps, a.log_period, bool(r.stats.list_kept))
+        bonds = [int(b) for b in np.concatenate([r0.bonds, r.bonds])]
+        assert len(steps) == len(bonds)
+        rows.append({"lambda": lam, "particle_timesteps_per_s": a.N * a.sweep_steps / dt,
+                     "us_per_step": round(dt / a.sweep_steps * 1e6, 3), "rebuilds": int(r.stats.rebuilds),
+                     "bond_trajectory": {"steps": steps, "bonds": bonds}})
+        print(f"# lambda {lam}: {rows[-1]['us_per_step']:.2f} us/step, bonds {bonds[0]} -> {bonds[-1]}",
+              file=sys.stderr, flush=True)
+        del S
+        torch.cuda.empty_cache()
+    return {"workload": f"self-assembly mixture N={a.N}, density 0.3, Langevin kT 0.05 dt 0.001, one start",
+            "unit": "particle-timesteps/s", "warmup": a.sweep_warmup, "steps": a.sweep_steps,
+            "log_period": a.log_period, "rows": rows}
+
+
+def vitrimer_bench(a):
+    """The vitrimer-like network: 4000 chains of 16 beads and 1600 crosslinker dimers (67,200 beads,
+    FENE K 30 R0 1.5, WCA, 10 % reactive sites with the swap potential eps 20 sigma 0.3 n 10, lambda 1)
+    at density 0.85, Langevin kT 1 dt 0.002: particle-timesteps/s after a gentle push-off (dt 2e-4)
+    of the grown start's 0.8 sigma contacts and a relaxation."""
+    import torch
+
+    import workloads as W
+    from paper_1912_08569_amd import System
+    t_gen = time.perf_counter()
+    s = W.vitrimer_network()
+    print(f"# vitrimer network: {s.N} beads generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    S = System.from_workload(s)
+    S.run(3000, S.integrator(dt=2e-4, kT=1.0, gamma=1.0, seed=23))
+    cfg = S.integrator(dt=0.002, kT=1.0, gamma=1.0, seed=23)
+    S.run(a.vit_warmup, cfg, step0=3000, log_period=a.log_period)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = S.run(a.vit_steps, cfg, step0=3000 + a.vit_warmup, log_period=a.log_period)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": "vitrimer-like network: 4000 chains x 16 beads + 1600 crosslinker dimers (67,200 beads), "
+                       "density 0.85, FENE K 30 R0 1.5, WCA, swap sites eps 20 sigma 0.3 n 10 lambda 1, "
+                       "Langevin kT 1 dt 0.002, log every 100 steps",
+           "unit": "particle-timesteps/s", "value": s.N * a.vit_steps / dt, "steps": a.vit_steps,
+           "us_per_step": round(dt / a.vit_steps * 1e6, 3), "rebuilds": int(r.stats.rebuilds),
+           "step_form": S.ctx.step_form, "mean_list_length": round(S.mean_list_length(), 3),
+           "bonds_final": int(r.bonds[-1]), "energy_final": float(r.ev[-1, 0])}
+    print(f"# vitrimer: {out['us_per_step']:.2f} us/step", file=sys.stderr, flush=True)
+    del S
+    torch.cuda.empty_cache()
+    return out
 
 
 def batch_bench(a):
@@ -231,6 +379,17 @@ def adjoint_bench(a):
            "fwd_plus_param_grad_over_fwd": (best + grad) / best, "hvp_over_fwd": hvp / best,
            "hvp_64_vectors_ms": hvp * 64 / 1e3, "hvp_64_batched_ms": hvp64 / 1e3,
            "hvp_batched_us_per_vector": hvp64 / 64, "hvp_batched_over_fwd": hvp64 / 64 / best}
+    # HVP roofline: per particle and vector the forward's bytes (pos 16, nn 4, list 4k, force out 16)
+    # plus the tangent vector in and the product out (16 + 16), i.e. 68 + 4k
+    kbar = S.mean_list_length()
+    hb = 68.0 + 4.0 * kbar
+    ach = s.N * hb / (hvp * 1e-6) / 1e9
+    ach64 = s.N * hb / (hvp64 / 64 * 1e-6) / 1e9
+    out["hvp_roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                           "algorithmic_bytes_per_particle": round(hb, 2), "mean_list_length": round(kbar, 3),
+                           "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "achieved_batched_per_vector": round(ach64, 1),
+                           "frac_batched": round(ach64 / HBM_PEAK_GBS, 4)}
     # one iteration of the lambda fit: 200 BAOAB steps forward, checkpointed backward (segments of 20)
     from paper_1912_08569_amd.autograd import SwapModel
     from paper_1912_08569_amd.fit import TrajectoryFit
@@ -366,6 +525,13 @@ def main():
     # warm-up (also relaxes the random start)
     S.run(a.warmup, cfg, step0=0, log_period=a.log_period, use_graph=use_graph)
     torch.cuda.synchronize()
+    if a.profile_kernel:
+        # counter runs: nothing but the step launches of a driver run, each launched directly
+        rk = S.run(a.kernel_steps, cfg, step0=a.warmup, log_period=a.log_period, time_kernels=True)
+        print(json.dumps({"kernel": "k_step", "N": a.N, "launches": int(rk.stats.kernel_launches),
+                          "kernel_us": rk.stats.kernel_ms / max(1, rk.stats.kernel_launches) * 1e3,
+                          "mean_list_length": S.mean_list_length()}), flush=True)
+        return
     # ---- timed region: exactly `steps` steps ------------------------------------------
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -382,27 +548,19 @@ def main():
     print(f"# {a.steps} steps in {sec * 1e3:.1f} ms ({sec / a.steps * 1e6:.2f} us/step; events "
           f"{ms_events:.1f} ms); rebuilds {st.rebuilds} rollbacks {st.rollbacks} chunks {st.chunks}",
           file=sys.stderr, flush=True)
-    # ---- dominant kernel: the fused step, each launch timed by events attached to it ----
-    # The kernel slows as its list ages (24.6 us on a fresh list, 27 us a hundred steps later,
-    # 1M particles), and the run rebuilds every steps/rebuilds steps, so the launches are timed
-    # in blocks of that length, each on a freshly built list.  Work is on copies of the state;
-    # launches come from C (no Python per launch).
-    life = max(1, min(a.kernel_reps, round(a.steps / max(1, st.rebuilds))))
-    n_blocks = -(-a.kernel_reps // life)
-    status = torch.zeros(rcl.RC_STATUS_WORDS, dtype=torch.int32, device=S.device)
-    ms, kbars = 0.0, []
-    for blk in range(n_blocks + 1):   # block 0 warms up and is not counted
-        S.build()
-        nn = S.nn
-        kbars.append(float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item()))  # n_swap | n_other << 16
-        pos_a, pos_b = S.pos.clone(), S.pos.clone()
-        vel = S.vel.clone()
-        t = api.rc_time_fused_steps(S.ctx, pos_a, pos_b, vel, S.nlist, S.nn, S.box, cfg,
-                                    10 ** 7 + blk * life, life, status)
-        if blk:
-            ms += t
-    kbar = sum(kbars[1:]) / n_blocks
-    t_kernel = ms / (n_blocks * life) * 1e-3
+    # ---- dominant kernel: the fused step, every launch of a driver run timed by its own events ----
+    # The kernel slows as its list ages (about 25 us on a fresh list, 27 us a hundred steps later at
+    # 1M particles), so it is timed over whole list lives: a further run of the driver continues the
+    # state with every plain step launched directly between events (the same trajectory, bit for
+    # bit, as graph replays), and the average is taken over all of its step launches.
+    nn = S.nn
+    k_before = float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())  # n_swap | n_other << 16
+    rk = S.run(a.kernel_steps, cfg, step0=a.warmup + a.steps, log_period=a.log_period, use_graph=use_graph,
+               time_kernels=True)
+    nn = S.nn
+    k_after = float(((nn & 0xFFFF) + (nn >> 16)).float().mean().item())
+    kbar = 0.5 * (k_before + k_after)
+    t_kernel = rk.stats.kernel_ms / max(1, rk.stats.kernel_launches) * 1e-3
     # Algorithmic bytes of one particle-step of the method (force pass: pos 16 + nn 4 + list 4k
     # + force out 16; integrate pass: pos, vel, force, reference position in 64, pos, vel out 32),
     # i.e. 132 + 4k.  The fused kernel does the whole step but never stores a force array or a
@@ -424,7 +582,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_step (fused force + BAOAB)", "kernel_us": round(t_kernel * 1e6, 3),
-            "timed_launches": n_blocks * life, "list_life_steps": life,
+            "timed_launches": int(rk.stats.kernel_launches), "timed_run_steps": a.kernel_steps,
+            "timed_run_rebuilds": int(rk.stats.rebuilds),
             "algorithmic_bytes_per_particle": round(bytes_per_particle, 2),
             "fused_kernel_bytes_per_particle": round(fused_bytes_per_particle, 2),
             "achieved_fused_bytes": round(achieved_fused, 1), "frac_fused_bytes": round(achieved_fused / HBM_PEAK_GBS, 4),
@@ -437,7 +596,7 @@ def main():
         "config": {"workload": f"swap/WCA self-assembly mixture, N={a.N}, density 0.3, lambda {a.lam}, "
                                "Langevin kT 0.05 dt 0.001, log every 100 steps",
                    "N": a.N, "lambda": a.lam, "graph": use_graph, "r_buff": a.r_buff, "rebuilds": int(st.rebuilds),
-                   "rollbacks": int(st.rollbacks), "chunks": int(st.chunks),
+                   "rollbacks": int(st.rollbacks), "chunks": int(st.chunks), "list_kept": int(st.list_kept),
                    "bonds_final": int(res.bonds[-1]) if res.bonds is not None and len(res.bonds) else None},
         "roofline": roof,
     }
@@ -451,6 +610,10 @@ def main():
     out["step_kernel_source_hash"] = step_kernel_source_hash()
     del S
     torch.cuda.empty_cache()
+    if not a.no_sweep:
+        out["lambda_sweep"] = lambda_sweep(a, sysw)
+    if not a.no_vitrimer:
+        out["vitrimer"] = vitrimer_bench(a)
     if not a.no_adjoint:
         out["adjoint"] = adjoint_bench(a)
     if not a.no_batch:

@@ -401,22 +401,27 @@ int rc_bond_count(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn
 
 /* ---- MD driver (hot-path step a6) --------------------------------------------
  * Advances (pos, vel) by n_steps steps of cfg, starting at step index step0,
- * on `stream`, and returns after synchronising it.  It (re)builds cells and
- * the list at entry, then runs chunks of fused steps, each chunk either
- * replayed from a captured hipGraph or launched directly, with one host sync
- * per chunk.  A list rebuild happens at a chunk boundary when any path length
- * passed soft_frac * r_buff/2.  If a chunk evaluated a force on a stale list
- * (a path length above r_buff/2) the chunk is rolled back from its snapshot
+ * on `stream`, and returns after synchronising it.  It bins and builds the
+ * list at entry (unless opt->keep_list continues the previous run's list),
+ * then runs chunks of fused steps, each chunk either replayed from a captured
+ * hipGraph or launched directly, with one host sync per chunk.  A list
+ * rebuild happens at a chunk boundary when any path length passed soft_frac *
+ * r_buff/2.  If a chunk evaluated a force on a stale list (a path length
+ * above r_buff/2) the state is restored from the snapshot of its list's build
  * and replayed up to the step where the soft threshold was first crossed;
- * the counter-based noise makes the replay exact.  Every log_period steps
- * (and at the end) it appends one row of 13 doubles (E, W, K at that step) to
- * ev_log and one bond count to bonds_log.  On an error return stats (if given)
- * still holds steps_done and log_rows, and pos / vel hold the state after
- * steps_done steps; after RC_ERR_NLIST_OVERFLOW with steps_done > 0 that state
- * owes its last step's final half kick, so the caller continues it (with a
- * larger k_max) by a call with resume = 1 for the remaining steps.  A single
- * system detects an overflow at the status read that ends the chunk after the
- * build and then returns the state at the build.  Buffers are caller owned: */
+ * the counter-based noise makes the replay exact.  Log rows (13 doubles: E,
+ * W, K at that step, appended to ev_log, and one bond count appended to
+ * bonds_log) are taken at every step index in [step0, step0 + n_steps) that
+ * is a multiple of log_period (none for log_period 0) and at the end; a run
+ * that continues the previous run's list (keep_list) skips the row of its
+ * first state when the previous run's last row already holds it.
+ * On an error return stats (if given) still holds steps_done and log_rows,
+ * and pos / vel hold the state after steps_done steps; after
+ * RC_ERR_NLIST_OVERFLOW with steps_done > 0 that state owes its last step's
+ * final half kick, so the caller continues it (with a larger k_max) by a
+ * call with resume = 1 for the remaining steps.  A single system detects an
+ * overflow at the status read that ends the chunk after the build and then
+ * returns the state at the build.  Buffers are caller owned: */
 typedef struct rc_md_buffers {
     float* pos;        /* [N*4] state in/out                                  */
     float* pos_alt;    /* [N*4] second position buffer                        */
@@ -441,7 +446,7 @@ typedef struct rc_md_options {
     int use_graph;      /* capture chunks as hipGraphs (1) or launch directly */
     int graph_steps;    /* steps per captured graph (even)                    */
     int max_chunk;      /* steps between host syncs (upper bound)             */
-    int log_period;     /* 0 = log only at the start and the end              */
+    int log_period;     /* rows at multiples of it and at the end; 0: the end */
     double soft_frac;   /* rebuild threshold as a fraction of r_buff/2        */
     int adapt;          /* 1: size chunks from the measured growth of the path
                            lengths so that rollbacks stay rare; 0: always
@@ -454,8 +459,24 @@ typedef struct rc_md_options {
     int resume;         /* 1: the state owes its last step's final half kick
                            (it is what an earlier call left when it returned an
                            error after steps_done > 0): the first step applies
-                           it, and n_steps = 0 applies just that kick.  The
-                           defaults (opt = NULL) are {1, 16, 256, 0, 0.8, 1, 1, 0}. */
+                           it, and n_steps = 0 applies just that kick.         */
+    int keep_list;      /* 1: continue on the list of the previous run instead of
+                           binning and building at entry, when the last call of
+                           this context (batch) that changed the state was an
+                           rc_md_run (rc_batch_run) that returned RC_OK with the
+                           same buffers, N, box and k_max and ended at step
+                           step0.  The caller promises that positions, images,
+                           the list and the cell workspace were not changed since
+                           (velocities may be).  Otherwise, and with resume = 1,
+                           the run builds at entry.  A rollback into the epoch
+                           the previous run began replays its steps from that
+                           epoch's snapshot (same results).                    */
+    int time_kernels;   /* 1: launch every step directly (no graphs, no
+                           one-workgroup replays), each step kernel between its
+                           own start and stop events; stats then sums their
+                           execution times.  Results are the same bit for bit.
+                           The defaults (opt = NULL) are
+                           {1, 16, 256, 0, 0.8, 1, 1, 0, 1, 0}.                */
 } rc_md_options;
 
 typedef struct rc_md_stats {
@@ -466,6 +487,11 @@ typedef struct rc_md_stats {
     int64_t log_rows;
     int32_t k_needed;   /* on RC_ERR_NLIST_OVERFLOW: the neighbour count found */
     int32_t flags;      /* last status flags                                  */
+    int64_t kernel_launches; /* time_kernels: step-kernel launches timed      */
+    double kernel_ms;   /* time_kernels: their summed execution time (ms)     */
+    double sums_ms;     /* time_kernels, RC_FORM_SUMS: the first passes' time */
+    int32_t list_kept;  /* 1: the run continued the previous run's list       */
+    int32_t pad;
 } rc_md_stats;
 
 int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,

@@ -42,17 +42,18 @@ def wrap(x, L):
 
 
 def baoab_step(pos, vel, types, tags, L, table, mass_by_type, dt, kT, gamma, seed, step,
-               force=None, extra=None, dim=3):
+               force=None, extra=None, dim=3, force_fn=None):
     """Advance (pos, vel) by one step; returns dict(pos, vel, image, F, F_old).
 
     extra(x) -> [N,3], if given, adds a further force (e.g. bond springs; x in
-    the same order as pos)."""
+    the same order as pos).  force_fn(x) -> [N,3], if given, evaluates the
+    potential's forces instead of ``swap_ref`` (e.g. the C brute force)."""
     x = np.asarray(pos, dtype=np.float64).copy()
     v = np.asarray(vel, dtype=np.float64).copy()
     m = np.asarray(mass_by_type, dtype=np.float64)[np.asarray(types)][:, None]
 
     def forces(y):
-        f = swap_ref.evaluate(y, types, L, table, scales=False)["F"]
+        f = force_fn(y) if force_fn is not None else swap_ref.evaluate(y, types, L, table, scales=False)["F"]
         return f if extra is None else f + extra(y)
 
     F = forces(x) if force is None else force

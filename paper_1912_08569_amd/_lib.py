@@ -80,14 +80,15 @@ class MdOptions(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("graph_steps", ctypes.c_int),
                 ("max_chunk", ctypes.c_int), ("log_period", ctypes.c_int),
                 ("soft_frac", ctypes.c_double), ("adapt", ctypes.c_int), ("one_block", ctypes.c_int),
-                ("resume", ctypes.c_int)]
+                ("resume", ctypes.c_int), ("keep_list", ctypes.c_int), ("time_kernels", ctypes.c_int)]
 
 
 class MdStats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
                 ("rollbacks", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("log_rows", ctypes.c_int64), ("k_needed", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
+                ("sums_ms", ctypes.c_double), ("list_kept", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p

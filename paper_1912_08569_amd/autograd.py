@@ -84,6 +84,7 @@ class SwapModel:
         d = x - self._ref
         d = d - self.L * torch.round(d / self.L)
         need = bool((d * d).sum(dim=1).max() > self.half_skin ** 2)
+        S.invalidate()   # positions written here, outside the driver
         S.pos[:, :3] = x[self._perm]
         if need:
             S.build()

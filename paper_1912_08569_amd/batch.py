@@ -86,6 +86,7 @@ class Batch:
         if seeds is not None:
             self.bc.set_seeds(seeds)
         self.built = False
+        self._continues = False     # the state is what the last run left (its list may be kept)
 
     @classmethod
     def from_workloads(cls, systems, **kw):
@@ -110,6 +111,7 @@ class Batch:
             if code != rcl.RC_OK:
                 raise RcError(code, "batch neighbour list build")
             self.built = True
+            self._continues = False
             return st[rcl.RC_ST_KMAX]
         raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour lists")
 
@@ -155,13 +157,16 @@ class Batch:
         return b
 
     def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
-            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True) -> BatchResult:
-        """Advance every replica n_steps under the chunked driver."""
+            graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True,
+            keep_list: bool = True, time_kernels: bool = False) -> BatchResult:
+        """Advance every replica n_steps under the chunked driver (log rows and keep_list as
+        System.run)."""
         rows = (n_steps // log_period + 2) if log_period > 0 else 1
         ev_log = torch.zeros((rows, self.R, 13), dtype=torch.float64, device=self.device)
         bonds_log = torch.zeros((rows, self.R), dtype=torch.int64, device=self.device)
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
-                             int(adapt), 0, 0)
+                             int(adapt), 0, 0, int(keep_list and self._continues), int(time_kernels))
+        self._continues = False
         for _ in range(4):
             try:
                 st = api.rc_batch_run(self.bc, self.md_buffers(ev_log, bonds_log), cfg, step0, n_steps, opts)
@@ -178,6 +183,7 @@ class Batch:
         else:
             raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour lists")
         self.built = True
+        self._continues = True
         n = int(st.log_rows)
         return BatchResult(stats=st, ev=ev_log[:n].cpu().numpy(), bonds=bonds_log[:n].cpu().numpy())
 

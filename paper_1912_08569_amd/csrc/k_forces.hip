@@ -7,6 +7,8 @@
 // Lambda_cab = sqrt(Lambda_ca Lambda_cb)).  d = x_a - x_c (minimum image).
 //   force on partner a from (c; a, b):  -w'_ca/r_ca w_cb d_ca
 //   force on the centre:                minus the sum of the two
+#include <hip/hip_ext.h>
+
 #include "rc_internal.h"
 #include "rc_gather.h"
 #include "rc_step.h"
@@ -383,6 +385,31 @@ static hipError_t launch_step_any(const StepArgs& a, bool ev, hipStream_t s) {
 }
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s) { return launch_step_any<false>(a, ev, s); }
+
+// A plain (no ev) step launch whose kernels each run between an event pair
+// (hipExtLaunchKernel records them around the kernel alone).
+template <bool BATCH>
+static hipError_t launch_step_timed_any(const StepArgs& a, hipStream_t s, hipEvent_t* sums, hipEvent_t* step) {
+    const size_t shm = sizeof(DevEntry) * a.tab.nt * a.tab.nt;
+    if (a.form == RC_FORM_SUMS) {
+        ForceArgs f = sums_args(a);
+        void* fargs[] = {&f};
+        const void* fn = BATCH ? reinterpret_cast<const void*>(&k_swap_sums<true>)
+                               : reinterpret_cast<const void*>(&k_swap_sums<false>);
+        hipError_t e = sums ? hipExtLaunchKernel(fn, dim3(nblk(a.N, kWave)), dim3(kWave), fargs, shm, s, sums[0],
+                                                 sums[1], 0)
+                            : hipLaunchKernel(fn, dim3(nblk(a.N, kWave)), dim3(kWave), fargs, shm, s);
+        if (e != hipSuccess) return e;
+    }
+    StepArgs arg = a;
+    void* args[] = {&arg};
+    return hipExtLaunchKernel(step_fn<BATCH>(false, a.width, a.form), dim3(nblk(a.N, kStepBlock)), dim3(kStepBlock),
+                              args, shm, s, step[0], step[1], 0);
+}
+
+hipError_t launch_step_timed(const StepArgs& a, bool batch, hipStream_t s, hipEvent_t* sums, hipEvent_t* step) {
+    return batch ? launch_step_timed_any<true>(a, s, sums, step) : launch_step_timed_any<false>(a, s, sums, step);
+}
 
 void step_kernel_info(bool ev, int width, int form, const void** fn) { *fn = step_fn<false>(ev, width, form); }
 

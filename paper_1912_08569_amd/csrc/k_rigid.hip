@@ -154,6 +154,7 @@ extern "C" int rc_rigid_step(rc_ctx* c, float* pos, float* vel, const float* for
                              int B, const int* centre, const int* first, const int* member, const float* offset,
                              const float* inertia, float* theta, float* omega, int N, rc_box box,
                              const rc_integrator* cfg, uint64_t step, int half, int* status, void* stream) {
+    if (c) c->md.valid = false;   // the state changes outside the driver
     if (!c) return RC_ERR_ARG;
     if (N < 1 || B < 1 || B > N) return fail(c, RC_ERR_ARG, "need 1 <= B <= N (B = %d, N = %d)", B, N);
     if (!pos || !vel || !force || !rtag || !centre || !first || !member || !offset || !inertia || !theta ||

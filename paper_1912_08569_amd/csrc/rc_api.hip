@@ -148,6 +148,7 @@ int rc_destroy(rc_ctx* c) {
 }
 
 int rc_set_lambda(rc_ctx* c, const double* lambda) {
+    if (c) c->md.valid = false;   // a replay into the last run's steps would use other forces
     if (!c || !lambda) return RC_ERR_ARG;
     const int nt = c->nt;
     for (int a = 0; a < nt; ++a)
@@ -183,6 +184,7 @@ int rc_soft_bonds(rc_ctx* c, const float* pos, const int* nlist, const int* nn, 
 }
 
 int rc_set_bonds(rc_ctx* c, const int* bonds, const int* rtag, int N, double K, double R0) {
+    if (c) c->md.valid = false;   // a replay into the last run's steps would use other forces
     if (!c) return RC_ERR_ARG;
     if (!bonds) {
         c->bonds = nullptr;
@@ -221,6 +223,7 @@ int rc_fene_forces(rc_ctx* c, const float* pos, int N, rc_box box, float* force,
 }
 
 int rc_set_table(rc_ctx* c, const rc_pair_coeff* table) {
+    if (c) c->md.valid = false;   // a replay into the last run's steps would use other forces
     if (!c || !table) return RC_ERR_ARG;
     const int nt = c->nt;
     for (int q = 0; q < nt * nt; ++q) {
@@ -294,6 +297,7 @@ int rc_cells_workspace_bytes(const rc_ctx* cc, int N, rc_box box, size_t* bytes)
 
 int rc_build_cells(rc_ctx* c, float* pos, float* vel, int* image, int* rtag, int N, rc_box box, void* ws,
                    size_t ws_bytes, void* stream) {
+    if (c) c->md.valid = false;   // the state or the list changes outside the driver
     int r = check_common(c, N, pos);
     if (r) return r;
     Box b;
@@ -326,6 +330,7 @@ int rc_build_cells(rc_ctx* c, float* pos, float* vel, int* image, int* rtag, int
 // fresh: the status words are written whole (the driver's rebuilds), else folded into
 static int build_nlist(rc_ctx* c, const float* pos, float* vel, int N, rc_box box, const void* ws, size_t ws_bytes,
                        int k_max, int* nlist, int* nn, int* status, bool fresh, void* stream) {
+    if (c) c->md.valid = false;   // the state or the list changes outside the driver
     int r = check_common(c, N, pos);
     if (r) return r;
     if (k_max < 1 || k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
@@ -395,6 +400,7 @@ int rc_compute_forces_noalloc(rc_ctx* c, const float* pos, const int* nlist, con
 int rc_integrate_step(rc_ctx* c, float* pos, float* vel, const float* force, int* image, int N, rc_box box,
                       const rc_integrator* cfg, uint64_t step, int half, double* kin, int* status,
                       void* stream) {
+    if (c) c->md.valid = false;   // the state or the list changes outside the driver
     int r = check_common(c, N, pos);
     if (r) return r;
     if (!vel || !force) return fail(c, RC_ERR_ARG, "vel / force are NULL");
@@ -479,6 +485,7 @@ static int fill_step_args(rc_ctx* c, StepArgs& a, const float* pos_in, float* po
 int rc_step_fused(rc_ctx* c, const float* pos_in, float* pos_out, float* vel, int* image, const int* nlist,
                   const int* nn, int k_max, int N, rc_box box, const rc_integrator* cfg, uint64_t step, int mode,
                   double soft_frac, double* ev, int* status, void* stream) {
+    if (c) c->md.valid = false;   // the state or the list changes outside the driver
     int r = check_common(c, N, pos_in);
     if (r) return r;
     if (!vel || !nlist || !nn || !status) return fail(c, RC_ERR_ARG, "vel / nlist / nn / status are NULL");
@@ -507,6 +514,7 @@ int rc_step_fused(rc_ctx* c, const float* pos_in, float* pos_out, float* vel, in
 int rc_time_fused_steps(rc_ctx* c, float* pos_a, float* pos_b, float* vel, const int* nlist, const int* nn,
                         int k_max, int N, rc_box box, const rc_integrator* cfg, uint64_t step0, int reps, int* status,
                         float* ms, void* stream) {
+    if (c) c->md.valid = false;   // the state or the list changes outside the driver
     int r = check_common(c, N, pos_a);
     if (r) return r;
     if (!pos_b || pos_b == pos_a || !vel || !nlist || !nn || !status || !ms || reps < 1)
@@ -727,6 +735,9 @@ struct PlainOps final : DriveOps {
         return RC_OK;
     }
     hipError_t launch(const StepArgs& a, bool ev) override { return launch_step(a, ev, s); }
+    hipError_t launch_timed(const StepArgs& a, hipEvent_t* sums, hipEvent_t* step) override {
+        return launch_step_timed(a, false, s, sums, step);
+    }
     int reduce_ev(int row) override {
         return reduce_rows(c, nblocks(N, kStepBlock), 0, kEvWords, buf->ev_log + (size_t)row * kEvWords, s);
     }
@@ -772,7 +783,7 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
     if (c->bonds && buf->rtag != c->bonds_rtag)
         return fail(c, RC_ERR_ARG, "with bonds, the md buffers' rtag must be the one given to rc_set_bonds");
-    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 1, 0};
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 1, 0, 1, 0};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
     if (opt.max_chunk < 1) opt.max_chunk = 256;

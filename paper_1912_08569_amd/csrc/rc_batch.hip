@@ -205,6 +205,7 @@ int rc_batch_layout(const rc_batch* b, int* n_slots, int* offsets) {
 }
 
 int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds) {
+    if (b) b->c.md.valid = false;   // a replay into the last run's steps would use other noise
     if (!b || !seeds) return RC_ERR_ARG;
     HIP_TRY(&b->c, hipDeviceSynchronize());
     HIP_TRY(&b->c, hipMemcpy(b->d_seeds, seeds, sizeof(uint64_t) * b->R, hipMemcpyHostToDevice));
@@ -236,6 +237,7 @@ int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes) {
 
 int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
                          void* stream) {
+    if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
     if (!b) return RC_ERR_ARG;
     int r = check_pos(b, pos);
     if (r) return r;
@@ -303,6 +305,7 @@ static int batch_build_nlist(rc_batch* b, const float* pos, float* vel, const vo
 
 int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
                          int* nlist, int* nn, int* status, void* stream) {
+    if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
     return batch_build_nlist(b, pos, vel, ws, ws_bytes, k_max, nlist, nn, status, false, stream);
 }
 
@@ -358,6 +361,7 @@ int rc_batch_bond_count(rc_batch* b, const float* pos, const int* nlist, const i
 int rc_batch_step_fused(rc_batch* b, const float* pos_in, float* pos_out, float* vel, int* image, const int* nlist,
                         const int* nn, int k_max, const rc_integrator* cfg, uint64_t step, int mode, double soft_frac,
                         double* ev, int* status, void* stream) {
+    if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
     if (!b) return RC_ERR_ARG;
     rc_ctx* c = &b->c;
     int r = check_pos(b, pos_in);
@@ -386,6 +390,7 @@ int rc_batch_step_fused(rc_batch* b, const float* pos_in, float* pos_out, float*
 int rc_batch_time_fused_steps(rc_batch* b, float* pos_a, float* pos_b, float* vel, const int* nlist, const int* nn,
                               int k_max, const rc_integrator* cfg, uint64_t step0, int reps, int* status, float* ms,
                               void* stream) {
+    if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
     if (!b) return RC_ERR_ARG;
     rc_ctx* c = &b->c;
     int r = check_pos(b, pos_a);
@@ -442,6 +447,9 @@ struct BatchOps final : DriveOps {
         return RC_OK;
     }
     hipError_t launch(const StepArgs& a, bool ev) override { return launch_step_batch(a, ev, s); }
+    hipError_t launch_timed(const StepArgs& a, hipEvent_t* sums, hipEvent_t* step) override {
+        return launch_step_timed(a, true, s, sums, step);
+    }
     int reduce_ev(int row) override {
         HIP_TRY(&b->c, launch_reduce_rows_batch(b->c.d_part, b->d_rep, b->R, 0, kEvWords,
                                                 buf->ev_log + (size_t)row * b->R * kEvWords, kEvWords, s));
@@ -483,7 +491,7 @@ extern "C" int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_inte
         return fail(c, RC_ERR_ARG, "md buffers incomplete");
     if (buf->k_max < 1 || buf->k_max > 512) return fail(c, RC_ERR_ARG, "k_max must be in [1, 512]");
     if (n_steps < 0) return fail(c, RC_ERR_ARG, "n_steps < 0");
-    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0, 0};
+    rc_md_options opt{1, 16, 256, 0, 0.8, 1, 0, 0, 1, 0};
     if (opt_in) opt = *opt_in;
     if (opt.graph_steps < 2 || (opt.graph_steps & 1)) opt.graph_steps = 16;
     if (opt.max_chunk < 1) opt.max_chunk = 256;

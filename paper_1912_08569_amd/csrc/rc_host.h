@@ -18,6 +18,34 @@ struct GraphCache {
     bool valid = false;
 };
 
+// What an rc_md_run that returned RC_OK left, for a next run that continues on
+// its list (rc_md_options.keep_list).  Cleared by every other call that
+// changes the state or the list.
+// The integrator settings a replay of earlier steps must share (compared bytewise).
+struct DynKey {
+    float minv[RC_MAX_TYPES], c2[RC_MAX_TYPES];
+    float dt, c1, noise_z, fene_k, fene_r02;
+    int langevin;
+    uint64_t seed;
+    const void* bonds;
+};
+DynKey dyn_key(const rc::StepArgs& a);
+
+struct MdRecord {
+    bool valid = false;
+    DynKey dyn{};               // its integrator settings
+    rc_md_buffers buf{};        // the buffers it ran on
+    int N = 0;
+    double L[3] = {0.0, 0.0, 0.0};
+    uint64_t step_end = 0;      // step index of the state it left (on-step velocities)
+    uint64_t ep_step = 0;       // step index of the state of its last list build (the snapshot)
+    int ep_cur = 0;             // position buffer that state was in (0 pos, 1 pos_alt)
+    bool ep_first = true;       // that state had on-step velocities (no half kick owed)
+    bool logged_end = false;    // its last log row is the state it left
+    double rate = 0.0;          // growth of the largest path length per step
+    float last_maxpath = 0.0f;  // largest path length since the build, at the end
+};
+
 struct rc_ctx {
     int device = 0;
     int nt = 0;
@@ -52,6 +80,9 @@ struct rc_ctx {
     hipEvent_t ev_sync = nullptr;       // the driver's wait event (no timing)
     GraphCache gc;
     void* noalloc_scratch = nullptr;    // device address of the fixed scratch on this device
+    MdRecord md;                        // the last run, for keep_list
+    std::vector<hipEvent_t> tk_events;  // event pairs of time_kernels
+    std::vector<int> tk_kind;           // per pair: 0 step kernel, 1 first pass of the sums form
     std::string err;
 };
 
@@ -126,6 +157,9 @@ struct DriveOps {
     // driver then restores from there instead of taking its own snapshot
     virtual bool rebuild_snapshot(const float4**, const float4**, const int4**) { return false; }
     virtual hipError_t launch_block(const StepArgs&, float4*, int) { return hipErrorNotSupported; }
+    // a plain step launch (no ev) with its kernels between event pairs: sums[0..1]
+    // around the first pass of the sums form (NULL otherwise), step[0..1] around the step
+    virtual hipError_t launch_timed(const StepArgs& a, hipEvent_t* sums, hipEvent_t* step) = 0;
 };
 
 // Chunked driver: speculative chunks of fused steps (graph replays where no

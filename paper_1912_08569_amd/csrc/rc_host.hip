@@ -159,6 +159,11 @@ int ensure_hsum(rc_ctx* c, size_t n) {
 
 void free_ctx_buffers(rc_ctx* c) {
     drop_graphs(c);
+    for (hipEvent_t e : c->tk_events)
+        if (e) (void)hipEventDestroy(e);
+    c->tk_events.clear();
+    c->tk_kind.clear();
+    c->md.valid = false;
     if (c->d_pl_j) (void)hipFree(c->d_pl_j);
     if (c->d_pl_o) (void)hipFree(c->d_pl_o);
     c->d_pl_j = nullptr;
@@ -324,7 +329,7 @@ static int add_node(rc_ctx* c, hipGraph_t g, hipGraphNode_t& prev, const void* f
     return RC_OK;
 }
 
-static int build_graphs(rc_ctx* c, const void* fn, const void* sums_fn, const StepArgs& tmpl, int G) {
+static int build_graphs(rc_ctx* c, const void* fn, const void* sums_fn, const StepArgs& tmpl, int G, hipStream_t s) {
     drop_graphs(c);
     const void* add_fn;
     add_step_kernel_info(&add_fn);
@@ -362,6 +367,8 @@ static int build_graphs(rc_ctx* c, const void* fn, const void* sums_fn, const St
             if ((r = add_node(c, g, prev, add_fn, args, 1, 1, 0))) return r;
         }
         HIP_TRY(c, hipGraphInstantiate(&c->gc.exec[p], g, nullptr, nullptr, 0));
+        // upload now: a first launch would otherwise pay it inside the run that uses the graph
+        HIP_TRY(c, hipGraphUpload(c->gc.exec[p], s));
     }
     c->gc.key = tmpl;
     c->gc.fn = fn;
@@ -372,6 +379,35 @@ static int build_graphs(rc_ctx* c, const void* fn, const void* sums_fn, const St
 
 static bool same_args(const StepArgs& x, const StepArgs& y) { return std::memcmp(&x, &y, sizeof(StepArgs)) == 0; }
 
+}  // namespace host
+}  // namespace rc
+
+DynKey dyn_key(const rc::StepArgs& a) {
+    DynKey k;
+    std::memset(&k, 0, sizeof k);   // padding too: keys are compared bytewise
+    std::memcpy(k.minv, a.minv, sizeof k.minv);
+    std::memcpy(k.c2, a.c2, sizeof k.c2);
+    k.dt = a.dt;
+    k.c1 = a.c1;
+    k.noise_z = a.noise_z;
+    k.fene_k = a.bonds ? a.fene_k : 0.0f;
+    k.fene_r02 = a.bonds ? a.fene_r02 : 0.0f;
+    k.langevin = a.langevin;
+    k.seed = a.seed;
+    k.bonds = a.bonds;
+    return k;
+}
+
+namespace rc {
+namespace host {
+
+static bool same_buffers(const rc_md_buffers& x, const rc_md_buffers& y) {
+    return x.pos == y.pos && x.pos_alt == y.pos_alt && x.vel == y.vel && x.image == y.image && x.rtag == y.rtag &&
+           x.nlist == y.nlist && x.nn == y.nn && x.k_max == y.k_max && x.cells_ws == y.cells_ws &&
+           x.cells_ws_bytes == y.cells_ws_bytes && x.snap_pos == y.snap_pos && x.snap_vel == y.snap_vel &&
+           x.snap_image == y.snap_image && x.status == y.status;
+}
+
 int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const StepArgs& tmpl, uint64_t step0,
              int n_steps, rc_md_options opt, rc_md_stats* stats, hipStream_t s) {
     const bool can_roll = buf->snap_pos && buf->snap_vel && (buf->snap_image || !buf->image);
@@ -379,7 +415,12 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     int r;
     rc_md_stats st{};
     int hst[RC_STATUS_WORDS] = {0};
+    const MdRecord prev = c->md;   // what the last run left (valid only if nothing changed the state since)
+    c->md.valid = false;           // set again only by a run that returns RC_OK
 
+    // Steps are counted absolutely: the state is at step s_cur, the run ends at s_end.
+    const uint64_t s_end = step0 + (uint64_t)n_steps;
+    uint64_t s_cur = step0;
     float* P[2] = {buf->pos, buf->pos_alt};
     int cur = 0;
     // Rollback state: one snapshot per list build (an epoch).  Every chunk of an epoch before the
@@ -389,22 +430,22 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     const float4 *ws_pos = nullptr, *ws_vel = nullptr;
     const int4* ws_image = nullptr;
     const bool snap_in_ws = ops.rebuild_snapshot(&ws_pos, &ws_vel, &ws_image);
-    int64_t epoch_start = 0;
-    int epoch_cur = 0, epoch_row = 0;
-    bool epoch_first = true;
+    uint64_t ep_step = step0;      // the epoch's first step (may precede step0 for a kept list)
+    int ep_cur = 0, ep_row = 0;
+    bool ep_first = true;
 
     // With the rebuilt state kept in the workspace, the list's overflow check is
     // deferred to the status read that ends the next chunk (one host wait less
     // per build): an overflow there restores the epoch's start and returns.
     const bool defer_check = snap_in_ws && can_roll;
     bool check_pending = false;
-    int64_t done = 0;
     int row = 0;
     auto overflow = [&]() -> int {
         st.k_needed = hst[RC_ST_KMAX];
         return fail(c, RC_ERR_NLIST_OVERFLOW, "a particle has %d neighbours (k_max %d)", hst[RC_ST_KMAX],
                     buf->k_max);
     };
+    bool first = opt.resume == 0;  // a resumed state owes its last step's final half kick
     auto rebuild = [&](int which) -> int {
         int rr = ops.rebuild(P[which]);
         if (rr) return rr;
@@ -427,13 +468,60 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         }
         if (stats) {
             st.flags = hst[RC_ST_FLAGS];
-            st.steps_done = done;
+            st.steps_done = s_cur > step0 ? (int64_t)(s_cur - step0) : 0;
             st.log_rows = row;
             *stats = st;
         }
         return code;
     };
 
+    // ---- per-launch timing (time_kernels) ---------------------------------------------
+    const bool timing = opt.time_kernels != 0;
+    size_t tk_used = 0;
+    // index of a fresh (start, stop) event pair; kind 1 marks a first pass of the sums form
+    auto tk_take = [&](size_t* q, int kind) -> int {
+        if (c->tk_events.size() < tk_used + 2) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            HIP_TRY(c, hipEventCreate(&e0));
+            HIP_TRY(c, hipEventCreate(&e1));
+            c->tk_events.push_back(e0);
+            c->tk_events.push_back(e1);
+            c->tk_kind.push_back(0);
+        }
+        *q = tk_used;
+        c->tk_kind[tk_used / 2] = kind;
+        tk_used += 2;
+        return RC_OK;
+    };
+    // after a status read: every timed launch of the chunk has completed
+    auto tk_collect = [&]() -> int {
+        for (size_t q = 0; q < tk_used; q += 2) {
+            float t = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&t, c->tk_events[q], c->tk_events[q + 1]));
+            if (c->tk_kind[q / 2]) {
+                st.sums_ms += t;
+            } else {
+                st.kernel_ms += t;
+                ++st.kernel_launches;
+            }
+        }
+        tk_used = 0;
+        return RC_OK;
+    };
+
+    const bool logging = buf->ev_log || buf->bonds_log;
+    const int lp = opt.log_period;
+    // a continued run does not log its first state again when the previous run ended with a row of it
+    const DynKey dyn = dyn_key(tmpl);
+    const bool kept = opt.keep_list && !opt.resume && prev.valid && prev.N == N && prev.step_end == step0 &&
+                      same_buffers(prev.buf, *buf) && std::memcmp(prev.L, tmpl.box.L, sizeof prev.L) == 0 &&
+                      std::memcmp(&prev.dyn, &dyn, sizeof dyn) == 0;
+    const bool skip_first_row = kept && prev.logged_end && lp > 0;
+    auto log_at = [&](uint64_t step) -> bool {
+        if (!logging || step < step0) return false;
+        if (step == step0 && skip_first_row) return false;
+        return lp > 0 && step % (uint64_t)lp == 0;
+    };
     auto log_now = [&](int which) -> int {
         if (buf->bonds_log) return ops.bonds(P[which], row);
         return RC_OK;
@@ -448,20 +536,39 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         a.step = step;
         a.step_base = nullptr;
         a.ev_part = ev ? c->d_part : nullptr;
-        HIP_TRY(c, ops.launch(a, ev));
+        if (timing && !ev && (mode == RC_STEP_START || mode == RC_STEP_CONT)) {
+            // the plain step launches (log steps and the finishing kick are other work)
+            const bool two = ops.graph_sums_fn() != nullptr;
+            size_t qk = 0, qs = 0;
+            int rr = tk_take(&qk, 0);
+            if (!rr && two) rr = tk_take(&qs, 1);
+            if (rr) return rr;
+            HIP_TRY(c, ops.launch_timed(a, two ? &c->tk_events[qs] : nullptr, &c->tk_events[qk]));
+        } else {
+            HIP_TRY(c, ops.launch(a, ev));
+        }
         if (ev && buf->ev_log) return ops.reduce_ev(row);
         return RC_OK;
     };
 
-    if ((r = rebuild(cur))) return finish(r);
-
-    const bool logging = buf->ev_log || buf->bonds_log;
-    const int lp = opt.log_period;
-    bool first = opt.resume == 0;  // a resumed state owes its last step's final half kick
     double rate = 0.0;           // growth of the largest path length per step
     float last_maxpath = 0.0f;
+    if (kept) {
+        // the previous run's list, snapshot and epoch carry over; its overflow check is done
+        need_snap = false;
+        ep_step = prev.ep_step;
+        ep_cur = prev.ep_cur;
+        ep_first = prev.ep_first;
+        ep_row = 0;               // rows of steps before step0 belong to the previous run
+        rate = prev.rate;
+        last_maxpath = prev.last_maxpath;
+        st.list_kept = 1;
+    } else if ((r = rebuild(cur))) {
+        return finish(r);
+    }
+
     const float hard = tmpl.hard;
-    const bool graphs = opt.use_graph != 0;
+    const bool graphs = opt.use_graph != 0 && !timing;
     const int G = opt.graph_steps;
     const bool blockrun = graphs && opt.one_block != 0 && ops.block_ok();
     if (graphs && !blockrun) {
@@ -470,14 +577,58 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         key.pos_out = reinterpret_cast<float4*>(buf->pos_alt);
         const void* fn = ops.graph_fn();
         if (!c->gc.valid || c->gc.steps != G || c->gc.fn != fn || !same_args(c->gc.key, key)) {
-            if ((r = build_graphs(c, fn, ops.graph_sums_fn(), key, G))) return finish(r);
+            if ((r = build_graphs(c, fn, ops.graph_sums_fn(), key, G, s))) return finish(r);
         }
     }
     uint64_t dev_base = ~0ull;   // value *d_step_base will hold once queued work ran
 
-    while (done < n_steps) {
+    // run `count` steps from the state at absolute step `from` (in P[cur])
+    auto run_steps = [&](uint64_t from, int64_t count) -> int {
+        int64_t k = 0;
+        while (k < count) {
+            const uint64_t step = from + (uint64_t)k;
+            const bool ev = log_at(step);
+            if (ev) {
+                int rr = log_now(cur);
+                if (rr) return rr;
+            }
+            if (graphs && !first && !ev && count - k >= G) {
+                // a graph replay must not cross a logging step
+                bool clear = true;
+                for (int64_t q = 1; q < G && clear; ++q) clear = !log_at(step + (uint64_t)q);
+                if (clear) {
+                    if (dev_base != step) HIP_TRY(c, launch_set_step(c->d_step_base, step, s));
+                    if (blockrun) {
+                        StepArgs a = tmpl;
+                        a.pos_in = reinterpret_cast<const float4*>(P[cur]);
+                        a.pos_out = reinterpret_cast<float4*>(P[cur ^ 1]);
+                        a.mode = RC_STEP_CONT;
+                        a.step = 0;
+                        a.step_base = c->d_step_base;
+                        a.ev_part = nullptr;
+                        HIP_TRY(c, ops.launch_block(a, reinterpret_cast<float4*>(P[cur]), G));
+                    } else {
+                        HIP_TRY(c, hipGraphLaunch(c->gc.exec[cur], s));
+                    }
+                    dev_base = step + G;
+                    k += G;
+                    continue;  // G is even: cur is unchanged
+                }
+            }
+            int rr = direct(step, first ? RC_STEP_START : RC_STEP_CONT, ev);
+            if (rr) return rr;
+            if (ev) ++row;
+            first = false;
+            cur ^= 1;
+            ++k;
+        }
+        return RC_OK;
+    };
+
+    bool first_chunk = true;
+    while (s_cur < s_end) {
         // ---- plan the chunk ---------------------------------------------------
-        int64_t C = std::min<int64_t>(n_steps - done, opt.max_chunk);
+        int64_t C = std::min<int64_t>((int64_t)(s_end - s_cur), opt.max_chunk);
         if (!can_roll) C = 1;
         else if (!opt.adapt) {
             // fixed chunks: stale chunks are rolled back
@@ -489,10 +640,11 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             const double room = (double)hard - (double)last_maxpath;
             const int64_t safe = (int64_t)std::floor(room / (1.5 * rate));
             C = std::max<int64_t>(1, std::min<int64_t>(C, safe));
-        } else if (done == 0) {
+        } else if (first_chunk) {
             C = std::min<int64_t>(C, 8);
         }
-        const int64_t chunk_start = done;
+        first_chunk = false;
+        const uint64_t chunk_start = s_cur;
         if (can_roll && need_snap) {
             if (!snap_in_ws)
                 HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(P[cur]),
@@ -501,77 +653,33 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
                                              reinterpret_cast<float4*>(buf->snap_pos),
                                              reinterpret_cast<float4*>(buf->snap_vel),
                                              reinterpret_cast<int4*>(buf->snap_image), N, s));
-            epoch_start = done;
-            epoch_cur = cur;
-            epoch_first = first;
-            epoch_row = row;
+            ep_step = s_cur;
+            ep_cur = cur;
+            ep_first = first;
+            ep_row = row;
             need_snap = false;
         }
         // one launch clears the chunk markers and sets the replays' step counter
-        HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, step0 + (uint64_t)chunk_start));
-        dev_base = step0 + (uint64_t)chunk_start;
+        HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, chunk_start));
+        dev_base = chunk_start;
         // ---- run it --------------------------------------------------------------
-        auto run_steps = [&](int64_t from, int64_t count) -> int {
-            int64_t k = 0;
-            while (k < count) {
-                const int64_t d = from + k;
-                const uint64_t step = step0 + (uint64_t)d;
-                const bool ev = logging && lp > 0 && (d % lp) == 0;
-                if (ev) {
-                    int rr = log_now(cur);
-                    if (rr) return rr;
-                }
-                if (graphs && !first && !ev && count - k >= G) {
-                    // a graph replay must not cross a logging step
-                    bool clear = true;
-                    if (logging && lp > 0) {
-                        const int64_t next_log = ((d + lp - 1) / lp) * lp;
-                        clear = next_log >= d + G || next_log == d;
-                        if (next_log == d) clear = false;
-                    }
-                    if (clear) {
-                        if (dev_base != step) HIP_TRY(c, launch_set_step(c->d_step_base, step, s));
-                        if (blockrun) {
-                            StepArgs a = tmpl;
-                            a.pos_in = reinterpret_cast<const float4*>(P[cur]);
-                            a.pos_out = reinterpret_cast<float4*>(P[cur ^ 1]);
-                            a.mode = RC_STEP_CONT;
-                            a.step = 0;
-                            a.step_base = c->d_step_base;
-                            a.ev_part = nullptr;
-                            HIP_TRY(c, ops.launch_block(a, reinterpret_cast<float4*>(P[cur]), G));
-                        } else {
-                            HIP_TRY(c, hipGraphLaunch(c->gc.exec[cur], s));
-                        }
-                        dev_base = step + G;
-                        k += G;
-                        continue;  // G is even: cur is unchanged
-                    }
-                }
-                int rr = direct(step, first ? RC_STEP_START : RC_STEP_CONT, ev);
-                if (rr) return rr;
-                if (ev) ++row;
-                first = false;
-                cur ^= 1;
-                ++k;
-            }
-            return RC_OK;
-        };
         if ((r = run_steps(chunk_start, C))) return finish(r);
         HIP_TRY(c, launch_fold_status(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
         if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
+        if (timing && (r = tk_collect())) return finish(r);
         ++st.chunks;
         const int f = hst[RC_ST_FLAGS];
         check_pending = false;
         if (f & RC_FLAG_NLIST_OVERFLOW) {
-            // the epoch ran on a truncated list: back to its start, which the caller resumes
-            cur = epoch_cur;
-            first = epoch_first;
-            row = epoch_row;
+            // the epoch ran on a truncated list (it began at a build of this run, whose
+            // check was deferred): back to its start, which the caller resumes
+            cur = ep_cur;
+            first = ep_first;
+            row = ep_row;
             HIP_TRY(c, launch_copy_state(ws_pos, ws_vel, buf->image ? ws_image : nullptr,
                                          reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
                                          reinterpret_cast<int4*>(buf->image), N, s, true));
-            done = epoch_start;
+            s_cur = ep_step;
             return finish(overflow());
         }
         if (f & RC_FLAG_LOST) return finish(fail(c, RC_ERR_LOST_PARTICLE, "a particle moved more than L/2 in one step"));
@@ -581,9 +689,9 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if (f & RC_FLAG_STALE) {
             if (!can_roll) return finish(fail(c, RC_ERR_ARG, "stale list without rollback buffers"));
             // roll back to the epoch's snapshot and replay up to the first soft crossing, then rebuild
-            cur = epoch_cur;
-            first = epoch_first;
-            row = epoch_row;
+            cur = ep_cur;
+            first = ep_first;
+            row = ep_row;
             if (snap_in_ws)   // the state the epoch's list build left (path lengths zero)
                 HIP_TRY(c, launch_copy_state(ws_pos, ws_vel, buf->image ? ws_image : nullptr,
                                              reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
@@ -595,20 +703,20 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
                                              reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
                                              reinterpret_cast<int4*>(buf->image), N, s));
             const int64_t soft_step = (int64_t)hst[RC_ST_FIRST_SOFT];
-            int64_t n_re = soft_step - (int64_t)((step0 + (uint64_t)epoch_start) & 0x7fffffff) + 1;
-            n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, chunk_start + C - epoch_start));
-            HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, step0 + (uint64_t)epoch_start));
-            dev_base = step0 + (uint64_t)epoch_start;
-            if ((r = run_steps(epoch_start, n_re))) return finish(r);
+            int64_t n_re = soft_step - (int64_t)(ep_step & 0x7fffffff) + 1;
+            n_re = std::max<int64_t>(1, std::min<int64_t>(n_re, (int64_t)(chunk_start + C - ep_step)));
+            HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, ep_step));
+            dev_base = ep_step;
+            if ((r = run_steps(ep_step, n_re))) return finish(r);
             HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
-            done = epoch_start + n_re;
+            s_cur = ep_step + (uint64_t)n_re;
             ++st.rollbacks;
             if ((r = rebuild(cur))) return finish(r);
             rate = std::max(rate, (double)mp / std::max<int64_t>(1, C));
             last_maxpath = 0.0f;
             continue;
         }
-        done = chunk_start + C;
+        s_cur = chunk_start + (uint64_t)C;
         rate = std::max(0.5 * rate, (double)(mp - last_maxpath) / (double)C);
         last_maxpath = mp;
         if (f & RC_FLAG_REBUILD) {
@@ -623,13 +731,19 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW)
             return finish(overflow());  // all steps done, the final half kick still due
     }
+    if (need_snap) {   // a build after the last chunk: its state owes the final half kick
+        ep_step = s_cur;
+        ep_cur = cur;
+        ep_first = false;
+        need_snap = false;
+    }
     {
         const bool ev = logging && buf->ev_log;
         if (logging) {
             if ((r = log_now(cur))) return finish(r);
         }
         if (!first) {
-            if ((r = direct(step0 + (uint64_t)n_steps, RC_STEP_FINISH, ev))) return finish(r);
+            if ((r = direct(s_end, RC_STEP_FINISH, ev))) return finish(r);
         } else if (ev) {
             // zero steps: report the state as it is
             if ((r = direct(step0, RC_STEP_OBSERVE, ev))) return finish(r);
@@ -639,8 +753,20 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     if (cur != 0) HIP_TRY(c, hipMemcpyAsync(buf->pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    st.steps_done = done;
-    st.log_rows = row;
+    if (timing && (r = tk_collect())) return finish(r);
+    // what the next run needs to continue on this list
+    c->md.valid = can_roll;
+    c->md.dyn = dyn;
+    c->md.buf = *buf;
+    c->md.N = N;
+    std::memcpy(c->md.L, tmpl.box.L, sizeof c->md.L);
+    c->md.step_end = s_end;
+    c->md.ep_step = ep_step;
+    c->md.ep_cur = ep_cur;
+    c->md.ep_first = ep_first;
+    c->md.rate = rate;
+    c->md.last_maxpath = last_maxpath;
+    c->md.logged_end = logging;
     return finish(RC_OK);
 }
 

@@ -416,6 +416,8 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, bool ev, hipStream_t s);
+// a plain step launch with its kernels between event pairs (sums: [2] or NULL, step: [2])
+hipError_t launch_step_timed(const StepArgs& a, bool batch, hipStream_t s, hipEvent_t* sums, hipEvent_t* step);
 // Small systems (at most kBlockMaxN particles, single system, walk or sums
 // form): G plain steps in one workgroup with the positions in LDS, the same
 // arithmetic as G launches of the step.  pos_final receives the positions

@@ -87,6 +87,9 @@ class System:
             api.rc_set_bonds(self.ctx, self.bonds, self.rtag, *self.fene)
             self.ev_fene = torch.zeros(7, dtype=torch.float64, device=dev)
         self.built = False
+        self._continues = False     # the state is what the last run left (its list may be kept)
+        self._form_stale = True     # the auto step form must be re-read from the list
+        self._log = None            # log rows of the last run (ev rows, then bond counts)
 
     @classmethod
     def from_workload(cls, sysw, **kw):
@@ -114,8 +117,10 @@ class System:
             if code != rcl.RC_OK:
                 raise RcError(code, "neighbour list build")
             self.built = True
+            self._continues = False
             if self.step_form == "auto":
                 self.ctx.set_step_form(self.auto_step_form())
+                self._form_stale = False
             return st[rcl.RC_ST_KMAX]
         raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
 
@@ -262,21 +267,33 @@ class System:
 
     def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
             graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True,
-            one_block: bool = True) -> RunResult:
+            one_block: bool = True, keep_list: bool = True, time_kernels: bool = False) -> RunResult:
         """Advance n_steps with the fused step kernel under the chunked driver.
 
+        Log rows are taken at the step indices in [step0, step0 + n_steps) that are multiples of
+        log_period (none for 0) and at the end; a continued run (keep_list) does not repeat the last
+        run's final row.
         one_block: with use_graph, systems of at most 1024 particles run each replay of graph_steps
-        steps in one workgroup launch (same results, bit for bit)."""
+        steps in one workgroup launch (same results, bit for bit).
+        keep_list: a run that starts where the last one ended (step0 = its last step) continues on
+        its neighbour list instead of building one at entry; code that writes the state tensors
+        directly calls invalidate() first.
+        time_kernels: launch every step directly with events around its kernels; the stats then
+        hold the summed kernel time (kernel_ms over kernel_launches)."""
         if self.step_form == "auto":
             if not self.built:
                 self.build()    # picks the form from the new list
-            else:               # from the list the last build left
+            elif self._form_stale:   # from the list the last run's builds left
                 self.ctx.set_step_form(self.auto_step_form())
+                self._form_stale = False
         rows = (n_steps // log_period + 2) if log_period > 0 else 1
-        ev_log = torch.zeros((rows, 13), dtype=torch.float64, device=self.device)
-        bonds_log = torch.zeros(rows, dtype=torch.int64, device=self.device)
+        if self._log is None or self._log.shape[0] < rows * 14:
+            self._log = torch.zeros(max(rows, 64) * 14, dtype=torch.float64, device=self.device)
+        ev_log = self._log[:rows * 13]
+        bonds_log = self._log[rows * 13:rows * 14]       # u64 counts in the same buffer (one copy back)
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
-                             int(adapt), int(one_block), 0)
+                             int(adapt), int(one_block), 0, int(keep_list and self._continues), int(time_kernels))
+        self._continues = False
         for _ in range(4):
             try:
                 st = api.rc_md_run(self.ctx, self.md_buffers(ev_log, bonds_log), self.N, self.box, cfg, step0,
@@ -294,8 +311,18 @@ class System:
         else:
             raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
         self.built = True
+        self._continues = True
+        if st.rebuilds > 0:
+            self._form_stale = True
         n = int(st.log_rows)
-        return RunResult(stats=st, ev=ev_log[:n].cpu().numpy(), bonds=bonds_log[:n].cpu().numpy())
+        host = self._log[:rows * 14].cpu()
+        ev = host[:rows * 13].view(rows, 13)[:n].numpy()
+        bonds = host[rows * 13:rows * 14].view(torch.int64)[:n].numpy()
+        return RunResult(stats=st, ev=ev, bonds=bonds)
+
+    def invalidate(self):
+        """Mark the state as changed outside the engine: the next run builds its list at entry."""
+        self._continues = False
 
     # ---- state in tag order ----------------------------------------------------------
     def state_by_tag(self):

@@ -380,3 +380,73 @@ def test_one_block_replays_equal_graph_replays(case):
     assert (ra.stats.rebuilds, ra.stats.rollbacks, ra.stats.chunks) == (rb.stats.rebuilds, rb.stats.rollbacks,
                                                                        rb.stats.chunks)
     assert ra.stats.steps_done == 400
+
+
+# --------------------------------------------------------------------------
+# consecutive runs: the second continues on the first's list
+# --------------------------------------------------------------------------
+
+def _same_state(A, B):
+    return all(np.array_equal(x, y) for x, y in zip(A.state_by_tag(), B.state_by_tag()))
+
+
+@pytest.mark.parametrize("n", [4000, 1000])
+def test_split_runs_equal_one_run_bitwise(n):
+    # a wide skin: no list build after the first, so run(10); run(10) and run(20) take the same steps
+    # (the finishing kick of the first run and the second run's first half kick are the one step's
+    # kicks), and the continued run builds nothing at entry.  Rows at multiples of the log period
+    # and at the end; the continued run does not repeat the first run's last row.
+    # (a start at least 1.0 apart: no pair deep in the core, so nothing moves far in 20 steps)
+    s = W.small_reactive(N=n, density=0.25, seed=61, table=W.swap_table_single(lam=0.8), kT=0.1, min_dist=1.0)
+    A, B = _system(s, r_buff=0.8), _system(s, r_buff=0.8)
+    for S in (A, B):
+        S.set_step_form("walk")
+    cfg = A.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=3)
+    ra1 = A.run(10, cfg, step0=0, log_period=5)
+    ra2 = A.run(10, cfg, step0=10, log_period=5)
+    rb = B.run(20, cfg, step0=0, log_period=5)
+    assert ra2.stats.list_kept == 1 and ra2.stats.rebuilds == 0 and rb.stats.rebuilds == 1
+    assert _same_state(A, B)
+    assert np.array_equal(np.concatenate([ra1.ev, ra2.ev]), rb.ev)
+    assert np.array_equal(np.concatenate([ra1.bonds, ra2.bonds]), rb.bonds)
+    # a list build between runs, or a new step index, starts the next run with a build
+    A.build()
+    assert A.run(5, cfg, step0=20).stats.list_kept == 0
+    assert A.run(5, cfg, step0=40).stats.list_kept == 0
+    assert A.run(5, cfg, step0=45).stats.list_kept == 1
+
+
+@pytest.mark.parametrize("n", [3000, 1000])
+def test_continued_run_rolls_back_into_the_previous_runs_epoch(n):
+    # a thin skin and long fixed chunks: the continued run's first chunk goes stale inside the epoch the
+    # first run began, and is replayed from that epoch's snapshot (the first run's last steps again),
+    # exactly as one run with one-step chunks takes them (the rollback test above, across two calls)
+    s = W.small_reactive(N=n, density=0.25, seed=46, table=W.swap_table_single(lam=1.0), kT=0.5)
+    A, B = _system(s, r_buff=0.06), _system(s, r_buff=0.06)
+    for S in (A, B):
+        S.set_step_form("walk")
+    cfg = A.integrator(dt=0.002, kT=0.5, gamma=1.0, seed=11)
+    kw = dict(max_chunk=64, adapt=False, soft_frac=1.0, log_period=100)
+    ra1 = A.run(150, cfg, step0=0, **kw)
+    ra2 = A.run(150, cfg, step0=150, **kw)
+    rb = B.run(300, cfg, step0=0, max_chunk=1, adapt=False, soft_frac=1.0, log_period=100)
+    assert ra2.stats.list_kept == 1 and ra2.stats.rollbacks > 0 and rb.stats.rollbacks == 0
+    assert ra1.stats.rebuilds + ra2.stats.rebuilds == rb.stats.rebuilds
+    assert _same_state(A, B)
+    # rows: 0, 100, end 150 | 200, end 300   against 0, 100, 200, end 300
+    assert np.array_equal(ra1.ev[:2], rb.ev[:2]) and np.array_equal(ra2.ev, rb.ev[2:])
+    assert np.array_equal(ra1.bonds[:2], rb.bonds[:2]) and np.array_equal(ra2.bonds, rb.bonds[2:])
+
+
+def test_timed_kernels_take_the_same_steps():
+    # time_kernels launches every step directly between events: the same trajectory as graph replays
+    s = W.assembly_mixture(N=20000, lam=1.0, seed=62, kT=0.05)
+    A, B = _system(s), _system(s)
+    cfg = A.integrator(dt=0.001, kT=0.05, gamma=1.0, seed=4)
+    ra = A.run(200, cfg, log_period=50, time_kernels=True)
+    rb = B.run(200, cfg, log_period=50)
+    assert _same_state(A, B)
+    assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
+    # every plain step launch is timed: all steps but the log steps (0, 50, 100, 150)
+    assert ra.stats.kernel_launches >= 196 and ra.stats.kernel_ms > 0.0
+    assert rb.stats.kernel_launches == 0

@@ -1,11 +1,18 @@
-"""Parity at the full 1,048,576-particle size, in the launch configuration
-the benchmark times (fused step kernel, graph-captured driver)."""
+"""Parity at the full 1,048,576-particle size.
+
+* Forces, energy, virial and bond count of both stand-alone force kernels
+  against the oracle, at the start and after 1000 steps (lambda 0.5).
+* The benchmark's own configuration (lambda 1, skin 0.3, k_max 32, walk form,
+  gather width 2, the packed list the list build writes): one step of its
+  fused step kernel through the driver against the oracle's BAOAB step, and
+  its hipGraph replays against direct launches, bit for bit.
+"""
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
-from oracle import swap_ref
+from oracle import dynamics_ref, swap_ref
 from parity_util import assert_energy, assert_forces, assert_virial
 
 pytestmark = pytest.mark.gpu
@@ -65,3 +72,63 @@ def test_fullsize_sampled_forces_vs_brute_force(big, brute_lib):
     err = np.abs(Fg - b["F"]).max(axis=1) / np.maximum(ref["A_F"][idx], 1e-30)
     assert err.max() < 1e-5
     assert np.array_equal(b["degree"], swap_ref.bond_degree(x, ty, s.L, s.table)[idx])
+
+
+@pytest.fixture(scope="module")
+def bench_workload():
+    return W.assembly_mixture(N=1048576, lam=1.0, seed=1003, kT=0.05)   # the benchmark's system
+
+
+def _bench_system(s):
+    from paper_1912_08569_amd import System
+    S = System.from_workload(s, r_buff=0.3, k_max=32)
+    S.build()
+    assert S.ctx.step_form == "walk"        # what "auto" picks for the mixture, as in the benchmark
+    return S
+
+
+def _ulp32(x):
+    x = np.abs(np.asarray(x, dtype=np.float32))
+    return (np.nextafter(x, np.float32(np.inf)) - x).astype(np.float64)
+
+
+def test_fullsize_bench_step_matches_oracle(bench_workload):
+    s = bench_workload
+    S = _bench_system(s)
+    dt, kT, gamma, seed, step = 0.001, 0.05, 1.0, 2003, 5
+    x0, v0, _, ty = S.state_by_tag()
+    S.run(1, S.integrator(dt=dt, kT=kT, gamma=gamma, seed=seed), step0=step)
+    x1, v1, img, _ = S.state_by_tag()
+    ref = dynamics_ref.baoab_step(x0, v0, ty, np.arange(s.N), s.L, s.table, s.mass, dt, kT, gamma, seed, step)
+    e0 = swap_ref.evaluate(x0, ty, s.L, s.table)
+    assert e0["n_pairs"] > 0
+    dx = np.abs(swap_ref.min_image(ref["pos"], x1.astype(np.float64), s.box))
+    # The final half kick uses the forces at the new positions, which the engine holds in FP32
+    # (a rounding of up to 3.8e-6 at |x| ~ 76 that the stiff eps 15 swap bonds turn into force
+    # differences of ~0.1): the oracle's kick is taken at the engine's positions.
+    e1 = swap_ref.evaluate(x1.astype(np.float64), ty, s.L, s.table)
+    m = s.mass[ty][:, None]
+    v_ref = ref["vel"] + 0.5 * dt * (e1["F"] - ref["F"]) / m
+    c2 = np.sqrt((1 - np.exp(-2 * gamma * dt)) * kT / m)
+    # velocity scale: the sizes of every term of the step (the force terms at their error scale)
+    vscale = np.abs(v0) + 4.0 * c2 + dt * (e0["A_F"] + e1["A_F"])[:, None] / m + np.abs(v_ref)
+    dv = np.abs(v1 - v_ref)
+    assert np.all(dv <= 2e-5 * vscale + 1e-7), f"velocity error {np.max(dv / (vscale + 1e-30)):.3e}"
+    assert np.all(dx <= 4 * _ulp32(ref["pos"]) + dt * 2e-5 * vscale), "position error over tolerance"
+    assert np.array_equal(img, ref["image"])
+
+
+def test_fullsize_bench_graph_replays_equal_direct_launches(bench_workload):
+    s = bench_workload
+    out = []
+    for use_graph in (True, False):
+        S = _bench_system(s)
+        cfg = S.integrator(dt=0.001, kT=0.05, gamma=1.0, seed=2003)
+        r = S.run(60, cfg, step0=5, log_period=100, use_graph=use_graph)
+        out.append((S.state_by_tag(), r))
+        del S
+        torch.cuda.empty_cache()
+    (sa, ra), (sb, rb) = out
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+    assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
+    assert ra.stats.chunks == rb.stats.chunks and ra.stats.rebuilds == rb.stats.rebuilds

@@ -7,7 +7,7 @@ import torch
 
 import workloads as W
 from oracle import dynamics_ref, fene_ref, swap_ref
-from parity_util import assert_forces
+from parity_util import assert_energy, assert_forces, assert_virial
 
 pytestmark = pytest.mark.gpu
 
@@ -100,17 +100,35 @@ def test_network_dynamics_keeps_springs_and_ends_on_oracle_values():
     assert 0.5 < T < 2.0        # thermostat at kT = 1 (bond formation releases heat)
 
 
+def _full_parity(S, s):
+    """Forces, energy, virial and bond count of the whole network (pairs + springs) against the oracle."""
+    F, ev = S.compute_forces(gather=True)
+    torch.cuda.synchronize()
+    x, _, _, ty = S.state_by_tag()
+    ref, f = _ref(x.astype(np.float64), ty, s)
+    assert_forces(S.by_tag(F), ref)
+    evh = ev.cpu().numpy()
+    assert_energy(evh[0], ref)
+    # virial scale: the pair terms' plus, per spring, its length (< R0 = 1.5) times its force size
+    ref["A_W"] = ref["A_W"] + 0.75 * float(np.sum(f["A_F"]))
+    assert_virial(evh[1:7], ref)
+    assert S.bond_count() == ref["bonds"]
+    return ref, f
+
+
 def test_full_network_runs():
-    # the 67,200-bead network: 4000 chains of 16 and 1600 crosslinker dimers at density 0.85
+    # the 67,200-bead network: 4000 chains of 16 and 1600 crosslinker dimers at density 0.85, checked
+    # against the oracle at the start and at the end of the run
     s = W.vitrimer_network()
     S = _system(s)
-    # the random-walk start has many 0.8 sigma contacts; 300 push-off steps leave springs near R0 that the
-    # 0.002 step then breaks, 3000 relax them (max spring length 1.32 after the push-off)
+    _full_parity(S, s)
+    # the grown start has many 0.8 sigma contacts; 3000 push-off steps at dt 2e-4 relax them before the
+    # run's dt 0.002 (300 left springs near R0 that the larger step then broke)
     S.run(3000, S.integrator(dt=2e-4, kT=1.0, gamma=1.0, seed=23))
     cfg = S.integrator(dt=0.002, kT=1.0, gamma=1.0, seed=23)
     r = S.run(1000, cfg, step0=3000, log_period=500)
-    x, _, _, ty = S.state_by_tag()
-    f = fene_ref.evaluate(x.astype(np.float64), s.L, s.bonds, *s.fene)
+    ref, f = _full_parity(S, s)
     assert f["n_bonds"] == 61600
-    assert int(r.bonds[-1]) == swap_ref.bond_count(x.astype(np.float64), ty, s.L, s.table)
+    assert int(r.bonds[-1]) == ref["bonds"]
+    assert abs(r.ev[-1, 0] - ref["E"]) <= 1e-5 * ref["A_E"]
     assert np.all(np.isfinite(r.ev))

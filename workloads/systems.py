@@ -437,74 +437,83 @@ def vitrimer_table(eps_site=20.0, sigma_site=0.3, n=10, rcut_site=0.45, lam=1.0)
     return t
 
 
-def _grow_chains(rng, L, n_chains, chain_len, n_dimers, bond, d_min, tries=24):
+def _grow_chains(rng, L, n_chains, chain_len, n_dimers, bond, d_min, tries=24, patience=8, max_rounds=5000):
     """Self-avoiding growth of chains and dimers in a periodic box: every
-    bead keeps a periodic distance > d_min from all earlier beads, and
-    consecutive beads of a molecule sit ``bond`` apart."""
-    # cells at least one bond plus d_min wide: every check reads the 27 cells around one point
-    w = max(bond + d_min, L / 256.0)
-    nc = max(3, int(L // w))
-    w = L / nc
-    grid = {}
-    pts = []
+    bead keeps a periodic distance > d_min from all other beads, and
+    consecutive beads of a molecule sit ``bond`` apart.
 
-    def cell(p):
-        return tuple(int(math.floor((p[a] + 0.5 * L) / w)) % nc for a in range(3))
-
-    def clear(cands, centre, reach):
-        """Candidates (all within reach - w of centre) with no bead within d_min."""
-        ok = np.ones(len(cands), dtype=bool)
-        near = []
-        c0 = cell(centre)
-        rng_c = range(-reach, reach + 1)
-        for dx in rng_c:
-            for dy in rng_c:
-                for dz in rng_c:
-                    near.extend(grid.get(((c0[0] + dx) % nc, (c0[1] + dy) % nc, (c0[2] + dz) % nc), ()))
-        if near:
-            q = np.asarray([pts[k] for k in set(near)])
-            d = cands[:, None, :] - q[None, :, :]
+    All molecules grow together, one bead per molecule and round: each
+    proposes ``tries`` random directions from its last bead and takes the
+    first candidate clear of every bead placed so far (a periodic k-d tree
+    query, library primitive); of two molecules whose new beads clash in the
+    same round the later one tries again.  A molecule that finds no clear
+    candidate ``patience`` rounds in a row is taken out and started anew."""
+    sizes = np.array([chain_len] * n_chains + [2] * n_dimers)
+    M = len(sizes)
+    P = np.zeros((M, int(sizes.max()), 3))     # bead positions in [0, L)
+    n = np.zeros(M, np.int64)                  # beads placed per molecule
+    fails = np.zeros(M, np.int64)
+    d2 = d_min * d_min
+    tree, recent = None, np.zeros((0, 3))
+    for _ in range(max_rounds):
+        active = np.nonzero(n < sizes)[0]
+        if active.size == 0:
+            break
+        # the tree holds the beads placed up to its build; later ones are checked directly while
+        # few candidates remain (the last rounds of the growth), else the tree is rebuilt
+        if tree is None or active.size * tries * len(recent) > 2e7:
+            placed = P[np.arange(P.shape[1])[None, :] < n[:, None]]
+            tree = cKDTree(placed, boxsize=L) if len(placed) else None
+            recent = np.zeros((0, 3))
+        # candidates: a random start for empty molecules, bond-length steps from the last bead otherwise
+        dirs = rng.standard_normal((active.size, tries, 3))
+        dirs /= np.linalg.norm(dirs, axis=2)[:, :, None]
+        last = P[active, np.maximum(n[active] - 1, 0)]
+        cand = last[:, None, :] + bond * dirs
+        empty = n[active] == 0
+        cand[empty] = rng.uniform(0.0, L, size=(int(empty.sum()), tries, 3))
+        cand = np.mod(cand, L)
+        cand = np.where(cand >= L, 0.0, cand)
+        flat = cand.reshape(-1, 3)
+        clear = np.ones(flat.shape[0], bool)
+        if tree is not None:
+            dist, _ = tree.query(flat, k=1, distance_upper_bound=d_min)
+            clear = dist > d_min
+        if len(recent):
+            d = flat[:, None, :] - recent[None, :, :]
             d -= L * np.round(d / L)
-            ok = ~np.any(np.einsum("cka,cka->ck", d, d) <= d_min * d_min, axis=1)
-        return ok
-
-    def add(p):
-        grid.setdefault(cell(p), []).append(len(pts))
-        pts.append(p)
-
-    def wrap(p):
-        return p - L * np.floor((p + 0.5 * L) / L)
-
-    reach1 = reach2 = 1
-    if nc < 3:
-        raise ValueError("box too small for the growth grid")
-    mols = []
-    sizes = [chain_len] * n_chains + [2] * n_dimers
-    for size in sizes:
-        while True:
-            start = len(pts)
-            p = wrap(rng.uniform(-0.5 * L, 0.5 * L, 3))
-            if not clear(p[None, :], p, reach1)[0]:
-                continue
-            add(p)
-            ok = True
-            for _ in range(size - 1):
-                dirs = rng.standard_normal((tries, 3))
-                dirs /= np.linalg.norm(dirs, axis=1)[:, None]
-                cands = wrap(pts[-1][None, :] + bond * dirs)
-                good = np.nonzero(clear(cands, pts[-1], reach2))[0]
-                if good.size == 0:
-                    ok = False
-                    break
-                add(cands[good[0]])
-            if ok:
-                mols.append((start, size))
-                break
-            # dead end: take the molecule out again and start elsewhere
-            for k in range(len(pts) - 1, start - 1, -1):
-                grid[cell(pts[k])].remove(k)
-            del pts[start:]
-    return np.asarray(pts), mols
+            clear &= ~np.any(np.einsum("cka,cka->ck", d, d) <= d2, axis=1)
+        clear = clear.reshape(active.size, tries)
+        has = clear.any(axis=1)
+        pick = np.argmax(clear, axis=1)
+        chosen = cand[np.arange(active.size), pick]
+        ok = has.copy()
+        # clashes among this round's new beads: the later molecule yields
+        idx = np.nonzero(ok)[0]
+        if idx.size > 1:
+            t2 = cKDTree(chosen[idx], boxsize=L)
+            for a, b in sorted(t2.query_pairs(d_min), key=lambda p: max(p)):
+                ia, ib = idx[a], idx[b]
+                if ok[ia] and ok[ib]:
+                    ok[max(ia, ib)] = False
+        mq = active[ok]
+        P[mq, n[mq]] = chosen[ok]
+        recent = np.concatenate([recent, chosen[ok]])
+        n[mq] += 1
+        fails[mq] = 0
+        stuck = active[~has]
+        fails[stuck] += 1
+        dead = stuck[fails[stuck] >= patience]
+        n[dead] = 0
+        fails[dead] = 0
+        if dead.size:
+            tree = None          # their beads leave the box: rebuild from what stays
+    else:
+        raise RuntimeError(f"chain growth did not finish in {max_rounds} rounds")
+    pts = P[np.arange(P.shape[1])[None, :] < sizes[:, None]]
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    mols = [(int(s), int(z)) for s, z in zip(starts, sizes)]
+    return pts - 0.5 * L, mols
 
 
 def vitrimer_network(n_chains=4000, chain_len=16, n_dimers=1600, density=0.85, site_frac=0.1, seed=1002,

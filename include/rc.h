@@ -299,6 +299,15 @@ int rc_integrate_step(rc_ctx* ctx, float* pos, float* vel, const float* force,
                       uint64_t step, int half, double* kin /* [6] | NULL */,
                       int* status /* NULL ok */, void* stream);
 
+/* rc_thermostat_normals: the normals xi the integrators above draw (Philox4x32-10
+ * keyed by seed, counter (tag, step), Box-Muller as described), for host-side
+ * integrators that must follow the engine's noise (the trajectory fit):
+ * out[k][t] = (xi_x, xi_y, xi_z, 0) of tag t in [0, N) at step step0 + k,
+ * xi_z = 0 for dim 2 (device, 16-byte aligned, [steps][N][4] floats, steps * N
+ * <= 2^31).  No context needed.                                               */
+int rc_thermostat_normals(uint64_t seed, uint64_t step0, int steps, int N, int dim,
+                          float* out /* [steps*N*4] */, void* stream);
+
 /* ---- rigid planar bodies (next-4: the patchy colloids of Sec. 3.2) ----------
  * Body b is the particle with tag centre[b] (a disk; its type's mass) plus the
  * massless member particles with tags member[first[b] .. first[b+1]) held at

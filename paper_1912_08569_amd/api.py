@@ -19,7 +19,7 @@ from ._lib import RcError, check
 __all__ = [
     "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
-    "rc_compute_forces_noalloc",
+    "rc_compute_forces_noalloc", "rc_thermostat_normals",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp", "rc_force_hvp_batch", "rc_partner_counts", "rc_stress_autocorrelation",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
     "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
@@ -211,6 +211,17 @@ def rc_compute_forces_noalloc(ctx: Context, pos, nlist, nn, bx, force, ev=None, 
     check(L.load().rc_compute_forces_noalloc(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
                                              _ptr(force), _ptr(ev), int(flags), _ptr(status), _stream(stream)),
           ctx.handle)
+
+
+def rc_thermostat_normals(seed, step0, steps, N, dim=3, device="cuda", stream=None) -> torch.Tensor:
+    """(steps, N, 4) float32 device tensor: the integrators' thermostat normals of tags 0..N-1 at steps
+    step0 .. step0 + steps - 1 (w = 0)."""
+    out = torch.empty((int(steps), int(N), 4), dtype=torch.float32, device=device)
+    code = L.load().rc_thermostat_normals(int(seed), int(step0), int(steps), int(N), int(dim), _ptr(out),
+                                          _stream(stream))
+    if code != L.RC_OK:
+        raise RcError(code, "rc_thermostat_normals")
+    return out
 
 
 def rc_integrate_step(ctx: Context, pos, vel, force, image, bx, cfg, step, half, kin=None, status=None,

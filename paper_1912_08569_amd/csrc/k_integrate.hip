@@ -1,4 +1,5 @@
 // Standalone BAOAB / velocity-Verlet half steps (rc_integrate_step).
+#include <algorithm>
 #include "rc_internal.h"
 
 namespace rc {
@@ -69,6 +70,28 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a) {
         double v[6] = {kin[0], kin[1], kin[2], kin[3], kin[4], kin[5]};
         block_sum_store<6>(v, a.kin_part + (size_t)blockIdx.x * kEvWords + 7);
     }
+}
+
+// The thermostat normals of tags [0, N) at steps step0 .. step0 + steps - 1,
+// as every integrating kernel draws them: out[k * N + t] = (xi_x, xi_y, xi_z, 0).
+__global__ __launch_bounds__(kBlock) void k_thermostat_normals(uint64_t seed, uint64_t step0, int steps, int N,
+                                                              float noise_z, float4* __restrict__ out) {
+    const long total = (long)steps * N;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const long k = i / N;
+        const int t = (int)(i - k * N);
+        float z0, z1, z2;
+        thermostat_normals(seed, (uint32_t)t, step0 + (uint64_t)k, z0, z1, z2);
+        out[i] = make_float4(z0, z1, noise_z * z2, 0.0f);
+    }
+}
+
+hipError_t launch_thermostat_normals(uint64_t seed, uint64_t step0, int steps, int N, float noise_z, float4* out,
+                                     hipStream_t s) {
+    const long total = (long)steps * N;
+    const int blocks = (int)std::min<long>((total + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_thermostat_normals, dim3(blocks), dim3(kBlock), 0, s, seed, step0, steps, N, noise_z, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_integrate(const IntegrateArgs& a, hipStream_t s) {

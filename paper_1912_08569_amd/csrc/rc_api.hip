@@ -397,6 +397,16 @@ int rc_compute_forces_noalloc(rc_ctx* c, const float* pos, const int* nlist, con
     return forces_into(c, pos, nlist, nn, k_max, N, box, force, ev, flags, status, rows, sums, S(stream));
 }
 
+int rc_thermostat_normals(uint64_t seed, uint64_t step0, int steps, int N, int dim, float* out, void* stream) {
+    if (!out || steps < 1 || N < 1 || N >= RC_MAX_TAG || (dim != 0 && dim != 2 && dim != 3)) return RC_ERR_ARG;
+    if ((long)steps * (long)N > (1L << 31)) return RC_ERR_UNSUPPORTED;
+    if (reinterpret_cast<uintptr_t>(out) & 15) return RC_ERR_ARG;
+    return launch_thermostat_normals(seed, step0, steps, N, dim == 2 ? 0.0f : 1.0f, reinterpret_cast<float4*>(out),
+                                     S(stream)) == hipSuccess
+               ? RC_OK
+               : RC_ERR_HIP;
+}
+
 int rc_integrate_step(rc_ctx* c, float* pos, float* vel, const float* force, int* image, int N, rc_box box,
                       const rc_integrator* cfg, uint64_t step, int half, double* kin, int* status,
                       void* stream) {

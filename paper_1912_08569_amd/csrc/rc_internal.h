@@ -476,6 +476,8 @@ struct IntegrateArgs {
     int* status;
 };
 hipError_t launch_integrate(const IntegrateArgs& a, hipStream_t s);
+hipError_t launch_thermostat_normals(uint64_t seed, uint64_t step0, int steps, int N, float noise_z, float4* out,
+                                     hipStream_t s);
 
 struct CellsArgs {
     float4* pos;

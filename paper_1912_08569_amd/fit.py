@@ -1,9 +1,11 @@
 """Gradient fit of lambda through a Langevin trajectory.
 
-The trajectory is BAOAB with a fixed, pre-drawn noise sequence (so it is a
-deterministic, differentiable function of lambda), the forces come from
+The trajectory is BAOAB with the engine's own thermostat noise (the normals
+``rc_md_run`` draws for the same seed, tags and steps, pre-drawn with
+``rc_thermostat_normals``), so it is a deterministic, differentiable function
+of lambda and follows the integrator of the engine; the forces come from
 ``swap_forces`` and the observable is the soft bond count per swap particle
-averaged over the steps.  Backpropagation through the trajectory uses
+(the sum of vhat over swap pairs, eq. pot) averaged over the steps.  Backpropagation through the trajectory uses
 checkpointed recomputation: only every ``segment``-th state is kept in the
 forward pass and each segment is recomputed in the backward pass, so memory
 grows with steps/segment instead of steps.
@@ -16,6 +18,7 @@ from typing import Dict, List
 import torch
 from torch.utils.checkpoint import checkpoint
 
+from . import api
 from .autograd import SwapModel, soft_bonds, swap_forces
 
 
@@ -23,7 +26,7 @@ class TrajectoryFit:
     """Loss (mean soft bonds per swap particle - target)^2 over ``steps`` BAOAB steps."""
 
     def __init__(self, model: SwapModel, x0, v0, masses, dt: float, kT: float, gamma: float, steps: int,
-                 segment: int, n_swap: int, seed: int = 0):
+                 segment: int, n_swap: int, seed: int = 0, step0: int = 0):
         self.model = model
         self.x0 = x0.detach().to(torch.float32)
         self.v0 = v0.detach().to(torch.float32)
@@ -32,9 +35,9 @@ class TrajectoryFit:
         c1 = math.exp(-gamma * dt)
         self.c1 = c1
         self.c2 = torch.sqrt((1.0 - c1 * c1) * kT * self.minv)
-        g = torch.Generator(device=self.x0.device)
-        g.manual_seed(seed)
-        self.noise = torch.randn((self.steps,) + tuple(self.x0.shape), generator=g, device=self.x0.device)
+        # x0 is in tag order: row t of step k is the noise of tag t at step step0 + k
+        xi = api.rc_thermostat_normals(seed, step0, self.steps, self.x0.shape[0], device=self.x0.device)
+        self.noise = xi[..., :3].contiguous()
         self.n_swap = int(n_swap)
 
     def _segment(self, k0: int, k1: int, theta, x, v, F):

@@ -68,3 +68,25 @@ def assert_pe(pe_gpu, ref, tol=TOL):
     e = np.where(s > 0, d / np.where(s > 0, s, 1.0), np.where(d > 0, np.inf, 0.0))
     assert e.max() <= tol, f"per-particle energy err {e.max():.3e}"
     return float(e.max())
+
+
+def vjp_scale(A_F, adj, table):
+    """Error scale of sum_m adj_m . dF_m/dtheta for theta = (eps, sigma, lambda) of each table entry.
+
+    Every sub-term of a force is a product of powers (sigma/r)^k (k <= 2n) times eps (times lambda and
+    the other factor for three-body terms), so the size of its derivative is at most 1/eps, 4 n/sigma
+    or 1/lambda times its own size; summed with |adj_m| over the particles, Sum_m |adj_m| A_F[m] times
+    that factor bounds the derivative's terms without the cancellation of random-sign adjoints."""
+    base = float(np.sum(np.linalg.norm(np.asarray(adj, dtype=np.float64)[:, :3], axis=1) * A_F))
+    nt = table.kind.shape[0]
+    out = np.zeros((nt, nt, 3))
+    for a in range(nt):
+        for b in range(nt):
+            if table.kind[a, b] == 0:
+                continue
+            n = 6 if table.kind[a, b] == 2 else int(table.n[a, b])
+            out[a, b, 0] = base / table.epsilon[a, b]
+            out[a, b, 1] = base * 4.0 * n / table.sigma[a, b]
+            lam = table.lam[a, b]
+            out[a, b, 2] = base / lam if lam > 0 else 0.0
+    return out

@@ -76,7 +76,7 @@ def step_kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1912_08569_amd", "csrc")
-    for name in ("k_forces.hip", "k_step_head.hip", "rc_internal.h", "rc_gather.h", "rc_step.h"):
+    for name in ("k_forces.hip", "rc_internal.h", "rc_gather.h", "rc_step.h"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

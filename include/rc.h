@@ -90,6 +90,8 @@ extern "C" {
 #define RC_ST_MAXPATH    2   /* largest path length since the build (float bits)   */
 #define RC_ST_FIRST_SOFT 3   /* first step whose new positions passed the soft skin */
 #define RC_ST_FIRST_HARD 4   /* first step whose force used a stale list           */
+#define RC_ST_NSWAP      5   /* swap-range entries of the last list build (sum over
+                                particles, saturating at 2^31 - 1)                 */
 #define RC_FLAG_NLIST_OVERFLOW 1
 #define RC_FLAG_REBUILD        2   /* a path length passed the soft skin threshold     */
 #define RC_FLAG_NONFINITE      4
@@ -168,16 +170,10 @@ int rc_set_gather_width(rc_ctx* ctx, int width);
  *     gives every (m, j) entry the factor (S_m - w) + (S_j - w), i.e. the
  *     triplet sum of eq. (3bp) rewritten as (S^2 - sum w^2)/2 per centre
  *     (linear in k; one float per particle of context-owned scratch).
- *   RC_FORM_HEAD: the walk form's terms, sums and order, with the loads
- *     reordered for short lists: the first slots of each list and of each
- *     swap partner's list are read before they are known to be needed, so
- *     a step waits on three rounds of memory latency instead of about eight
- *     (single systems only; a batch takes it as RC_FORM_WALK).
- * All are exact rewritings of the same energy; results differ by rounding
+ * Both are exact rewritings of the same energy; results differ by rounding
  * order only.  RC_ERR_ARG for other values.                                 */
 #define RC_FORM_WALK 0
 #define RC_FORM_SUMS 1
-#define RC_FORM_HEAD 2
 int rc_set_step_form(rc_ctx* ctx, int form);
 
 /* ---- status ---------------------------------------------------------------
@@ -500,7 +496,7 @@ typedef struct rc_md_stats {
     double kernel_ms;   /* time_kernels: their summed execution time (ms)     */
     double sums_ms;     /* time_kernels, RC_FORM_SUMS: the first passes' time */
     int32_t list_kept;  /* 1: the run continued the previous run's list       */
-    int32_t pad;
+    int32_t nswap;      /* RC_ST_NSWAP of the list in use at the end          */
 } rc_md_stats;
 
 int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,

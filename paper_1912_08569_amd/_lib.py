@@ -28,11 +28,12 @@ RC_KIND_NONE, RC_KIND_SWAP, RC_KIND_WCA = 0, 1, 2
 RC_TYPE_BITS = 4
 RC_MAX_TYPES = 16
 RC_STATUS_WORDS = 8
+RC_ST_NSWAP = 5
 RC_NOALLOC_MAX_N = 1048576
 RC_ST_FLAGS, RC_ST_KMAX, RC_ST_MAXPATH, RC_ST_FIRST_SOFT, RC_ST_FIRST_HARD = 0, 1, 2, 3, 4
 RC_FLAG_NLIST_OVERFLOW, RC_FLAG_REBUILD, RC_FLAG_NONFINITE, RC_FLAG_LOST, RC_FLAG_STALE = 1, 2, 4, 8, 16
 RC_FORCE_ACCUMULATE, RC_FORCE_GATHER, RC_FORCE_SUMS = 1, 4, 8
-RC_FORM_WALK, RC_FORM_SUMS, RC_FORM_HEAD = 0, 1, 2
+RC_FORM_WALK, RC_FORM_SUMS = 0, 1
 RC_HALF_FIRST, RC_HALF_SECOND = 0, 1
 RC_STEP_START, RC_STEP_CONT, RC_STEP_FINISH, RC_STEP_OBSERVE = 0, 1, 2, 3
 RC_INTEGRATOR_NVE, RC_INTEGRATOR_LANGEVIN = 0, 1
@@ -88,7 +89,7 @@ class MdStats(ctypes.Structure):
                 ("rollbacks", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("log_rows", ctypes.c_int64), ("k_needed", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
-                ("sums_ms", ctypes.c_double), ("list_kept", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("sums_ms", ctypes.c_double), ("list_kept", ctypes.c_int32), ("nswap", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p

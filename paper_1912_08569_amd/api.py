@@ -139,7 +139,7 @@ class Context:
         check(L.load().rc_set_table(self.handle, arr), self.handle)
 
     def set_step_form(self, form: str):
-        f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS, "head": L.RC_FORM_HEAD}[form]
+        f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS}[form]
         check(L.load().rc_set_step_form(self.handle, f), self.handle)
         self.step_form = form
 
@@ -388,7 +388,7 @@ class BatchContext:
         check(L.load().rc_batch_set_gather_width(self.handle, int(width)), batch=self.handle)
 
     def set_step_form(self, form: str):
-        f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS, "head": L.RC_FORM_HEAD}[form]
+        f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS}[form]
         check(L.load().rc_batch_set_step_form(self.handle, f), batch=self.handle)
 
     def close(self):

@@ -434,18 +434,29 @@ __device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, c
     return total;
 }
 
-// block maximum of the list length (no same-address atomics per wave)
-__device__ __forceinline__ void block_max_store(int cnt, int* __restrict__ out) {
-    __shared__ int s_m[kBlock / kWave];
-    int m = cnt;
+// block maximum of the list length and block sum of the swap-range lengths
+// (no same-address atomics per wave): out[0] and out[nb] of the block's slot
+__device__ __forceinline__ void block_max_store(int cnt, int ns, int* __restrict__ out, int nb) {
+    __shared__ int s_m[kBlock / kWave], s_n[kBlock / kWave];
+    int m = cnt, t_ns = ns;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) s_m[threadIdx.x / kWave] = m;
+    for (int o = 32; o > 0; o >>= 1) {
+        m = max(m, __shfl_xor(m, o, kWave));
+        t_ns += __shfl_xor(t_ns, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        s_m[threadIdx.x / kWave] = m;
+        s_n[threadIdx.x / kWave] = t_ns;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) t = max(t, s_m[w]);
-        *out = t;
+        int t = 0, u = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            t = max(t, s_m[w]);
+            u += s_n[w];
+        }
+        out[0] = t;
+        out[nb] = u;
     }
 }
 
@@ -472,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(NlistArgs a) {
         if (a.vel) a.vel[i].w = 0.0f;
     }
     if (a.pl_j) pack_wave_lists(i, i < a.N, packed, a.nlist, a.k_max, a.N, a.pl_j, a.pl_o);
-    block_max_store(total, a.block_max + blockIdx.x);
+    block_max_store(total, nn_swap(packed), a.block_max + blockIdx.x, nb);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_list(const int* __restrict__ nlist, const int* __restrict__ nn,
@@ -510,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
         if (a.vel) a.vel[i].w = 0.0f;
     }
     if (a.pl_j) pack_wave_lists(i, i < a.N, packed, a.nlist, a.k_max, a.N, a.pl_j, a.pl_o);
-    block_max_store(total, a.block_max + blockIdx.x);
+    block_max_store(total, nn_swap(packed), a.block_max + blockIdx.x, gridDim.x);
 }
 
 // one block: fold the per-block maxima into the status word
@@ -521,12 +532,21 @@ __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
 __global__ __launch_bounds__(1024) void k_nlist_status(const int* __restrict__ block_max, int nb, int k_max,
                                                       int* __restrict__ status, int fresh) {
     __shared__ int red[1024];
+    __shared__ long long red_ns[1024];
     int m = 0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) m = max(m, block_max[b]);
+    long long t_ns = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        m = max(m, block_max[b]);
+        t_ns += block_max[nb + b];
+    }
     red[threadIdx.x] = m;
+    red_ns[threadIdx.x] = t_ns;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w) {
+            red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+            red_ns[threadIdx.x] += red_ns[threadIdx.x + w];
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -541,6 +561,7 @@ __global__ __launch_bounds__(1024) void k_nlist_status(const int* __restrict__ b
             status[RC_ST_KMAX] = max(status[RC_ST_KMAX], red[0]);
             status[RC_ST_FLAGS] |= ovf;
         }
+        status[RC_ST_NSWAP] = (int)min(red_ns[0], (long long)0x7fffffff);   // the latest list's
     }
 }
 

@@ -351,7 +351,6 @@ static const void* step_fn_form(bool ev, int width) {
 
 template <bool BATCH>
 static const void* step_fn(bool ev, int width, int form) {
-    if (!BATCH && form == RC_FORM_HEAD) return step_head_fn(ev);
     return form == RC_FORM_SUMS ? step_fn_form<BATCH, true>(ev, width) : step_fn_form<BATCH, false>(ev, width);
 }
 

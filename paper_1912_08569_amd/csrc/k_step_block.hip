@@ -83,7 +83,7 @@ static const void* block_fn() {
 // Whether a system fits: particle count, form and the LDS the kernel needs
 // (its static gather slices plus the dynamic part) within one workgroup.
 bool step_block_fits(int N, int nt, int form) {
-    if (N < 1 || N > kBlockMaxN || form == RC_FORM_HEAD) return false;
+    if (N < 1 || N > kBlockMaxN) return false;
     const void* fn = form == RC_FORM_SUMS ? block_fn<true>() : block_fn<false>();
     hipFuncAttributes at{};
     if (hipFuncGetAttributes(&at, fn) != hipSuccess) return false;

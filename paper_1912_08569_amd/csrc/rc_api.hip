@@ -253,7 +253,7 @@ int rc_set_gather_width(rc_ctx* c, int width) {
 
 int rc_set_step_form(rc_ctx* c, int form) {
     if (!c) return RC_ERR_ARG;
-    if (form != RC_FORM_WALK && form != RC_FORM_SUMS && form != RC_FORM_HEAD)
+    if (form != RC_FORM_WALK && form != RC_FORM_SUMS)
         return fail(c, RC_ERR_ARG, "unknown step form %d", form);
     c->step_form = form;
     return RC_OK;

@@ -223,7 +223,7 @@ int rc_batch_set_gather_width(rc_batch* b, int width) {
 
 int rc_batch_set_step_form(rc_batch* b, int form) {
     if (!b) return RC_ERR_ARG;
-    if (form != RC_FORM_WALK && form != RC_FORM_SUMS && form != RC_FORM_HEAD)
+    if (form != RC_FORM_WALK && form != RC_FORM_SUMS)
         return fail(&b->c, RC_ERR_ARG, "unknown step form %d", form);
     b->c.step_form = form;
     return RC_OK;

@@ -60,7 +60,7 @@ struct rc_ctx {
     int* d_blk = nullptr;               // per-block status slots of the step kernel
     int blk_cap = 0;                    // slots allocated (blocks)
     int gather_width = 2;               // flattened list entries per lane and pass of the step kernel
-    int step_form = RC_FORM_WALK;       // RC_FORM_WALK | RC_FORM_SUMS | RC_FORM_HEAD
+    int step_form = RC_FORM_WALK;       // RC_FORM_WALK | RC_FORM_SUMS
     float* d_ssum = nullptr;            // per-particle switching sums of the sums form
     size_t ssum_cap = 0;                // floats allocated
     double* d_hsum = nullptr;           // per-particle (S, dS) of the Hessian-vector product

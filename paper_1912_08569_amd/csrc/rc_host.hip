@@ -71,7 +71,7 @@ CellsLayout cells_layout(int N, uint32_t nkeys) {
     l.rank = o; o = al(o + 4 * (size_t)N);
     l.order = o; o = al(o + 4 * (size_t)N);
     l.bsums = o; o = al(o + 4 * (nk / kScanTile + 2));
-    l.bmax = o; o = al(o + 4 * ((size_t)N / kBlock + 2));
+    l.bmax = o; o = al(o + 8 * ((size_t)N / kBlock + 2));   // per block: largest list, then swap-range sums
     l.tpos = o; o = al(o + 16 * (size_t)N);
     l.tvel = o; o = al(o + 16 * (size_t)N);
     l.timage = o; o = al(o + 16 * (size_t)N);
@@ -468,6 +468,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         }
         if (stats) {
             st.flags = hst[RC_ST_FLAGS];
+            st.nswap = hst[RC_ST_NSWAP];
             st.steps_done = s_cur > step0 ? (int64_t)(s_cur - step0) : 0;
             st.log_rows = row;
             *stats = st;
@@ -751,8 +752,8 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if (logging) ++row;
     }
     if (cur != 0) HIP_TRY(c, hipMemcpyAsync(buf->pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(hst, buf->status, sizeof hst, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
+    // the status read waits for all of the run's work (pinned copy and an event, no blocking sync)
+    if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
     if (timing && (r = tk_collect())) return finish(r);
     // what the next run needs to continue on this list
     c->md.valid = can_roll;

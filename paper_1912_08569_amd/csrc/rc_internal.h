@@ -403,7 +403,7 @@ struct StepArgs {
     const int* chunk_rep;      // [N / 64] replica of each 64-slot chunk
     const uint64_t* seeds;     // [R] thermostat keys
     int width;                 // gather width of the non-logging steps: 1, 2 or 4 (read by the launcher)
-    int form;                  // RC_FORM_WALK, RC_FORM_SUMS or RC_FORM_HEAD (read by the launcher)
+    int form;                  // RC_FORM_WALK or RC_FORM_SUMS (read by the launcher)
     float* ssum;               // [N] per-particle switching sums (RC_FORM_SUMS)
     // packed list (single systems): per wavefront the flattened entries of its
     // 64 particles, neighbour index and owner lane (pack_wave_lists)
@@ -428,7 +428,6 @@ bool step_block_fits(int N, int nt, int form);
 hipError_t launch_step_block(const StepArgs& a, float4* pos_final, unsigned long long* step_base, int G,
                              hipStream_t s);
 // the head-form step kernel (same launch shape and arguments as k_step)
-const void* step_head_fn(bool ev);
 void step_kernel_info(bool ev, int width, int form, const void** fn);
 hipError_t launch_step_batch(const StepArgs& a, bool ev, hipStream_t s);
 void step_batch_kernel_info(int width, int form, const void** fn);

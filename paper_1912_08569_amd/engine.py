@@ -88,7 +88,6 @@ class System:
             self.ev_fene = torch.zeros(7, dtype=torch.float64, device=dev)
         self.built = False
         self._continues = False     # the state is what the last run left (its list may be kept)
-        self._form_stale = True     # the auto step form must be re-read from the list
         self._log = None            # log rows of the last run (ev rows, then bond counts)
 
     @classmethod
@@ -119,8 +118,7 @@ class System:
             self.built = True
             self._continues = False
             if self.step_form == "auto":
-                self.ctx.set_step_form(self.auto_step_form())
-                self._form_stale = False
+                self.ctx.set_step_form(self._form_for(int(st[rcl.RC_ST_NSWAP])))
             return st[rcl.RC_ST_KMAX]
         raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
 
@@ -225,9 +223,9 @@ class System:
         self.ctx.set_gather_width(width)
 
     def set_step_form(self, form: str):
-        """"walk" (one pass, partner sums by list walks), "sums" (two passes), "head" (the walk form with
-        list heads read ahead, for short lists) or "auto" (walk or sums by the mean swap-range length, chosen at
-        every build of the list from Python and at the start of every run): speed only."""
+        """"walk" (one pass, partner sums by list walks), "sums" (two passes) or "auto" (walk or sums by
+        the mean swap-range length of the list, chosen at every build from the status word it writes and
+        after every run that rebuilt): speed only."""
         self.step_form = form
         if form == "auto":
             if self.built:
@@ -238,6 +236,11 @@ class System:
     def auto_step_form(self) -> str:
         """The form "auto" picks for the current list: "sums" or "walk"."""
         return "sums" if self.mean_swap_length() >= self.AUTO_SUMS_KSWAP else "walk"
+
+    def _form_for(self, nswap: int) -> str:
+        """The auto form for a list whose swap ranges hold nswap entries in all (the status word the
+        list build writes, so no device work is needed to choose)."""
+        return "sums" if nswap >= self.AUTO_SUMS_KSWAP * self.N else "walk"
 
     def mean_swap_length(self) -> float:
         """Mean length of the swap range of the last list build."""
@@ -280,12 +283,8 @@ class System:
         directly calls invalidate() first.
         time_kernels: launch every step directly with events around its kernels; the stats then
         hold the summed kernel time (kernel_ms over kernel_launches)."""
-        if self.step_form == "auto":
-            if not self.built:
-                self.build()    # picks the form from the new list
-            elif self._form_stale:   # from the list the last run's builds left
-                self.ctx.set_step_form(self.auto_step_form())
-                self._form_stale = False
+        if self.step_form == "auto" and not self.built:
+            self.build()    # picks the form from the new list
         rows = (n_steps // log_period + 2) if log_period > 0 else 1
         if self._log is None or self._log.shape[0] < rows * 14:
             self._log = torch.zeros(max(rows, 64) * 14, dtype=torch.float64, device=self.device)
@@ -312,8 +311,8 @@ class System:
             raise RcError(rcl.RC_ERR_NLIST_OVERFLOW, "could not size the neighbour list")
         self.built = True
         self._continues = True
-        if st.rebuilds > 0:
-            self._form_stale = True
+        if self.step_form == "auto" and st.rebuilds > 0:   # the next run takes the form of the last list
+            self.ctx.set_step_form(self._form_for(st.nswap))
         n = int(st.log_rows)
         host = self._log[:rows * 14].cpu()
         ev = host[:rows * 13].view(rows, 13)[:n].numpy()

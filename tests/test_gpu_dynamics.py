@@ -90,47 +90,6 @@ def test_fused_step_sums_form_matches_oracle(lam):
     _one_step_check(s, "nve", 0.002, 0.0, 0.0, 2010, 78, form="walk")
 
 
-@pytest.mark.parametrize("kind", ["langevin", "nve"])
-def test_fused_step_head_form_matches_oracle(kind):
-    # short lists (the mixture: list heads cover almost every particle) and long lists (dense reactive
-    # system: the slots beyond the heads and partners with more than two swap neighbours are walked)
-    s = W.assembly_mixture(N=20000, lam=1.0, seed=1004, kT=0.05)
-    _one_step_check(s, kind, 0.001, 0.05, 1.0, 2004, 99, form="head")
-    s = W.small_reactive(N=3000, density=0.5, seed=1011, min_dist=0.85, table=W.swap_table_single(lam=0.6))
-    _one_step_check(s, kind, 0.002, 0.1, 1.0, 2011, 7, form="head")
-
-
-@pytest.mark.parametrize("case", ["mixture", "dense"])
-def test_head_form_step_equals_walk_form(case):
-    # the head form reorders loads, not the terms: one step from the same state agrees with the walk form
-    # to rounding (bitwise where the compiler contracts both forms alike), and so do the logged sums
-    if case == "mixture":
-        s = W.assembly_mixture(N=30000, lam=1.0, seed=61, kT=0.05)
-        cfg_kw = dict(dt=0.001, kT=0.05, gamma=1.0, seed=3)
-    else:
-        s = W.small_reactive(N=3000, density=0.5, seed=62, min_dist=0.85, table=W.swap_table_single(lam=0.6))
-        cfg_kw = dict(dt=0.002, kT=0.1, gamma=1.0, seed=3)
-    out = []
-    for form in ("walk", "head"):
-        S = _system(s)
-        S.set_step_form(form)
-        S.build()
-        if form == "walk":
-            x0, _, _, ty = S.state_by_tag()
-        r = S.run(1, S.integrator(**cfg_kw), step0=11, log_period=1, use_graph=False)
-        out.append((S.state_by_tag(), r.ev, r.bonds))
-    (sa, eva, ba), (sb, evb, bb) = out
-    xa, va, ia, _ = sa
-    xb, vb, ib, _ = sb
-    assert np.array_equal(ia, ib) and np.array_equal(ba, bb)
-    # forces agree to rounding of their term sums: |dv| <= dt * 2e-6 * (per-particle force scale) / m
-    a_f = swap_ref.evaluate(x0, ty, s.L, s.table)["A_F"] / s.mass[ty]
-    vtol = 2e-6 * cfg_kw["dt"] * a_f[:, None] + 1e-6 * np.abs(va) + 1e-8
-    assert np.all(np.abs(va - vb) <= vtol), f"{np.max(np.abs(va - vb) / vtol):.3g}"
-    assert np.all(np.abs(xa - xb) <= 2 * _ulp32(xa) + cfg_kw["dt"] * vtol)
-    assert np.allclose(eva, evb, rtol=1e-6, atol=1e-6 * np.abs(eva).max())
-
-
 def test_sums_form_graph_and_direct_launches_agree_bitwise():
     s = W.small_reactive(N=4000, density=0.4, seed=52, table=W.swap_table_single(lam=0.5), kT=0.1)
     A, B = _system(s), _system(s)

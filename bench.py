@@ -528,9 +528,17 @@ def main():
     if a.profile_kernel:
         # counter runs: nothing but the step launches of a driver run, each launched directly
         rk = S.run(a.kernel_steps, cfg, step0=a.warmup, log_period=a.log_period, time_kernels=True)
-        print(json.dumps({"kernel": "k_step", "N": a.N, "launches": int(rk.stats.kernel_launches),
-                          "kernel_us": rk.stats.kernel_ms / max(1, rk.stats.kernel_launches) * 1e3,
-                          "mean_list_length": S.mean_list_length()}), flush=True)
+        out = {"kernel": "k_step", "N": a.N, "launches": int(rk.stats.kernel_launches),
+               "kernel_us": rk.stats.kernel_ms / max(1, rk.stats.kernel_launches) * 1e3,
+               "mean_list_length": S.mean_list_length(), "step_kernel_source_hash": step_kernel_source_hash()}
+        if a.copy_calibration:   # a plain 256 MiB device copy: the scale of the byte counters
+            src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            out["copy_calibration_bytes"] = int(src.numel() * 4)
+        print(json.dumps(out), flush=True)
         return
     # ---- timed region: exactly `steps` steps ------------------------------------------
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -22,7 +22,9 @@
  * Memory.  Every array argument is caller-owned DEVICE memory on the device
  * that was current at rc_create, unless the comment says "host".  The library
  * allocates device memory only inside an rc_ctx / rc_batch (parameter table,
- * reduction scratch, status word); it never frees caller memory.
+ * FP64 reduction rows, per-block status slots: O(ntypes^2 + N/64)) and, unless
+ * the caller attaches a workspace (rc_set_workspace), its large scratch too;
+ * it never frees caller memory.
  *
  * Streams.  Every launch is asynchronous on the caller's hipStream_t (passed
  * as void*; NULL = the null stream).  Functions that return a host value
@@ -175,6 +177,29 @@ int rc_set_gather_width(rc_ctx* ctx, int width);
 #define RC_FORM_WALK 0
 #define RC_FORM_SUMS 1
 int rc_set_step_form(rc_ctx* ctx, int form);
+
+/* ---- caller-owned workspace ---------------------------------------------------
+ * The context's large scratch -- the packed copy of the list that the fused
+ * step reads (5 bytes per slot, ceil(N/64) * 64 * k_max slots), the switching
+ * sums of the two-pass form (4 bytes per particle) and the first-pass sums of
+ * the Hessian-vector products (16 bytes per particle and tangent vector) --
+ * can live in caller-owned device memory:
+ * rc_workspace_bytes: the size for N particles, lists of k_max slots and up to
+ *   nvec tangent vectors per rc_force_hvp_batch call (host out).
+ * rc_set_workspace: attach ws (device, 256-byte aligned, at least that many
+ *   bytes; the caller keeps it alive and does not touch it while attached;
+ *   NULL detaches).  Synchronises the device once; the context's own copies of
+ *   these buffers are freed.  While a workspace is attached the context never
+ *   allocates them: a call that needs more (a larger N or k_max, more vectors)
+ *   returns RC_ERR_WORKSPACE and launches nothing.  Without one, the context
+ *   allocates them itself on first use (growing them synchronises the device).
+ * rc_ctx_device_bytes: device memory the context itself holds (host out): the
+ *   coefficient table, the FP64 reduction rows and per-block status slots
+ *   (O(ntypes^2 + N/64)), plus the large scratch above when no workspace is
+ *   attached.                                                                */
+int rc_workspace_bytes(const rc_ctx* ctx, int N, int k_max, int nvec, size_t* bytes /* host */);
+int rc_set_workspace(rc_ctx* ctx, void* ws, size_t bytes, int N, int k_max, int nvec);
+int rc_ctx_device_bytes(const rc_ctx* ctx, size_t* bytes /* host */);
 
 /* ---- status ---------------------------------------------------------------
  * rc_clear_status: zero a status word (async).  rc_read_status: synchronise
@@ -612,7 +637,9 @@ int rc_soft_bonds(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn
  *   batch happens when any replica needs one.  Synchronises the stream.
  * rc_batch_build_nlist also writes the packed copy of the lists that the
  *   batch's fused step reads (as rc_build_nlist does for one system).
- * rc_batch_time_fused_steps: as rc_time_fused_steps for the batch.          */
+ * rc_batch_time_fused_steps: as rc_time_fused_steps for the batch.
+ * rc_batch_workspace_bytes / rc_batch_set_workspace: as rc_workspace_bytes /
+ *   rc_set_workspace for the batch's n_slots slots (no tangent vectors).    */
 typedef struct rc_batch rc_batch;
 
 int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tables /* host */,
@@ -622,6 +649,8 @@ const char* rc_batch_last_error(const rc_batch* b);
 int rc_batch_layout(const rc_batch* b, int* n_slots /* host */, int* offsets /* host [R+1] | NULL */);
 int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds /* host [R] */);
 int rc_batch_set_gather_width(rc_batch* b, int width);
+int rc_batch_workspace_bytes(const rc_batch* b, int k_max, size_t* bytes /* host */);
+int rc_batch_set_workspace(rc_batch* b, void* ws, size_t bytes, int k_max);
 int rc_batch_set_step_form(rc_batch* b, int form);
 int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes /* host */);
 int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,

@@ -114,6 +114,11 @@ _SIGS = {
     "rc_build_nlist": ([_VP, _VP, _VP, _I, Box, _VP, ctypes.c_size_t, _I, _VP, _VP, _VP, _VP], _I),
     "rc_compute_forces": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
     "rc_thermostat_normals": ([_U64, _U64, _I, _I, _I, _VP, _VP], _I),
+    "rc_workspace_bytes": ([_VP, _I, _I, _I, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "rc_set_workspace": ([_VP, _VP, ctypes.c_size_t, _I, _I, _I], _I),
+    "rc_ctx_device_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "rc_batch_workspace_bytes": ([_VP, _I, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "rc_batch_set_workspace": ([_VP, _VP, ctypes.c_size_t, _I], _I),
     "rc_compute_forces_noalloc": ([_VP, _VP, _VP, _VP, _I, _I, Box, _VP, _VP, _U, _VP, _VP], _I),
     "rc_integrate_step": ([_VP, _VP, _VP, _VP, _VP, _I, Box, ctypes.POINTER(Integrator), _U64, _I,
                            _VP, _VP, _VP], _I),

@@ -19,7 +19,8 @@ from ._lib import RcError, check
 __all__ = [
     "Context", "RcError", "box", "integrator", "pack_positions", "unpack_positions",
     "rc_cells_workspace_bytes", "rc_build_cells", "rc_build_nlist", "rc_compute_forces",
-    "rc_compute_forces_noalloc", "rc_thermostat_normals",
+    "rc_compute_forces_noalloc", "rc_thermostat_normals", "rc_workspace_bytes", "rc_set_workspace",
+    "rc_ctx_device_bytes", "rc_batch_workspace_bytes", "rc_batch_set_workspace",
     "rc_integrate_step", "rc_step_fused", "rc_bond_count", "rc_md_run", "rc_force_hvp", "rc_force_hvp_batch", "rc_partner_counts", "rc_stress_autocorrelation",
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
     "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
@@ -131,6 +132,15 @@ class Context:
     def set_gather_width(self, width: int):
         check(L.load().rc_set_gather_width(self.handle, int(width)), self.handle)
 
+    def workspace_bytes(self, N: int, k_max: int, nvec: int = 1) -> int:
+        return rc_workspace_bytes(self, N, k_max, nvec)
+
+    def set_workspace(self, ws: Optional[torch.Tensor], N: int = 0, k_max: int = 0, nvec: int = 0):
+        rc_set_workspace(self, ws, N, k_max, nvec)
+
+    def device_bytes(self) -> int:
+        return rc_ctx_device_bytes(self)
+
     def set_table(self, table):
         """New eps, sigma, lambda (same kinds, exponents and cutoffs)."""
         nt = self.ntypes
@@ -211,6 +221,35 @@ def rc_compute_forces_noalloc(ctx: Context, pos, nlist, nn, bx, force, ev=None, 
     check(L.load().rc_compute_forces_noalloc(ctx.handle, _ptr(pos), _ptr(nlist), _ptr(nn), _kmax(nlist, N), N, bx,
                                              _ptr(force), _ptr(ev), int(flags), _ptr(status), _stream(stream)),
           ctx.handle)
+
+
+def rc_workspace_bytes(ctx: "Context", N, k_max, nvec=1) -> int:
+    out = ctypes.c_size_t()
+    check(L.load().rc_workspace_bytes(ctx.handle, int(N), int(k_max), int(nvec), ctypes.byref(out)), ctx.handle)
+    return int(out.value)
+
+
+def rc_set_workspace(ctx: "Context", ws: Optional[torch.Tensor], N=0, k_max=0, nvec=0):
+    """Attach a caller-owned device workspace (a uint8 tensor of rc_workspace_bytes) or detach (None)."""
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+    check(L.load().rc_set_workspace(ctx.handle, _ptr(ws), nbytes, int(N), int(k_max), int(nvec)), ctx.handle)
+
+
+def rc_ctx_device_bytes(ctx: "Context") -> int:
+    out = ctypes.c_size_t()
+    check(L.load().rc_ctx_device_bytes(ctx.handle, ctypes.byref(out)), ctx.handle)
+    return int(out.value)
+
+
+def rc_batch_workspace_bytes(bc: "BatchContext", k_max) -> int:
+    out = ctypes.c_size_t()
+    check(L.load().rc_batch_workspace_bytes(bc.handle, int(k_max), ctypes.byref(out)), batch=bc.handle)
+    return int(out.value)
+
+
+def rc_batch_set_workspace(bc: "BatchContext", ws: Optional[torch.Tensor], k_max=0):
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+    check(L.load().rc_batch_set_workspace(bc.handle, _ptr(ws), nbytes, int(k_max)), batch=bc.handle)
 
 
 def rc_thermostat_normals(seed, step0, steps, N, dim=3, device="cuda", stream=None) -> torch.Tensor:

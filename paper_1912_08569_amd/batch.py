@@ -87,6 +87,7 @@ class Batch:
             self.bc.set_seeds(seeds)
         self.built = False
         self._continues = False     # the state is what the last run left (its list may be kept)
+        self._attach_workspace()
 
     @classmethod
     def from_workloads(cls, systems, **kw):
@@ -96,6 +97,15 @@ class Batch:
     def _grow(self, k_needed: int):
         self.k_max = int(max(k_needed + 4, int(self.k_max * 1.5)))
         self.nlist = torch.zeros(self.k_max * self.n_slots, dtype=torch.int32, device=self.device)
+        self._attach_workspace()
+
+    def _attach_workspace(self):
+        """The batch's large scratch (packed lists, switching sums) in a torch-owned buffer."""
+        self.work = None
+        api.rc_batch_set_workspace(self.bc, None)
+        self.work = torch.empty(api.rc_batch_workspace_bytes(self.bc, self.k_max), dtype=torch.uint8,
+                                device=self.device)
+        api.rc_batch_set_workspace(self.bc, self.work, self.k_max)
 
     def build(self):
         """Bin, re-order and build every replica's list (grows k_max on overflow)."""

@@ -244,6 +244,23 @@ int rc_set_table(rc_ctx* c, const rc_pair_coeff* table) {
     return RC_OK;
 }
 
+int rc_workspace_bytes(const rc_ctx* c, int N, int k_max, int nvec, size_t* bytes) {
+    if (!c || !bytes || N < 1 || k_max < 1 || k_max > 512 || nvec < 0) return RC_ERR_ARG;
+    *bytes = ws_layout(plist_entries(N, k_max), (size_t)N, (size_t)N * (size_t)nvec).total;
+    return RC_OK;
+}
+
+int rc_set_workspace(rc_ctx* c, void* ws, size_t bytes, int N, int k_max, int nvec) {
+    if (!c) return RC_ERR_ARG;
+    return set_workspace(c, ws, bytes, N, k_max, nvec);
+}
+
+int rc_ctx_device_bytes(const rc_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return RC_ERR_ARG;
+    *bytes = ctx_device_bytes(c);
+    return RC_OK;
+}
+
 int rc_set_gather_width(rc_ctx* c, int width) {
     if (!c) return RC_ERR_ARG;
     if (width != 1 && width != 2 && width != 4) return fail(c, RC_ERR_ARG, "gather width must be 1, 2 or 4");

@@ -214,6 +214,16 @@ int rc_batch_set_seeds(rc_batch* b, const uint64_t* seeds) {
     return RC_OK;
 }
 
+int rc_batch_workspace_bytes(const rc_batch* b, int k_max, size_t* bytes) {
+    if (!b) return RC_ERR_ARG;
+    return rc_workspace_bytes(&b->c, b->n_slots, k_max, 0, bytes);
+}
+
+int rc_batch_set_workspace(rc_batch* b, void* ws, size_t bytes, int k_max) {
+    if (!b) return RC_ERR_ARG;
+    return set_workspace(&b->c, ws, bytes, b->n_slots, k_max, 0);
+}
+
 int rc_batch_set_gather_width(rc_batch* b, int width) {
     if (!b) return RC_ERR_ARG;
     if (width != 1 && width != 2 && width != 4) return fail(&b->c, RC_ERR_ARG, "gather width must be 1, 2 or 4");

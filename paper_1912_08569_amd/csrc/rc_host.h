@@ -81,6 +81,9 @@ struct rc_ctx {
     GraphCache gc;
     void* noalloc_scratch = nullptr;    // device address of the fixed scratch on this device
     MdRecord md;                        // the last run, for keep_list
+    // caller-owned workspace (rc_set_workspace): when attached, the packed list, the switching sums
+    // and the HVP sums live there, and the ensure_* functions never allocate them
+    void* ws_user = nullptr;
     std::vector<hipEvent_t> tk_events;  // event pairs of time_kernels
     std::vector<int> tk_kind;           // per pair: 0 step kernel, 1 first pass of the sums form
     std::string err;
@@ -110,6 +113,16 @@ struct CellsLayout {
 CellsLayout cells_layout(int N, uint32_t nkeys);
 
 int ensure_part(rc_ctx* c, size_t bytes);
+// Layout of a caller-owned workspace holding a packed list of plist entries,
+// n_ssum switching sums and n_hsum HVP sums (offsets and total, 256-byte aligned).
+struct WsLayout {
+    size_t pl_j, pl_o, ssum, hsum, total;
+};
+WsLayout ws_layout(size_t plist, size_t n_ssum, size_t n_hsum);
+size_t plist_entries(int N, int k_max);   // ceil(N / 64) * 64 * k_max
+// attach (ws != NULL) or detach a caller-owned workspace sized for (N, k_max, nvec)
+int set_workspace(rc_ctx* c, void* ws, size_t bytes, int N, int k_max, int nvec);
+size_t ctx_device_bytes(const rc_ctx* c);
 int ensure_ssum(rc_ctx* c, size_t n);   // d_ssum for n particles (drops graphs when it moves)
 int ensure_hsum(rc_ctx* c, size_t n);   // d_hsum for n particles
 // packed-list arrays for N particles and k_max slots (drops graphs when they move)

@@ -90,8 +90,68 @@ int ensure_part(rc_ctx* c, size_t bytes) {
     return RC_OK;
 }
 
+size_t plist_entries(int N, int k_max) { return (size_t)((N + kWave - 1) / kWave) * kWave * (size_t)k_max; }
+
+WsLayout ws_layout(size_t plist, size_t n_ssum, size_t n_hsum) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    WsLayout l{};
+    size_t o = 0;
+    l.pl_j = o; o = al(o + sizeof(int) * plist);
+    l.pl_o = o; o = al(o + plist);
+    l.ssum = o; o = al(o + sizeof(float) * n_ssum);
+    l.hsum = o; o = al(o + 2 * sizeof(double) * n_hsum);
+    l.total = o;
+    return l;
+}
+
+int set_workspace(rc_ctx* c, void* ws, size_t bytes, int N, int k_max, int nvec) {
+    if (ws && (N < 1 || k_max < 1 || k_max > 512 || nvec < 0))
+        return fail(c, RC_ERR_ARG, "workspace sizes: N >= 1, 1 <= k_max <= 512, nvec >= 0");
+    const size_t E = ws ? plist_entries(N, k_max) : 0;
+    const WsLayout l = ws_layout(E, ws ? (size_t)N : 0, ws ? (size_t)N * (size_t)nvec : 0);
+    if (ws && bytes < l.total) return fail(c, RC_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", l.total, bytes);
+    if (ws && (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(c, RC_ERR_ARG, "workspace not 256-byte aligned");
+    drop_graphs(c);
+    c->md.valid = false;   // the packed copy of the list moves
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (!c->ws_user) {     // the context's own buffers go
+        if (c->d_pl_j) (void)hipFree(c->d_pl_j);
+        if (c->d_pl_o) (void)hipFree(c->d_pl_o);
+        if (c->d_ssum) (void)hipFree(c->d_ssum);
+        if (c->d_hsum) (void)hipFree(c->d_hsum);
+    }
+    c->d_pl_j = nullptr;
+    c->d_pl_o = nullptr;
+    c->d_ssum = nullptr;
+    c->d_hsum = nullptr;
+    c->pl_cap = c->ssum_cap = c->hsum_cap = 0;
+    c->pl_nlist = nullptr;
+    c->ws_user = ws;
+    if (ws) {
+        char* w = static_cast<char*>(ws);
+        c->d_pl_j = reinterpret_cast<int*>(w + l.pl_j);
+        c->d_pl_o = reinterpret_cast<unsigned char*>(w + l.pl_o);
+        c->d_ssum = reinterpret_cast<float*>(w + l.ssum);
+        c->d_hsum = reinterpret_cast<double*>(w + l.hsum);
+        c->pl_cap = E;
+        c->ssum_cap = (size_t)N;
+        c->hsum_cap = (size_t)N * (size_t)nvec;
+    }
+    return RC_OK;
+}
+
+size_t ctx_device_bytes(const rc_ctx* c) {
+    size_t b = sizeof(DevEntry) * (size_t)c->nt * (size_t)c->nt + sizeof(unsigned long long) + c->part_bytes +
+               sizeof(int) * 3 * (size_t)c->blk_cap;
+    if (!c->ws_user) b += 5 * c->pl_cap + sizeof(float) * c->ssum_cap + 2 * sizeof(double) * c->hsum_cap;
+    return b;
+}
+
 int ensure_ssum(rc_ctx* c, size_t n) {
     if (c->ssum_cap >= n) return RC_OK;
+    if (c->ws_user)
+        return fail(c, RC_ERR_WORKSPACE, "the attached workspace holds switching sums of %zu particles, %zu needed",
+                    c->ssum_cap, n);
     drop_graphs(c);
     HIP_TRY(c, hipDeviceSynchronize());
     if (c->d_ssum) (void)hipFree(c->d_ssum);
@@ -118,8 +178,11 @@ int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s) {
 }
 
 int ensure_plist(rc_ctx* c, int N, int k_max) {
-    const size_t n = (size_t)((N + kWave - 1) / kWave) * kWave * (size_t)k_max;
+    const size_t n = plist_entries(N, k_max);
     if (c->pl_cap >= n) return RC_OK;
+    if (c->ws_user)
+        return fail(c, RC_ERR_WORKSPACE, "the attached workspace holds a packed list of %zu entries, %zu needed",
+                    c->pl_cap, n);
     drop_graphs(c);
     HIP_TRY(c, hipDeviceSynchronize());
     if (c->d_pl_j) (void)hipFree(c->d_pl_j);
@@ -148,6 +211,9 @@ int packed_list_for(rc_ctx* c, const int* nlist, const int* nn, int k_max, int N
 
 int ensure_hsum(rc_ctx* c, size_t n) {
     if (c->hsum_cap >= n) return RC_OK;
+    if (c->ws_user)
+        return fail(c, RC_ERR_WORKSPACE, "the attached workspace holds HVP sums for %zu particle-vectors, %zu needed",
+                    c->hsum_cap, n);
     HIP_TRY(c, hipDeviceSynchronize());
     if (c->d_hsum) (void)hipFree(c->d_hsum);
     c->d_hsum = nullptr;
@@ -164,8 +230,8 @@ void free_ctx_buffers(rc_ctx* c) {
     c->tk_events.clear();
     c->tk_kind.clear();
     c->md.valid = false;
-    if (c->d_pl_j) (void)hipFree(c->d_pl_j);
-    if (c->d_pl_o) (void)hipFree(c->d_pl_o);
+    if (c->d_pl_j && !c->ws_user) (void)hipFree(c->d_pl_j);
+    if (c->d_pl_o && !c->ws_user) (void)hipFree(c->d_pl_o);
     c->d_pl_j = nullptr;
     c->d_pl_o = nullptr;
     c->pl_cap = 0;
@@ -178,8 +244,9 @@ void free_ctx_buffers(rc_ctx* c) {
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_step_base) (void)hipFree(c->d_step_base);
     if (c->d_blk) (void)hipFree(c->d_blk);
-    if (c->d_ssum) (void)hipFree(c->d_ssum);
-    if (c->d_hsum) (void)hipFree(c->d_hsum);
+    if (c->d_ssum && !c->ws_user) (void)hipFree(c->d_ssum);
+    if (c->d_hsum && !c->ws_user) (void)hipFree(c->d_hsum);
+    c->ws_user = nullptr;
     c->d_hsum = nullptr;
     c->hsum_cap = 0;
     c->d_tab = nullptr;

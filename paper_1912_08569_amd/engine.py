@@ -89,6 +89,16 @@ class System:
         self.built = False
         self._continues = False     # the state is what the last run left (its list may be kept)
         self._log = None            # log rows of the last run (ev rows, then bond counts)
+        # the context's large scratch (packed list, switching sums, HVP sums) in a torch-owned buffer
+        self._attach_workspace(nvec=1)
+
+    def _attach_workspace(self, nvec: int):
+        self._ws_nvec = int(nvec)
+        nb = self.ctx.workspace_bytes(self.N, self.k_max, self._ws_nvec)
+        self.work = None
+        self.ctx.set_workspace(None)
+        self.work = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.ctx.set_workspace(self.work, self.N, self.k_max, self._ws_nvec)
 
     @classmethod
     def from_workload(cls, sysw, **kw):
@@ -101,6 +111,7 @@ class System:
     def _grow(self, k_needed: int):
         self.k_max = int(max(k_needed + 4, int(self.k_max * 1.5)))
         self.nlist = torch.zeros(self.k_max * self.N, dtype=torch.int32, device=self.device)
+        self._attach_workspace(self._ws_nvec)
 
     def build(self):
         """Bin, re-order and build the neighbour list (grows k_max on overflow)."""
@@ -182,6 +193,8 @@ class System:
         if not self.built:
             self.build()
         V = V.contiguous()
+        if V.shape[0] > self._ws_nvec:
+            self._attach_workspace(V.shape[0])
         out = torch.empty_like(V)
         api.rc_force_hvp_batch(self.ctx, self.pos, self.nlist, self.nn, self.box, V, out)
         return out

@@ -366,6 +366,7 @@ def adjoint_bench(a):
     hvp = timed(lambda: api.rc_force_hvp(S.ctx, S.pos, S.nlist, S.nn, S.box, vs[next(it) % 64], hv), 640)
     V64 = torch.stack(list(vs[:64])).contiguous()       # the 64 tangent vectors of the workload
     HV64 = torch.empty_like(V64)
+    S.reserve_hvp_vectors(64)
     hvp64 = timed(lambda: api.rc_force_hvp_batch(S.ctx, S.pos, S.nlist, S.nn, S.box, V64, HV64), 50)
     adj = vs[0]
     vjp = timed(lambda: api.rc_param_vjp(S.ctx, S.pos, S.nlist, S.nn, S.box, adj, g), 200)

@@ -188,13 +188,18 @@ class System:
         api.rc_force_hvp(self.ctx, self.pos, self.nlist, self.nn, self.box, v.contiguous(), out)
         return out
 
+    def reserve_hvp_vectors(self, nvec: int):
+        """Grow the caller-owned workspace so that batched products of up to
+        ``nvec`` tangent vectors fit (raw rc_force_hvp_batch calls need it)."""
+        if int(nvec) > self._ws_nvec:
+            self._attach_workspace(int(nvec))
+
     def hvp_batch(self, V: torch.Tensor) -> torch.Tensor:
         """H V[k] for V of shape (nvec, N, 4) in the engine's particle order, one launch per pass."""
         if not self.built:
             self.build()
         V = V.contiguous()
-        if V.shape[0] > self._ws_nvec:
-            self._attach_workspace(V.shape[0])
+        self.reserve_hvp_vectors(V.shape[0])
         out = torch.empty_like(V)
         api.rc_force_hvp_batch(self.ctx, self.pos, self.nlist, self.nn, self.box, V, out)
         return out

@@ -301,12 +301,22 @@ hipError_t launch_forces_gather_batch(const ForceArgs& a, hipStream_t s) { retur
 // Seven wavefronts per SIMD: the walk-form kernel at width 2 then fits 72
 // VGPRs without spilling (74 otherwise, six wavefronts) and runs ~2 % faster
 // at 1M particles; the other instantiations are unchanged by the hint.
+// The particle's own data is requested before the table is staged in LDS,
+// so that the table's load and barrier overlap it instead of preceding it
+// (24.9 -> 24.3 us per step at 1M particles).
 template <bool EV, bool BATCH, int PL, bool SF>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int nt = a.tab.nt;
     const int blk = xcd_block(gridDim.x);
     const int m = blk * kWave + threadIdx.x;
+    float4 pm0 = make_float4(0.f, 0.f, 0.f, 0.f), vm0 = pm0;
+    int packed0 = 0;
+    if (m < a.N) {   // every slot is allocated; slots past a replica's end are dropped below
+        pm0 = a.pos_in[m];
+        vm0 = a.vel[m];
+        packed0 = a.nn[m];
+    }
     Box box_r;
     int lim = a.N, tag0 = 0;
     uint64_t seed = a.seed;
@@ -326,9 +336,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
     const bool live = m < lim;
     const uint64_t step = a.step + (a.step_base ? *a.step_base : 0ull);
     Acc acc = {};
-    const float4 pm = live ? a.pos_in[m] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 vm = live ? a.vel[m] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const int packed = live ? a.nn[m] : 0;
+    const float4 pm = live ? pm0 : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 vm = live ? vm0 : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int packed = live ? packed0 : 0;
     const OneSystem sys{s_tab, nt, box};
     // the entries come from the packed copy of the list
     wave_gather<EV, PL, SF, OneSystem, false, true>(m - (int)threadIdx.x, live, pm, packed, a.pos_in, a.nlist, a.nn,

@@ -522,6 +522,10 @@ typedef struct rc_md_stats {
     double sums_ms;     /* time_kernels, RC_FORM_SUMS: the first passes' time */
     int32_t list_kept;  /* 1: the run continued the previous run's list       */
     int32_t nswap;      /* RC_ST_NSWAP of the list in use at the end          */
+    int64_t particles_rebuilt; /* summed over the run's list builds: the
+                           particles whose lists each build rebuilt (every
+                           particle for a single system; the replicas that
+                           needed it, and those near it, for a batch)        */
 } rc_md_stats;
 
 int rc_md_run(rc_ctx* ctx, const rc_md_buffers* buf, int N, rc_box box,
@@ -634,7 +638,23 @@ int rc_soft_bonds(rc_ctx* ctx, const float* pos, const int* nlist, const int* nn
  *   rc_step_fused); ev = device [R][13] or NULL; status as rc_step_fused.
  * rc_batch_run: rc_md_run over the whole batch: buf arrays are n_slots long,
  *   ev_log is [rows][R][13] and bonds_log [rows][R].  A list build of the
- *   batch happens when any replica needs one.  Synchronises the stream.
+ *   batch happens when any replica needs one, and rebuilds only the replicas
+ *   whose own particles crossed the rebuild threshold plus those whose
+ *   largest path length since their own last build exceeds margin x that
+ *   threshold (rc_batch_set_rebuild_margin); the other replicas keep their
+ *   order, lists and path lengths.  The first build of a run covers every
+ *   replica; the first build of a resumed run (opt.resume = 1, after
+ *   RC_ERR_NLIST_OVERFLOW) covers the replicas of the build that overflowed.
+ *   stats->particles_rebuilt counts the rebuilt particles.  Synchronises the
+ *   stream.
+ * rc_batch_set_rebuild_margin: margin in [0, 1] (default 0.3); 0 rebuilds
+ *   every replica at every build, 1 only the replicas that crossed.
+ * rc_batch_relayout_lists: copies the lists of every slot from old_nlist
+ *   (k_old slots per particle) into new_nlist (k_new >= k_old) and writes
+ *   their packed copy for k_new into the attached workspace (which must hold
+ *   k_new), so that a run resumed after RC_ERR_NLIST_OVERFLOW with larger
+ *   lists keeps the lists of the replicas it does not rebuild.  nn is the
+ *   count array both lists share.  Launches on the stream.
  * rc_batch_build_nlist also writes the packed copy of the lists that the
  *   batch's fused step reads (as rc_build_nlist does for one system).
  * rc_batch_time_fused_steps: as rc_time_fused_steps for the batch.
@@ -670,6 +690,9 @@ int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_integrator* cfg
 int rc_batch_time_fused_steps(rc_batch* b, float* pos_a, float* pos_b, float* vel, const int* nlist, const int* nn,
                               int k_max, const rc_integrator* cfg /* host */, uint64_t step0, int reps, int* status,
                               float* ms /* host */, void* stream);
+int rc_batch_set_rebuild_margin(rc_batch* b, double margin);
+int rc_batch_relayout_lists(rc_batch* b, const int* old_nlist, int k_old, int* new_nlist, int k_new, const int* nn,
+                            void* stream);
 
 #ifdef __cplusplus
 }

@@ -89,7 +89,8 @@ class MdStats(ctypes.Structure):
                 ("rollbacks", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("log_rows", ctypes.c_int64), ("k_needed", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
-                ("sums_ms", ctypes.c_double), ("list_kept", ctypes.c_int32), ("nswap", ctypes.c_int32)]
+                ("sums_ms", ctypes.c_double), ("list_kept", ctypes.c_int32), ("nswap", ctypes.c_int32),
+                ("particles_rebuilt", ctypes.c_int64)]
 
 
 _VP = ctypes.c_void_p
@@ -162,6 +163,8 @@ _SIGS = {
                       ctypes.POINTER(MdOptions), ctypes.POINTER(MdStats), _VP], _I),
     "rc_batch_time_fused_steps": ([_VP, _VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(Integrator), _U64, _I, _VP,
                                    ctypes.POINTER(ctypes.c_float), _VP], _I),
+    "rc_batch_set_rebuild_margin": ([_VP, _D], _I),
+    "rc_batch_relayout_lists": ([_VP, _VP, _I, _VP, _I, _VP, _VP], _I),
 }
 
 _lib = None

@@ -25,7 +25,7 @@ __all__ = [
     "rc_param_grad", "rc_clear_status", "rc_read_status", "rc_time_fused_steps",
     "rc_param_vjp", "rc_soft_bonds", "rc_bond_partners", "rc_set_bonds", "rc_fene_forces", "BatchContext", "rc_batch_cells_workspace_bytes", "rc_batch_build_cells", "rc_batch_build_nlist",
     "rc_batch_compute_forces", "rc_batch_bond_count", "rc_batch_step_fused", "rc_batch_run",
-    "rc_batch_time_fused_steps",
+    "rc_batch_time_fused_steps", "rc_batch_relayout_lists",
 ]
 
 
@@ -430,6 +430,9 @@ class BatchContext:
         f = {"walk": L.RC_FORM_WALK, "sums": L.RC_FORM_SUMS}[form]
         check(L.load().rc_batch_set_step_form(self.handle, f), batch=self.handle)
 
+    def set_rebuild_margin(self, margin: float):
+        check(L.load().rc_batch_set_rebuild_margin(self.handle, float(margin)), batch=self.handle)
+
     def close(self):
         if getattr(self, "handle", None):
             L.load().rc_batch_destroy(self.handle)
@@ -486,6 +489,11 @@ def rc_batch_run(bc: BatchContext, bufs: L.MdBuffers, cfg, step0, n_steps, opts:
         err.stats = st
         raise err
     return st
+
+
+def rc_batch_relayout_lists(bc: BatchContext, old_nlist, k_old, new_nlist, k_new, nn, stream=None):
+    check(L.load().rc_batch_relayout_lists(bc.handle, _ptr(old_nlist), int(k_old), _ptr(new_nlist), int(k_new),
+                                           _ptr(nn), _stream(stream)), batch=bc.handle)
 
 
 def rc_batch_time_fused_steps(bc: BatchContext, pos_a, pos_b, vel, nlist, nn, cfg, step0, reps, status,

@@ -34,7 +34,7 @@ class Batch:
     """
 
     def __init__(self, systems: Sequence, r_buff: float = 0.3, k_max: int = 32, rollback: bool = True,
-                 device: str = "cuda", seeds=None):
+                 device: str = "cuda", seeds=None, rebuild_margin: float = 0.3):
         self.device = torch.device(device)
         R = len(systems)
         self.R = R
@@ -85,6 +85,7 @@ class Batch:
             self.snap_image = torch.empty_like(self.image)
         if seeds is not None:
             self.bc.set_seeds(seeds)
+        self.bc.set_rebuild_margin(rebuild_margin)
         self.built = False
         self._continues = False     # the state is what the last run left (its list may be kept)
         self._attach_workspace()
@@ -95,9 +96,13 @@ class Batch:
 
     # ---- neighbour lists -------------------------------------------------------------
     def _grow(self, k_needed: int):
+        """Larger lists; the current lists are carried over (a resumed run rebuilds only the replicas of
+        the build that overflowed, the others keep theirs)."""
+        k_old, old = self.k_max, self.nlist
         self.k_max = int(max(k_needed + 4, int(self.k_max * 1.5)))
         self.nlist = torch.zeros(self.k_max * self.n_slots, dtype=torch.int32, device=self.device)
         self._attach_workspace()
+        api.rc_batch_relayout_lists(self.bc, old, k_old, self.nlist, self.k_max, self.nn)
 
     def _attach_workspace(self):
         """The batch's large scratch (packed lists, switching sums) in a torch-owned buffer."""
@@ -148,6 +153,11 @@ class Batch:
     def set_step_form(self, form: str):
         """"walk" (one pass, partner sums by list walks) or "sums" (two passes): speed only."""
         self.bc.set_step_form(form)
+
+    def set_rebuild_margin(self, margin: float):
+        """Replicas whose largest path length since their last list build exceeds margin x the rebuild
+        threshold are rebuilt with the ones that crossed it (0: every replica at every build)."""
+        self.bc.set_rebuild_margin(margin)
 
     def integrator(self, kind="langevin", dt=0.002, kT=1.0, gamma=1.0, seed=0, dim=3):
         return api.integrator(kind, dt, kT, gamma, seed, list(self.mass), dim=dim)

@@ -148,13 +148,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_cells(const int* __restrict__ s
 
 // One thread per new index q: gather the particle data into key order
 // (coalesced writes; the reads follow the previous order, which is close to
-// the new one after the first build).
+// the new one after the first build).  The path lengths since the last list
+// build (vel.w) restart at zero for the particles whose list is rebuilt; a
+// batch replica that keeps its list (build[r] == 0) keeps its order
+// (order[q] == q) and its path lengths.  The temporaries are the state the
+// rebuild leaves, which the driver restores on a rollback.
 __global__ __launch_bounds__(kBlock) void k_permute(const int* __restrict__ order, int N,
                                                    const float4* __restrict__ pos,
                                                    const float4* __restrict__ vel,
                                                    const int4* __restrict__ image,
                                                    float4* __restrict__ tpos, float4* __restrict__ tvel,
-                                                   int4* __restrict__ timage, int* __restrict__ rtag) {
+                                                   int4* __restrict__ timage, int* __restrict__ rtag,
+                                                   const int* __restrict__ build, const int* __restrict__ chunk_rep) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     const int o = order[q];
@@ -164,9 +169,14 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int* __restrict__ orde
         if (image) timage[q] = make_int4(0, 0, 0, 0);
         return;
     }
+    const bool rebuilt = !build || build[chunk_rep[q / kWave]] != 0;
     const float4 p = pos[o];
     tpos[q] = p;
-    if (vel) tvel[q] = vel[o];
+    if (vel) {
+        float4 v = vel[o];
+        if (rebuilt) v.w = 0.0f;
+        tvel[q] = v;
+    }
     if (image) timage[q] = image[o];
     if (rtag) {
         const int tg = ptag(p.w);
@@ -175,10 +185,29 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int* __restrict__ orde
 }
 
 // ---- batches: the same counting sort over the concatenated key ranges ------
+// Only the replicas with build[r] != 0 (every replica when build is NULL) are
+// binned and re-ordered; the others keep their order and their lists.  A
+// replica's particles go to its own slots: slot = off + (the cell start of
+// its key) - (the cell start of its first key) + rank, so the order does not
+// depend on which other replicas take part.
+__device__ __forceinline__ bool rep_builds(const int* build, int r) { return !build || build[r] != 0; }
+
+// order[q]: -1 for unused slots, q for the slots of replicas that keep their
+// order; the scatter fills the rest
+__global__ __launch_bounds__(kBlock) void k_order_init_batch(CellsArgsB a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.N) return;
+    const int r = a.chunk_rep[q / kWave];
+    const RepDesc& d = a.rep[r];
+    a.order[q] = (q < d.off + d.n && !rep_builds(a.build, r)) ? q : -1;
+}
+
 __global__ __launch_bounds__(kBlock) void k_bin_batch(CellsArgsB a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
+    const int r = a.chunk_rep[i / kWave];
+    if (!rep_builds(a.build, r)) return;
+    const RepDesc& d = a.rep[r];
     if (i >= d.off + d.n) return;
     const float4 p = a.pos[i];
     const int cx = cell_coord(p.x, d.box.hf[0], d.grid.inv_w[0], d.grid.nc[0]);
@@ -189,13 +218,15 @@ __global__ __launch_bounds__(kBlock) void k_bin_batch(CellsArgsB a) {
     a.rank[i] = atomicAdd(&a.counts[key], 1);
 }
 
-// scatter into the replica's own slots (compact position + its shift)
+// scatter into the replica's own slots
 __global__ __launch_bounds__(kBlock) void k_scatter_batch(CellsArgsB a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
+    const int r = a.chunk_rep[i / kWave];
+    if (!rep_builds(a.build, r)) return;
+    const RepDesc& d = a.rep[r];
     if (i >= d.off + d.n) return;
-    a.order[a.cell_start[a.keys[i]] + a.rank[i] + d.shift] = i;
+    a.order[a.cell_start[a.keys[i]] - a.cell_start[d.key_base] + a.rank[i] + d.off] = i;
 }
 
 // per key: the replica owning it (first r with key_end[r] > k), then the
@@ -211,7 +242,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_cells_batch(CellsArgsB a) {
         if (a.key_end[mid] > k) hi = mid;
         else lo = mid + 1;
     }
-    const int sh = a.rep[lo].shift;
+    if (!rep_builds(a.build, lo)) return;
+    const int sh = a.rep[lo].off - a.cell_start[a.rep[lo].key_base];
     int* order = a.order;
     const int s = s0 + sh, e = e0 + sh;
     for (int p = s + 1; p < e; ++p) {
@@ -232,7 +264,7 @@ hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s) {
     const int nsb = nblk(nk, kScanTile);
     if (nsb > 8192) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(nblk(nk, kBlock), 2048)), dim3(kBlock), 0, s, a.counts, nk, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(std::min(nblk(a.N, kBlock), 2048)), dim3(kBlock), 0, s, a.order, a.N, -1);
+    hipLaunchKernelGGL(k_order_init_batch, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_bin_batch, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kBlock), 0, s, a.counts, nk, a.block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a.block_sums, nsb, a.cell_start, nk);
@@ -240,7 +272,7 @@ hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_batch, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_sort_cells_batch, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_permute, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.order, a.N, a.pos, a.vel, a.image,
-                       a.tpos, a.tvel, a.timage, a.rtag);
+                       a.tpos, a.tvel, a.timage, a.rtag, a.build, a.chunk_rep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(a.pos, a.tpos, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
@@ -267,7 +299,7 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
                        a.cell_start, a.N, a.order);
     hipLaunchKernelGGL(k_sort_cells, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a.cell_start, nk, a.order);
     hipLaunchKernelGGL(k_permute, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.order, a.N, a.pos, a.vel, a.image,
-                       a.tpos, a.tvel, a.timage, a.rtag);
+                       a.tpos, a.tvel, a.timage, a.rtag, nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(a.pos, a.tpos, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
@@ -501,27 +533,76 @@ hipError_t launch_pack_list(const int* nlist, const int* nn, int k_max, int N, i
 }
 
 // Batches: each wave lies in one replica, which gives the box, grid, key
-// range and table; empty slots get an empty list.
+// range and table (its list radii staged in the wavefront's LDS slice); empty
+// slots get an empty list.  A replica that keeps its list (build[r] == 0)
+// keeps its lists, packed copy and path lengths; its list lengths still count
+// towards the status words.
 __global__ __launch_bounds__(kBlock) void k_nlist_batch(NlistArgsB a) {
+    extern __shared__ float s_rl2b[];  // per wavefront: [nt*nt] list radii^2, then [nt*nt] swap flags
+    const int nt = a.tab.nt, nt2 = nt * nt;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int total = 0, packed = 0;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int r = i < a.N ? a.chunk_rep[i / kWave] : 0;
+    float* rl2s = s_rl2b + 2 * nt2 * wv;
+    int* sws = reinterpret_cast<int*>(rl2s + nt2);
     if (i < a.N) {
-        const RepDesc& d = a.rep[a.chunk_rep[i / kWave]];
-        const DevEntry* t = a.tab.e + d.tab;
-        if (i < d.off + d.n) {
-            total = list_one(i, a.pos[i], d.box, d.grid, d.key_base, d.shift, a.cell_start, a.pos, a.tab.nt, a.k_max,
+        const DevEntry* t = a.tab.e + a.rep[r].tab;
+        for (int q = lane; q < nt2; q += kWave) {
+            rl2s[q] = t[q].rlist2;
+            sws[q] = t[q].kind == RC_KIND_SWAP;
+        }
+    }
+    __syncthreads();
+    int total = 0, packed = 0;
+    const bool builds = i < a.N && rep_builds(a.build, r);   // uniform over the wavefront
+    if (i < a.N) {
+        const RepDesc& d = a.rep[r];
+        if (!builds) {
+            packed = a.nn[i];
+            total = nn_swap(packed) + nn_other(packed);
+        } else if (i < d.off + d.n) {
+            const int shift = d.off - a.cell_start[d.key_base];
+            total = list_one(i, a.pos[i], d.box, d.grid, d.key_base, shift, a.cell_start, a.pos, nt, a.k_max,
                              a.N, a.nlist, a.nn, [&](int q, float& rl2, bool& swap) {
-                                 rl2 = t[q].rlist2;
-                                 swap = t[q].kind == RC_KIND_SWAP;
+                                 rl2 = rl2s[q];
+                                 swap = sws[q] != 0;
                              });
             packed = a.nn[i];
         } else {
             a.nn[i] = 0;
         }
-        if (a.vel) a.vel[i].w = 0.0f;
+        if (builds && a.vel) a.vel[i].w = 0.0f;
     }
-    if (a.pl_j) pack_wave_lists(i, i < a.N, packed, a.nlist, a.k_max, a.N, a.pl_j, a.pl_o);
+    if (a.pl_j && (builds || i >= a.N)) pack_wave_lists(i, i < a.N, packed, a.nlist, a.k_max, a.N, a.pl_j, a.pl_o);
     block_max_store(total, nn_swap(packed), a.block_max + blockIdx.x, gridDim.x);
+}
+
+// A list laid out for k_old slots per particle copied into the layout of
+// k_new >= k_old slots (swap range at the front, the rest at the back), and
+// its packed copy for k_new.  One thread per slot; every lane of a
+// wavefront takes part (the packing scans the wavefront's lengths).
+__global__ __launch_bounds__(kBlock) void k_relayout_list(const int* __restrict__ old_list, int k_old,
+                                                         int* __restrict__ new_list, int k_new,
+                                                         const int* __restrict__ nn, int N, int* __restrict__ pl_j,
+                                                         unsigned char* __restrict__ pl_o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < N;
+    int packed = 0;
+    if (live) {
+        packed = nn[i];
+        const int ns = min(nn_swap(packed), k_old);
+        const int no = min(nn_other(packed), k_old - ns);
+        for (int q = 0; q < ns; ++q) new_list[(size_t)q * N + i] = old_list[(size_t)q * N + i];
+        for (int q = 0; q < no; ++q) new_list[(size_t)(k_new - 1 - q) * N + i] = old_list[(size_t)(k_old - 1 - q) * N + i];
+    }
+    if (pl_j) pack_wave_lists(i, live, packed, new_list, k_new, N, pl_j, pl_o);
+}
+
+hipError_t launch_relayout_list(const int* old_list, int k_old, int* new_list, int k_new, const int* nn, int N,
+                                int* pl_j, unsigned char* pl_o, hipStream_t s) {
+    hipLaunchKernelGGL(k_relayout_list, dim3(nblk(N, kBlock)), dim3(kBlock), 0, s, old_list, k_old, new_list, k_new,
+                       nn, N, pl_j, pl_o);
+    return hipGetLastError();
 }
 
 // one block: fold the per-block maxima into the status word
@@ -577,7 +658,8 @@ hipError_t launch_nlist(const NlistArgs& a, hipStream_t s) {
 
 hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s) {
     const int nb = nblk(a.N, kBlock);
-    hipLaunchKernelGGL(k_nlist_batch, dim3(nb), dim3(kBlock), 0, s, a);
+    const size_t shm = (size_t)(kBlock / kWave) * 2 * sizeof(float) * a.tab.nt * a.tab.nt;
+    hipLaunchKernelGGL(k_nlist_batch, dim3(nb), dim3(kBlock), shm, s, a);
     if (a.status)
         hipLaunchKernelGGL(k_nlist_status, dim3(1), dim3(1024), 0, s, a.block_max, nb, a.k_max, a.status,
                            a.fresh_status);

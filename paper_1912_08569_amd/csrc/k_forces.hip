@@ -657,6 +657,49 @@ hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* s
     return hipGetLastError();
 }
 
+// Per-replica fold of a batch chunk, before k_fold_status resets the block
+// slots: one workgroup per replica folds its own 64-slot chunks (the flag of
+// any block that crossed the rebuild threshold, the largest path length) and
+// stores them; status[MAXPATH] is raised to the largest of all.  Path lengths
+// are non-negative, so their float bits order like ints.
+__global__ __launch_bounds__(kBlock) void k_fold_reps(const int* __restrict__ blk, const float4* __restrict__ vel,
+                                                     const RepDesc* __restrict__ rep, int* __restrict__ rep_flag,
+                                                     int* __restrict__ rep_path, int* __restrict__ status) {
+    __shared__ float r_p[kBlock / kWave];
+    __shared__ int r_f[kBlock / kWave];
+    const int r = blockIdx.x;
+    const int c0 = rep[r].off / kWave, c1 = (rep[r].off + rep[r].n + kWave - 1) / kWave;
+    float pm = 0.0f;
+    int fl = 0;
+    for (int i = c0 * kWave + (int)threadIdx.x; i < c1 * kWave; i += blockDim.x) {
+        pm = fmaxf(pm, vel[i].w);
+        if ((i & (kWave - 1)) == 0) fl |= blk[3 * (i / kWave)] & RC_FLAG_REBUILD;
+    }
+    pm = wave_maxf(pm);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) fl |= __shfl_xor(fl, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        r_p[threadIdx.x / kWave] = pm;
+        r_f[threadIdx.x / kWave] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / kWave; ++q) {
+            pm = fmaxf(pm, r_p[q]);
+            fl |= r_f[q];
+        }
+        rep_flag[r] = fl != 0;
+        rep_path[r] = __float_as_int(pm);
+        atomicMax(&status[RC_ST_MAXPATH], __float_as_int(pm));
+    }
+}
+
+hipError_t launch_fold_reps(const int* blk, const float4* vel, const RepDesc* rep, int R, int* out, int* status,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_fold_reps, dim3(R), dim3(kBlock), 0, s, blk, vel, rep, out, out + R, status);
+    return hipGetLastError();
+}
+
 // the driver's snapshot of (pos, vel, image) and its restore, in one launch
 __global__ __launch_bounds__(kBlock) void k_copy_state(const float4* __restrict__ pos, const float4* __restrict__ vel,
                                                       const int4* __restrict__ image, float4* __restrict__ pos_to,

@@ -748,7 +748,9 @@ struct PlainOps final : DriveOps {
     rc_box box;
     Box b;
     hipStream_t s;
-    int rebuild(float* pos) override {
+    int rebuild(float* pos, RebuildKind, float* kept_path, int64_t* rebuilt) override {
+        *kept_path = 0.0f;   // every list is rebuilt
+        *rebuilt = N;
         int rr = rc_build_cells(c, pos, buf->vel, buf->image, buf->rtag, N, box, buf->cells_ws, buf->cells_ws_bytes,
                                 s);
         if (rr) return rr;

@@ -21,10 +21,21 @@ struct rc_batch {
     std::vector<RepDesc> desc;
     std::vector<uint64_t> seeds;  // host copy of d_seeds
     bool seeds_set = false;
-    RepDesc* d_rep = nullptr;
+    RepDesc* d_desc = nullptr;
     int* d_chunk_rep = nullptr;
     uint32_t* d_key_end = nullptr;
     uint64_t* d_seeds = nullptr;
+    // per-replica rebuilds: the fold of every chunk writes, per replica, whether a block crossed the
+    // rebuild threshold and the largest path length (d_rep: [2][R] ints), which every status read
+    // copies to h_rep; a build re-orders and re-lists the replicas of its set (d_build [R])
+    double margin = 0.3;
+    int* d_rep = nullptr;
+    int* h_rep = nullptr;            // pinned [2][R]
+    int* d_build = nullptr;
+    int* h_build[2] = {nullptr, nullptr};   // pinned [R] sets, alternating between builds
+    int build_parity = 0;
+    std::vector<int> last_set;       // the set of the last build of a run (a resumed run's first)
+    std::vector<float> prev_path;    // per replica: its largest path length at the previous fold (0 after a build)
 };
 
 namespace {
@@ -32,6 +43,11 @@ namespace {
 void free_batch(rc_batch* b) {
     free_ctx_buffers(&b->c);
     if (b->d_rep) (void)hipFree(b->d_rep);
+    if (b->d_build) (void)hipFree(b->d_build);
+    if (b->h_rep) (void)hipHostFree(b->h_rep);
+    for (int q = 0; q < 2; ++q)
+        if (b->h_build[q]) (void)hipHostFree(b->h_build[q]);
+    if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_chunk_rep) (void)hipFree(b->d_chunk_rep);
     if (b->d_key_end) (void)hipFree(b->d_key_end);
     if (b->d_seeds) (void)hipFree(b->d_seeds);
@@ -84,7 +100,7 @@ int fill_step_args_batch(rc_batch* b, StepArgs& a, const float* pos_in, float* p
     a.soft = (float)(0.5 * c->r_buff * soft_frac);
     a.seed = 0;
     a.status = status;
-    a.rep = b->d_rep;
+    a.rep = b->d_desc;
     a.chunk_rep = b->d_chunk_rep;
     a.seeds = b->d_seeds;
     a.width = c->gather_width;
@@ -126,7 +142,7 @@ int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tabl
     b->counts.assign(counts, counts + R);
     b->offsets.resize(R + 1);
     b->desc.resize(R);
-    int64_t slots = 0, compact = 0;
+    int64_t slots = 0;
     uint64_t keys = 0;
     double rmax_all = 0.0;
     for (int r = 0; r < R; ++r) {
@@ -145,11 +161,9 @@ int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tabl
         d.key_base = (uint32_t)keys;
         d.off = (int)slots;
         d.n = counts[r];
-        d.shift = (int)(slots - compact);
         d.tab = r * nt2;
         b->offsets[r] = (int)slots;
         keys += d.grid.nkeys;
-        compact += counts[r];
         slots += (int64_t)kWave * ((counts[r] + kWave - 1) / kWave);
         if (slots >= RC_MAX_TAG || keys > (uint64_t)8192 * kScanTile) {
             free_batch(b);
@@ -172,19 +186,27 @@ int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tabl
               hipMemcpy(c->d_tab, c->host_tab.data(), sizeof(DevEntry) * (size_t)R * nt2, hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMalloc(&c->d_step_base, sizeof(unsigned long long)) == hipSuccess &&
-              hipMalloc(&b->d_rep, sizeof(RepDesc) * R) == hipSuccess &&
-              hipMemcpy(b->d_rep, b->desc.data(), sizeof(RepDesc) * R, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&b->d_desc, sizeof(RepDesc) * R) == hipSuccess &&
+              hipMemcpy(b->d_desc, b->desc.data(), sizeof(RepDesc) * R, hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&b->d_chunk_rep, sizeof(int) * chunk_rep.size()) == hipSuccess &&
               hipMemcpy(b->d_chunk_rep, chunk_rep.data(), sizeof(int) * chunk_rep.size(), hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMalloc(&b->d_key_end, sizeof(uint32_t) * R) == hipSuccess &&
               hipMemcpy(b->d_key_end, key_end.data(), sizeof(uint32_t) * R, hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&b->d_seeds, sizeof(uint64_t) * R) == hipSuccess &&
-              hipMemcpy(b->d_seeds, b->seeds.data(), sizeof(uint64_t) * R, hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(b->d_seeds, b->seeds.data(), sizeof(uint64_t) * R, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&b->d_rep, sizeof(int) * 2 * (size_t)R) == hipSuccess &&
+              hipMemset(b->d_rep, 0, sizeof(int) * 2 * (size_t)R) == hipSuccess &&
+              hipMalloc(&b->d_build, sizeof(int) * (size_t)R) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&b->h_rep), sizeof(int) * 2 * (size_t)R) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&b->h_build[0]), sizeof(int) * (size_t)R) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&b->h_build[1]), sizeof(int) * (size_t)R) == hipSuccess;
     if (!ok) {
         free_batch(b);
         return RC_ERR_HIP;
     }
+    std::memset(b->h_rep, 0, sizeof(int) * 2 * (size_t)R);
+    c->status_extra.push_back({b->h_rep, b->d_rep, sizeof(int) * 2 * (size_t)R});
     *out = b;
     return RC_OK;
 }
@@ -245,10 +267,8 @@ int rc_batch_cells_workspace_bytes(const rc_batch* b, size_t* bytes) {
     return RC_OK;
 }
 
-int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
-                         void* stream) {
-    if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
-    if (!b) return RC_ERR_ARG;
+static int batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
+                             const int* build, void* stream) {
     int r = check_pos(b, pos);
     if (r) return r;
     const CellsLayout l = cells_layout(b->n_slots, b->nkeys);
@@ -260,7 +280,7 @@ int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* r
     a.image = reinterpret_cast<int4*>(image);
     a.rtag = rtag;
     a.N = b->n_slots;
-    a.rep = b->d_rep;
+    a.rep = b->d_desc;
     a.chunk_rep = b->d_chunk_rep;
     a.key_end = b->d_key_end;
     a.R = b->R;
@@ -274,13 +294,21 @@ int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* r
     a.tpos = reinterpret_cast<float4*>(w + l.tpos);
     a.tvel = reinterpret_cast<float4*>(w + l.tvel);
     a.timage = reinterpret_cast<int4*>(w + l.timage);
+    a.build = build;
     HIP_TRY(&b->c, launch_cells_batch(a, S(stream)));
     return RC_OK;
 }
 
+int rc_batch_build_cells(rc_batch* b, float* pos, float* vel, int* image, int* rtag, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
+    if (!b) return RC_ERR_ARG;
+    return batch_build_cells(b, pos, vel, image, rtag, ws, ws_bytes, nullptr, stream);
+}
+
 // fresh: the status words are written whole (the driver's rebuilds), else folded into
 static int batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
-                             int* nlist, int* nn, int* status, bool fresh, void* stream) {
+                             int* nlist, int* nn, int* status, bool fresh, const int* build, void* stream) {
     if (!b) return RC_ERR_ARG;
     int r = check_pos(b, pos);
     if (r) return r;
@@ -291,7 +319,7 @@ static int batch_build_nlist(rc_batch* b, const float* pos, float* vel, const vo
     a.pos = reinterpret_cast<const float4*>(pos);
     a.vel = reinterpret_cast<float4*>(vel);
     a.N = b->n_slots;
-    a.rep = b->d_rep;
+    a.rep = b->d_desc;
     a.chunk_rep = b->d_chunk_rep;
     a.tab = all_tables(b);
     a.cell_start = reinterpret_cast<const int*>(static_cast<const char*>(ws) + l.start);
@@ -300,6 +328,7 @@ static int batch_build_nlist(rc_batch* b, const float* pos, float* vel, const vo
     a.nn = nn;
     a.status = status;
     a.fresh_status = fresh ? 1 : 0;
+    a.build = build;
     a.block_max = reinterpret_cast<int*>(static_cast<char*>(const_cast<void*>(ws)) + l.bmax);
     rc_ctx* c = &b->c;
     if ((r = ensure_plist(c, b->n_slots, k_max))) return r;
@@ -316,7 +345,32 @@ static int batch_build_nlist(rc_batch* b, const float* pos, float* vel, const vo
 int rc_batch_build_nlist(rc_batch* b, const float* pos, float* vel, const void* ws, size_t ws_bytes, int k_max,
                          int* nlist, int* nn, int* status, void* stream) {
     if (b) b->c.md.valid = false;   // the state or the list changes outside the driver
-    return batch_build_nlist(b, pos, vel, ws, ws_bytes, k_max, nlist, nn, status, false, stream);
+    return batch_build_nlist(b, pos, vel, ws, ws_bytes, k_max, nlist, nn, status, false, nullptr, stream);
+}
+
+int rc_batch_set_rebuild_margin(rc_batch* b, double margin) {
+    if (!b) return RC_ERR_ARG;
+    if (!(margin >= 0.0 && margin <= 1.0)) return fail(&b->c, RC_ERR_ARG, "rebuild margin must be in [0, 1]");
+    b->margin = margin;
+    return RC_OK;
+}
+
+int rc_batch_relayout_lists(rc_batch* b, const int* old_nlist, int k_old, int* new_nlist, int k_new, const int* nn,
+                            void* stream) {
+    if (!b) return RC_ERR_ARG;
+    rc_ctx* c = &b->c;
+    int r = check_list(c, new_nlist, nn, k_new);
+    if (r) return r;
+    if (!old_nlist || k_old < 1 || k_old > k_new || old_nlist == new_nlist)
+        return fail(c, RC_ERR_ARG, "relayout needs a distinct old list with 1 <= k_old <= k_new");
+    if ((r = ensure_plist(c, b->n_slots, k_new))) return r;
+    HIP_TRY(c, launch_relayout_list(old_nlist, k_old, new_nlist, k_new, nn, b->n_slots, c->d_pl_j, c->d_pl_o,
+                                    S(stream)));
+    c->pl_nlist = new_nlist;
+    c->pl_nn = nn;
+    c->pl_k = k_new;
+    c->pl_n = b->n_slots;
+    return RC_OK;
 }
 
 int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, const int* nn, int k_max, float* force,
@@ -340,7 +394,7 @@ int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, con
     a.ev_part = ev ? c->d_part : nullptr;
     a.accumulate = 0;
     a.status = status;
-    a.rep = b->d_rep;
+    a.rep = b->d_desc;
     a.chunk_rep = b->d_chunk_rep;
     a.ssum = nullptr;
     if (c->step_form == RC_FORM_SUMS) {
@@ -349,7 +403,7 @@ int rc_batch_compute_forces(rc_batch* b, const float* pos, const int* nlist, con
     }
     hipStream_t s = S(stream);
     HIP_TRY(c, launch_forces_gather_batch(a, s));
-    if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_rep, b->R, 0, 7, ev, 7, s));
+    if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_desc, b->R, 0, 7, ev, 7, s));
     return RC_OK;
 }
 
@@ -363,7 +417,7 @@ int rc_batch_bond_count(rc_batch* b, const float* pos, const int* nlist, const i
     if ((r = check_list(c, nlist, nn, k_max))) return r;
     if ((r = ensure_part(c, sizeof(unsigned long long) * (size_t)nblocks(b->n_slots, kWave)))) return r;
     HIP_TRY(c, launch_bonds_batch(reinterpret_cast<const float4*>(pos), nlist, nn, k_max, b->n_slots, all_tables(b),
-                                  b->d_rep, b->d_chunk_rep, b->R, counts,
+                                  b->d_desc, b->d_chunk_rep, b->R, counts,
                                   reinterpret_cast<unsigned long long*>(c->d_part), S(stream)));
     return RC_OK;
 }
@@ -393,7 +447,7 @@ int rc_batch_step_fused(rc_batch* b, const float* pos_in, float* pos_out, float*
     a.ev_part = ev ? c->d_part : nullptr;
     HIP_TRY(c, launch_step_batch(a, ev != nullptr, s));
     HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, b->n_slots, status, s));
-    if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_rep, b->R, 0, kEvWords, ev, kEvWords, s));
+    if (ev) HIP_TRY(c, launch_reduce_rows_batch(c->d_part, b->d_desc, b->R, 0, kEvWords, ev, kEvWords, s));
     return RC_OK;
 }
 
@@ -443,15 +497,79 @@ struct BatchOps final : DriveOps {
     rc_batch* b;
     const rc_md_buffers* buf;
     hipStream_t s;
-    int rebuild(float* pos) override {
-        int rr = rc_batch_build_cells(b, pos, buf->vel, buf->image, buf->rtag, buf->cells_ws, buf->cells_ws_bytes, s);
+    float soft = 0.0f;   // the rebuild threshold of the path lengths
+    // The set of replicas a build re-orders and re-lists, from the last status read's per-replica
+    // fold: those with a block that crossed the rebuild threshold and those whose largest path
+    // length exceeds margin x that threshold.  Uploaded from a pinned buffer (the two buffers
+    // alternate; a status read, which waits for the stream, separates two builds).
+    int rebuild(float* pos, RebuildKind kind, float* kept_path, int64_t* rebuilt) override {
+        const int R = b->R;
+        int* set = b->h_build[b->build_parity];
+        b->build_parity ^= 1;
+        const int* flag = b->h_rep;
+        const int* path = b->h_rep + R;
+        float kp = 0.0f;
+        int64_t nre = 0;
+        const bool retry = kind == kRebuildRetry && (int)b->last_set.size() == R;
+        for (int r = 0; r < R; ++r) {
+            int on = 1;
+            if (retry) {
+                on = b->last_set[r];
+            } else if (kind == kRebuildFlagged) {
+                float pr;
+                std::memcpy(&pr, &path[r], sizeof pr);
+                on = flag[r] != 0 || pr > (float)b->margin * soft;
+                if (!on) kp = std::max(kp, pr);
+            }
+            set[r] = on;
+            if (on) nre += b->counts[r];
+        }
+        if (kind == kRebuildFlagged || retry) b->last_set.assign(set, set + R);
+        else b->last_set.clear();   // a full build: a retry rebuilds everything
+        if ((int)b->prev_path.size() != R) b->prev_path.assign(R, 0.0f);
+        for (int r = 0; r < R; ++r) {
+            if (set[r]) {
+                b->prev_path[r] = 0.0f;
+            } else {
+                float pr;
+                std::memcpy(&pr, &path[r], sizeof pr);
+                b->prev_path[r] = pr;
+            }
+        }
+        *kept_path = kp;
+        *rebuilt = nre;
+        HIP_TRY(&b->c, hipMemcpyAsync(b->d_build, set, sizeof(int) * (size_t)R, hipMemcpyHostToDevice, s));
+        int rr = batch_build_cells(b, pos, buf->vel, buf->image, buf->rtag, buf->cells_ws, buf->cells_ws_bytes,
+                                   b->d_build, s);
         if (rr) return rr;
         return batch_build_nlist(b, pos, buf->vel, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
-                                 buf->nn, buf->status, true, s);
+                                 buf->nn, buf->status, true, b->d_build, s);
+    }
+    hipError_t fold(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t st) override {
+        if (vel) {
+            hipError_t e = launch_fold_reps(blk, vel, b->d_desc, b->R, b->d_rep, status, st);
+            if (e != hipSuccess) return e;
+        }
+        return launch_fold_status(blk, nb, nullptr, N, status, st);
+    }
+    bool read_after_replay() override { return true; }
+    // growth of each replica's largest path length since the previous fold (or its build)
+    bool path_growth(int64_t C, double* growth) override {
+        const int R = b->R;
+        if ((int)b->prev_path.size() != R) b->prev_path.assign(R, 0.0f);
+        double g = 0.0;
+        for (int r = 0; r < R; ++r) {
+            float pr;
+            std::memcpy(&pr, &b->h_rep[R + r], sizeof pr);
+            g = std::max(g, (double)(pr - b->prev_path[r]));
+            b->prev_path[r] = pr;
+        }
+        *growth = g / (double)std::max<int64_t>(C, 1);
+        return true;
     }
     int bonds(const float* pos, int row) override {
         HIP_TRY(&b->c, launch_bonds_batch(reinterpret_cast<const float4*>(pos), buf->nlist, buf->nn, buf->k_max,
-                                          b->n_slots, all_tables(b), b->d_rep, b->d_chunk_rep, b->R,
+                                          b->n_slots, all_tables(b), b->d_desc, b->d_chunk_rep, b->R,
                                           buf->bonds_log + (size_t)row * b->R,
                                           reinterpret_cast<unsigned long long*>(b->c.d_part), s));
         return RC_OK;
@@ -461,7 +579,7 @@ struct BatchOps final : DriveOps {
         return launch_step_timed(a, true, s, sums, step);
     }
     int reduce_ev(int row) override {
-        HIP_TRY(&b->c, launch_reduce_rows_batch(b->c.d_part, b->d_rep, b->R, 0, kEvWords,
+        HIP_TRY(&b->c, launch_reduce_rows_batch(b->c.d_part, b->d_desc, b->R, 0, kEvWords,
                                                 buf->ev_log + (size_t)row * b->R * kEvWords, kEvWords, s));
         return RC_OK;
     }
@@ -517,5 +635,6 @@ extern "C" int rc_batch_run(rc_batch* b, const rc_md_buffers* buf, const rc_inte
     ops.b = b;
     ops.buf = buf;
     ops.s = s;
+    ops.soft = tmpl.soft;
     return md_drive(c, ops, buf, b->n_slots, tmpl, step0, n_steps, opt, stats, s);
 }

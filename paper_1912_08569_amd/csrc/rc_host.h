@@ -86,6 +86,13 @@ struct rc_ctx {
     void* ws_user = nullptr;
     std::vector<hipEvent_t> tk_events;  // event pairs of time_kernels
     std::vector<int> tk_kind;           // per pair: 0 step kernel, 1 first pass of the sums form
+    // device words copied to (pinned) host memory with every status read (a batch's per-replica fold)
+    struct StatusExtra {
+        void* host;
+        const void* dev;
+        size_t bytes;
+    };
+    std::vector<StatusExtra> status_extra;
     std::string err;
 };
 
@@ -145,13 +152,34 @@ int compile_table(int nt, const rc_pair_coeff* table, double r_buff, DevEntry* o
 void drop_graphs(rc_ctx* c);
 
 // What the chunked driver needs from a system (one or a batch).
+enum RebuildKind {
+    kRebuildAll = 0,      // the first build of a run: every particle
+    kRebuildFlagged = 1,  // a build the status flags asked for
+    kRebuildRetry = 2,    // the first build of a resumed run: the set of the build that overflowed
+};
 struct DriveOps {
     virtual ~DriveOps() = default;
     // cell sort (permutes pos, vel, image) and list build from pos; the list
     // kernels write the status words whole: KMAX and the overflow flag of the
     // new list, MAXPATH zero and the chunk markers cleared (as a chunk reset
-    // leaves them)
-    virtual int rebuild(float* pos) = 0;
+    // leaves them).  A system may rebuild part of its particles (a batch: the
+    // replicas that need it); *kept_path receives the largest path length of
+    // the particles that keep their lists (0 when every list is rebuilt) and
+    // *rebuilt the number of particles whose lists were rebuilt.
+    virtual int rebuild(float* pos, RebuildKind kind, float* kept_path, int64_t* rebuilt) = 0;
+    // fold the step kernel's per-block status slots into the status word (and
+    // reset them); vel non-NULL: also raise MAXPATH to the largest path length
+    virtual hipError_t fold(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s) {
+        return launch_fold_status(blk, nb, vel, N, status, s);
+    }
+    // whether a rollback's replay is folded and read back before its rebuild
+    // (a partial rebuild takes its set from the state the replay ends in)
+    virtual bool read_after_replay() { return false; }
+    // after a chunk's status read: the largest growth per step of any part's
+    // largest path length over the chunk's C steps, when the system keeps
+    // lists of different ages (a batch after partial rebuilds); false: the
+    // driver uses the growth of the overall largest path length
+    virtual bool path_growth(int64_t, double*) { return false; }
     // bond count(s) of the state in pos into log row `row`
     virtual int bonds(const float* pos, int row) = 0;
     // one step launch with a filled StepArgs (ev: partial rows to ctx->d_part)

@@ -166,6 +166,8 @@ int read_status_spin(rc_ctx* c, const int* d_status, int* hst, hipStream_t s) {
     if (!c->h_status) HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(int) * RC_STATUS_WORDS));
     if (!c->ev_sync) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
     HIP_TRY(c, hipMemcpyAsync(c->h_status, d_status, sizeof(int) * RC_STATUS_WORDS, hipMemcpyDeviceToHost, s));
+    for (const rc_ctx::StatusExtra& x : c->status_extra)
+        HIP_TRY(c, hipMemcpyAsync(x.host, x.dev, x.bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipEventRecord(c->ev_sync, s));
     // a blocking synchronisation costs tens of microseconds of wake-up per call; the driver calls
     // this once per chunk, so it spins on the event instead
@@ -513,10 +515,13 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
                     buf->k_max);
     };
     bool first = opt.resume == 0;  // a resumed state owes its last step's final half kick
-    auto rebuild = [&](int which) -> int {
-        int rr = ops.rebuild(P[which]);
+    float kept_path = 0.0f;        // largest path length of the particles the last build kept
+    auto rebuild = [&](int which, RebuildKind kind) -> int {
+        int64_t nre = 0;
+        int rr = ops.rebuild(P[which], kind, &kept_path, &nre);
         if (rr) return rr;
         ++st.rebuilds;
+        st.particles_rebuilt += nre;
         need_snap = true;
         if (defer_check) {
             check_pending = true;
@@ -631,7 +636,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         rate = prev.rate;
         last_maxpath = prev.last_maxpath;
         st.list_kept = 1;
-    } else if ((r = rebuild(cur))) {
+    } else if ((r = rebuild(cur, opt.resume ? kRebuildRetry : kRebuildAll))) {
         return finish(r);
     }
 
@@ -732,7 +737,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         dev_base = chunk_start;
         // ---- run it --------------------------------------------------------------
         if ((r = run_steps(chunk_start, C))) return finish(r);
-        HIP_TRY(c, launch_fold_status(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
+        HIP_TRY(c, ops.fold(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
         if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
         if (timing && (r = tk_collect())) return finish(r);
         ++st.chunks;
@@ -746,7 +751,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             row = ep_row;
             HIP_TRY(c, launch_copy_state(ws_pos, ws_vel, buf->image ? ws_image : nullptr,
                                          reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
-                                         reinterpret_cast<int4*>(buf->image), N, s, true));
+                                         reinterpret_cast<int4*>(buf->image), N, s));
             s_cur = ep_step;
             return finish(overflow());
         }
@@ -760,10 +765,10 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             cur = ep_cur;
             first = ep_first;
             row = ep_row;
-            if (snap_in_ws)   // the state the epoch's list build left (path lengths zero)
+            if (snap_in_ws)   // the state the epoch's list build left (its path lengths included)
                 HIP_TRY(c, launch_copy_state(ws_pos, ws_vel, buf->image ? ws_image : nullptr,
                                              reinterpret_cast<float4*>(P[cur]), reinterpret_cast<float4*>(buf->vel),
-                                             reinterpret_cast<int4*>(buf->image), N, s, true));
+                                             reinterpret_cast<int4*>(buf->image), N, s));
             else
                 HIP_TRY(c, launch_copy_state(reinterpret_cast<const float4*>(buf->snap_pos),
                                              reinterpret_cast<const float4*>(buf->snap_vel),
@@ -776,20 +781,27 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, ep_step));
             dev_base = ep_step;
             if ((r = run_steps(ep_step, n_re))) return finish(r);
-            HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
+            if (ops.read_after_replay()) {   // the replay's own flags and path lengths choose the set
+                HIP_TRY(c, ops.fold(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
+                if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
+            } else {
+                HIP_TRY(c, launch_fold_status(c->d_blk, nb, nullptr, N, buf->status, s));  // drop replay flags
+            }
             s_cur = ep_step + (uint64_t)n_re;
             ++st.rollbacks;
-            if ((r = rebuild(cur))) return finish(r);
+            if ((r = rebuild(cur, kRebuildFlagged))) return finish(r);
             rate = std::max(rate, (double)mp / std::max<int64_t>(1, C));
-            last_maxpath = 0.0f;
+            last_maxpath = kept_path;
             continue;
         }
         s_cur = chunk_start + (uint64_t)C;
-        rate = std::max(0.5 * rate, (double)(mp - last_maxpath) / (double)C);
+        double growth = 0.0;
+        if (!ops.path_growth(C, &growth)) growth = (double)(mp - last_maxpath) / (double)C;
+        rate = std::max(0.5 * rate, growth);
         last_maxpath = mp;
         if (f & RC_FLAG_REBUILD) {
-            if ((r = rebuild(cur))) return finish(r);
-            last_maxpath = 0.0f;
+            if ((r = rebuild(cur, kRebuildFlagged))) return finish(r);
+            last_maxpath = kept_path;
         }
     }
     // ---- final half kick (and the last log row) ------------------------------------

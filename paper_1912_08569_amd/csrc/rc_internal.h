@@ -236,7 +236,6 @@ struct RepDesc {
     uint32_t key_base;
     int off;       // first slot
     int n;         // particles
-    int shift;     // off minus the replica's first position in the compact key order
     int tab;       // first entry of its nt*nt table in the batch table array
     int pad;
 };
@@ -611,6 +610,7 @@ struct CellsArgsB {
     float4* tpos;
     float4* tvel;
     int4* timage;
+    const int* build;       // [R] nonzero: the replica is re-ordered (NULL: every replica)
 };
 hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s);
 
@@ -630,8 +630,18 @@ struct NlistArgsB {
     int* pl_j;              // packed copy of the list (NULL: none), see pack_wave_lists
     unsigned char* pl_o;
     int fresh_status;       // as in NlistArgs
+    const int* build;       // [R] nonzero: the replica's list is rebuilt (NULL: every replica)
 };
 hipError_t launch_nlist_batch(const NlistArgsB& a, hipStream_t s);
+// a list of k_old slots per particle copied into a layout of k_new >= k_old slots, with its packed copy
+// (pl_j NULL: none)
+hipError_t launch_relayout_list(const int* old_list, int k_old, int* new_list, int k_new, const int* nn, int N,
+                                int* pl_j, unsigned char* pl_o, hipStream_t s);
+// per-replica fold of a chunk (before launch_fold_status resets the slots), into out [2][R]:
+// out[r] = 1 when a block of replica r crossed the rebuild threshold, out[R + r] = the largest path
+// length of its slots (float bits); status[MAXPATH] is raised to the largest of all
+hipError_t launch_fold_reps(const int* blk, const float4* vel, const RepDesc* rep, int R, int* out, int* status,
+                            hipStream_t s);
 
 // per-replica bond counts: part = one u64 per 64-slot chunk, count = [R]
 hipError_t launch_bonds_batch(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,

@@ -201,3 +201,38 @@ def test_batch_list_overflow_mid_run_resumes_exactly():
     assert A.k_max > kmax0
     for r in range(len(reps)):
         assert all(np.array_equal(x, y) for x, y in zip(A.state_by_tag(r), B.state_by_tag(r))), f"replica {r}"
+
+
+def test_partial_rebuilds_keep_valid_lists_and_match_oracle():
+    # per-replica rebuilds: a build re-lists only the replicas that crossed (or neared) the rebuild
+    # threshold; the others keep their order, lists and path lengths.  After a long run every replica's
+    # current list must still hold every pair inside the cutoff: forces from the lists in place (no
+    # rebuild) against the oracle, bonds exact, and every path length below the stale threshold.
+    # (margin 1: only the replicas that crossed are rebuilt, the most partial builds)
+    reps = _mixed_replicas()
+    B = _batch(reps, seeds=range(20, 26), r_buff=0.3, rebuild_margin=1.0)
+    cfg = B.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=0)
+    rb = B.run(1200, cfg, log_period=300)
+    n_all = int(sum(s.N for s in reps))
+    st = rb.stats
+    assert st.steps_done == 1200 and st.rebuilds > 2
+    assert 0 < st.particles_rebuilt < st.rebuilds * n_all, "every build re-listed every replica"
+    assert B.vel[:, 3].max().item() <= 0.5 * 0.3 + 1e-6
+    F, ev = B.compute_forces()
+    bonds = B.bond_count()
+    evh = ev.cpu().numpy()
+    for r, s in enumerate(reps):
+        xyz, _, _, ty = B.state_by_tag(r)
+        ref = swap_ref.evaluate(xyz, ty, s.L, s.table)
+        assert_forces(B.by_tag(F, r), ref)
+        assert_energy(evh[r, 0], ref)
+        assert int(bonds[r]) == ref["bonds"], f"replica {r}"
+
+
+def test_zero_margin_rebuilds_every_replica():
+    reps = _mixed_replicas()
+    B = _batch(reps, seeds=range(6), rebuild_margin=0.0)
+    cfg = B.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=0)
+    rb = B.run(300, cfg, log_period=100)
+    n_all = int(sum(s.N for s in reps))
+    assert rb.stats.rebuilds > 1 and rb.stats.particles_rebuilt == rb.stats.rebuilds * n_all

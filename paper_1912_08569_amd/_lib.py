@@ -179,13 +179,20 @@ def declared_symbols():
 
 
 def load():
-    """Load librc.so; raises if it has not been built."""
+    """Load librc.so; raises if it has not been built.
+
+    torch is imported first: its wheel carries its own HIP and HSA runtimes,
+    and librc.so must bind to those (the ones that own the device memory it
+    is handed).  Loaded before torch, librc.so would map the system ROCm
+    runtime, and torch would then map its own beside it: two HIP runtimes in
+    one process, which can fail to bring up the device."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build the HIP engine first "
                            "(python -m paper_1912_08569_amd.build)")
+    import torch  # noqa: F401  (its HIP runtime first)
     lib = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in _SIGS.items():
         fn = getattr(lib, name)

@@ -90,3 +90,27 @@ def test_oracle_is_not_imported_by_the_package():
     code = "import sys, paper_1912_08569_amd; print(any(m.startswith('oracle') for m in sys.modules))"
     out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT).decode().strip()
     assert out == "False"
+
+
+_ONE_RUNTIME = r"""
+import sys
+sys.path.insert(0, {root!r})
+import numpy
+import workloads as W
+W.patchy_mixture(n_tri=40, n_di=60, L=12.0)    # host-side set-up (scipy k-d trees) before the engine
+import paper_1912_08569_amd  # noqa: F401      (torch not imported before)
+hip = sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l))
+hsa = sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'libhsa-runtime64' in l))
+print(len(hip), len(hsa), hip, hsa)
+"""
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    # librc.so binds to the HIP runtime torch brings (the one that owns the tensors it is given): a process
+    # that sets up a workload and then imports the package, with torch never imported before, maps one
+    # HIP and one HSA runtime, not the system ROCm's beside torch's
+    out = subprocess.run(["python", "-c", _ONE_RUNTIME.format(root=ROOT)], capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    n_hip, n_hsa = (int(x) for x in out.stdout.split()[:2])
+    assert n_hip == 1 and n_hsa == 1, out.stdout

@@ -11,13 +11,29 @@ from oracle import rigid_ref, swap_ref
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(autouse=True)
-def _device_first():
-    # the device is brought up before the workload's host-side set-up runs (as in every other GPU test
-    # file, where an engine object exists before the first input is generated)
-    import torch
-    torch.zeros(1, device="cuda")
-    yield
+_FRESH = r"""
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np
+import workloads as W
+s = W.patchy_mixture()                        # host-side set-up first, torch not imported yet
+from paper_1912_08569_amd import System       # then the engine (it brings torch's HIP runtime first)
+S = System.from_workload(s)
+F, ev = S.compute_forces()
+print("ok", s.N, bool(np.isfinite(F.cpu().numpy()).all()))
+"""
+
+
+def test_fresh_process_sets_up_the_workload_before_the_device():
+    # a process that generates the patchy mixture before its first device use, with torch imported only by
+    # the engine package (the order that once mapped two HIP runtimes and failed to bring up the device)
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    print("fresh process: patchy_mixture, then System and compute_forces", flush=True)
+    out = subprocess.run(["python", "-c", _FRESH.format(root=root)], capture_output=True, text=True, timeout=240)
+    assert out.returncode == 0, out.stderr[-3000:]
+    assert out.stdout.split()[0] == "ok" and out.stdout.split()[-1] == "True", out.stdout
 
 
 def _bodies(s):

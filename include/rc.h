@@ -470,6 +470,9 @@ typedef struct rc_md_buffers {
     int* status;       /* [RC_STATUS_WORDS]                                   */
     double* ev_log;    /* [rows*13] | NULL, rows = n_steps/log_period + 1     */
     unsigned long long* bonds_log; /* [rows] | NULL                           */
+    /* ev_log and bonds_log may be device memory or pinned host memory (the
+       driver's kernels write them; the run's final status read waits for
+       them); every other buffer is device memory.                          */
 } rc_md_buffers;
 
 typedef struct rc_md_options {

@@ -651,6 +651,8 @@ __global__ __launch_bounds__(kBlock) void k_fold_status(int* __restrict__ blk, i
 }
 
 hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s) {
+    // at most 256 blocks: each ends with atomics on the same status words (2048 blocks took 26 us at 1M
+    // particles against 8.5 us)
     const int work = vel ? std::max(N, nb) : nb;
     hipLaunchKernelGGL(k_fold_status, dim3(std::max(1, std::min(nblk(work, kBlock), 256))), dim3(kBlock), 0, s,
                        blk, nb, vel, N, status);
@@ -737,13 +739,30 @@ hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // fixed-order FP64 reduction of block partial rows
 // ---------------------------------------------------------------------------
+// Thread t's slice of one word: rows t, t + 256, t + 512, ... added in that
+// order; the loads of 32 rows are issued before their adds (the same sum,
+// without a load round trip per row).
+__device__ __forceinline__ double strided_row_sum(const double* __restrict__ p, int nblocks, int q) {
+    constexpr int U = 32;
+    double s = 0.0;
+    int b = threadIdx.x;
+    for (; b + (U - 1) * kBlock < nblocks; b += U * kBlock) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[(size_t)(b + u * kBlock) * kEvWords + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; b < nblocks; b += kBlock) s += p[(size_t)b * kEvWords + q];
+    return s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* __restrict__ part, int nblocks,
                                                        int first, int count, double* __restrict__ out) {
     // one block per output word; each thread sums a strided slice, then a tree
     __shared__ double red[kBlock];
     const int q = first + blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[(size_t)b * kEvWords + q];
+    const double s = strided_row_sum(part, nblocks, q);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -753,9 +772,51 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* __restrict
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// The same sums in two launches, for the driver's log rows: first every
+// (thread slice t, word q) sum of k_reduce_rows, one thread each, with the
+// threads of a wavefront on consecutive words of consecutive rows (coalesced
+// reads spread over many CUs instead of 13 CUs each reading every row), then
+// per word the same tree over the 256 slices.  Bit for bit k_reduce_rows.
+__global__ __launch_bounds__(kWave) void k_row_slices(const double* __restrict__ part, int nblocks, int first,
+                                                     int count, double* __restrict__ slice) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kBlock * count) return;
+    const int t = i / count, q = first + i % count;
+    constexpr int U = 16;
+    double s = 0.0;
+    int b = t;
+    for (; b + (U - 1) * kBlock < nblocks; b += U * kBlock) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = part[(size_t)(b + u * kBlock) * kEvWords + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; b < nblocks; b += kBlock) s += part[(size_t)b * kEvWords + q];
+    slice[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_tree(const double* __restrict__ slice, int count,
+                                                    double* __restrict__ out) {
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = slice[threadIdx.x * count + blockIdx.x];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3(count), dim3(kBlock), 0, s, part, nblocks, first, count, out);
+                              hipStream_t s, double* slice) {
+    if (slice && count <= kEvWords) {
+        hipLaunchKernelGGL(k_row_slices, dim3(nblk((long)kBlock * count, kWave)), dim3(kWave), 0, s, part, nblocks,
+                           first, count, slice);
+        hipLaunchKernelGGL(k_row_tree, dim3(count), dim3(kBlock), 0, s, slice, count, out);
+    } else {
+        hipLaunchKernelGGL(k_reduce_rows, dim3(count), dim3(kBlock), 0, s, part, nblocks, first, count, out);
+    }
     return hipGetLastError();
 }
 
@@ -769,8 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows_batch(const double* __re
     const double* p = part + (size_t)(d.off / kWave) * kEvWords;
     const int nblocks = (d.n + kWave - 1) / kWave;
     const int q = first + blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += p[(size_t)b * kEvWords + q];
+    const double s = strided_row_sum(p, nblocks, q);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {

@@ -62,7 +62,7 @@ int check_common(rc_ctx* c, int N, const void* pos) {
 }
 
 int reduce_rows(rc_ctx* c, int nb, int first, int count, double* out, hipStream_t s) {
-    HIP_TRY(c, launch_reduce_rows(c->d_part, nb, first, count, out, s));
+    HIP_TRY(c, launch_reduce_rows(c->d_part, nb, first, count, out, s, c->d_slices));
     return RC_OK;
 }
 
@@ -131,8 +131,11 @@ int rc_create(rc_ctx** out, int ntypes, const rc_pair_coeff* table, double r_buf
         hipMemcpy(c->d_tab, c->host_tab.data(), sizeof(DevEntry) * ntypes * ntypes,
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMalloc(&c->d_step_base, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_slices, sizeof(double) * kRowSlices) != hipSuccess ||
         noalloc_scratch_here(c->device, &c->noalloc_scratch) != hipSuccess) {
         if (c->d_tab) (void)hipFree(c->d_tab);
+        if (c->d_step_base) (void)hipFree(c->d_step_base);
+        if (c->d_slices) (void)hipFree(c->d_slices);
         delete c;
         return RC_ERR_HIP;
     }

@@ -57,6 +57,7 @@ struct rc_ctx {
     double* d_part = nullptr;           // block partial rows (13 doubles each) or param partials
     size_t part_bytes = 0;
     unsigned long long* d_step_base = nullptr;
+    double* d_slices = nullptr;         // kRowSlices doubles: the two-launch row reduction
     int* d_blk = nullptr;               // per-block status slots of the step kernel
     int blk_cap = 0;                    // slots allocated (blocks)
     int gather_width = 2;               // flattened list entries per lane and pass of the step kernel

@@ -142,7 +142,7 @@ int set_workspace(rc_ctx* c, void* ws, size_t bytes, int N, int k_max, int nvec)
 
 size_t ctx_device_bytes(const rc_ctx* c) {
     size_t b = sizeof(DevEntry) * (size_t)c->nt * (size_t)c->nt + sizeof(unsigned long long) + c->part_bytes +
-               sizeof(int) * 3 * (size_t)c->blk_cap;
+               sizeof(int) * 3 * (size_t)c->blk_cap + (c->d_slices ? sizeof(double) * kRowSlices : 0);
     if (!c->ws_user) b += 5 * c->pl_cap + sizeof(float) * c->ssum_cap + 2 * sizeof(double) * c->hsum_cap;
     return b;
 }
@@ -245,6 +245,8 @@ void free_ctx_buffers(rc_ctx* c) {
     if (c->d_tab) (void)hipFree(c->d_tab);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_step_base) (void)hipFree(c->d_step_base);
+    if (c->d_slices) (void)hipFree(c->d_slices);
+    c->d_slices = nullptr;
     if (c->d_blk) (void)hipFree(c->d_blk);
     if (c->d_ssum && !c->ws_user) (void)hipFree(c->d_ssum);
     if (c->d_hsum && !c->ws_user) (void)hipFree(c->d_hsum);

@@ -529,9 +529,11 @@ hipError_t launch_bond_partners(const float4* pos, const int* nlist, const int* 
 hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t s);
 hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s);
 
-// reduce nblocks partial rows of 13 doubles into out[first .. first+count)
+// reduce nblocks partial rows of 13 doubles into out[first .. first+count) (fixed order); slice:
+// NULL, or scratch of kRowSlices doubles for the same sums in two launches that spread the reads
+constexpr int kRowSlices = 256 * 13;
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
-                              hipStream_t s);
+                              hipStream_t s, double* slice = nullptr);
 // clear the chunk-local status markers (keeping KMAX, MAXPATH and the overflow flag) and, if
 // step_base is not NULL, set *step_base = step
 hipError_t launch_status_reset_chunk(int* status, hipStream_t s, unsigned long long* step_base = nullptr,

@@ -305,9 +305,11 @@ class System:
             self.build()    # picks the form from the new list
         rows = (n_steps // log_period + 2) if log_period > 0 else 1
         if self._log is None or self._log.shape[0] < rows * 14:
-            self._log = torch.zeros(max(rows, 64) * 14, dtype=torch.float64, device=self.device)
+            # pinned host memory, which the driver's kernels write directly: the rows are on the host when
+            # the run returns (its last status read waits for them), with no copy back
+            self._log = torch.zeros(max(rows, 64) * 14, dtype=torch.float64, pin_memory=True)
         ev_log = self._log[:rows * 13]
-        bonds_log = self._log[rows * 13:rows * 14]       # u64 counts in the same buffer (one copy back)
+        bonds_log = self._log[rows * 13:rows * 14]       # u64 counts in the same buffer
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
                              int(adapt), int(one_block), 0, int(keep_list and self._continues), int(time_kernels))
         self._continues = False
@@ -332,9 +334,9 @@ class System:
         if self.step_form == "auto" and st.rebuilds > 0:   # the next run takes the form of the last list
             self.ctx.set_step_form(self._form_for(st.nswap))
         n = int(st.log_rows)
-        host = self._log[:rows * 14].cpu()
-        ev = host[:rows * 13].view(rows, 13)[:n].numpy()
-        bonds = host[rows * 13:rows * 14].view(torch.int64)[:n].numpy()
+        host = self._log[:rows * 14]
+        ev = host[:rows * 13].view(rows, 13)[:n].numpy().copy()
+        bonds = host[rows * 13:rows * 14].view(torch.int64)[:n].numpy().copy()
         return RunResult(stats=st, ev=ev, bonds=bonds)
 
     def invalidate(self):

@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=1000)
     p.add_argument("--seq-steps", type=int, default=200, help="steps of each replica run alone")
     p.add_argument("--no-tune", action="store_true", help="batched run with the default launch settings")
+    p.add_argument("--tune-walk", action="store_true",
+                   help="let the batch autotuner try the walk form too (2-4x slower on the replica set)")
     p.add_argument("--no-adjoint", action="store_true", help="skip the forward/adjoint timings")
     p.add_argument("--only-extras", action="store_true", help="skip the 1M-particle run (debugging)")
     p.add_argument("--no-dumbbells", action="store_true", help="skip the dumbbell-mixture size sweep")
@@ -264,14 +266,16 @@ def batch_bench(a):
           flush=True)
     mk_cfg = lambda S, seed=0: S.integrator(dt=0.002, kT=0.1, gamma=1.0, seed=seed)  # noqa: E731
     tuned = None
-    r_buff, form, width, G = 0.3, "walk", 2, 16
+    r_buff, form, width, G = 0.3, "sums", 4, 32   # the tuned settings of the replica set
     if not a.no_tune:
         factory = lambda rb: Batch(reps, r_buff=rb, seeds=range(R))  # noqa: E731
         probe = factory(0.3)
         cfg = mk_cfg(probe)
         del probe
+        # every candidate from the same start, timed over the benchmark's own window
         tuned = tune.autotune(factory, cfg, signature=f"replica_set R={R} N={ntot} seed=1004",
-                              r_buffs=(0.2, 0.3, 0.45), steps=200, warmup=100, cache=None,
+                              r_buffs=(0.2, 0.3, 0.45), forms=("sums", "walk") if a.tune_walk else ("sums",),
+                              steps=a.batch_steps, warmup=200, cache=None,
                               log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         r_buff, form, width, G = tuned["r_buff"], tuned["form"], tuned["width"], tuned["graph_steps"]
     B = Batch(reps, r_buff=r_buff, seeds=range(R))

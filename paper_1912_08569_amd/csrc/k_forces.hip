@@ -660,11 +660,22 @@ hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* s
 }
 
 // Per-replica fold of a batch chunk, before k_fold_status resets the block
-// slots: one workgroup per replica folds its own 64-slot chunks (the flag of
-// any block that crossed the rebuild threshold, the largest path length) and
-// stores them; status[MAXPATH] is raised to the largest of all.  Path lengths
-// are non-negative, so their float bits order like ints.
-__global__ __launch_bounds__(kBlock) void k_fold_reps(const int* __restrict__ blk, const float4* __restrict__ vel,
+// slots, in two launches: the largest path length of every 64-slot chunk
+// (one wavefront per chunk, all chunks in parallel), then one workgroup per
+// replica over its chunks' maxima and block flags, which stores the flag of
+// any block that crossed the rebuild threshold and the largest path length;
+// status[MAXPATH] is raised to the largest of all.  Path lengths are
+// non-negative, so their float bits order like ints.
+__global__ __launch_bounds__(kBlock) void k_chunk_paths(const float4* __restrict__ vel, int nb,
+                                                       float* __restrict__ chunk_path) {
+    const int ch = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (ch >= nb) return;   // uniform per wavefront
+    const float p = wave_maxf(vel[(size_t)ch * kWave + (threadIdx.x & (kWave - 1))].w);
+    if ((threadIdx.x & (kWave - 1)) == 0) chunk_path[ch] = p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fold_reps(const int* __restrict__ blk,
+                                                     const float* __restrict__ chunk_path,
                                                      const RepDesc* __restrict__ rep, int* __restrict__ rep_flag,
                                                      int* __restrict__ rep_path, int* __restrict__ status) {
     __shared__ float r_p[kBlock / kWave];
@@ -673,9 +684,9 @@ __global__ __launch_bounds__(kBlock) void k_fold_reps(const int* __restrict__ bl
     const int c0 = rep[r].off / kWave, c1 = (rep[r].off + rep[r].n + kWave - 1) / kWave;
     float pm = 0.0f;
     int fl = 0;
-    for (int i = c0 * kWave + (int)threadIdx.x; i < c1 * kWave; i += blockDim.x) {
-        pm = fmaxf(pm, vel[i].w);
-        if ((i & (kWave - 1)) == 0) fl |= blk[3 * (i / kWave)] & RC_FLAG_REBUILD;
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+        pm = fmaxf(pm, chunk_path[c]);
+        fl |= blk[3 * c] & RC_FLAG_REBUILD;
     }
     pm = wave_maxf(pm);
 #pragma unroll
@@ -696,9 +707,10 @@ __global__ __launch_bounds__(kBlock) void k_fold_reps(const int* __restrict__ bl
     }
 }
 
-hipError_t launch_fold_reps(const int* blk, const float4* vel, const RepDesc* rep, int R, int* out, int* status,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_fold_reps, dim3(R), dim3(kBlock), 0, s, blk, vel, rep, out, out + R, status);
+hipError_t launch_fold_reps(const int* blk, const float4* vel, int nb, const RepDesc* rep, int R, int* out,
+                            float* chunk_path, int* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_paths, dim3(nblk((long)nb * kWave, kBlock)), dim3(kBlock), 0, s, vel, nb, chunk_path);
+    hipLaunchKernelGGL(k_fold_reps, dim3(R), dim3(kBlock), 0, s, blk, chunk_path, rep, out, out + R, status);
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ struct rc_batch {
     int* d_rep = nullptr;
     int* h_rep = nullptr;            // pinned [2][R]
     int* d_build = nullptr;
+    float* d_chunk_path = nullptr;   // [n_slots / 64] scratch of the fold
     int* h_build[2] = {nullptr, nullptr};   // pinned [R] sets, alternating between builds
     int build_parity = 0;
     std::vector<int> last_set;       // the set of the last build of a run (a resumed run's first)
@@ -44,6 +45,7 @@ void free_batch(rc_batch* b) {
     free_ctx_buffers(&b->c);
     if (b->d_rep) (void)hipFree(b->d_rep);
     if (b->d_build) (void)hipFree(b->d_build);
+    if (b->d_chunk_path) (void)hipFree(b->d_chunk_path);
     if (b->h_rep) (void)hipHostFree(b->h_rep);
     for (int q = 0; q < 2; ++q)
         if (b->h_build[q]) (void)hipHostFree(b->h_build[q]);
@@ -198,6 +200,7 @@ int rc_batch_create(rc_batch** out, int R, int ntypes, const rc_pair_coeff* tabl
               hipMalloc(&b->d_rep, sizeof(int) * 2 * (size_t)R) == hipSuccess &&
               hipMemset(b->d_rep, 0, sizeof(int) * 2 * (size_t)R) == hipSuccess &&
               hipMalloc(&b->d_build, sizeof(int) * (size_t)R) == hipSuccess &&
+              hipMalloc(&b->d_chunk_path, sizeof(float) * (size_t)(slots / kWave)) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void**>(&b->h_rep), sizeof(int) * 2 * (size_t)R) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void**>(&b->h_build[0]), sizeof(int) * (size_t)R) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void**>(&b->h_build[1]), sizeof(int) * (size_t)R) == hipSuccess;
@@ -547,7 +550,7 @@ struct BatchOps final : DriveOps {
     }
     hipError_t fold(int* blk, int nb, const float4* vel, int N, int* status, hipStream_t st) override {
         if (vel) {
-            hipError_t e = launch_fold_reps(blk, vel, b->d_desc, b->R, b->d_rep, status, st);
+            hipError_t e = launch_fold_reps(blk, vel, nb, b->d_desc, b->R, b->d_rep, b->d_chunk_path, status, st);
             if (e != hipSuccess) return e;
         }
         return launch_fold_status(blk, nb, nullptr, N, status, st);

@@ -700,6 +700,24 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         return RC_OK;
     };
 
+    // The run's finishing work: the bond count of the final state, the final half kick with the last
+    // log row, the positions back into buf->pos.
+    auto finishing = [&]() -> int {
+        const bool ev = logging && buf->ev_log;
+        int rr;
+        if (logging && (rr = log_now(cur))) return rr;
+        if (!first) {
+            if ((rr = direct(s_end, RC_STEP_FINISH, ev))) return rr;
+        } else if (ev) {
+            // zero steps: report the state as it is
+            if ((rr = direct(step0, RC_STEP_OBSERVE, ev))) return rr;
+        }
+        if (logging) ++row;
+        if (cur != 0) HIP_TRY(c, hipMemcpyAsync(buf->pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
+        return RC_OK;
+    };
+    bool finished = false;   // the finishing work ran with the last chunk and its status read confirmed it
+
     bool first_chunk = true;
     while (s_cur < s_end) {
         // ---- plan the chunk ---------------------------------------------------
@@ -740,6 +758,16 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         // ---- run it --------------------------------------------------------------
         if ((r = run_steps(chunk_start, C))) return finish(r);
         HIP_TRY(c, ops.fold(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
+        // The run's last chunk queues the finishing work before its status read, so that one host wait
+        // covers both.  The read confirms it when no force of the chunk or of the finishing step was
+        // evaluated on a stale list (MAXPATH, the largest path length of the final state, at most the
+        // stale threshold); otherwise the chunk is rolled back and replayed as below, which undoes it.
+        // Only a chunk the planner expects to stay below the rebuild threshold speculates (adaptive
+        // chunks with a measured growth rate), so a fallback is rare and the run's build schedule is
+        // the one without speculation.
+        const bool spec = can_roll && !timing && opt.adapt && rate > 0.0 && chunk_start + (uint64_t)C == s_end &&
+                          (double)last_maxpath + 1.5 * rate * (double)C < (double)tmpl.soft;
+        if (spec && (r = finishing())) return finish(r);
         if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
         if (timing && (r = tk_collect())) return finish(r);
         ++st.chunks;
@@ -761,7 +789,7 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if (f & RC_FLAG_NONFINITE) return finish(fail(c, RC_ERR_NONFINITE, "non-finite position or velocity"));
         float mp;
         std::memcpy(&mp, &hst[RC_ST_MAXPATH], sizeof mp);
-        if (f & RC_FLAG_STALE) {
+        if ((f & RC_FLAG_STALE) || (spec && mp > hard)) {
             if (!can_roll) return finish(fail(c, RC_ERR_ARG, "stale list without rollback buffers"));
             // roll back to the epoch's snapshot and replay up to the first soft crossing, then rebuild
             cur = ep_cur;
@@ -801,41 +829,34 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         if (!ops.path_growth(C, &growth)) growth = (double)(mp - last_maxpath) / (double)C;
         rate = std::max(0.5 * rate, growth);
         last_maxpath = mp;
+        if (spec) {   // done; a rebuild the flags ask for is left to the next run on this list
+            finished = true;
+            break;
+        }
         if (f & RC_FLAG_REBUILD) {
             if ((r = rebuild(cur, kRebuildFlagged))) return finish(r);
             last_maxpath = kept_path;
         }
     }
-    // ---- final half kick (and the last log row) ------------------------------------
-    if (check_pending) {  // the list of the last build has not been checked yet
+    // ---- final half kick (and the last log row), unless the last chunk did it ----------
+    if (!finished) {
+        if (check_pending) {  // the list of the last build has not been checked yet
+            if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
+            check_pending = false;
+            if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW)
+                return finish(overflow());  // all steps done, the final half kick still due
+        }
+        if (need_snap) {   // a build after the last chunk: its state owes the final half kick
+            ep_step = s_cur;
+            ep_cur = cur;
+            ep_first = false;
+            need_snap = false;
+        }
+        if ((r = finishing())) return finish(r);
+        // the status read waits for all of the run's work (pinned copy and an event, no blocking sync)
         if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
-        check_pending = false;
-        if (hst[RC_ST_FLAGS] & RC_FLAG_NLIST_OVERFLOW)
-            return finish(overflow());  // all steps done, the final half kick still due
+        if (timing && (r = tk_collect())) return finish(r);
     }
-    if (need_snap) {   // a build after the last chunk: its state owes the final half kick
-        ep_step = s_cur;
-        ep_cur = cur;
-        ep_first = false;
-        need_snap = false;
-    }
-    {
-        const bool ev = logging && buf->ev_log;
-        if (logging) {
-            if ((r = log_now(cur))) return finish(r);
-        }
-        if (!first) {
-            if ((r = direct(s_end, RC_STEP_FINISH, ev))) return finish(r);
-        } else if (ev) {
-            // zero steps: report the state as it is
-            if ((r = direct(step0, RC_STEP_OBSERVE, ev))) return finish(r);
-        }
-        if (logging) ++row;
-    }
-    if (cur != 0) HIP_TRY(c, hipMemcpyAsync(buf->pos, P[cur], 16 * (size_t)N, hipMemcpyDeviceToDevice, s));
-    // the status read waits for all of the run's work (pinned copy and an event, no blocking sync)
-    if ((r = read_status_spin(c, buf->status, hst, s))) return finish(r);
-    if (timing && (r = tk_collect())) return finish(r);
     // what the next run needs to continue on this list
     c->md.valid = can_roll;
     c->md.dyn = dyn;

@@ -641,9 +641,10 @@ hipError_t launch_relayout_list(const int* old_list, int k_old, int* new_list, i
                                 int* pl_j, unsigned char* pl_o, hipStream_t s);
 // per-replica fold of a chunk (before launch_fold_status resets the slots), into out [2][R]:
 // out[r] = 1 when a block of replica r crossed the rebuild threshold, out[R + r] = the largest path
-// length of its slots (float bits); status[MAXPATH] is raised to the largest of all
-hipError_t launch_fold_reps(const int* blk, const float4* vel, const RepDesc* rep, int R, int* out, int* status,
-                            hipStream_t s);
+// length of its slots (float bits); status[MAXPATH] is raised to the largest of all.  nb = slots / 64
+// chunks; chunk_path: scratch of nb floats
+hipError_t launch_fold_reps(const int* blk, const float4* vel, int nb, const RepDesc* rep, int R, int* out,
+                            float* chunk_path, int* status, hipStream_t s);
 
 // per-replica bond counts: part = one u64 per 64-slot chunk, count = [R]
 hipError_t launch_bonds_batch(const float4* pos, const int* nlist, const int* nn, int k_max, int N, Table tab,

@@ -11,10 +11,12 @@ Four knobs change only the speed of a run, never its physics:
 * the neighbour-list skin r_buff (longer lists against fewer rebuilds; the
   trajectory changes only by rounding order).
 
-``autotune`` times short runs of every candidate on a throw-away copy of the
-workload (``factory(r_buff)`` builds a fresh ``System`` or ``Batch``) and
-returns the fastest; results are cached in a JSON file keyed by a workload
-signature, so a second call with the same signature costs nothing.
+``autotune`` times short runs of every candidate, each on a fresh copy of the
+workload (``factory(r_buff)`` builds a new ``System`` or ``Batch`` from the
+same start, so every candidate runs the same stretch of the trajectory: a
+relaxing start rebuilds its lists more often than a settled one) and returns
+the fastest; results are cached in a JSON file keyed by a workload signature,
+so a second call with the same signature costs nothing.
 """
 from __future__ import annotations
 
@@ -60,28 +62,23 @@ def autotune(factory: Callable[[float], object], cfg, signature: str, r_buffs: S
         if hit:
             return hit
     results = []
-    step0 = 0
     for rb in r_buffs:
-        obj = factory(float(rb))
-        obj.run(warmup, cfg, step0=step0)
-        step0 += warmup
         for form, w, G in itertools.product(forms, widths, graph_steps):
+            obj = factory(float(rb))
             obj.set_step_form(form)
             obj.set_gather_width(int(w))
-            obj.run(2 * int(G), cfg, step0=step0, graph_steps=int(G))   # graphs built, caches warm
-            step0 += 2 * int(G)
+            obj.run(warmup, cfg, step0=0, graph_steps=int(G))   # graphs built, caches warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = obj.run(steps, cfg, step0=step0, graph_steps=int(G))
+            r = obj.run(steps, cfg, step0=warmup, graph_steps=int(G))
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            step0 += steps
             results.append({"r_buff": float(rb), "form": form, "width": int(w), "graph_steps": int(G),
                             "us_per_step": dt / steps * 1e6, "rebuilds": int(r.stats.rebuilds)})
             if log:
                 log(f"tune {signature}: r_buff {rb} {form} width {w} graph_steps {G}: "
-                    f"{dt / steps * 1e6:.2f} us/step")
-        del obj
+                    f"{dt / steps * 1e6:.2f} us/step, {int(r.stats.rebuilds)} builds")
+            del obj
         torch.cuda.empty_cache()
     best = min(results, key=lambda x: x["us_per_step"])
     out = dict(best)

@@ -259,6 +259,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_cells_batch(CellsArgsB a) {
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
+// The permuted state back from the temporaries, in one launch (vel and image may be NULL)
+__global__ __launch_bounds__(kBlock) void k_copy_back(const float4* __restrict__ tpos, const float4* __restrict__ tvel,
+                                                     const int4* __restrict__ timage, float4* __restrict__ pos,
+                                                     float4* __restrict__ vel, int4* __restrict__ image, int N) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    pos[i] = tpos[i];
+    if (vel) vel[i] = tvel[i];
+    if (image) image[i] = timage[i];
+}
+
 hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s) {
     const int nk = (int)a.nkeys;
     const int nsb = nblk(nk, kScanTile);
@@ -273,14 +284,9 @@ hipError_t launch_cells_batch(const CellsArgsB& a, hipStream_t s) {
     hipLaunchKernelGGL(k_sort_cells_batch, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_permute, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.order, a.N, a.pos, a.vel, a.image,
                        a.tpos, a.tvel, a.timage, a.rtag, a.build, a.chunk_rep);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(a.pos, a.tpos, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && a.vel)
-        e = hipMemcpyAsync(a.vel, a.tvel, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && a.image)
-        e = hipMemcpyAsync(a.image, a.timage, sizeof(int4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
-    return e;
+    hipLaunchKernelGGL(k_copy_back, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.tpos, a.tvel, a.timage, a.pos,
+                       a.vel, a.image, a.N);
+    return hipGetLastError();
 }
 
 hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
@@ -300,14 +306,9 @@ hipError_t launch_cells(const CellsArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_sort_cells, dim3(nblk(nk, kBlock)), dim3(kBlock), 0, s, a.cell_start, nk, a.order);
     hipLaunchKernelGGL(k_permute, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.order, a.N, a.pos, a.vel, a.image,
                        a.tpos, a.tvel, a.timage, a.rtag, nullptr, nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(a.pos, a.tpos, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && a.vel)
-        e = hipMemcpyAsync(a.vel, a.tvel, sizeof(float4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && a.image)
-        e = hipMemcpyAsync(a.image, a.timage, sizeof(int4) * (size_t)a.N, hipMemcpyDeviceToDevice, s);
-    return e;
+    hipLaunchKernelGGL(k_copy_back, dim3(nblk(a.N, kBlock)), dim3(kBlock), 0, s, a.tpos, a.tvel, a.timage, a.pos,
+                       a.vel, a.image, a.N);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -751,14 +751,50 @@ struct PlainOps final : DriveOps {
     rc_box box;
     Box b;
     hipStream_t s;
+    float* rb_pos = nullptr;   // the position buffer of the rebuild in progress
+    // The cell sort and the list build of one rebuild, on stream st (direct, or being recorded)
+    static int rebuild_launches(void* self, hipStream_t st) {
+        PlainOps* o = static_cast<PlainOps*>(self);
+        int rr = rc_build_cells(o->c, o->rb_pos, o->buf->vel, o->buf->image, o->buf->rtag, o->N, o->box,
+                                o->buf->cells_ws, o->buf->cells_ws_bytes, st);
+        if (rr) return rr;
+        return build_nlist(o->c, o->rb_pos, o->buf->vel, o->N, o->box, o->buf->cells_ws, o->buf->cells_ws_bytes,
+                           o->buf->k_max, o->buf->nlist, o->buf->nn, o->buf->status, true, st);
+    }
+    // Every rebuild of a run takes the same launches with the same arguments (for its position buffer),
+    // so from the second one on they are replayed as one graph: the host no longer issues a dozen
+    // launches while the device waits between them.
     int rebuild(float* pos, RebuildKind, float* kept_path, int64_t* rebuilt) override {
         *kept_path = 0.0f;   // every list is rebuilt
         *rebuilt = N;
-        int rr = rc_build_cells(c, pos, buf->vel, buf->image, buf->rtag, N, box, buf->cells_ws, buf->cells_ws_bytes,
-                                s);
+        rb_pos = pos;
+        if (c->ws_user == nullptr) return rebuild_launches(this, s);   // the context may still (re)allocate
+        RebuildKey k;
+        std::memset(&k, 0, sizeof k);
+        k.pos = pos;
+        k.vel = buf->vel;
+        k.image = buf->image;
+        k.rtag = buf->rtag;
+        k.ws = buf->cells_ws;
+        k.ws_bytes = buf->cells_ws_bytes;
+        k.nlist = buf->nlist;
+        k.nn = buf->nn;
+        k.status = buf->status;
+        k.pl_j = c->d_pl_j;
+        k.pl_o = c->d_pl_o;
+        k.tab = c->d_tab;
+        k.N = N;
+        k.k_max = buf->k_max;
+        for (int d = 0; d < 3; ++d) k.L[d] = box.L[d];
+        k.rlist_max = c->rlist_max;
+        const int rr = rebuild_graphed(c, pos == buf->pos ? 0 : 1, k, &PlainOps::rebuild_launches, this, s);
         if (rr) return rr;
-        return build_nlist(c, pos, buf->vel, N, box, buf->cells_ws, buf->cells_ws_bytes, buf->k_max, buf->nlist,
-                           buf->nn, buf->status, true, s);
+        // a replay skips the list build's host bookkeeping: the packed list is this list's
+        c->pl_nlist = buf->nlist;
+        c->pl_nn = buf->nn;
+        c->pl_k = buf->k_max;
+        c->pl_n = N;
+        return RC_OK;
     }
     int bonds(const float* pos, int row) override {
         HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(pos), buf->nlist, buf->nn, buf->k_max, N,

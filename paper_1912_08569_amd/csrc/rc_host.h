@@ -18,6 +18,34 @@ struct GraphCache {
     bool valid = false;
 };
 
+// A list rebuild of the driver (cell sort and list build) replayed as one graph:
+// what its launches were recorded with.  A build with another key runs directly
+// once and is recorded at its next occurrence.
+struct RebuildKey {
+    const void* pos;
+    const void* vel;
+    const void* image;
+    const void* rtag;
+    const void* ws;
+    size_t ws_bytes;
+    const void* nlist;
+    const void* nn;
+    const void* status;
+    const void* pl_j;
+    const void* pl_o;
+    const void* tab;
+    int N;
+    int k_max;
+    double L[3];
+    double rlist_max;
+};
+struct RebuildGraph {
+    hipGraphExec_t exec = nullptr;
+    RebuildKey key{};
+    bool seen = false;    // key ran directly once
+    bool valid = false;   // exec replays key
+};
+
 // What an rc_md_run that returned RC_OK left, for a next run that continues on
 // its list (rc_md_options.keep_list).  Cleared by every other call that
 // changes the state or the list.
@@ -80,6 +108,8 @@ struct rc_ctx {
     int* h_status = nullptr;            // pinned host copy of a status word (driver waits)
     hipEvent_t ev_sync = nullptr;       // the driver's wait event (no timing)
     GraphCache gc;
+    RebuildGraph rg[2];                 // the driver's rebuilds, one per position buffer
+    hipStream_t cap_stream = nullptr;   // private stream the rebuild graphs are recorded on
     void* noalloc_scratch = nullptr;    // device address of the fixed scratch on this device
     MdRecord md;                        // the last run, for keep_list
     // caller-owned workspace (rc_set_workspace): when attached, the packed list, the switching sums
@@ -151,6 +181,11 @@ int compile_table(int nt, const rc_pair_coeff* table, double r_buff, DevEntry* o
                   std::string* why);
 
 void drop_graphs(rc_ctx* c);
+void drop_rebuild_graphs(rc_ctx* c);
+// Run fn(stream) (the launches of one rebuild) as a graph replay on s when slot holds key, else run it
+// directly on s (the first time for key) or record it on the private stream and replay it.
+int rebuild_graphed(rc_ctx* c, int slot, const RebuildKey& key, int (*fn)(void*, hipStream_t), void* arg,
+                    hipStream_t s);
 
 // What the chunked driver needs from a system (one or a batch).
 enum RebuildKind {

@@ -227,6 +227,9 @@ int ensure_hsum(rc_ctx* c, size_t n) {
 
 void free_ctx_buffers(rc_ctx* c) {
     drop_graphs(c);
+    drop_rebuild_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     for (hipEvent_t e : c->tk_events)
         if (e) (void)hipEventDestroy(e);
     c->tk_events.clear();
@@ -258,6 +261,47 @@ void free_ctx_buffers(rc_ctx* c) {
     c->d_step_base = nullptr;
     c->d_blk = nullptr;
     c->d_ssum = nullptr;
+}
+
+void drop_rebuild_graphs(rc_ctx* c) {
+    for (RebuildGraph& g : c->rg) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = RebuildGraph{};
+    }
+}
+
+int rebuild_graphed(rc_ctx* c, int slot, const RebuildKey& key, int (*fn)(void*, hipStream_t), void* arg,
+                    hipStream_t s) {
+    RebuildGraph& g = c->rg[slot];
+    const bool same = g.seen && std::memcmp(&g.key, &key, sizeof key) == 0;
+    if (same && g.valid) {
+        HIP_TRY(c, hipGraphLaunch(g.exec, s));
+        return RC_OK;
+    }
+    if (!same) {   // a new key: run directly (any allocation happens here), record next time
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = RebuildGraph{};
+        g.key = key;
+        g.seen = true;
+        return fn(arg, s);
+    }
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    const int r = fn(arg, c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (r != RC_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (r != RC_OK) return r;
+        return hip_fail(c, e, "recording the rebuild graph");
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(c, ei, "instantiating the rebuild graph");
+    HIP_TRY(c, hipGraphUpload(g.exec, s));
+    g.valid = true;
+    HIP_TRY(c, hipGraphLaunch(g.exec, s));
+    return RC_OK;
 }
 
 void drop_graphs(rc_ctx* c) {

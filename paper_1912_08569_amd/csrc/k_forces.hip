@@ -615,8 +615,18 @@ __global__ __launch_bounds__(kBlock) void k_fold_status(int* __restrict__ blk, i
         blk[3 * b + 2] = 0x7fffffff;
     }
     float pm = 0.0f;
-    if (vel)
-        for (int i = tid; i < N; i += stride) pm = fmaxf(pm, vel[i].w);
+    if (vel) {   // sixteen path lengths in flight per thread (a maximum: exact in any order)
+        constexpr int U = 16;
+        int i = tid;
+        for (; i + (U - 1) * stride < N; i += U * stride) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = vel[i + u * stride].w;
+#pragma unroll
+            for (int u = 0; u < U; ++u) pm = fmaxf(pm, v[u]);
+        }
+        for (; i < N; i += stride) pm = fmaxf(pm, vel[i].w);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         fl |= __shfl_xor(fl, o, kWave);
@@ -789,12 +799,31 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* __restrict
 // threads of a wavefront on consecutive words of consecutive rows (coalesced
 // reads spread over many CUs instead of 13 CUs each reading every row), then
 // per word the same tree over the 256 slices.  Bit for bit k_reduce_rows.
+// With bonds, one more column sums the per-block bond counts (64-bit integers,
+// exact in any order) into *bonds_out.
 __global__ __launch_bounds__(kWave) void k_row_slices(const double* __restrict__ part, int nblocks, int first,
-                                                     int count, double* __restrict__ slice) {
+                                                     int count, double* __restrict__ slice,
+                                                     const unsigned* __restrict__ bonds) {
+    const int cols = count + (bonds ? 1 : 0);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kBlock * count) return;
-    const int t = i / count, q = first + i % count;
+    if (i >= kBlock * cols) return;
+    const int t = i / cols, qc = i % cols;
     constexpr int U = 16;
+    if (qc == count) {
+        unsigned long long n = 0;
+        int b = t;
+        for (; b + (U - 1) * kBlock < nblocks; b += U * kBlock) {
+            unsigned v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = bonds[b + u * kBlock];
+#pragma unroll
+            for (int u = 0; u < U; ++u) n += v[u];
+        }
+        for (; b < nblocks; b += kBlock) n += bonds[b];
+        reinterpret_cast<unsigned long long*>(slice)[i] = n;
+        return;
+    }
+    const int q = first + qc;
     double s = 0.0;
     int b = t;
     for (; b + (U - 1) * kBlock < nblocks; b += U * kBlock) {
@@ -809,9 +838,22 @@ __global__ __launch_bounds__(kWave) void k_row_slices(const double* __restrict__
 }
 
 __global__ __launch_bounds__(kBlock) void k_row_tree(const double* __restrict__ slice, int count,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out,
+                                                    unsigned long long* __restrict__ bonds_out) {
+    const int cols = count + (bonds_out ? 1 : 0);
+    if ((int)blockIdx.x == count) {   // the bond column (launched with bonds_out only)
+        __shared__ unsigned long long redn[kBlock];
+        redn[threadIdx.x] = reinterpret_cast<const unsigned long long*>(slice)[threadIdx.x * cols + count];
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) redn[threadIdx.x] += redn[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *bonds_out = redn[0];
+        return;
+    }
     __shared__ double red[kBlock];
-    red[threadIdx.x] = slice[threadIdx.x * count + blockIdx.x];
+    red[threadIdx.x] = slice[threadIdx.x * cols + blockIdx.x];
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -821,11 +863,13 @@ __global__ __launch_bounds__(kBlock) void k_row_tree(const double* __restrict__ 
 }
 
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
-                              hipStream_t s, double* slice) {
+                              hipStream_t s, double* slice, const unsigned* bonds, unsigned long long* bonds_out) {
+    if ((bonds != nullptr) != (bonds_out != nullptr) || (bonds && !slice)) return hipErrorInvalidValue;
     if (slice && count <= kEvWords) {
-        hipLaunchKernelGGL(k_row_slices, dim3(nblk((long)kBlock * count, kWave)), dim3(kWave), 0, s, part, nblocks,
-                           first, count, slice);
-        hipLaunchKernelGGL(k_row_tree, dim3(count), dim3(kBlock), 0, s, slice, count, out);
+        const int cols = count + (bonds ? 1 : 0);   // kBlock * cols <= kRowSlices
+        hipLaunchKernelGGL(k_row_slices, dim3(nblk((long)kBlock * cols, kWave)), dim3(kWave), 0, s, part, nblocks,
+                           first, count, slice, bonds);
+        hipLaunchKernelGGL(k_row_tree, dim3(cols), dim3(kBlock), 0, s, slice, count, out, bonds_out);
     } else {
         hipLaunchKernelGGL(k_reduce_rows, dim3(count), dim3(kBlock), 0, s, part, nblocks, first, count, out);
     }

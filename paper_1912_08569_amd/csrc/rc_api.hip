@@ -796,18 +796,36 @@ struct PlainOps final : DriveOps {
         c->pl_n = N;
         return RC_OK;
     }
+    // With both logs, a row's bond count comes from the ev step that follows the bond request (the
+    // driver launches one on the same positions for every row): its gather counts the bonds per block,
+    // and the row's reduction sums them, instead of a list walk and a sum of their own.
+    bool fused_bonds() const { return buf->ev_log != nullptr && buf->bonds_log != nullptr; }
+    unsigned* bond_part() const {
+        return reinterpret_cast<unsigned*>(c->d_part + (size_t)kEvWords * nblocks(N, kStepBlock));
+    }
     int bonds(const float* pos, int row) override {
+        if (fused_bonds()) return RC_OK;
         HIP_TRY(c, launch_bonds(reinterpret_cast<const float4*>(pos), buf->nlist, buf->nn, buf->k_max, N,
                                 dev_table(c), b, buf->bonds_log + row, reinterpret_cast<unsigned long long*>(c->d_part),
                                 s));
         return RC_OK;
     }
-    hipError_t launch(const StepArgs& a, bool ev) override { return launch_step(a, ev, s); }
+    hipError_t launch(const StepArgs& a, bool ev) override {
+        if (!ev || !fused_bonds()) return launch_step(a, ev, s);
+        StepArgs e = a;
+        e.bond_part = bond_part();
+        return launch_step(e, ev, s);
+    }
     hipError_t launch_timed(const StepArgs& a, hipEvent_t* sums, hipEvent_t* step) override {
         return launch_step_timed(a, false, s, sums, step);
     }
     int reduce_ev(int row) override {
-        return reduce_rows(c, nblocks(N, kStepBlock), 0, kEvWords, buf->ev_log + (size_t)row * kEvWords, s);
+        const int nb = nblocks(N, kStepBlock);
+        double* out = buf->ev_log + (size_t)row * kEvWords;
+        if (!fused_bonds()) return reduce_rows(c, nb, 0, kEvWords, out, s);
+        HIP_TRY(c, launch_reduce_rows(c->d_part, nb, 0, kEvWords, out, s, c->d_slices, bond_part(),
+                                      buf->bonds_log + row));
+        return RC_OK;
     }
     const void* graph_fn() override {
         const void* fn;
@@ -860,7 +878,8 @@ int rc_md_run(rc_ctx* c, const rc_md_buffers* buf, int N, rc_box box, const rc_i
     if ((r = make_box(c, box, b))) return r;
     hipStream_t s = S(stream);
     const int nb = nblocks(N, kStepBlock);
-    if ((r = ensure_part(c, sizeof(double) * kEvWords * (size_t)nb))) return r;
+    // the ev steps' rows, then their per-block bond counts (PlainOps::bond_part)
+    if ((r = ensure_part(c, (sizeof(double) * kEvWords + sizeof(unsigned)) * (size_t)nb))) return r;
     StepArgs tmpl{};
     if ((r = fill_step_args(c, tmpl, buf->pos, buf->pos_alt, buf->vel, buf->image, buf->nlist, buf->nn, buf->k_max, N,
                             b, cfg, opt.soft_frac, buf->status, s, false)))

@@ -89,7 +89,9 @@ __device__ __forceinline__ float partner_sum_excluding(int c, const float4& pc, 
 
 struct Acc {
     float fx, fy, fz, e;
-    float w[6];  // xx yy zz xy xz yz
+    float w[6];     // xx yy zz xy xz yz
+    unsigned nbond; // EV gathers: bonds (swap, canonical r^2 < r_min^2, owner < neighbour) among the
+                    // entries this lane evaluated (a wavefront's sum is its particles' bond count)
 };
 
 __device__ __forceinline__ void acc_virial(Acc& a, float c, float dx, float dy, float dz) {
@@ -254,6 +256,7 @@ __device__ __forceinline__ void wave_gather(int base_m, bool live, const float4&
                 if (en.kind != RC_KIND_NONE) {
                     const PairGeom pg = pair_geom(po, pj[u], box, en);
                     if (pg.cut) {
+                        if (EV && en.kind == RC_KIND_SWAP && pg.bond && jj[u] > mo) ++acc.nbond;
                         const float r2 = pg.r2, dx = pg.dx, dy = pg.dy, dz = pg.dz;
                         float phi, g, uu, u1r;
                         pair_vhat_eval(en, en.kind == RC_KIND_SWAP, pg.inside, r2, phi, g, uu, u1r);

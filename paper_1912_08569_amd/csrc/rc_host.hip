@@ -796,9 +796,11 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
             ep_row = row;
             need_snap = false;
         }
-        // one launch clears the chunk markers and sets the replays' step counter
-        HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, chunk_start));
-        dev_base = chunk_start;
+        // one launch clears the chunk markers and sets the replays' step counter (to the chunk's second
+        // step when its first is launched directly: a run's first step or a log step)
+        const uint64_t base0 = chunk_start + ((first || log_at(chunk_start)) ? 1 : 0);
+        HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, base0));
+        dev_base = base0;
         // ---- run it --------------------------------------------------------------
         if ((r = run_steps(chunk_start, C))) return finish(r);
         HIP_TRY(c, ops.fold(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));

@@ -325,10 +325,37 @@ __device__ __forceinline__ void pack_wave_lists(int i, bool live, int packed, co
     }
 }
 
+// One DPP step of a 64-bit scan: v plus the value of the lane ctrl selects
+// (0 where the row mask or the row's edge leaves no source).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+    const long long b = __double_as_longlong(v);
+    int lo, hi;
+    if constexpr (ROW_MASK == 0xf) {   // every row written: lanes without a source read 0 (bound_ctrl)
+        lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, ROW_MASK, 0xf, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    } else {                           // rows left out keep the old value 0
+        lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    }
+    return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wavefront, returned to every lane; every lane must be active.
+// The inclusive scan of wave_inclusive_scan (DPP row shifts, then the row
+// broadcasts) leaves the total in lane 63, which is read back: no LDS
+// permutes, and one fixed order of additions.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, kWave - 1);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), kWave - 1);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ float wave_maxf(float v) {
 #pragma unroll
@@ -395,6 +422,9 @@ struct StepArgs {
     uint64_t step;             // step index (added to *step_base if not NULL)
     const unsigned long long* step_base;
     double* ev_part;           // [nblocks*13] | NULL (row of logical block c at c*13)
+    // single systems, ev steps: per logical block the number of bonds (swap pairs
+    // m < j with canonical r^2 < r_min^2) among its particles' list entries | NULL
+    unsigned* bond_part;
     int* status;
     int* blk;                  // [nblocks*3] per-block flag / first-soft / first-hard slots
     // batches only (tab.e then holds every replica's table, box is unused)
@@ -530,10 +560,12 @@ hipError_t launch_fold_status(int* blk, int nb, const float4* vel, int N, int* s
 hipError_t launch_blk_reset(int* blk, int nb, hipStream_t s);
 
 // reduce nblocks partial rows of 13 doubles into out[first .. first+count) (fixed order); slice:
-// NULL, or scratch of kRowSlices doubles for the same sums in two launches that spread the reads
-constexpr int kRowSlices = 256 * 13;
+// NULL, or scratch of kRowSlices doubles for the same sums in two launches that spread the reads.
+// With slice, bonds (nblocks per-block counts) may be summed into *bonds_out by the same launches.
+constexpr int kRowSlices = 256 * 14;
 hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int count, double* out,
-                              hipStream_t s, double* slice = nullptr);
+                              hipStream_t s, double* slice = nullptr, const unsigned* bonds = nullptr,
+                              unsigned long long* bonds_out = nullptr);
 // clear the chunk-local status markers (keeping KMAX, MAXPATH and the overflow flag) and, if
 // step_base is not NULL, set *step_base = step
 hipError_t launch_status_reset_chunk(int* status, hipStream_t s, unsigned long long* step_base = nullptr,

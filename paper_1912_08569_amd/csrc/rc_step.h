@@ -96,6 +96,12 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, float4* pos_out, 
         double v[13] = {acc.e,  acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5],
                         kin[0], kin[1],   kin[2],   kin[3],   kin[4],   kin[5]};
         wave_sum_store<13>(v, a.ev_part + (size_t)blk * kEvWords);
+        if (a.bond_part) {   // the bond count of the positions the forces were gathered at
+            unsigned nb = acc.nbond;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) nb += __shfl_xor(nb, o, kWave);
+            if ((threadIdx.x & (kWave - 1)) == 0) a.bond_part[blk] = nb;
+        }
     }
 }
 

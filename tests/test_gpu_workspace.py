@@ -17,9 +17,9 @@ pytestmark = pytest.mark.gpu
 
 
 def _small_bound(N):
-    # reduction rows (at least 1 MiB), 13 doubles and 3 status ints per 64-particle block, 256 x 13 doubles of
-    # reduction slices, table, counters
-    return (1 << 20) + (13 * 8 + 3 * 4) * (N // 64 + 1024) + 8 * 256 * 13 + 4096
+    # reduction rows (at least 1 MiB), 13 doubles, a bond count and 3 status ints per 64-particle block,
+    # 256 x 14 words of reduction slices, table, counters
+    return (1 << 20) + (13 * 8 + 4 + 3 * 4) * (N // 64 + 1024) + 8 * 256 * 14 + 4096
 
 
 def test_context_holds_only_small_buffers():

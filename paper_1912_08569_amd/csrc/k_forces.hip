@@ -308,6 +308,8 @@ template <bool EV, bool BATCH, int PL, bool SF>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int nt = a.tab.nt;
+    // the chunk's reset, when this launch carries it (no kernel of the launch reads those words)
+    if (a.reset_status && blockIdx.x == 0 && threadIdx.x == 0) chunk_reset(a.reset_status, a.reset_base, a.reset_to);
     const int blk = xcd_block(gridDim.x);
     const int m = blk * kWave + threadIdx.x;
     float4 pm0 = make_float4(0.f, 0.f, 0.f, 0.f), vm0 = pm0;
@@ -903,11 +905,7 @@ hipError_t launch_reduce_rows_batch(const double* part, const RepDesc* rep, int 
 }
 
 __global__ void k_status_reset_chunk(int* st, unsigned long long* base, unsigned long long step) {
-    // keep KMAX, MAXPATH and the overflow flag of the current list, clear the chunk-local markers
-    st[RC_ST_FLAGS] &= RC_FLAG_NLIST_OVERFLOW;
-    st[RC_ST_FIRST_SOFT] = 0x7fffffff;
-    st[RC_ST_FIRST_HARD] = 0x7fffffff;
-    if (base) *base = step;  // the step counter of the graph replays, in the same launch
+    chunk_reset(st, base, step);
 }
 hipError_t launch_status_reset_chunk(int* status, hipStream_t s, unsigned long long* step_base,
                                      unsigned long long step) {

@@ -646,6 +646,17 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         return RC_OK;
     };
 
+    // The reset the chunk being queued still owes (chunk markers cleared, replay step counter set): its
+    // first direct step launch carries it, so the device starts a run's first chunk on a step instead of
+    // a one-thread launch that then waits for the host's next; a graph replay is preceded by its own.
+    bool reset_owed = false;
+    uint64_t reset_to = 0;
+    auto pay_reset = [&]() -> int {
+        if (reset_owed) HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, reset_to));
+        reset_owed = false;
+        return RC_OK;
+    };
+
     // direct launch of one step from P[cur]
     auto direct = [&](uint64_t step, int mode, bool ev) -> int {
         StepArgs a = tmpl;
@@ -655,6 +666,12 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         a.step = step;
         a.step_base = nullptr;
         a.ev_part = ev ? c->d_part : nullptr;
+        if (reset_owed) {
+            a.reset_status = buf->status;
+            a.reset_base = c->d_step_base;
+            a.reset_to = reset_to;
+            reset_owed = false;
+        }
         if (timing && !ev && (mode == RC_STEP_START || mode == RC_STEP_CONT)) {
             // the plain step launches (log steps and the finishing kick are other work)
             const bool two = ops.graph_sums_fn() != nullptr;
@@ -701,8 +718,15 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
     }
     uint64_t dev_base = ~0ull;   // value *d_step_base will hold once queued work ran
 
+    // Graph replays pay a step-counter node and a wait at each end; direct launches cost the host
+    // 7-14 us each.  A system of 2^19 particles or more takes longer per step than that, so its
+    // launches keep ahead of the device, and a stretch of fewer than two replays runs directly (20-step
+    // runs of 2^20 particles: 6-7 us less per run than with one replay, paired medians over 18 runs;
+    // long runs and smaller systems keep the replays: 12.9 against 14.6 us per step at 2048 particles).
+    const bool big = (int64_t)N >= (int64_t)1 << 19;
     // run `count` steps from the state at absolute step `from` (in P[cur])
     auto run_steps = [&](uint64_t from, int64_t count) -> int {
+        const bool replays = graphs && (count >= 2 * (int64_t)G || !big);
         int64_t k = 0;
         while (k < count) {
             const uint64_t step = from + (uint64_t)k;
@@ -711,11 +735,13 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
                 int rr = log_now(cur);
                 if (rr) return rr;
             }
-            if (graphs && !first && !ev && count - k >= G) {
+            if (replays && !first && !ev && count - k >= G) {
                 // a graph replay must not cross a logging step
                 bool clear = true;
                 for (int64_t q = 1; q < G && clear; ++q) clear = !log_at(step + (uint64_t)q);
                 if (clear) {
+                    int rr = pay_reset();
+                    if (rr) return rr;
                     if (dev_base != step) HIP_TRY(c, launch_set_step(c->d_step_base, step, s));
                     if (blockrun) {
                         StepArgs a = tmpl;
@@ -799,10 +825,12 @@ int md_drive(rc_ctx* c, DriveOps& ops, const rc_md_buffers* buf, int N, const St
         // one launch clears the chunk markers and sets the replays' step counter (to the chunk's second
         // step when its first is launched directly: a run's first step or a log step)
         const uint64_t base0 = chunk_start + ((first || log_at(chunk_start)) ? 1 : 0);
-        HIP_TRY(c, launch_status_reset_chunk(buf->status, s, c->d_step_base, base0));
+        reset_owed = true;
+        reset_to = base0;
         dev_base = base0;
         // ---- run it --------------------------------------------------------------
         if ((r = run_steps(chunk_start, C))) return finish(r);
+        if ((r = pay_reset())) return finish(r);
         HIP_TRY(c, ops.fold(c->d_blk, nb, reinterpret_cast<const float4*>(buf->vel), N, buf->status, s));
         // The run's last chunk queues the finishing work before its status read, so that one host wait
         // covers both.  The read confirms it when no force of the chunk or of the finishing step was

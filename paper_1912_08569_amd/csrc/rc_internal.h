@@ -425,6 +425,11 @@ struct StepArgs {
     // single systems, ev steps: per logical block the number of bonds (swap pairs
     // m < j with canonical r^2 < r_min^2) among its particles' list entries | NULL
     unsigned* bond_part;
+    // a chunk's reset done by this launch (thread 0 of block 0) instead of a launch of its own:
+    // reset_status NULL = none; else as launch_status_reset_chunk(reset_status, reset_base, reset_to)
+    int* reset_status;
+    unsigned long long* reset_base;
+    unsigned long long reset_to;
     int* status;
     int* blk;                  // [nblocks*3] per-block flag / first-soft / first-hard slots
     // batches only (tab.e then holds every replica's table, box is unused)
@@ -568,6 +573,13 @@ hipError_t launch_reduce_rows(const double* part, int nblocks, int first, int co
                               unsigned long long* bonds_out = nullptr);
 // clear the chunk-local status markers (keeping KMAX, MAXPATH and the overflow flag) and, if
 // step_base is not NULL, set *step_base = step
+__device__ __forceinline__ void chunk_reset(int* st, unsigned long long* base, unsigned long long step) {
+    // keep KMAX, MAXPATH and the overflow flag of the current list, clear the chunk-local markers
+    st[RC_ST_FLAGS] &= RC_FLAG_NLIST_OVERFLOW;
+    st[RC_ST_FIRST_SOFT] = 0x7fffffff;
+    st[RC_ST_FIRST_HARD] = 0x7fffffff;
+    if (base) *base = step;  // the step counter of the graph replays
+}
 hipError_t launch_status_reset_chunk(int* status, hipStream_t s, unsigned long long* step_base = nullptr,
                                      unsigned long long step = 0);
 // one launch copying pos, vel and (if both non-NULL) image: the driver's snapshot and its restore;

@@ -441,18 +441,25 @@ __device__ __forceinline__ int list_one(int i, const float4& pi, const Box& b, c
         o = ow0;                                             \
         _Pragma("unroll") for (int q = 0; q < 8; ++q) o = ((t) >= pre[q]) ? ow[q] : o; \
     } while (0)
-        int oc;
-        RC_LOCATE(0, oc);
-        float4 pc = pos[oc >> 1];
-        for (int t = 0; t < tot; ++t) {
-            const int jc = t + (oc >> 1);
-            const bool wc = (oc & 1) != 0;
-            const float4 pcur = pc;
-            if (t + 1 < tot) {  // request the next candidate first
-                RC_LOCATE(t + 1, oc);
-                pc = pos[t + 1 + (oc >> 1)];
+        // candidates in groups of four, all four positions requested before any is tested (in candidate
+        // order, so the list is the same): 102 -> 95 us per build at 1M particles; one ahead, two, three,
+        // six or eight at a time, or the next group requested during the current one, were slower
+        constexpr int kAhead = 4;
+        for (int t0 = 0; t0 < tot; t0 += kAhead) {
+            int oq[kAhead];
+            float4 pq[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                oq[u] = 0;
+                pq[u] = pi;
+                if (t0 + u < tot) {
+                    RC_LOCATE(t0 + u, oq[u]);
+                    pq[u] = pos[t0 + u + (oq[u] >> 1)];
+                }
             }
-            consider(jc, pcur, wc);
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u)
+                if (t0 + u < tot) consider(t0 + u + (oq[u] >> 1), pq[u], (oq[u] & 1) != 0);
         }
 #undef RC_LOCATE
     }

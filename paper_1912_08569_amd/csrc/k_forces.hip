@@ -308,8 +308,6 @@ template <bool EV, bool BATCH, int PL, bool SF>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void k_step(StepArgs a) {
     extern __shared__ DevEntry s_tab[];
     const int nt = a.tab.nt;
-    // the chunk's reset, when this launch carries it (no kernel of the launch reads those words)
-    if (a.reset_status && blockIdx.x == 0 && threadIdx.x == 0) chunk_reset(a.reset_status, a.reset_base, a.reset_to);
     const int blk = xcd_block(gridDim.x);
     const int m = blk * kWave + threadIdx.x;
     float4 pm0 = make_float4(0.f, 0.f, 0.f, 0.f), vm0 = pm0;
@@ -348,6 +346,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
     if (!BATCH && a.bonds && live)
         fene_add<EV>(ptag(pm.w), pm, a.bonds, a.rtag, a.pos_in, box, a.fene_k, a.fene_r02, acc);
     step_finish<EV>(a, a.pos_out, m, blk, live, pm, vm, acc, box, tag0, seed, step);
+    // the chunk's reset, when this launch carries it (no kernel of the launch reads those words); at the
+    // end, so that its argument's load does not hold up the start of every wavefront (25.15 -> 24.79 us)
+    if (a.reset_status && blockIdx.x == 0 && threadIdx.x == 0) chunk_reset(a.reset_status, a.reset_base, a.reset_to);
 }
 
 // Step kernels by (ev, batch, width, form); log steps use the default width.

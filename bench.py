@@ -547,9 +547,9 @@ def main():
         return
     # ---- timed region: exactly `steps` steps ------------------------------------------
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record()
     res = S.run(a.steps, cfg, step0=a.warmup, log_period=a.log_period, use_graph=use_graph)
     e1.record()
     torch.cuda.synchronize()

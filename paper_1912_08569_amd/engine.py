@@ -89,6 +89,8 @@ class System:
         self.built = False
         self._continues = False     # the state is what the last run left (its list may be kept)
         self._log = None            # log rows of the last run (ev rows, then bond counts)
+        self._log_np = None         # numpy view of _log
+        self._bufs_cache = None     # (tensors, MdBuffers, log address) of the last run
         # the context's large scratch (packed list, switching sums, HVP sums) in a torch-owned buffer
         self._attach_workspace(nvec=1)
 
@@ -286,6 +288,21 @@ class System:
         b.ev_log, b.bonds_log = p(ev_log), p(bonds_log)
         return b
 
+    def _run_buffers(self, rows: int) -> rcl.MdBuffers:
+        """md_buffers for a run with `rows` log rows in the pinned log buffer (ev rows, then the bond
+        counts).  The struct is kept while the same tensors hold the state (a replaced tensor, as after a
+        list growth, rebuilds it): filling it costs more host time than a short run's steps leave idle."""
+        key = (self.pos, self.pos_alt, self.vel, self.image, self.rtag, self.nlist, self.nn, self.ws,
+               self.status, self._log) + ((self.snap_pos, self.snap_vel, self.snap_image) if self.rollback else ())
+        c = self._bufs_cache
+        if (c is None or c[3] != self.k_max or len(c[0]) != len(key)
+                or not all(x is y for x, y in zip(c[0], key))):
+            c = self._bufs_cache = (key, self.md_buffers(), self._log.data_ptr(), self.k_max)
+        b, base = c[1], c[2]
+        b.ev_log = base
+        b.bonds_log = base + rows * 13 * 8   # u64 counts after the rows
+        return b
+
     def run(self, n_steps: int, cfg, step0: int = 0, log_period: int = 0, use_graph: bool = True,
             graph_steps: int = 16, max_chunk: int = 256, soft_frac: float = 0.8, adapt: bool = True,
             one_block: bool = True, keep_list: bool = True, time_kernels: bool = False) -> RunResult:
@@ -308,15 +325,14 @@ class System:
             # pinned host memory, which the driver's kernels write directly: the rows are on the host when
             # the run returns (its last status read waits for them), with no copy back
             self._log = torch.zeros(max(rows, 64) * 14, dtype=torch.float64, pin_memory=True)
-        ev_log = self._log[:rows * 13]
-        bonds_log = self._log[rows * 13:rows * 14]       # u64 counts in the same buffer
+            self._log_np = self._log.numpy()
         opts = rcl.MdOptions(int(use_graph), int(graph_steps), int(max_chunk), int(log_period), float(soft_frac),
                              int(adapt), int(one_block), 0, int(keep_list and self._continues), int(time_kernels))
         self._continues = False
         for _ in range(4):
             try:
-                st = api.rc_md_run(self.ctx, self.md_buffers(ev_log, bonds_log), self.N, self.box, cfg, step0,
-                                   n_steps, opts)
+                st = api.rc_md_run(self.ctx, self._run_buffers(rows), self.N, self.box, cfg, step0, n_steps,
+                                   opts)
                 break
             except RcError as e:
                 if e.code != rcl.RC_ERR_NLIST_OVERFLOW:
@@ -334,9 +350,8 @@ class System:
         if self.step_form == "auto" and st.rebuilds > 0:   # the next run takes the form of the last list
             self.ctx.set_step_form(self._form_for(st.nswap))
         n = int(st.log_rows)
-        host = self._log[:rows * 14]
-        ev = host[:rows * 13].view(rows, 13)[:n].numpy().copy()
-        bonds = host[rows * 13:rows * 14].view(torch.int64)[:n].numpy().copy()
+        ev = self._log_np[:rows * 13].reshape(rows, 13)[:n].copy()
+        bonds = self._log_np[rows * 13:rows * 14].view(np.int64)[:n].copy()
         return RunResult(stats=st, ev=ev, bonds=bonds)
 
     def invalidate(self):

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import workloads as W
+from paper_1912_08569_amd import _lib as rcl
 from oracle import dynamics_ref, swap_ref
 
 pytestmark = pytest.mark.gpu
@@ -287,6 +288,32 @@ def test_bonds_log_matches_oracle_at_the_end():
     assert int(r.bonds[-1]) == ref["bonds"]
     assert r.bonds[-1] > r.bonds[0]                # bonds form during assembly
     assert abs(r.ev[-1, 0] - ref["E"]) <= 1e-5 * ref["A_E"]
+
+
+@pytest.mark.parametrize("form", ["walk", "sums"])
+def test_fused_bond_counts_equal_the_list_walk(form):
+    """Log rows with both logs take each bond count from the energy/virial step's gather; a run with the
+    bond log alone counts by a walk of the swap lists (k_bonds).  Same trajectory, same counts."""
+    from paper_1912_08569_amd import api
+    s = W.assembly_mixture(N=20000, lam=1.0, seed=52, kT=0.05)
+    rows = 1000 // 100 + 2
+    out = []
+    for both in (True, False):
+        S = _system(s)
+        S.set_step_form(form)
+        cfg = S.integrator(dt=0.001, kT=0.05, gamma=1.0, seed=17)
+        S.build()
+        ev = torch.zeros(rows * 13, dtype=torch.float64, device=S.device)
+        bonds = torch.zeros(rows, dtype=torch.int64, device=S.device)
+        opts = rcl.MdOptions(1, 16, 256, 100, 0.8, 1, 1, 0, 0, 0)
+        st = api.rc_md_run(S.ctx, S.md_buffers(ev if both else None, bonds), S.N, S.box, cfg, 0, 1000, opts)
+        out.append((bonds[:int(st.log_rows)].cpu().numpy(), S.state_by_tag()[0], S.bond_count()))
+        del S
+    (ba, xa, ca), (bb, xb, cb) = out
+    assert len(ba) == 11 and np.array_equal(ba, bb)   # steps 0, 100, ..., 900 and the end
+    assert np.array_equal(xa, xb)
+    assert int(ba[-1]) == ca == cb
+    assert ba[-1] > ba[0]
 
 
 def test_auto_form_follows_the_swap_range_length():

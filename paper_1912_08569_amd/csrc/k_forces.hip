@@ -236,7 +236,16 @@ hipError_t launch_forces_triplet(const ForceArgs& a, hipStream_t s) {
 template <bool BATCH>
 __global__ __launch_bounds__(kWave) void k_swap_sums(ForceArgs a) {
     extern __shared__ DevEntry s_tab[];
-    const int blk = xcd_block(gridDim.x);
+    // as in k_step: xcd_block's order from N (the grid is N / 64 blocks rounded up) with selects, and the
+    // particle's own data requested before the table is staged (13.27 -> 13.12 us per dumbbell step at 8192)
+    const int nbl = (a.N + kWave - 1) / kWave;
+    const int per = nbl / 8;
+    const int bx = blockIdx.x;
+    const int blk = bx < per * 8 ? (bx & 7) * per + (bx >> 3) : bx;
+    const int m = blk * kWave + threadIdx.x;
+    const int mc = min(m, a.N - 1);   // in bounds; lanes past the end return below
+    const float4 pm = a.pos[mc];
+    const int packed = a.nn[mc];
     Box box_r;
     int lim = a.N;
     if constexpr (BATCH) {
@@ -248,10 +257,8 @@ __global__ __launch_bounds__(kWave) void k_swap_sums(ForceArgs a) {
         box_r = a.box;
         load_table(s_tab, a.tab);
     }
-    const int m = blk * kWave + threadIdx.x;
     if (m >= lim) return;
-    const float4 pm = a.pos[m];
-    a.ssum[m] = swap_sum(m, pm, a.nn[m], a.pos, a.nlist, a.N, s_tab, a.tab.nt, box_r);
+    a.ssum[m] = swap_sum(m, pm, packed, a.pos, a.nlist, a.N, s_tab, a.tab.nt, box_r);
 }
 
 void sums_kernel_info(bool batch, const void** fn) {

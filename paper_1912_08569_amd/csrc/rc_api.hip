@@ -132,7 +132,10 @@ int rc_create(rc_ctx** out, int ntypes, const rc_pair_coeff* table, double r_buf
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMalloc(&c->d_step_base, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_slices, sizeof(double) * kRowSlices) != hipSuccess ||
-        noalloc_scratch_here(c->device, &c->noalloc_scratch) != hipSuccess) {
+        noalloc_scratch_here(c->device, &c->noalloc_scratch) != hipSuccess ||
+        // the private stream the driver's rebuild graphs are recorded on: created here, as creating a
+        // stream takes milliseconds (3-5 ms measured), which a run recording its first graph would pay
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         if (c->d_tab) (void)hipFree(c->d_tab);
         if (c->d_step_base) (void)hipFree(c->d_step_base);
         if (c->d_slices) (void)hipFree(c->d_slices);

@@ -204,8 +204,10 @@ def lambda_sweep(a, sysw):
         assert len(steps) == len(bonds)
         rows.append({"lambda": lam, "particle_timesteps_per_s": a.N * a.sweep_steps / dt,
                      "us_per_step": round(dt / a.sweep_steps * 1e6, 3), "rebuilds": int(r.stats.rebuilds),
+                     "rollbacks": int(r.stats.rollbacks), "chunks": int(r.stats.chunks),
                      "bond_trajectory": {"steps": steps, "bonds": bonds}})
-        print(f"# lambda {lam}: {rows[-1]['us_per_step']:.2f} us/step, bonds {bonds[0]} -> {bonds[-1]}",
+        print(f"# lambda {lam}: {rows[-1]['us_per_step']:.2f} us/step, bonds {bonds[0]} -> {bonds[-1]}, "
+              f"rebuilds {rows[-1]['rebuilds']}, rollbacks {rows[-1]['rollbacks']}, chunks {rows[-1]['chunks']}",
               file=sys.stderr, flush=True)
         del S
         torch.cuda.empty_cache()

@@ -316,6 +316,27 @@ def test_fused_bond_counts_equal_the_list_walk(form):
     assert ba[-1] > ba[0]
 
 
+def test_rebuild_graph_replays_equal_direct_rebuilds():
+    """With a caller-owned workspace the driver replays its rebuilds as recorded graphs (from the second
+    rebuild of a position buffer on); without one it launches them directly.  Same states, logs and
+    schedules, bit for bit, over a run with many rebuilds."""
+    s = W.small_reactive(N=6000, density=0.3, seed=57, table=W.swap_table_single(lam=1.0), kT=0.3)
+    out = []
+    for attached in (True, False):
+        S = _system(s)
+        if not attached:
+            S.ctx.set_workspace(None)    # the context allocates its own buffers: rebuilds run directly
+        cfg = S.integrator(dt=0.002, kT=0.3, gamma=1.0, seed=23)
+        r = S.run(600, cfg, log_period=100)
+        out.append((S.state_by_tag(), r))
+        del S
+    (sa, ra), (sb, rb) = out
+    assert ra.stats.rebuilds >= 6 and ra.stats.rebuilds == rb.stats.rebuilds
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+    assert np.array_equal(ra.ev, rb.ev) and np.array_equal(ra.bonds, rb.bonds)
+    assert ra.stats.chunks == rb.stats.chunks and ra.stats.rollbacks == rb.stats.rollbacks
+
+
 def test_auto_form_follows_the_swap_range_length():
     # "auto" picks the two-pass form for an all-reactive system and the walk form for the site/colloid
     # mixture, before the first run's steps (speed only: both forms are checked against the oracle)

@@ -78,6 +78,11 @@ def test_planar_run_stays_in_the_plane():
     assert abs(ke2 / 2.0 - 1.0) < 0.12, ke2
 
 
+@pytest.mark.parametrize("form", ["walk", "sums"])
+def test_fused_step_unequal_pair_lambdas(form):
+    _one_step_check(W.unequal_lambda_mixture(N=3000, seed=62), "langevin", 0.002, 0.1, 1.0, 5, 7, form=form)
+
+
 def test_fused_step_matches_oracle_mixture():
     s = W.assembly_mixture(N=20000, lam=1.0, seed=1003, kT=0.05)
     _one_step_check(s, "langevin", 0.001, 0.05, 1.0, 2003, 123456789)

@@ -59,6 +59,14 @@ def test_assembly_mixture_small(lam, gather):
     _check_all(_system(s), s, gather)
 
 
+@pytest.mark.parametrize("gather", [False, True, "sums"])
+def test_unequal_pair_lambdas(gather):
+    # every swap pair with its own lambda and epsilon: triplet weights from unequal entries (reading 4)
+    s = W.unequal_lambda_mixture()
+    ref, _ = _check_all(_system(s), s, gather)
+    assert ref["n_triplets"] > 100
+
+
 def test_boundary_straddling_pairs():
     # triplets across every face and edge of the box
     L = 9.0

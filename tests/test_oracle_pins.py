@@ -140,6 +140,47 @@ def test_scenario_a_no_three_body_force(lam):
     assert a["E3"] == pytest.approx(lam * 1.0, abs=1e-14)
 
 
+def three_type_table(lam_ab, lam_bc, eps_ab=1.0, eps_bc=2.5):
+    """Swap pairs A-B and B-C with their own lambda and epsilon (types 0 = A, 1 = B, 2 = C); nothing else."""
+    t = W.PairTable.empty(3)
+    t.set(0, 1, W.KIND_SWAP, eps_ab, 1.0, 10, 1.5, lam_ab)
+    t.set(1, 2, W.KIND_SWAP, eps_bc, 1.0, 10, 1.5, lam_bc)
+    return t
+
+
+@pytest.mark.parametrize("lam_ab,lam_bc", [(0.5, 1.5), (1.0, 0.0), (2.0, 0.3)])
+def test_unequal_lambdas_at_rmin_give_the_geometric_mean(lam_ab, lam_bc):
+    """Reading of the triplet weight for unequal pair coefficients: Lambda_abc = sqrt(Lambda_ab Lambda_bc)
+    (Sec. 2 coefficient list), so with both partners of B inside r_min (vhat = 1, Fig. 1a) the three-body
+    energy is sqrt(lambda_ab eps_ab lambda_bc eps_bc) and no three-body force acts; lambda_bc = 0 removes
+    the term although the A-B pair alone would carry one."""
+    rm = 2.0 ** 0.1
+    pos = [[-0.99 * rm, 0, 0], [0, 0, 0], [0, 0.995 * rm, 0]]
+    ty = [0, 1, 2]
+    a = ev(pos, ty, 50.0, three_type_table(lam_ab, lam_bc))
+    b = ev(pos, ty, 50.0, three_type_table(0.0, 0.0))
+    assert a["E3"] == pytest.approx(math.sqrt(lam_ab * 1.0 * lam_bc * 2.5), rel=1e-13, abs=1e-15)
+    assert np.abs(a["F"] - b["F"]).max() < 1e-12
+    assert a["E"] - b["E"] == pytest.approx(a["E3"], rel=1e-12, abs=1e-15)
+
+
+def test_unequal_lambdas_forces_are_minus_energy_gradient():
+    """The same triplet with both partners in the attractive tail (vhat < 1): central differences of the
+    energy give the forces with unequal pair coefficients too."""
+    pos = np.array([[-1.21, 0.05, 0.0], [0.0, 0.0, 0.02], [0.03, 1.27, 0.0]])
+    ty = [0, 1, 2]
+    tab = three_type_table(0.7, 1.6)
+    out = ev(pos, ty, 50.0, tab)
+    assert out["E3"] != 0.0
+    h = 1e-6
+    for i in range(3):
+        for d in range(3):
+            p1 = pos.copy(); p1[i, d] += h
+            p0 = pos.copy(); p0[i, d] -= h
+            g = (ev(p1, ty, 50.0, tab)["E"] - ev(p0, ty, 50.0, tab)["E"]) / (2 * h)
+            assert out["F"][i, d] == pytest.approx(-g, rel=1e-6, abs=1e-7)
+
+
 def test_scenario_c_both_partners_feel_force():
     rm = 2.0 ** 0.1
     pos = [[-1.2, 0, 0], [0, 0, 0], [0, 1.25, 0]]

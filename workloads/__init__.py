@@ -29,7 +29,7 @@ from .systems import (  # noqa: F401
     KIND_NONE, KIND_SWAP, KIND_WCA, WCA_CUT_FACTOR,
     PairTable, System, fp32_box, wrap_fp32,
     swap_table_single, assembly_table,
-    small_reactive, assembly_mixture, replica_set, cluster, vitrimer_network, vitrimer_table,
+    small_reactive, unequal_lambda_mixture, assembly_mixture, replica_set, cluster, vitrimer_network, vitrimer_table,
     dumbbell_mixture, dumbbell_table, planar_reactive, patchy_mixture, patchy_table,
     maxwell_velocities, rsa_positions,
 )

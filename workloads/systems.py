@@ -327,6 +327,25 @@ def small_reactive(N=1000, density=0.2, seed=1001, min_dist=0.8, kT=0.1,
                   name=f"reactive N={N} rho={density}")
 
 
+def unequal_lambda_mixture(N=6000, density=0.3, seed=61, kT=0.1, min_dist=0.85) -> System:
+    """Three reactive types whose swap pairs each carry their own lambda, epsilon, sigma and cutoff, so a
+    triplet's weight combines unequal entries; type 1 - type 1 is WCA.  Uniform random sequential
+    addition."""
+    tab = PairTable.empty(3)
+    tab.set(0, 0, KIND_SWAP, 1.0, 1.0, 10, 1.5, 1.0)
+    tab.set(0, 1, KIND_SWAP, 1.5, 0.9, 10, 1.4, 0.4)
+    tab.set(0, 2, KIND_SWAP, 0.8, 1.1, 10, 1.6, 1.7)
+    tab.set(1, 2, KIND_SWAP, 2.0, 1.0, 10, 1.5, 0.9)
+    tab.set(1, 1, KIND_WCA, 1.0, 0.9, 6)
+    rng = np.random.default_rng(seed)
+    L = fp32_box(N, density)
+    pos, types = rsa_positions(rng, L, [N // 3, N // 3, N - 2 * (N // 3)], np.full((3, 3), min_dist))
+    mass = np.ones(3)
+    vel = maxwell_velocities(rng, types, mass, kT)
+    return System(pos=pos, types=types, L=L, table=tab, mass=mass, vel=vel,
+                  name=f"unequal-lambda mixture N={N}")
+
+
 def assembly_mixture(N=1048576, lam=1.0, density=0.3, seed=1003, kT=0.05,
                      frac_sites=0.5, min_frac=1.0) -> System:
     """Inert WCA colloids + reactive sites at total density ``density``.

@@ -204,6 +204,16 @@ def test_swap_barrier_symmetric_triplet(lam):
     assert tri - bonded == pytest.approx(3.0 * (lam + pv["barrier_over_eps_minus_lambda"]), abs=1e-12)
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 1.5])
+def test_per_particle_split_of_a_symmetric_triplet(lam):
+    """The per-particle split (half of each pair term to each particle, each triplet term to its centre)
+    in closed form: A-B-A with both pairs at r_min (v = -eps, vhat = 1) gives the A ends -eps/2 each and
+    the centre B 2 (-eps/2) + lambda eps."""
+    rm = 2.0 ** 0.1
+    out = ev([[-rm, 0, 0], [0, 0, 0], [rm, 0, 0]], [0, 1, 0], 50.0, two_type_table(lam, eps=3.0))
+    assert out["pe"] == pytest.approx([-1.5, 3.0 * (lam - 1.0), -1.5], abs=1e-12)
+
+
 @pytest.mark.parametrize("lam", [0.0, 1.0, 1.7])
 def test_equilateral_triangle(lam):
     # one reactive type: three pairs at r_min and three centres with two partners each
